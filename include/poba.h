@@ -1,0 +1,258 @@
+/*
+ * poba.h - C ABI of the MI355X (gfx950) power-series bundle-adjustment library.
+ *
+ * The library computes one Levenberg-Marquardt (LM) iteration of bundle
+ * adjustment the way Power Bundle Adjustment does (Weber, Demmel, Chan,
+ * Cremers, arXiv 2204.12834): residuals and Jacobian blocks of every
+ * observation, the block-diagonal damped normal-equation blocks, the Schur
+ * complement system for the cameras solved by the power series of the inverse
+ * Schur complement, back-substitution for the landmarks, and the accept/reject
+ * decision with the damping update.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Cameras are float64 [n_cams][9]: angle-axis rotation (3), translation (3),
+ *    focal length, radial k1, radial k2 (the BAL camera layout; the camera
+ *    looks down its -z axis; a point projects to f (1 + k1 |p|^2 + k2 |p|^4) p
+ *    with p = -P_xy / P_z, P = R(omega) X + t).  Landmarks are float64
+ *    [n_lms][3].  Observations are float64 [n_obs][2] pixel positions with
+ *    int32 camera and landmark indices.  The residual is model minus
+ *    observation; the cost is F = 1/2 sum_i rho(|r_i|^2) (Sec. 4 of the
+ *    paper; rho is the identity for the squared loss).
+ *  - Pointers documented [dev] are device pointers on the current HIP device;
+ *    [host] pointers are host memory.  The caller owns every buffer.  The
+ *    library never allocates device memory: all scratch lives in a caller
+ *    workspace whose size poba_workspace_bytes returns.
+ *  - Every call is asynchronous on the given stream (a hipStream_t passed as
+ *    void*; NULL is the default stream) unless stated otherwise.  Errors that
+ *    the host can detect are returned at once.  Errors that only the device
+ *    can see are OR-ed into a device status word (poba_solve_info.status,
+ *    poba_lm_state.status) so that calls stay free of host synchronisation.
+ *  - A handle may be used by one stream at a time; distinct handles are
+ *    independent.  Results are bitwise reproducible for the same inputs,
+ *    device and launch configuration: no floating-point atomics are used.
+ */
+#ifndef POBA_H
+#define POBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t poba_status;
+
+enum {
+    POBA_OK = 0,
+    POBA_ERR_INVALID_ARG = 1,  /* null pointer, negative size, bad enum value   */
+    POBA_ERR_INDEX_RANGE = 2,  /* an observation index is outside its range      */
+    POBA_ERR_NOT_SPD = 4,      /* a damped block had a non-positive pivot (bit)  */
+    POBA_ERR_NONFINITE = 8,    /* a residual or cost was not finite (bit)        */
+    POBA_ERR_HIP = 16,         /* a HIP runtime call or kernel launch failed     */
+    POBA_ERR_WORKSPACE = 32,   /* workspace missing, misaligned or too small     */
+    POBA_ERR_STATE = 64        /* call not valid in the handle's current state   */
+};
+
+/* Storage precision of the per-observation Jacobian blocks and of the
+ * landmark-side vectors of the series (Sec. 5 implements single- and
+ * double-precision solvers).  Camera-side vectors, U^-1, accumulations, the
+ * cost and the LM decision are float64 in every mode. */
+enum { POBA_F64 = 0, POBA_F32 = 1, POBA_F32_BF16J = 2 };
+
+/* D^T D of Sec. 4.1: Marquardt = diag(J^T J) clamped to [1e-6, 1e32]; identity = I. */
+enum { POBA_DAMP_MARQUARDT = 0, POBA_DAMP_IDENTITY = 1 };
+
+/* Loss on |r_i|^2: squared (Sec. 4) or Huber with IRLS reweighting. */
+enum { POBA_LOSS_L2 = 0, POBA_LOSS_HUBER = 1 };
+
+typedef void *poba_stream; /* hipStream_t */
+typedef struct poba_problem_s *poba_problem;
+
+/* [host] Problem description. */
+typedef struct {
+    int32_t n_cams;     /* >= 1 */
+    int32_t n_lms;      /* >= 1 */
+    int64_t n_obs;      /* >= 0, < 2^31 */
+    int32_t precision;  /* POBA_F64 / POBA_F32 / POBA_F32_BF16J */
+    int32_t damping;    /* POBA_DAMP_* */
+    int32_t loss;       /* POBA_LOSS_* */
+    int32_t piece_size; /* observations per camera-pass work item; 0 = default (2048) */
+    double huber_delta; /* pixels; used when loss == POBA_LOSS_HUBER, must be > 0 */
+} poba_desc;
+
+/* [dev] Written by poba_power_solve. */
+typedef struct {
+    int32_t stop_order; /* highest power of P in the result (Sec. 4.3, x(m))  */
+    int32_t stopped;    /* 1 if the stop rule (eq. qcriterion) ended the series early */
+    int32_t status;     /* OR of POBA_ERR_* bits seen on the device            */
+    int32_t reserved;
+    double norm_x;      /* |x(stop_order)|_2 over all camera parameters        */
+    double norm_v;      /* |x(stop_order) - x(stop_order - 1)|_2               */
+} poba_solve_info;
+
+/* [dev] LM state carried between poba_lm_step calls; set up by poba_lm_init. */
+typedef struct {
+    double lambda;         /* damping for the next step                          */
+    double nu;             /* growth factor applied on the next rejection        */
+    double cost;           /* F at the current state                             */
+    double cost_new;       /* F at state + step of the last iteration            */
+    double model_decrease; /* L(0) - L(dx) of the last iteration                 */
+    double gain;           /* (F - F_new) / (L(0) - L(dx)) of the last iteration */
+    int32_t iteration;     /* LM iterations taken (accepted or not)              */
+    int32_t accepted;      /* last step accepted                                 */
+    int32_t done;          /* 1 once converged or out of iterations              */
+    int32_t need_linearize;/* 1 if the next step must re-evaluate J and r        */
+    int32_t stop_order;    /* series order used by the last step                 */
+    int32_t status;        /* OR of POBA_ERR_* bits seen on the device           */
+    int32_t n_accepted;    /* accepted steps so far                              */
+    int32_t converged;     /* 1 if the relative function tolerance was met       */
+} poba_lm_state;
+
+/* [host] LM settings; poba_lm_default_options fills the values of Sec. 5.1. */
+typedef struct {
+    double lambda0;    /* initial damping (1e-4)                               */
+    double func_tol;   /* stop when (F_old - F_new) / F_old < func_tol (1e-6)  */
+    double eps;        /* series stop threshold of eq. qcriterion (0.01); 0 = fixed order */
+    double eta;        /* accept iff gain ratio > eta (1e-3)                   */
+    double lambda_min; /* damping clamp (1e-16)                                */
+    double lambda_max; /* damping clamp (1e16)                                 */
+    int32_t m;         /* maximal series order, number of P applications (20)  */
+    int32_t max_iters; /* maximal LM iterations (50)                           */
+} poba_lm_options;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t poba_version(void);
+
+/* Human-readable name of a status value (or of its lowest set bit). */
+const char *poba_status_string(poba_status s);
+
+/* Fills *o with the LM settings of Sec. 5.1. */
+void poba_lm_default_options(poba_lm_options *o);
+
+/* Bytes of device workspace a problem needs (pure host computation; 0 if the
+ * description is invalid).  The workspace holds the observation orders, the
+ * Jacobian blocks in both orders, all per-camera and per-landmark blocks and
+ * vectors, and the scratch of every call.  Rough size per observation:
+ * 2 x 24 Jacobian scalars + 60 bytes; per landmark about 200 bytes. */
+size_t poba_workspace_bytes(const poba_desc *d);
+
+/* Builds a problem: validates the indices, sorts the observations into a
+ * landmark-major and a camera-major order (stable, by original index), and
+ * lays out the work tiles of both passes.  obs_cam, obs_lm [dev] int32
+ * [n_obs]; obs_xy [dev] float64 [n_obs][2]; workspace [dev], 256-byte
+ * aligned, at least poba_workspace_bytes(d) bytes, owned by the caller and
+ * used by the handle until poba_destroy.  The inputs are copied and may be
+ * freed after the call returns.  Synchronises the stream (set-up only).
+ * Returns POBA_ERR_INDEX_RANGE if an index is out of range. */
+poba_status poba_create(const poba_desc *d, const int32_t *obs_cam, const int32_t *obs_lm,
+                        const double *obs_xy, void *workspace, size_t workspace_bytes,
+                        poba_stream stream, poba_problem *out);
+
+/* Releases the host-side handle (the workspace stays the caller's). */
+poba_status poba_destroy(poba_problem p);
+
+/* Sec. 4 and 4.1: evaluates residuals r_i and Jacobian blocks J_p (2x9),
+ * J_l (2x3) at cams [dev] float64 [n_cams][9], lms [dev] float64 [n_lms][3];
+ * applies the Huber reweighting if configured; stores the blocks (rounded to
+ * the storage precision) in both observation orders; accumulates the
+ * undamped blocks U = J_p^T J_p, V = J_l^T J_l and b_p = J_p^T r,
+ * b_l = J_l^T r in float64 from the rounded blocks; writes F to cost [dev]
+ * (one float64; may be NULL). */
+poba_status poba_linearize(poba_problem p, const double *cams, const double *lms, double *cost,
+                           poba_stream stream);
+
+/* Sec. 4.2-4.3: with the blocks of the last poba_linearize, forms
+ * U_lambda = U + lambda D_p^T D_p and V_lambda likewise (eq. normal), inverts
+ * every block in float64, forms b~ = b_p - W V^-1 b_l (eq. Schur), sums the
+ * power series x(m) = -sum_{i=0..m} (U^-1 W V^-1 W^T)^i U^-1 b~ (eqs.
+ * S_approx, x_approx) matrix-free, stopping early when
+ * (i+1) |x(i) - x(i-1)| / |x(i)| < eps (eq. qcriterion; eps = 0 gives the
+ * fixed order m), and back-substitutes dx_l = -V^-1 (b_l + W^T dx_p) (the
+ * sign that solves eq. normal; the paper prints -b_l).
+ * dx_cams [dev] float64 [n_cams][9], dx_lms [dev] float64 [n_lms][3],
+ * info [dev] (may be NULL).  lambda > 0, 0 <= m <= 100000, eps >= 0. */
+poba_status poba_power_solve(poba_problem p, double lambda, int32_t m, double eps, double *dx_cams,
+                             double *dx_lms, poba_solve_info *info, poba_stream stream);
+
+/* Resets an LM state [dev]: lambda = lambda0, nu = 2, iteration 0, needs a
+ * linearisation, not done. */
+poba_status poba_lm_init(poba_problem p, poba_lm_state *st, const poba_lm_options *o,
+                         poba_stream stream);
+
+/* One LM iteration (Sec. 5.1 "LM loop") on the state cams, lms [dev] (updated
+ * in place when the step is accepted) and st [dev]: linearises if the last
+ * step was accepted (or on the first call), solves with st->lambda as
+ * poba_power_solve does (order o->m, threshold o->eps), evaluates F at the
+ * trial state and the undamped linear-model decrease L(0) - L(dx), accepts
+ * iff F_new is finite, L(0) - L(dx) > 0 and the gain ratio exceeds o->eta,
+ * and updates lambda (success: lambda *= max(1/3, 1 - (2 rho - 1)^3), nu = 2;
+ * failure: lambda *= nu, nu *= 2).  Once st->done is set, further calls do
+ * nothing.  No host synchronisation: the call can be captured in a graph. */
+poba_status poba_lm_step(poba_problem p, double *cams, double *lms, poba_lm_state *st,
+                         const poba_lm_options *o, poba_stream stream);
+
+/* Model pixel positions out_xy [dev] float64 [n_obs][2] of observations
+ * (obs_cam, obs_lm [dev] int32 [n_obs]) at cams, lms [dev].  Needs no handle;
+ * indices must be in range (they are not checked). */
+poba_status poba_project(int64_t n_obs, const int32_t *obs_cam, const int32_t *obs_lm,
+                         const double *cams, const double *lms, double *out_xy,
+                         poba_stream stream);
+
+/* ---- inspection (tests, diagnostics) ---------------------------------- */
+
+/* Copies the undamped blocks of the last linearisation: U [dev] float64
+ * [n_cams][9][9], V [dev] float64 [n_lms][3][3], b_p [n_cams][9],
+ * b_l [n_lms][3].  Any pointer may be NULL. */
+poba_status poba_get_blocks(poba_problem p, double *U, double *V, double *bp, double *bl,
+                            poba_stream stream);
+
+/* Copies the stored Jacobian blocks of one order (0 = landmark-major,
+ * 1 = camera-major), widened to float64 and put back in original
+ * observation order: Jp [dev] [n_obs][2][9], Jl [dev] [n_obs][2][3].
+ * r [dev] [n_obs][2] receives the (reweighted) residual; it may be NULL. */
+poba_status poba_get_jacobians(poba_problem p, int32_t order, double *Jp, double *Jl, double *r,
+                               poba_stream stream);
+
+/* The observation orders: perm_lm, perm_cam [dev] int32 [n_obs] (original
+ * index of each position), lm_off [dev] int32 [n_lms + 1], cam_off [dev]
+ * int32 [n_cams + 1].  Any pointer may be NULL. */
+poba_status poba_get_orders(poba_problem p, int32_t *perm_lm, int32_t *perm_cam, int32_t *lm_off,
+                            int32_t *cam_off, poba_stream stream);
+
+/* One application of P = U^-1 W V^-1 W^T (Sec. 4.3) with the damped
+ * inverses of the last poba_power_solve: v_out = P v_in, both [dev] float64
+ * [n_cams][9]. */
+poba_status poba_apply_P(poba_problem p, const double *v_in, double *v_out, poba_stream stream);
+
+/* ---- timing (benchmarks) ---------------------------------------------- */
+
+/* Kernel classes timed with events when profiling is on. */
+enum {
+    POBA_K_LINEARIZE = 0, /* both linearisation passes                   */
+    POBA_K_INVERSE = 1,   /* damped block inversions                      */
+    POBA_K_LM_PASS = 2,   /* landmark pass: t_l = W^T v, s_l = V^-1 t_l   */
+    POBA_K_CAM_PASS = 3,  /* camera pass: per-piece partial W s           */
+    POBA_K_CAM_FIN = 4,   /* camera finalize: U^-1, series sum, norms     */
+    POBA_K_BACKSUB = 5,   /* back-substitution                            */
+    POBA_K_EVAL = 6,      /* trial cost and model decrease                */
+    POBA_K_OTHER = 7,
+    POBA_K_COUNT = 8
+};
+
+/* Turns per-launch event timing on (1) or off (0).  While on, every launch
+ * is bracketed by hipEventRecord on its stream; timings accumulate until
+ * read.  At most 65536 timed launches between reads. */
+poba_status poba_profile_enable(poba_problem p, int32_t enable);
+
+/* Synchronises on the recorded events and returns, per kernel class, the
+ * summed milliseconds ms[POBA_K_COUNT] and launch counts n[POBA_K_COUNT]
+ * [host] since the last read; then clears them. */
+poba_status poba_profile_read(poba_problem p, double *ms, int64_t *n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POBA_H */

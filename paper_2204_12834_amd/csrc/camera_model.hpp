@@ -1,0 +1,165 @@
+// Residual and Jacobian blocks of one observation (float64).
+//
+// Camera (BAL layout): omega (angle-axis), t, f, k1, k2.  With
+// theta^2 = omega.omega, A = sin(theta)/theta, B = (1 - cos(theta))/theta^2:
+//
+//   R X = X + A (omega x X) + B (omega x (omega x X))          (Rodrigues)
+//   P   = R X + t,   p = -P_xy / P_z,   d = 1 + k1 |p|^2 + k2 |p|^4
+//   pi  = f d p,     r = pi - o
+//
+// d(R X)/d omega_j follows from the product rule on the three terms, with
+// dA/domega_j = C omega_j and dB/domega_j = D omega_j where
+// C = A'(theta)/theta = (theta cos(theta) - sin(theta)) / theta^3 and
+// D = B'(theta)/theta = (theta sin(theta) - 2 (1 - cos(theta))) / theta^4;
+// A, B, C, D switch to their Taylor series below theta^2 = 1e-3.
+//
+// Floating-point contraction is off inside these functions so that the
+// landmark-major and camera-major passes, which both call them, produce
+// bit-identical blocks wherever the compiler inlines them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace poba {
+
+struct ObsEval {
+    double r[2];
+    double J[24];  // J_p row 0 (9), J_p row 1 (9), J_l row 0 (3), J_l row 1 (3)
+};
+
+__device__ __forceinline__ void rodrigues_coeffs(double th2, double& A, double& B, double& C, double& D) {
+#pragma clang fp contract(off)
+    if (th2 < 1e-3) {
+        const double t4 = th2 * th2, t6 = t4 * th2;
+        A = 1.0 - th2 / 6.0 + t4 / 120.0 - t6 / 5040.0;
+        B = 0.5 - th2 / 24.0 + t4 / 720.0 - t6 / 40320.0;
+        C = -1.0 / 3.0 + th2 / 30.0 - t4 / 840.0 + t6 / 45360.0;
+        D = -1.0 / 12.0 + th2 / 180.0 - t4 / 6720.0 + t6 / 453600.0;
+    } else {
+        const double th = sqrt(th2);
+        double s, c;
+        sincos(th, &s, &c);
+        const double omc = 2.0 * sin(0.5 * th) * sin(0.5 * th);
+        A = s / th;
+        B = omc / th2;
+        C = (th * c - s) / (th2 * th);
+        D = (th * s - 2.0 * omc) / (th2 * th2);
+    }
+}
+
+__device__ __forceinline__ void cross3(const double* a, const double* b, double* o) {
+#pragma clang fp contract(off)
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Camera-frame point of landmark X (no derivatives).
+__device__ __forceinline__ void transform_point(const double* cam, const double* X, double* P) {
+#pragma clang fp contract(off)
+    const double* w = cam;
+    const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    double A, B, C, D;
+    rodrigues_coeffs(th2, A, B, C, D);
+    double wx[3], wwx[3];
+    cross3(w, X, wx);
+    cross3(w, wx, wwx);
+    for (int k = 0; k < 3; ++k) P[k] = X[k] + A * wx[k] + B * wwx[k] + cam[3 + k];
+}
+
+__device__ __forceinline__ void project_point(const double* cam, const double* X, double* px) {
+#pragma clang fp contract(off)
+    double P[3];
+    transform_point(cam, X, P);
+    const double iz = 1.0 / P[2];
+    const double p0 = -P[0] * iz, p1 = -P[1] * iz;
+    const double r2 = p0 * p0 + p1 * p1;
+    const double d = 1.0 + cam[7] * r2 + cam[8] * r2 * r2;
+    px[0] = cam[6] * d * p0;
+    px[1] = cam[6] * d * p1;
+}
+
+__device__ __forceinline__ void evaluate_obs(const double* cam, const double* X, double ox, double oy, ObsEval& e) {
+#pragma clang fp contract(off)
+    const double* w = cam;
+    const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    double A, B, C, D;
+    rodrigues_coeffs(th2, A, B, C, D);
+    double wx[3], wwx[3];
+    cross3(w, X, wx);
+    cross3(w, wx, wwx);
+    double P[3];
+    for (int k = 0; k < 3; ++k) P[k] = X[k] + A * wx[k] + B * wwx[k] + cam[3 + k];
+
+    // rotation matrix R = I + A [w]x + B [w]x^2, [w]x^2 = w w^T - th2 I
+    double R[3][3];
+    R[0][0] = 1.0 + B * (w[0] * w[0] - th2);
+    R[1][1] = 1.0 + B * (w[1] * w[1] - th2);
+    R[2][2] = 1.0 + B * (w[2] * w[2] - th2);
+    R[0][1] = -A * w[2] + B * w[0] * w[1];
+    R[1][0] = A * w[2] + B * w[0] * w[1];
+    R[0][2] = A * w[1] + B * w[0] * w[2];
+    R[2][0] = -A * w[1] + B * w[0] * w[2];
+    R[1][2] = -A * w[0] + B * w[1] * w[2];
+    R[2][1] = A * w[0] + B * w[1] * w[2];
+
+    // dRX[k][j] = d(R X)_k / d omega_j
+    //   = C w_j (w x X)_k + A (e_j x X)_k + D w_j (w x (w x X))_k
+    //     + B ( (e_j x (w x X))_k + (w x (e_j x X))_k )
+    double dRX[3][3];
+    for (int j = 0; j < 3; ++j) {
+        double ej[3] = {0.0, 0.0, 0.0};
+        ej[j] = 1.0;
+        double ejX[3], ejwx[3], wejX[3];
+        cross3(ej, X, ejX);
+        cross3(ej, wx, ejwx);
+        cross3(w, ejX, wejX);
+        for (int k = 0; k < 3; ++k)
+            dRX[k][j] = C * w[j] * wx[k] + A * ejX[k] + D * w[j] * wwx[k] + B * (ejwx[k] + wejX[k]);
+    }
+
+    const double iz = 1.0 / P[2];
+    const double p[2] = {-P[0] * iz, -P[1] * iz};
+    const double r2 = p[0] * p[0] + p[1] * p[1];
+    const double f = cam[6], k1 = cam[7], k2 = cam[8];
+    const double d = 1.0 + k1 * r2 + k2 * r2 * r2;
+    const double dd = 2.0 * (k1 + 2.0 * k2 * r2);  // d(d)/dp = dd * p^T
+
+    e.r[0] = f * d * p[0] - ox;
+    e.r[1] = f * d * p[1] - oy;
+
+    // dpi/dp = f (d I + p dd p^T);  dp/dP = [[-iz, 0, P0 iz^2], [0, -iz, P1 iz^2]]
+    double dpi_dp[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) dpi_dp[a][b] = f * ((a == b ? d : 0.0) + p[a] * dd * p[b]);
+    const double dp_dP[2][3] = {{-iz, 0.0, P[0] * iz * iz}, {0.0, -iz, P[1] * iz * iz}};
+    double JP[2][3];
+    for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 3; ++c) JP[a][c] = dpi_dp[a][0] * dp_dP[0][c] + dpi_dp[a][1] * dp_dP[1][c];
+
+    for (int a = 0; a < 2; ++a) {
+        double* Jp = e.J + 9 * a;
+        for (int j = 0; j < 3; ++j) Jp[j] = JP[a][0] * dRX[0][j] + JP[a][1] * dRX[1][j] + JP[a][2] * dRX[2][j];
+        for (int j = 0; j < 3; ++j) Jp[3 + j] = JP[a][j];
+        Jp[6] = d * p[a];
+        Jp[7] = f * r2 * p[a];
+        Jp[8] = f * r2 * r2 * p[a];
+        double* Jl = e.J + 18 + 3 * a;
+        for (int j = 0; j < 3; ++j) Jl[j] = JP[a][0] * R[0][j] + JP[a][1] * R[1][j] + JP[a][2] * R[2][j];
+    }
+}
+
+// Huber on s = |r|^2: rho(s) = s (s <= delta^2), 2 delta sqrt(s) - delta^2 otherwise;
+// IRLS weight w = rho'(s) = min(1, delta / sqrt(s)).
+__device__ __forceinline__ void huber(double s, double delta, double& rho, double& w) {
+    if (s <= delta * delta) {
+        rho = s;
+        w = 1.0;
+    } else {
+        const double rs = sqrt(s);
+        rho = 2.0 * delta * rs - delta * delta;
+        w = delta / rs;
+    }
+}
+
+}  // namespace poba

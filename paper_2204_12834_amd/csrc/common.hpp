@@ -1,0 +1,337 @@
+// Shared definitions of the gfx950 power-series bundle-adjustment library:
+// the problem handle, the workspace layout, storage types and wave helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "poba.h"
+
+namespace poba {
+using Problem = ::poba_problem_s;
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kDefaultPiece = 2048;
+constexpr uint32_t kHeadBit = 0x80000000u;
+constexpr uint32_t kIndexMask = 0x7fffffffu;
+constexpr int kMaxProfiled = 65536;
+constexpr int kTickets = 8;
+
+// ---------------------------------------------------------------- storage --
+
+// bfloat16 payload (upper half of a float32).
+struct bf16_t {
+    uint16_t bits;
+};
+
+__host__ __device__ inline float bf16_to_float(uint16_t b) {
+    uint32_t u = uint32_t(b) << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+__host__ __device__ inline uint16_t float_to_bf16(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return uint16_t(u >> 16);
+}
+
+// Per-observation Jacobian record: 24 scalars, J_p row 0 (9), J_p row 1 (9),
+// J_l row 0 (3), J_l row 1 (3).  Stored structure-of-arrays in 16-byte groups:
+// group g of observation i lives at byte (g * npad + i) * 16.
+template <typename TJ>
+struct JLayout;
+template <>
+struct JLayout<double> {
+    static constexpr int kPerGroup = 2;
+    static constexpr int kGroups = 12;
+};
+template <>
+struct JLayout<float> {
+    static constexpr int kPerGroup = 4;
+    static constexpr int kGroups = 6;
+};
+template <>
+struct JLayout<bf16_t> {
+    static constexpr int kPerGroup = 8;
+    static constexpr int kGroups = 3;
+};
+
+template <typename TJ>
+__device__ __forceinline__ void store_J(void* base, int64_t npad, int64_t i, const double* v);
+
+template <>
+__device__ __forceinline__ void store_J<double>(void* base, int64_t npad, int64_t i, const double* v) {
+    double2* b = reinterpret_cast<double2*>(base);
+#pragma unroll
+    for (int g = 0; g < 12; ++g) b[g * npad + i] = make_double2(v[2 * g], v[2 * g + 1]);
+}
+template <>
+__device__ __forceinline__ void store_J<float>(void* base, int64_t npad, int64_t i, const double* v) {
+    float4* b = reinterpret_cast<float4*>(base);
+#pragma unroll
+    for (int g = 0; g < 6; ++g)
+        b[g * npad + i] = make_float4(float(v[4 * g]), float(v[4 * g + 1]), float(v[4 * g + 2]), float(v[4 * g + 3]));
+}
+template <>
+__device__ __forceinline__ void store_J<bf16_t>(void* base, int64_t npad, int64_t i, const double* v) {
+    uint4* b = reinterpret_cast<uint4*>(base);
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        uint32_t w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            uint32_t lo = float_to_bf16(float(v[8 * g + 2 * k]));
+            uint32_t hi = float_to_bf16(float(v[8 * g + 2 * k + 1]));
+            w[k] = lo | (hi << 16);
+        }
+        b[g * npad + i] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+// Rounds a record to the storage type and back (the values every pass sees).
+template <typename TJ>
+__device__ __forceinline__ double round_to_storage(double v);
+template <>
+__device__ __forceinline__ double round_to_storage<double>(double v) { return v; }
+template <>
+__device__ __forceinline__ double round_to_storage<float>(double v) { return double(float(v)); }
+template <>
+__device__ __forceinline__ double round_to_storage<bf16_t>(double v) {
+    return double(bf16_to_float(float_to_bf16(float(v))));
+}
+
+template <typename TJ, typename TC>
+__device__ __forceinline__ void load_J(const void* base, int64_t npad, int64_t i, TC* v);
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+template <typename TC>
+__device__ __forceinline__ void load_J_d(const void* base, int64_t npad, int64_t i, TC* v) {
+    const d2v* b = reinterpret_cast<const d2v*>(base);
+#pragma unroll
+    for (int g = 0; g < 12; ++g) {
+        d2v x = __builtin_nontemporal_load(&b[g * npad + i]);
+        v[2 * g] = TC(x.x);
+        v[2 * g + 1] = TC(x.y);
+    }
+}
+template <typename TC>
+__device__ __forceinline__ void load_J_f(const void* base, int64_t npad, int64_t i, TC* v) {
+    const f4v* b = reinterpret_cast<const f4v*>(base);
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+        f4v x = __builtin_nontemporal_load(&b[g * npad + i]);
+        v[4 * g] = TC(x.x);
+        v[4 * g + 1] = TC(x.y);
+        v[4 * g + 2] = TC(x.z);
+        v[4 * g + 3] = TC(x.w);
+    }
+}
+template <typename TC>
+__device__ __forceinline__ void load_J_b(const void* base, int64_t npad, int64_t i, TC* v) {
+    const u4v* b = reinterpret_cast<const u4v*>(base);
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        u4v x = __builtin_nontemporal_load(&b[g * npad + i]);
+        uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[8 * g + 2 * k] = TC(bf16_to_float(uint16_t(w[k] & 0xffffu)));
+            v[8 * g + 2 * k + 1] = TC(bf16_to_float(uint16_t(w[k] >> 16)));
+        }
+    }
+}
+template <>
+__device__ __forceinline__ void load_J<double, double>(const void* b, int64_t n, int64_t i, double* v) { load_J_d(b, n, i, v); }
+template <>
+__device__ __forceinline__ void load_J<float, float>(const void* b, int64_t n, int64_t i, float* v) { load_J_f(b, n, i, v); }
+template <>
+__device__ __forceinline__ void load_J<float, double>(const void* b, int64_t n, int64_t i, double* v) { load_J_f(b, n, i, v); }
+template <>
+__device__ __forceinline__ void load_J<bf16_t, float>(const void* b, int64_t n, int64_t i, float* v) { load_J_b(b, n, i, v); }
+template <>
+__device__ __forceinline__ void load_J<bf16_t, double>(const void* b, int64_t n, int64_t i, double* v) { load_J_b(b, n, i, v); }
+
+// ------------------------------------------------------------ wave helpers --
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+// Mask of lanes 0..lane inclusive.
+__device__ __forceinline__ uint64_t mask_upto(int lane) {
+    return lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+}
+
+// Inclusive segmented scan over the wave.  seg_start is the first lane of the
+// calling lane's segment; after the call v[k] holds the sum of v[k] over
+// lanes seg_start..lane.
+template <typename T, int K>
+__device__ __forceinline__ void segmented_scan(T* v, int lane, int seg_start) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const bool take = lane - d >= seg_start;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            T y = __shfl_up(v[k], d, kWave);
+            if (take) v[k] += y;
+        }
+    }
+}
+
+// Butterfly sum over the wave (every lane gets the total).
+template <typename T, int K>
+__device__ __forceinline__ void wave_sum(T* v) {
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], d, kWave);
+    }
+}
+
+// Error-free sum (Knuth TwoSum) for compensated float64 accumulation.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+    s = a + b;
+    double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// ---------------------------------------------------------------- control --
+
+// Device control block of a handle.
+struct Ctrl {
+    double lambda;       // damping of the current solve
+    double red[8];       // results of grid reductions
+    double norm_x2, norm_v2;
+    int32_t active;      // 1 while the current call does work
+    int32_t lin;         // 1 if the current lm step linearises
+    int32_t stopped;     // series ended by the stop rule
+    int32_t stop_order;  // last order summed
+    int32_t status;      // OR of POBA_ERR_* bits
+    int32_t accepted;    // last lm step accepted
+    uint32_t ticket[kTickets];
+};
+
+enum Ticket { kTicketCost = 0, kTicketNorm = 1, kTicketEval = 2, kTicketSpare = 3 };
+
+// ---------------------------------------------------------------- handle --
+
+struct Buffers {
+    // observation orders
+    int32_t* perm_l;      // [N] original index at each landmark-major position
+    int32_t* perm_c;      // [N] original index at each camera-major position
+    uint32_t* lo_cam;     // [N] camera at each landmark-major position | head bit
+    int32_t* co_lm;       // [N] landmark at each camera-major position
+    int32_t* lm_off;      // [nl+1]
+    int32_t* cam_off;     // [nc+1]
+    int32_t* nel;         // [nl] non-empty landmarks in order
+    int32_t* tile_start;  // [ntiles+1] first landmark-major position of each 64-tile
+    int32_t* seg_base;    // [ntiles] index into nel of each tile's first segment
+    int32_t* piece_cam;   // [npieces_max]
+    int32_t* piece_begin; // [npieces_max]
+    int32_t* piece_end;   // [npieces_max]
+    int32_t* cam_piece;   // [nc+1]
+    double* obs_lo;       // [N][2] observations, landmark-major
+    double* obs_co;       // [N][2] observations, camera-major
+    // linearisation
+    void* J_lo;           // Jacobian records, landmark-major
+    void* J_co;           // Jacobian records, camera-major
+    double* r_lo;         // [N][2] reweighted residual, landmark-major
+    double* U;            // [nc][81] undamped
+    double* bp;           // [nc][9]
+    double* V;            // [nl][6] undamped, packed (00 01 02 11 12 22)
+    double* bl;           // [nl][3]
+    // solve
+    double* Uinv;         // [nc][81]
+    void* Vinv;           // [nl][6] storage type
+    void* s;              // [nl][4] storage type (landmark vector of the series)
+    double* v;            // [nc][9] current series term
+    void* vq;             // [nc][12] current term in storage type (gather copy)
+    double* x;            // [nc][9] series sum
+    double* part;         // [npieces_max][54] per-piece partial sums
+    double* dxl;          // [nl][3] landmark step (lm step)
+    double* dxp;          // [nc][9] camera step (lm step)
+    double* cams_new;     // [nc][9]
+    double* lms_new;      // [nl][3]
+    double* red_part;     // [kRedParts][4] grid-reduction partials
+    double* cam_norm;     // [nc][2] per-camera norm partials
+    Ctrl* ctrl;
+    void* sort_tmp;       // radix-sort scratch
+    size_t sort_tmp_bytes;
+    int32_t* keys_tmp;    // [N]
+    int32_t* vals_tmp;    // [N]
+    int32_t* keys_out;    // [N]
+    int32_t* iota;        // [N]
+    int32_t* scratch_i;   // [max(nc, nl) + 2]
+};
+
+struct Sizes {
+    int32_t nc, nl;
+    int64_t N, npad, ntiles, npieces_max;
+    int piece;
+    int jbytes;  // bytes per stored Jacobian scalar
+    int sbytes;  // bytes per stored landmark-side scalar
+    int64_t red_parts;
+};
+
+struct ProfileSlot {
+    hipEvent_t start, stop;
+    int cls;
+};
+
+}  // namespace poba
+
+struct poba_problem_s {
+    poba_desc d;
+    poba::Sizes z;
+    poba::Buffers b;
+    int64_t npieces = 0;
+    int64_t nnel = 0;
+    hipStream_t last_stream = nullptr;
+    // profiling
+    bool profiling = false;
+    std::vector<poba::ProfileSlot> slots;
+    size_t slot_used = 0;
+    double prof_ms[POBA_K_COUNT] = {0};
+    int64_t prof_n[POBA_K_COUNT] = {0};
+};
+
+namespace poba {
+
+// Workspace layout (defined in setup.hip).
+bool compute_sizes(const poba_desc* d, Sizes* z);
+size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t sort_tmp_bytes);
+size_t sort_tmp_upper_bound(int64_t N);
+
+// Launch bracketing for profiling.
+void prof_begin(Problem* p, int cls, hipStream_t s, ProfileSlot** slot);
+void prof_end(ProfileSlot* slot, hipStream_t s);
+
+struct ProfScope {
+    ProfileSlot* slot = nullptr;
+    hipStream_t s;
+    ProfScope(Problem* p, int cls, hipStream_t st) : s(st) { prof_begin(p, cls, st, &slot); }
+    ~ProfScope() { prof_end(slot, s); }
+};
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline poba_status hip_check(hipError_t e) { return e == hipSuccess ? POBA_OK : POBA_ERR_HIP; }
+
+#define POBA_LAUNCH_CHECK()                                  \
+    do {                                                     \
+        if (hipGetLastError() != hipSuccess) return POBA_ERR_HIP; \
+    } while (0)
+
+}  // namespace poba

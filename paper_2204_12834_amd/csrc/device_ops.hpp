@@ -1,0 +1,183 @@
+// Device building blocks shared by the passes: the landmark-tile iteration with
+// its segmented reduction, deterministic block and grid reductions, and the
+// small symmetric block inverses.
+#pragma once
+
+#include "common.hpp"
+
+namespace poba {
+
+// ------------------------------------------------------ landmark-tile loop --
+//
+// One wavefront walks the landmark-major positions of its tile in chunks of
+// 64.  `obs(i, valid, cam, seg, v)` fills K values for position i (zero when
+// !valid); seg indexes the non-empty-landmark list of the landmark owning i.
+// A segmented inclusive scan over the chunk (carrying the open segment into
+// the next chunk) leaves every landmark's total in its last position, where
+// `tail(seg, v)` is called.  No other wavefront touches the tile's landmarks.
+template <typename T, int K, typename Obs, typename Tail>
+__device__ __forceinline__ void tile_landmarks(const uint32_t* __restrict__ lo_cam, const int32_t* __restrict__ tile_start,
+                                               const int32_t* __restrict__ seg_base, int64_t tile, Obs&& obs,
+                                               Tail&& tail) {
+    const int lane = lane_id();
+    const int32_t start = tile_start[tile];
+    const int32_t end = tile_start[tile + 1];
+    int32_t seg = seg_base[tile] - 1;  // segment open at the chunk start
+    T carry[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) carry[k] = T(0);
+    for (int32_t base = start; base < end; base += kWave) {
+        const int32_t i = base + lane;
+        const bool valid = i < end;
+        const uint32_t w = valid ? lo_cam[i] : 0u;
+        const bool head = valid && (w & kHeadBit);
+        const uint64_t hm = ballot64(head);
+        const uint64_t hu = hm & mask_upto(lane);
+        const int seg_start = hu ? 63 - __builtin_clzll(hu) : 0;
+        const int32_t my_seg = seg + __popcll(hu);
+        T v[K];
+        obs(i, valid, int32_t(w & kIndexMask), my_seg, v);
+        if (lane == 0 && !head) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] += carry[k];
+        }
+        segmented_scan<T, K>(v, lane, seg_start);
+        const int last = min(end - base, kWave) - 1;
+        bool is_tail;
+        if (lane < last) {
+            is_tail = (hm >> (lane + 1)) & 1ull;
+        } else if (lane == last) {
+            is_tail = (i + 1 == end) || (lo_cam[i + 1] & kHeadBit);
+        } else {
+            is_tail = false;
+        }
+        if (is_tail) tail(my_seg, v);
+#pragma unroll
+        for (int k = 0; k < K; ++k) carry[k] = __shfl(v[k], last, kWave);
+        seg += __popcll(hm);
+    }
+}
+
+// --------------------------------------------------------- block reductions --
+
+// Sum of K values over the block; the result is valid in thread 0.  lds holds
+// kWavesPerBlock * K doubles.
+template <int K>
+__device__ __forceinline__ void block_sum(double* v, double* lds) {
+    wave_sum<double, K>(v);
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int nw = blockDim.x / kWave;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[w * K + k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+            for (int j = 0; j < nw; ++j) s += lds[j * K + k];
+            v[k] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Deterministic grid-wide sum: every block passes its block total (thread 0's
+// v); the last block to arrive sums all block totals in block order with
+// compensated (TwoSum) accumulation and returns true in all its threads with
+// the totals in thread 0's out[].  The ticket is reset for the next use.
+template <int K>
+__device__ __forceinline__ bool grid_sum_last(const double* v, double* partials, uint32_t* ticket, uint32_t nblocks,
+                                              double* out, double* lds) {
+    __shared__ int is_last;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) partials[size_t(blockIdx.x) * K + k] = v[k];
+        __threadfence();
+        const uint32_t t = atomicAdd(ticket, 1u);
+        is_last = (t == nblocks - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+    double s[K], e[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] = e[k] = 0.0;
+    for (uint32_t bI = threadIdx.x; bI < nblocks; bI += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const volatile double* pp = partials;
+            double t, err;
+            two_sum(s[k], pp[size_t(bI) * K + k], t, err);
+            s[k] = t;
+            e[k] += err;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] += e[k];
+    block_sum<K>(s, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[k] = s[k];
+        atomicExch(ticket, 0u);
+    }
+    return true;
+}
+
+// -------------------------------------------------------- small inverses --
+
+// Damping diagonal of one block entry (Sec. 4.1 D^T D): Marquardt uses the
+// clamped diagonal of J^T J, identity uses 1.
+__device__ __forceinline__ double damp_diag(double diag, int damping) {
+    return damping == POBA_DAMP_MARQUARDT ? fmin(fmax(diag, 1e-6), 1e32) : 1.0;
+}
+
+// Inverse of the damped 3x3 block V + lambda D (packed 00 01 02 11 12 22) by
+// Cholesky; returns false (and the inverse of the damping diagonal) if a pivot
+// is not positive.
+__device__ __forceinline__ bool inv3_damped(const double* V, double lam, int damping, double* out) {
+    const double d0 = damp_diag(V[0], damping), d1 = damp_diag(V[3], damping), d2 = damp_diag(V[5], damping);
+    const double a00 = V[0] + lam * d0, a01 = V[1], a02 = V[2];
+    const double a11 = V[3] + lam * d1, a12 = V[4], a22 = V[5] + lam * d2;
+    bool ok = a00 > 0.0;
+    const double l00 = sqrt(a00);
+    const double l10 = a01 / l00, l20 = a02 / l00;
+    const double q11 = a11 - l10 * l10;
+    ok = ok && q11 > 0.0;
+    const double l11 = sqrt(q11);
+    const double l21 = (a12 - l20 * l10) / l11;
+    const double q22 = a22 - l20 * l20 - l21 * l21;
+    ok = ok && q22 > 0.0;
+    const double l22 = sqrt(q22);
+    // M = L^-1 (lower)
+    const double m00 = 1.0 / l00, m11 = 1.0 / l11, m22 = 1.0 / l22;
+    const double m10 = -l10 * m00 * m11;
+    const double m21 = -l21 * m11 * m22;
+    const double m20 = -(l20 * m00 + l21 * m10) * m22;
+    // inverse = M^T M
+    out[0] = m00 * m00 + m10 * m10 + m20 * m20;
+    out[1] = m10 * m11 + m20 * m21;
+    out[2] = m20 * m22;
+    out[3] = m11 * m11 + m21 * m21;
+    out[4] = m21 * m22;
+    out[5] = m22 * m22;
+    ok = ok && isfinite(out[0]) && isfinite(out[3]) && isfinite(out[5]);
+    if (!ok) {
+        const double e0 = lam * d0, e1 = lam * d1, e2 = lam * d2;
+        out[0] = e0 > 0.0 ? 1.0 / e0 : 0.0;
+        out[1] = out[2] = out[4] = 0.0;
+        out[3] = e1 > 0.0 ? 1.0 / e1 : 0.0;
+        out[5] = e2 > 0.0 ? 1.0 / e2 : 0.0;
+    }
+    return ok;
+}
+
+template <typename T>
+__device__ __forceinline__ void sym3_apply(const T* A, const T* x, T* y) {
+    y[0] = A[0] * x[0] + A[1] * x[1] + A[2] * x[2];
+    y[1] = A[1] * x[0] + A[3] * x[1] + A[4] * x[2];
+    y[2] = A[2] * x[0] + A[4] * x[1] + A[5] * x[2];
+}
+
+}  // namespace poba

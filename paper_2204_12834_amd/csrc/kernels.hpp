@@ -1,0 +1,21 @@
+// Host-side entry points shared between translation units of the library.
+#pragma once
+
+#include "common.hpp"
+
+namespace poba {
+
+// Linearisation passes; gate (device, may be null) skips the work when 0.
+poba_status launch_linearize(Problem* p, const double* cams, const double* lms, const int32_t* gate,
+                             double* cost_out, double* cost_out2, hipStream_t s);
+
+// Damped inverses, reduced right-hand side, power series and
+// back-substitution with the damping in ctrl->lambda; skipped unless
+// ctrl->active.  Writes dx_cams / dx_lms; info (device, may be null).
+poba_status launch_solve(Problem* p, int m, double eps, double* dx_cams, double* dx_lms, poba_solve_info* info,
+                         hipStream_t s);
+
+// Sets ctrl->lambda = lam, ctrl->active = 1 and clears the series flags.
+poba_status launch_begin_solve(Problem* p, double lam, hipStream_t s);
+
+}  // namespace poba

@@ -1,0 +1,201 @@
+// Linearisation (Sec. 4 and 4.1): residuals, Jacobian blocks, and the
+// undamped normal-equation blocks U = J_p^T J_p, V = J_l^T J_l, b_p = J_p^T r,
+// b_l = J_l^T r, plus the cost F = 1/2 sum rho(|r_i|^2).
+//
+// Two passes evaluate every observation once per order: the landmark-major
+// pass stores the landmark-major Jacobian records and residuals and reduces V
+// and b_l per landmark segment; the camera-major pass stores the camera-major
+// records and reduces U and b_p per camera piece.  Both passes accumulate the
+// blocks in float64 from the Jacobian values rounded to the storage precision,
+// so U, V and W are built from one and the same J.
+#include "camera_model.hpp"
+#include "device_ops.hpp"
+#include "kernels.hpp"
+
+namespace poba {
+
+template <typename TJ>
+__global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const double* __restrict__ cams,
+                                                   const double* __restrict__ lms, int loss, double delta,
+                                                   const int32_t* gate, double* cost_out, double* cost_out2,
+                                                   Ctrl* ctrl) {
+    __shared__ double lds[kWavesPerBlock * 2];
+    if (gate && !*gate) return;
+    const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+    double cost = 0.0, bad = 0.0;
+    if (tile < z.ntiles) {
+        tile_landmarks<double, 9>(
+            b.lo_cam, b.tile_start, b.seg_base, tile,
+            [&](int32_t i, bool valid, int32_t cam, int32_t seg, double* v) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) v[k] = 0.0;
+                if (!valid) return;
+                const int32_t l = b.nel[seg];
+                double C[9], X[3];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) C[k] = cams[9 * int64_t(cam) + k];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) X[k] = lms[3 * int64_t(l) + k];
+                ObsEval e;
+                evaluate_obs(C, X, b.obs_lo[2 * int64_t(i)], b.obs_lo[2 * int64_t(i) + 1], e);
+                const double s2 = e.r[0] * e.r[0] + e.r[1] * e.r[1];
+                double rho = s2, w = 1.0;
+                if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, w);
+                cost += 0.5 * rho;
+                if (!isfinite(rho)) bad = 1.0;
+                const double sw = sqrt(w);
+                double J[24];
+#pragma unroll
+                for (int k = 0; k < 24; ++k) J[k] = sw * e.J[k];
+                store_J<TJ>(b.J_lo, z.npad, i, J);
+#pragma unroll
+                for (int k = 0; k < 24; ++k) J[k] = round_to_storage<TJ>(J[k]);
+                const double r0 = sw * e.r[0], r1 = sw * e.r[1];
+                b.r_lo[2 * int64_t(i)] = r0;
+                b.r_lo[2 * int64_t(i) + 1] = r1;
+                const double* a = J + 18;  // J_l row 0
+                const double* c = J + 21;  // J_l row 1
+                v[0] = a[0] * a[0] + c[0] * c[0];
+                v[1] = a[0] * a[1] + c[0] * c[1];
+                v[2] = a[0] * a[2] + c[0] * c[2];
+                v[3] = a[1] * a[1] + c[1] * c[1];
+                v[4] = a[1] * a[2] + c[1] * c[2];
+                v[5] = a[2] * a[2] + c[2] * c[2];
+                v[6] = a[0] * r0 + c[0] * r1;
+                v[7] = a[1] * r0 + c[1] * r1;
+                v[8] = a[2] * r0 + c[2] * r1;
+            },
+            [&](int32_t seg, const double* v) {
+                const int64_t l = b.nel[seg];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) b.V[6 * l + k] = v[k];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) b.bl[3 * l + k] = v[6 + k];
+            });
+    }
+    double tot[2] = {cost, bad};
+    block_sum<2>(tot, lds);
+    double out[2];
+    if (grid_sum_last<2>(tot, b.red_part, &ctrl->ticket[kTicketCost], gridDim.x, out, lds) && threadIdx.x == 0) {
+        ctrl->red[0] = out[0];
+        if (cost_out) *cost_out = out[0];
+        if (cost_out2) *cost_out2 = out[0];
+        if (out[1] != 0.0 || !isfinite(out[0])) atomicOr(&ctrl->status, POBA_ERR_NONFINITE);
+    }
+}
+
+// Camera-major pass: one block per camera piece.  Accumulates the upper
+// triangle of J_p^T J_p (45 values) and J_p^T r (9) in float64.
+template <typename TJ>
+__global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const double* __restrict__ cams,
+                                                    const double* __restrict__ lms, int loss, double delta,
+                                                    const int32_t* gate) {
+    __shared__ double lds[kWavesPerBlock * 54];
+    if (gate && !*gate) return;
+    const int32_t p = blockIdx.x;
+    const int32_t cam = b.piece_cam[p];
+    const int32_t a = b.piece_begin[p], e = b.piece_end[p];
+    double C[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) C[k] = cams[9 * int64_t(cam) + k];
+    double acc[54];
+#pragma unroll
+    for (int k = 0; k < 54; ++k) acc[k] = 0.0;
+    for (int32_t i = a + threadIdx.x; i < e; i += kBlock) {
+        const int64_t l = b.co_lm[i];
+        double X[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
+        ObsEval ev;
+        evaluate_obs(C, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], ev);
+        double w = 1.0;
+        if (loss == POBA_LOSS_HUBER) {
+            double rho;
+            huber(ev.r[0] * ev.r[0] + ev.r[1] * ev.r[1], delta, rho, w);
+        }
+        const double sw = sqrt(w);
+        double J[24];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) J[k] = sw * ev.J[k];
+        store_J<TJ>(b.J_co, z.npad, i, J);
+#pragma unroll
+        for (int k = 0; k < 18; ++k) J[k] = round_to_storage<TJ>(J[k]);
+        const double r0 = sw * ev.r[0], r1 = sw * ev.r[1];
+        int idx = 0;
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+#pragma unroll
+            for (int c = r; c < 9; ++c) acc[idx++] += J[r] * J[c] + J[9 + r] * J[9 + c];
+        }
+#pragma unroll
+        for (int r = 0; r < 9; ++r) acc[45 + r] += J[r] * r0 + J[9 + r] * r1;
+    }
+    block_sum<54>(acc, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 54; ++k) b.part[54 * int64_t(p) + k] = acc[k];
+    }
+}
+
+// Sums each camera's pieces into the full symmetric U (81) and b_p (9).
+__global__ __launch_bounds__(kBlock) void k_lin_cam_fin(Buffers b, Sizes z, const int32_t* gate) {
+    if (gate && !*gate) return;
+    const int32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= z.nc) return;
+    double acc[54];
+#pragma unroll
+    for (int k = 0; k < 54; ++k) acc[k] = 0.0;
+    for (int32_t p = b.cam_piece[c]; p < b.cam_piece[c + 1]; ++p) {
+#pragma unroll
+        for (int k = 0; k < 54; ++k) acc[k] += b.part[54 * int64_t(p) + k];
+    }
+    double* U = b.U + 81 * int64_t(c);
+    int idx = 0;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+#pragma unroll
+        for (int cc = r; cc < 9; ++cc) {
+            U[9 * r + cc] = acc[idx];
+            U[9 * cc + r] = acc[idx];
+            ++idx;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 9; ++r) b.bp[9 * int64_t(c) + r] = acc[45 + r];
+}
+
+template <typename TJ>
+poba_status launch_linearize_t(Problem* p, const double* cams, const double* lms, const int32_t* gate,
+                               double* cost_out, double* cost_out2, hipStream_t s) {
+    const Buffers& b = p->b;
+    const Sizes& z = p->z;
+    const double delta = p->d.huber_delta;
+    const int loss = p->d.loss;
+    ProfScope prof(p, POBA_K_LINEARIZE, s);
+    hipLaunchKernelGGL(k_lin_lm<TJ>, dim3(unsigned(ceil_div(z.ntiles, kWavesPerBlock))), dim3(kBlock), 0, s, b, z,
+                       cams, lms, loss, delta, gate, cost_out, cost_out2, b.ctrl);
+    if (p->npieces > 0)
+        hipLaunchKernelGGL(k_lin_cam<TJ>, dim3(unsigned(p->npieces)), dim3(kBlock), 0, s, b, z, cams, lms, loss, delta,
+                           gate);
+    hipLaunchKernelGGL(k_lin_cam_fin, dim3(unsigned(ceil_div(z.nc, kBlock))), dim3(kBlock), 0, s, b, z, gate);
+    return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
+}
+
+poba_status launch_linearize(Problem* p, const double* cams, const double* lms, const int32_t* gate,
+                             double* cost_out, double* cost_out2, hipStream_t s) {
+    switch (p->d.precision) {
+        case POBA_F64: return launch_linearize_t<double>(p, cams, lms, gate, cost_out, cost_out2, s);
+        case POBA_F32: return launch_linearize_t<float>(p, cams, lms, gate, cost_out, cost_out2, s);
+        default: return launch_linearize_t<bf16_t>(p, cams, lms, gate, cost_out, cost_out2, s);
+    }
+}
+
+}  // namespace poba
+
+using namespace poba;
+
+extern "C" poba_status poba_linearize(poba_problem p, const double* cams, const double* lms, double* cost,
+                                      poba_stream stream) {
+    if (!p || !cams || !lms) return POBA_ERR_INVALID_ARG;
+    return launch_linearize(p, cams, lms, nullptr, cost, nullptr, reinterpret_cast<hipStream_t>(stream));
+}

@@ -1,0 +1,501 @@
+// Problem set-up: workspace layout, observation orders and work tiles.
+//
+// The paper groups Jacobian blocks per landmark (Sec. 5 "Efficient storage").
+// Here every observation is kept in two orders: landmark-major (for W^T v,
+// the landmark side of the series) and camera-major (for W s, the camera
+// side), each a stable sort of the observations by (index, original
+// position).  Landmark-major positions are cut into 64-observation tiles; a
+// tile owns the landmarks whose first observation falls inside it, so a
+// wavefront reduces whole landmark segments without talking to other waves.
+// Camera-major positions are cut into pieces of at most `piece` observations
+// that never straddle two cameras.
+#include <hipcub/hipcub.hpp>
+
+#include "camera_model.hpp"
+#include "common.hpp"
+
+namespace poba {
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+bool compute_sizes(const poba_desc* d, Sizes* z) {
+    if (!d) return false;
+    if (d->n_cams < 1 || d->n_lms < 1 || d->n_obs < 0 || d->n_obs >= (int64_t(1) << 31)) return false;
+    if (d->precision < POBA_F64 || d->precision > POBA_F32_BF16J) return false;
+    if (d->damping != POBA_DAMP_MARQUARDT && d->damping != POBA_DAMP_IDENTITY) return false;
+    if (d->loss != POBA_LOSS_L2 && d->loss != POBA_LOSS_HUBER) return false;
+    if (d->loss == POBA_LOSS_HUBER && !(d->huber_delta > 0.0)) return false;
+    if (d->piece_size < 0) return false;
+    z->nc = d->n_cams;
+    z->nl = d->n_lms;
+    z->N = d->n_obs;
+    z->npad = std::max<int64_t>(ceil_div(z->N, kWave) * kWave, kWave);
+    z->ntiles = z->N / kWave + 1;
+    z->piece = d->piece_size ? d->piece_size : kDefaultPiece;
+    z->piece = std::max(64, std::min(z->piece, 1 << 20));
+    z->npieces_max = z->N / z->piece + z->nc + 1;
+    z->jbytes = d->precision == POBA_F64 ? 8 : (d->precision == POBA_F32 ? 4 : 2);
+    z->sbytes = d->precision == POBA_F64 ? 8 : 4;
+    z->red_parts = std::max<int64_t>(ceil_div(z->ntiles, kWavesPerBlock), ceil_div(z->nc, kBlock)) + 1;
+    return true;
+}
+
+size_t sort_tmp_upper_bound(int64_t N) {
+    // onesweep radix sort scratch: lookback state and histograms, well below
+    // this bound for every supported size (checked against the query in
+    // poba_create).
+    return (size_t(64) << 20) + size_t(N) * 8;
+}
+
+size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t sort_tmp_bytes) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        off = align_up(off, 256);
+        char* p = base ? base + off : nullptr;
+        off += std::max<size_t>(bytes, 1);
+        return p;
+    };
+    const size_t N = size_t(z.N), nc = size_t(z.nc), nl = size_t(z.nl);
+    const size_t jrec = size_t(z.npad) * 24 * z.jbytes;
+    Buffers t{};
+    t.perm_l = (int32_t*)take(N * 4);
+    t.perm_c = (int32_t*)take(N * 4);
+    t.lo_cam = (uint32_t*)take(N * 4);
+    t.co_lm = (int32_t*)take(N * 4);
+    t.lm_off = (int32_t*)take((nl + 1) * 4);
+    t.cam_off = (int32_t*)take((nc + 1) * 4);
+    t.nel = (int32_t*)take(nl * 4);
+    t.tile_start = (int32_t*)take(size_t(z.ntiles + 1) * 4);
+    t.seg_base = (int32_t*)take(size_t(z.ntiles) * 4);
+    t.piece_cam = (int32_t*)take(size_t(z.npieces_max) * 4);
+    t.piece_begin = (int32_t*)take(size_t(z.npieces_max) * 4);
+    t.piece_end = (int32_t*)take(size_t(z.npieces_max) * 4);
+    t.cam_piece = (int32_t*)take((nc + 1) * 4);
+    t.obs_lo = (double*)take(N * 16);
+    t.obs_co = (double*)take(N * 16);
+    t.J_lo = take(jrec);
+    t.J_co = take(jrec);
+    t.r_lo = (double*)take(N * 16);
+    t.U = (double*)take(nc * 81 * 8);
+    t.bp = (double*)take(nc * 9 * 8);
+    t.V = (double*)take(nl * 6 * 8);
+    t.bl = (double*)take(nl * 3 * 8);
+    t.Uinv = (double*)take(nc * 81 * 8);
+    t.Vinv = take(nl * 6 * z.sbytes);
+    t.s = take(nl * 4 * 8);  // also holds float64 landmark vectors
+    t.v = (double*)take(nc * 9 * 8);
+    t.vq = take(nc * 12 * 8);
+    t.x = (double*)take(nc * 9 * 8);
+    t.part = (double*)take(size_t(z.npieces_max) * 54 * 8);
+    t.dxl = (double*)take(nl * 3 * 8);
+    t.dxp = (double*)take(nc * 9 * 8);
+    t.cams_new = (double*)take(nc * 9 * 8);
+    t.lms_new = (double*)take(nl * 3 * 8);
+    t.red_part = (double*)take(size_t(z.red_parts) * 4 * 8);
+    t.cam_norm = (double*)take(nc * 2 * 8);
+    t.ctrl = (Ctrl*)take(sizeof(Ctrl));
+    t.keys_tmp = (int32_t*)take(N * 4);
+    t.vals_tmp = (int32_t*)take(N * 4);
+    t.keys_out = (int32_t*)take(N * 4);
+    t.iota = (int32_t*)take(N * 4);
+    t.scratch_i = (int32_t*)take(2 * (std::max(nc, nl) + 2) * 4);
+    t.sort_tmp_bytes = sort_tmp_bytes;
+    t.sort_tmp = take(sort_tmp_bytes);
+    if (b) *b = t;
+    return align_up(off, 256);
+}
+
+// ------------------------------------------------------------------ kernels --
+
+__global__ void k_check_indices(const int32_t* obs_cam, const int32_t* obs_lm, int64_t N, int32_t nc,
+                                int32_t nl, int32_t* err, int32_t* iota) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    iota[i] = int32_t(i);
+    const int32_t c = obs_cam[i], l = obs_lm[i];
+    if (c < 0 || c >= nc || l < 0 || l >= nl) atomicOr(err, 1);
+}
+
+// off[k] = first sorted position whose key is >= k (k = 0..n); keys sorted.
+__global__ void k_segment_offsets(const int32_t* keys, int64_t N, int32_t n, int32_t* off) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i > N) return;
+    const int32_t prev = i == 0 ? -1 : keys[i - 1];
+    const int32_t cur = i == N ? n : keys[i];
+    for (int32_t k = prev + 1; k <= cur; ++k) off[k] = int32_t(i);
+}
+
+__global__ void k_gather_orders(const int32_t* perm_l, const int32_t* perm_c, const int32_t* obs_cam,
+                                const int32_t* obs_lm, const double* obs_xy, const int32_t* lm_off,
+                                const int32_t* sorted_lm, int64_t N, uint32_t* lo_cam, int32_t* co_lm,
+                                double* obs_lo, double* obs_co) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t ol = perm_l[i];
+    const int32_t l = sorted_lm[i];
+    const bool head = lm_off[l] == int32_t(i);
+    lo_cam[i] = uint32_t(obs_cam[ol]) | (head ? kHeadBit : 0u);
+    obs_lo[2 * i] = obs_xy[2 * ol];
+    obs_lo[2 * i + 1] = obs_xy[2 * ol + 1];
+    const int32_t oc = perm_c[i];
+    co_lm[i] = obs_lm[oc];
+    obs_co[2 * i] = obs_xy[2 * oc];
+    obs_co[2 * i + 1] = obs_xy[2 * oc + 1];
+}
+
+// flags[l] = 1 if landmark l has an observation.
+__global__ void k_nonempty_flags(const int32_t* lm_off, int32_t nl, int32_t* flags) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl) return;
+    flags[i] = lm_off[i + 1] > lm_off[i] ? 1 : 0;
+}
+
+// nel[rank[l]] = l for non-empty l (rank = exclusive scan of the flags).
+__global__ void k_compact_nonempty(const int32_t* lm_off, const int32_t* rank, int32_t nl, int32_t* nel) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl) return;
+    if (lm_off[i + 1] > lm_off[i]) nel[rank[i]] = i;
+}
+
+// Tile t covers landmark-major positions [tile_start[t], tile_start[t+1]):
+// tile_start[t] is the first landmark head at or after 64 t (N if none), and
+// seg_base[t] counts the non-empty landmarks whose head precedes it.  An empty
+// landmark shares its offset with the next non-empty one, so the lower bound
+// over lm_off already lands on a head.
+__global__ void k_tiles(const int32_t* lm_off, const int32_t* rank, int32_t nl, int64_t N, int64_t ntiles,
+                        int32_t* tile_start, int32_t* seg_base) {
+    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t > ntiles) return;
+    if (t == ntiles) {
+        tile_start[t] = int32_t(N);
+        return;
+    }
+    const int64_t target = t * kWave;
+    int32_t lo = 0, hi = nl;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (int64_t(lm_off[mid]) < target) lo = mid + 1; else hi = mid;
+    }
+    tile_start[t] = lo >= nl ? int32_t(N) : lm_off[lo];
+    seg_base[t] = rank[lo];
+}
+
+__global__ void k_piece_counts(const int32_t* cam_off, int32_t nc, int32_t piece, int32_t* counts) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > nc) return;
+    if (c == nc) {
+        counts[c] = 0;
+        return;
+    }
+    const int32_t len = cam_off[c + 1] - cam_off[c];
+    counts[c] = (len + piece - 1) / piece;
+}
+
+__global__ void k_piece_fill(const int32_t* cam_off, const int32_t* cam_piece, int32_t nc, int32_t piece,
+                             int32_t* piece_cam, int32_t* piece_begin, int32_t* piece_end) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const int32_t a = cam_off[c], b = cam_off[c + 1];
+    int32_t p = cam_piece[c];
+    for (int32_t s = a; s < b; s += piece, ++p) {
+        piece_cam[p] = c;
+        piece_begin[p] = s;
+        piece_end[p] = min(s + piece, b);
+    }
+}
+
+__global__ void k_init_ctrl(Ctrl* ctrl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctrl->lambda = 0.0;
+        for (int k = 0; k < 8; ++k) ctrl->red[k] = 0.0;
+        ctrl->norm_x2 = ctrl->norm_v2 = 0.0;
+        ctrl->active = 0;
+        ctrl->lin = 0;
+        ctrl->stopped = 0;
+        ctrl->stop_order = 0;
+        ctrl->status = 0;
+        ctrl->accepted = 0;
+        for (int k = 0; k < kTickets; ++k) ctrl->ticket[k] = 0u;
+    }
+}
+
+__global__ void k_zero_f64(double* p, int64_t n) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__global__ void k_project(int64_t N, const int32_t* obs_cam, const int32_t* obs_lm, const double* cams,
+                          const double* lms, double* out) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double cam[9], X[3], px[2];
+    const int32_t c = obs_cam[i], l = obs_lm[i];
+    for (int k = 0; k < 9; ++k) cam[k] = cams[9 * int64_t(c) + k];
+    for (int k = 0; k < 3; ++k) X[k] = lms[3 * int64_t(l) + k];
+    project_point(cam, X, px);
+    out[2 * i] = px[0];
+    out[2 * i + 1] = px[1];
+}
+
+static unsigned grid_for(int64_t n, int block = kBlock) { return unsigned(std::max<int64_t>(ceil_div(n, block), 1)); }
+
+static int key_bits(int32_t n) {
+    int b = 1;
+    while ((int64_t(1) << b) < int64_t(n)) ++b;
+    return b;
+}
+
+// ------------------------------------------------------------------ profiling --
+
+void prof_begin(Problem* p, int cls, hipStream_t s, ProfileSlot** slot) {
+    *slot = nullptr;
+    if (!p || !p->profiling) return;
+    if (p->slot_used >= p->slots.size()) return;
+    ProfileSlot* sl = &p->slots[p->slot_used++];
+    sl->cls = cls;
+    (void)hipEventRecord(sl->start, s);
+    *slot = sl;
+}
+
+void prof_end(ProfileSlot* slot, hipStream_t s) {
+    if (slot) (void)hipEventRecord(slot->stop, s);
+}
+
+}  // namespace poba
+
+using namespace poba;
+
+extern "C" {
+
+int32_t poba_version(void) { return 10000; }
+
+const char* poba_status_string(poba_status s) {
+    if (s == POBA_OK) return "ok";
+    if (s & POBA_ERR_INVALID_ARG) return "invalid argument";
+    if (s & POBA_ERR_INDEX_RANGE) return "observation index out of range";
+    if (s & POBA_ERR_NOT_SPD) return "damped block not positive definite";
+    if (s & POBA_ERR_NONFINITE) return "non-finite value";
+    if (s & POBA_ERR_HIP) return "HIP runtime error";
+    if (s & POBA_ERR_WORKSPACE) return "workspace missing or too small";
+    if (s & POBA_ERR_STATE) return "invalid state";
+    return "unknown status";
+}
+
+void poba_lm_default_options(poba_lm_options* o) {
+    if (!o) return;
+    o->lambda0 = 1e-4;
+    o->func_tol = 1e-6;
+    o->eps = 0.01;
+    o->eta = 1e-3;
+    o->lambda_min = 1e-16;
+    o->lambda_max = 1e16;
+    o->m = 20;
+    o->max_iters = 50;
+}
+
+size_t poba_workspace_bytes(const poba_desc* d) {
+    Sizes z;
+    if (!compute_sizes(d, &z)) return 0;
+    return layout(d, z, nullptr, nullptr, sort_tmp_upper_bound(z.N));
+}
+
+poba_status poba_create(const poba_desc* d, const int32_t* obs_cam, const int32_t* obs_lm, const double* obs_xy,
+                        void* workspace, size_t workspace_bytes, poba_stream stream, poba_problem* out) {
+    if (!out) return POBA_ERR_INVALID_ARG;
+    *out = nullptr;
+    Sizes z;
+    if (!compute_sizes(d, &z)) return POBA_ERR_INVALID_ARG;
+    if (z.N > 0 && (!obs_cam || !obs_lm || !obs_xy)) return POBA_ERR_INVALID_ARG;
+    const size_t need = poba_workspace_bytes(d);
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255u))
+        return POBA_ERR_WORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+    Problem* p = new Problem();
+    p->d = *d;
+    p->z = z;
+    layout(d, z, reinterpret_cast<char*>(workspace), &p->b, sort_tmp_upper_bound(z.N));
+    Buffers& b = p->b;
+    const int64_t N = z.N;
+    poba_status st = POBA_OK;
+
+    auto fail = [&](poba_status e) {
+        delete p;
+        return e;
+    };
+
+    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, s, b.ctrl);
+    int32_t* err = b.scratch_i;  // reuse scratch for the error flag, cleared below
+    if (hipMemsetAsync(err, 0, sizeof(int32_t), s) != hipSuccess) return fail(POBA_ERR_HIP);
+    if (N > 0) {
+        hipLaunchKernelGGL(k_check_indices, dim3(grid_for(N)), dim3(kBlock), 0, s, obs_cam, obs_lm, N, z.nc, z.nl,
+                           err, b.iota);
+    }
+    int32_t herr = 0;
+    if (hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess) return fail(POBA_ERR_HIP);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
+    if (herr) return fail(POBA_ERR_INDEX_RANGE);
+
+    if (N > 0) {
+        // stable radix sorts: (landmark, original index) and (camera, original index)
+        size_t tmp = 0;
+        hipcub::DoubleBuffer<int32_t> kb(b.keys_out, b.keys_tmp), vb(b.perm_l, b.vals_tmp);
+        if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, kb, vb, int(N), 0, key_bits(z.nl), s) != hipSuccess)
+            return fail(POBA_ERR_HIP);
+        if (tmp > b.sort_tmp_bytes) return fail(POBA_ERR_WORKSPACE);
+        // landmark-major
+        if (hipMemcpyAsync(b.keys_out, obs_lm, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        if (hipMemcpyAsync(b.perm_l, b.iota, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        tmp = b.sort_tmp_bytes;
+        if (hipcub::DeviceRadixSort::SortPairs(b.sort_tmp, tmp, kb, vb, int(N), 0, key_bits(z.nl), s) != hipSuccess)
+            return fail(POBA_ERR_HIP);
+        if (kb.Current() != b.keys_out)
+            if (hipMemcpyAsync(b.keys_out, kb.Current(), N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        if (vb.Current() != b.perm_l)
+            if (hipMemcpyAsync(b.perm_l, vb.Current(), N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        hipLaunchKernelGGL(k_segment_offsets, dim3(grid_for(N + 1)), dim3(kBlock), 0, s, b.keys_out, N, z.nl, b.lm_off);
+        // keep the sorted landmark keys for the head flags: stash in co_lm for now
+        if (hipMemcpyAsync(b.co_lm, b.keys_out, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
+
+        // camera-major
+        size_t tmp2 = 0;
+        hipcub::DoubleBuffer<int32_t> kc(b.keys_out, b.keys_tmp), vc(b.perm_c, b.vals_tmp);
+        if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp2, kc, vc, int(N), 0, key_bits(z.nc), s) != hipSuccess)
+            return fail(POBA_ERR_HIP);
+        if (tmp2 > b.sort_tmp_bytes) return fail(POBA_ERR_WORKSPACE);
+        if (hipMemcpyAsync(b.keys_out, obs_cam, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        if (hipMemcpyAsync(b.perm_c, b.iota, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        tmp2 = b.sort_tmp_bytes;
+        if (hipcub::DeviceRadixSort::SortPairs(b.sort_tmp, tmp2, kc, vc, int(N), 0, key_bits(z.nc), s) != hipSuccess)
+            return fail(POBA_ERR_HIP);
+        if (kc.Current() != b.keys_out)
+            if (hipMemcpyAsync(b.keys_out, kc.Current(), N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        if (vc.Current() != b.perm_c)
+            if (hipMemcpyAsync(b.perm_c, vc.Current(), N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        hipLaunchKernelGGL(k_segment_offsets, dim3(grid_for(N + 1)), dim3(kBlock), 0, s, b.keys_out, N, z.nc, b.cam_off);
+        // sorted landmark keys move to keys_tmp before co_lm is overwritten
+        if (hipMemcpyAsync(b.keys_tmp, b.co_lm, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        hipLaunchKernelGGL(k_gather_orders, dim3(grid_for(N)), dim3(kBlock), 0, s, b.perm_l, b.perm_c, obs_cam, obs_lm,
+                           obs_xy, b.lm_off, b.keys_tmp, N, b.lo_cam, b.co_lm, b.obs_lo, b.obs_co);
+    } else {
+        hipLaunchKernelGGL(k_segment_offsets, dim3(1), dim3(kBlock), 0, s, b.keys_out, int64_t(0), z.nl, b.lm_off);
+        hipLaunchKernelGGL(k_segment_offsets, dim3(1), dim3(kBlock), 0, s, b.keys_out, int64_t(0), z.nc, b.cam_off);
+    }
+
+    // non-empty landmark list and tiles
+    {
+        const int64_t half = std::max<int64_t>(z.nc, z.nl) + 2;
+        int32_t* flags = b.scratch_i;
+        int32_t* rank = b.scratch_i + half;
+        hipLaunchKernelGGL(k_nonempty_flags, dim3(grid_for(z.nl)), dim3(kBlock), 0, s, b.lm_off, z.nl, flags);
+        if (hipMemsetAsync(flags + z.nl, 0, 4, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        size_t tmp = 0;
+        if (hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, flags, rank, z.nl + 1, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        if (tmp > b.sort_tmp_bytes) return fail(POBA_ERR_WORKSPACE);
+        tmp = b.sort_tmp_bytes;
+        if (hipcub::DeviceScan::ExclusiveSum(b.sort_tmp, tmp, flags, rank, z.nl + 1, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        hipLaunchKernelGGL(k_compact_nonempty, dim3(grid_for(z.nl)), dim3(kBlock), 0, s, b.lm_off, rank, z.nl, b.nel);
+        hipLaunchKernelGGL(k_tiles, dim3(grid_for(z.ntiles + 1)), dim3(kBlock), 0, s, b.lm_off, rank, z.nl, N, z.ntiles,
+                           b.tile_start, b.seg_base);
+        int32_t nnel = 0;
+        if (hipMemcpyAsync(&nnel, rank + z.nl, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
+        p->nnel = nnel;
+    }
+    // camera pieces
+    {
+        int32_t* counts = b.scratch_i;
+        hipLaunchKernelGGL(k_piece_counts, dim3(grid_for(z.nc + 1)), dim3(kBlock), 0, s, b.cam_off, z.nc, z.piece, counts);
+        size_t tmp = 0;
+        if (hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, counts, b.cam_piece, z.nc + 1, s) != hipSuccess)
+            return fail(POBA_ERR_HIP);
+        if (tmp > b.sort_tmp_bytes) return fail(POBA_ERR_WORKSPACE);
+        tmp = b.sort_tmp_bytes;
+        if (hipcub::DeviceScan::ExclusiveSum(b.sort_tmp, tmp, counts, b.cam_piece, z.nc + 1, s) != hipSuccess)
+            return fail(POBA_ERR_HIP);
+        hipLaunchKernelGGL(k_piece_fill, dim3(grid_for(z.nc)), dim3(kBlock), 0, s, b.cam_off, b.cam_piece, z.nc, z.piece,
+                           b.piece_cam, b.piece_begin, b.piece_end);
+        int32_t np = 0;
+        if (hipMemcpyAsync(&np, b.cam_piece + z.nc, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
+        if (np > z.npieces_max) return fail(POBA_ERR_STATE);
+        p->npieces = np;
+    }
+    // blocks of landmarks without observations are never written by a pass
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nl) * 6)), dim3(kBlock), 0, s, b.V, int64_t(z.nl) * 6);
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nl) * 3)), dim3(kBlock), 0, s, b.bl, int64_t(z.nl) * 3);
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nl) * 4)), dim3(kBlock), 0, s, (double*)b.s, int64_t(z.nl) * 4);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
+    if (hipGetLastError() != hipSuccess) return fail(POBA_ERR_HIP);
+    *out = p;
+    return st;
+}
+
+poba_status poba_destroy(poba_problem p) {
+    if (!p) return POBA_ERR_INVALID_ARG;
+    for (auto& sl : p->slots) {
+        hipEventDestroy(sl.start);
+        hipEventDestroy(sl.stop);
+    }
+    delete p;
+    return POBA_OK;
+}
+
+poba_status poba_project(int64_t n_obs, const int32_t* obs_cam, const int32_t* obs_lm, const double* cams,
+                         const double* lms, double* out_xy, poba_stream stream) {
+    if (n_obs < 0) return POBA_ERR_INVALID_ARG;
+    if (n_obs == 0) return POBA_OK;
+    if (!obs_cam || !obs_lm || !cams || !lms || !out_xy) return POBA_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_project, dim3(grid_for(n_obs)), dim3(kBlock), 0, reinterpret_cast<hipStream_t>(stream), n_obs,
+                       obs_cam, obs_lm, cams, lms, out_xy);
+    return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
+}
+
+poba_status poba_get_orders(poba_problem p, int32_t* perm_lm, int32_t* perm_cam, int32_t* lm_off, int32_t* cam_off,
+                            poba_stream stream) {
+    if (!p) return POBA_ERR_INVALID_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const Buffers& b = p->b;
+    const int64_t N = p->z.N;
+    if (perm_lm && N && hipMemcpyAsync(perm_lm, b.perm_l, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return POBA_ERR_HIP;
+    if (perm_cam && N && hipMemcpyAsync(perm_cam, b.perm_c, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return POBA_ERR_HIP;
+    if (lm_off && hipMemcpyAsync(lm_off, b.lm_off, (p->z.nl + 1) * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return POBA_ERR_HIP;
+    if (cam_off && hipMemcpyAsync(cam_off, b.cam_off, (p->z.nc + 1) * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return POBA_ERR_HIP;
+    return POBA_OK;
+}
+
+poba_status poba_profile_enable(poba_problem p, int32_t enable) {
+    if (!p) return POBA_ERR_INVALID_ARG;
+    if (enable && p->slots.empty()) {
+        p->slots.resize(kMaxProfiled);
+        for (auto& sl : p->slots) {
+            if (hipEventCreate(&sl.start) != hipSuccess || hipEventCreate(&sl.stop) != hipSuccess) return POBA_ERR_HIP;
+        }
+    }
+    p->profiling = enable != 0;
+    return POBA_OK;
+}
+
+poba_status poba_profile_read(poba_problem p, double* ms, int64_t* n) {
+    if (!p) return POBA_ERR_INVALID_ARG;
+    for (size_t i = 0; i < p->slot_used; ++i) {
+        ProfileSlot& sl = p->slots[i];
+        if (hipEventSynchronize(sl.stop) != hipSuccess) return POBA_ERR_HIP;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, sl.start, sl.stop) != hipSuccess) return POBA_ERR_HIP;
+        p->prof_ms[sl.cls] += t;
+        p->prof_n[sl.cls] += 1;
+    }
+    p->slot_used = 0;
+    for (int k = 0; k < POBA_K_COUNT; ++k) {
+        if (ms) ms[k] = p->prof_ms[k];
+        if (n) n[k] = p->prof_n[k];
+        p->prof_ms[k] = 0.0;
+        p->prof_n[k] = 0;
+    }
+    return POBA_OK;
+}
+
+}  // extern "C"

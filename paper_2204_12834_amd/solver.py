@@ -1,0 +1,229 @@
+"""Python binding of the C ABI: argument marshalling only.
+
+PyTorch supplies device memory and streams; every step of the computation
+runs in the HIP kernels of libpoba.so.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import torch
+
+from . import _lib
+
+_PREC_BYTES = {"f64": 8, "f32": 4, "bf16": 2}
+
+
+def _ptr(t: torch.Tensor | None) -> ctypes.c_void_p:
+    if t is None:
+        return ctypes.c_void_p(0)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, device, shape=None) -> torch.Tensor:
+    t = torch.as_tensor(t, dtype=dtype, device=device).contiguous()
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+    return t
+
+
+@dataclasses.dataclass
+class LMOptions:
+    """LM settings of Sec. 5.1 (defaults) as passed to poba_lm_step."""
+    lambda0: float = 1e-4
+    func_tol: float = 1e-6
+    eps: float = 0.01
+    eta: float = 1e-3
+    lambda_min: float = 1e-16
+    lambda_max: float = 1e16
+    m: int = 20
+    max_iters: int = 50
+
+    def c(self) -> _lib.PobaLMOptions:
+        return _lib.PobaLMOptions(self.lambda0, self.func_tol, self.eps, self.eta, self.lambda_min,
+                                  self.lambda_max, int(self.m), int(self.max_iters))
+
+
+def default_options() -> LMOptions:
+    lib = _lib.load()
+    o = _lib.PobaLMOptions()
+    lib.poba_lm_default_options(ctypes.byref(o))
+    return LMOptions(o.lambda0, o.func_tol, o.eps, o.eta, o.lambda_min, o.lambda_max, o.m, o.max_iters)
+
+
+def read_solve_info(t: torch.Tensor) -> dict:
+    raw = bytes(t.cpu().numpy().tobytes())
+    info = _lib.PobaSolveInfo.from_buffer_copy(raw)
+    return {f: getattr(info, f) for f, _ in _lib.PobaSolveInfo._fields_}
+
+
+def read_lm_state(t: torch.Tensor) -> dict:
+    raw = bytes(t.cpu().numpy().tobytes())
+    st = _lib.PobaLMState.from_buffer_copy(raw)
+    out = {f: getattr(st, f) for f, _ in _lib.PobaLMState._fields_}
+    out["lambda"] = out.pop("lambda_")
+    return out
+
+
+def workspace_bytes(n_cams, n_lms, n_obs, precision="f64", damping="marquardt", loss="l2", huber_delta=0.0,
+                    piece_size=0) -> int:
+    lib = _lib.load()
+    d = _lib.PobaDesc(int(n_cams), int(n_lms), int(n_obs), _lib.PRECISION[precision], _lib.DAMPING[damping],
+                      _lib.LOSS[loss], int(piece_size), float(huber_delta))
+    return int(lib.poba_workspace_bytes(ctypes.byref(d)))
+
+
+class Problem:
+    """A bundle-adjustment problem held on one GPU (poba_create ... poba_destroy)."""
+
+    def __init__(self, obs_cam, obs_lm, obs_xy, n_cams: int, n_lms: int, precision: str = "f64",
+                 damping: str = "marquardt", loss: str = "l2", huber_delta: float = 0.0, piece_size: int = 0,
+                 device="cuda", stream=None):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        self.precision = precision
+        self.n_cams, self.n_lms = int(n_cams), int(n_lms)
+        obs_cam = _dev(obs_cam, torch.int32, self.device)
+        obs_lm = _dev(obs_lm, torch.int32, self.device)
+        self.n_obs = int(obs_cam.numel())
+        obs_xy = _dev(obs_xy, torch.float64, self.device, (self.n_obs, 2))
+        self.desc = _lib.PobaDesc(self.n_cams, self.n_lms, self.n_obs, _lib.PRECISION[precision],
+                                  _lib.DAMPING[damping], _lib.LOSS[loss], int(piece_size), float(huber_delta))
+        nbytes = int(self.lib.poba_workspace_bytes(ctypes.byref(self.desc)))
+        if nbytes == 0:
+            raise _lib.PobaError("poba_workspace_bytes", 1)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws_ptr = self.workspace.data_ptr() + off
+        self._ws_bytes = nbytes
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.lib.poba_create(ctypes.byref(self.desc), _ptr(obs_cam), _ptr(obs_lm), _ptr(obs_xy),
+                                      ctypes.c_void_p(self._ws_ptr), ctypes.c_size_t(nbytes), _stream(stream),
+                                      ctypes.byref(h))
+        _lib.check("poba_create", rc)
+        self.handle = h
+        self._info = torch.zeros(32, dtype=torch.uint8, device=self.device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.poba_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- hot path --------------------------------------------------------
+
+    def linearize(self, cams: torch.Tensor, lms: torch.Tensor, cost: torch.Tensor | None = None, stream=None):
+        cams = _dev(cams, torch.float64, self.device, (self.n_cams, 9))
+        lms = _dev(lms, torch.float64, self.device, (self.n_lms, 3))
+        if cost is None:
+            cost = torch.zeros(1, dtype=torch.float64, device=self.device)
+        _lib.check("poba_linearize", self.lib.poba_linearize(self.handle, _ptr(cams), _ptr(lms), _ptr(cost),
+                                                             _stream(stream)))
+        return cost
+
+    def power_solve(self, lam: float, m: int, eps: float = 0.0, dx_cams=None, dx_lms=None, info=None,
+                    stream=None):
+        if dx_cams is None:
+            dx_cams = torch.empty(self.n_cams, 9, dtype=torch.float64, device=self.device)
+        if dx_lms is None:
+            dx_lms = torch.empty(self.n_lms, 3, dtype=torch.float64, device=self.device)
+        info = self._info if info is None else info
+        _lib.check("poba_power_solve", self.lib.poba_power_solve(self.handle, float(lam), int(m), float(eps),
+                                                                 _ptr(dx_cams), _ptr(dx_lms), _ptr(info),
+                                                                 _stream(stream)))
+        return dx_cams, dx_lms, info
+
+    def lm_init(self, opts: LMOptions | None = None, state: torch.Tensor | None = None, stream=None):
+        opts = opts or LMOptions()
+        if state is None:
+            state = torch.zeros(ctypes.sizeof(_lib.PobaLMState), dtype=torch.uint8, device=self.device)
+        o = opts.c()
+        _lib.check("poba_lm_init", self.lib.poba_lm_init(self.handle, _ptr(state), ctypes.byref(o),
+                                                         _stream(stream)))
+        return state
+
+    def lm_step(self, cams: torch.Tensor, lms: torch.Tensor, state: torch.Tensor, opts: LMOptions | None = None,
+                stream=None):
+        """One LM iteration; cams, lms (float64 device tensors) are updated in place."""
+        opts = opts or LMOptions()
+        if cams.dtype != torch.float64 or not cams.is_contiguous() or tuple(cams.shape) != (self.n_cams, 9):
+            raise ValueError("cams must be a contiguous float64 [n_cams, 9] device tensor")
+        if lms.dtype != torch.float64 or not lms.is_contiguous() or tuple(lms.shape) != (self.n_lms, 3):
+            raise ValueError("lms must be a contiguous float64 [n_lms, 3] device tensor")
+        o = opts.c()
+        _lib.check("poba_lm_step", self.lib.poba_lm_step(self.handle, _ptr(cams), _ptr(lms), _ptr(state),
+                                                         ctypes.byref(o), _stream(stream)))
+
+    # -- inspection --------------------------------------------------------
+
+    def get_blocks(self, stream=None):
+        U = torch.empty(self.n_cams, 9, 9, dtype=torch.float64, device=self.device)
+        V = torch.empty(self.n_lms, 3, 3, dtype=torch.float64, device=self.device)
+        bp = torch.empty(self.n_cams, 9, dtype=torch.float64, device=self.device)
+        bl = torch.empty(self.n_lms, 3, dtype=torch.float64, device=self.device)
+        _lib.check("poba_get_blocks", self.lib.poba_get_blocks(self.handle, _ptr(U), _ptr(V), _ptr(bp), _ptr(bl),
+                                                               _stream(stream)))
+        return U, V, bp, bl
+
+    def get_jacobians(self, order: int = 0, stream=None):
+        Jp = torch.empty(self.n_obs, 2, 9, dtype=torch.float64, device=self.device)
+        Jl = torch.empty(self.n_obs, 2, 3, dtype=torch.float64, device=self.device)
+        r = torch.empty(self.n_obs, 2, dtype=torch.float64, device=self.device)
+        _lib.check("poba_get_jacobians", self.lib.poba_get_jacobians(self.handle, int(order), _ptr(Jp), _ptr(Jl),
+                                                                     _ptr(r), _stream(stream)))
+        return Jp, Jl, r
+
+    def get_orders(self, stream=None):
+        pl = torch.empty(self.n_obs, dtype=torch.int32, device=self.device)
+        pc = torch.empty(self.n_obs, dtype=torch.int32, device=self.device)
+        lo = torch.empty(self.n_lms + 1, dtype=torch.int32, device=self.device)
+        co = torch.empty(self.n_cams + 1, dtype=torch.int32, device=self.device)
+        _lib.check("poba_get_orders", self.lib.poba_get_orders(self.handle, _ptr(pl), _ptr(pc), _ptr(lo), _ptr(co),
+                                                               _stream(stream)))
+        return pl, pc, lo, co
+
+    def apply_P(self, v: torch.Tensor, stream=None):
+        v = _dev(v, torch.float64, self.device, (self.n_cams, 9))
+        out = torch.empty_like(v)
+        _lib.check("poba_apply_P", self.lib.poba_apply_P(self.handle, _ptr(v), _ptr(out), _stream(stream)))
+        return out
+
+    # -- timing ------------------------------------------------------------
+
+    def profile(self, enable: bool = True):
+        _lib.check("poba_profile_enable", self.lib.poba_profile_enable(self.handle, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        ms = (ctypes.c_double * 8)()
+        n = (ctypes.c_int64 * 8)()
+        _lib.check("poba_profile_read", self.lib.poba_profile_read(self.handle, ms, n))
+        return {k: (ms[i], n[i]) for i, k in enumerate(_lib.KERNEL_CLASSES)}
+
+
+def project(obs_cam, obs_lm, cams, lms, device="cuda", stream=None) -> torch.Tensor:
+    """Model pixel positions [n_obs, 2] (poba_project)."""
+    lib = _lib.load()
+    obs_cam = _dev(obs_cam, torch.int32, device)
+    obs_lm = _dev(obs_lm, torch.int32, device)
+    cams = _dev(cams, torch.float64, device)
+    lms = _dev(lms, torch.float64, device)
+    n = int(obs_cam.numel())
+    if n and (int(obs_cam.min()) < 0 or int(obs_cam.max()) >= cams.shape[0] or int(obs_lm.min()) < 0
+              or int(obs_lm.max()) >= lms.shape[0]):
+        raise ValueError("observation index out of range")
+    out = torch.empty(n, 2, dtype=torch.float64, device=device)
+    _lib.check("poba_project", lib.poba_project(n, _ptr(obs_cam), _ptr(obs_lm), _ptr(cams), _ptr(lms), _ptr(out),
+                                                _stream(stream)))
+    return out

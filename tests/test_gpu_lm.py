@@ -1,0 +1,81 @@
+"""LM iterations on the device against the oracle's LM loop (Sec. 5.1)."""
+import functools
+
+import numpy as np
+import pytest
+
+from paper_2204_12834_amd import synth
+from gpu_common import Case, log, np_, rel
+from oracle import lm as olm
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _run_gpu(case, precision, opts, iters):
+    from paper_2204_12834_amd.solver import LMOptions, read_lm_state
+    prob = case.problem(precision)
+    cams, lms = case.state()
+    o = LMOptions(lambda0=opts.lambda0, func_tol=opts.func_tol, eps=opts.eps, eta=opts.eta, m=opts.m,
+                  max_iters=opts.max_iters)
+    st = prob.lm_init(o)
+    trace = []
+    for _ in range(iters):
+        prob.lm_step(cams, lms, st, o)
+        trace.append(read_lm_state(st))
+        if trace[-1]["done"]:
+            break
+    return trace, np_(cams), np_(lms)
+
+
+@pytest.mark.parametrize("name", ["c1", "city_small"])
+def test_lm_trajectory_f64(name):
+    log(f"lm trajectory {name}")
+    if name == "c1":
+        case = Case(synth.config("c1"))
+    else:
+        case = Case(synth.city_scene(n_cams=60, n_lms=3000, seed=5, name="city_small"), delta=3.0)
+    s = case.scene
+    opts = olm.LMOptions(max_iters=10, m=20, eps=0.0, huber_delta=case.delta)
+    ref = olm.lm(s.cams0, s.lms0, s.obs_cam, s.obs_lm, case.obs, opts)
+    trace, cams, lms = _run_gpu(case, "f64", opts, 10)
+    assert len(trace) == len(ref.iterations)
+    for g, o in zip(trace, ref.iterations):
+        assert abs(g["cost"] - (o.cost_new if o.accepted else o.cost)) <= 1e-9 * o.cost
+        assert abs(g["cost_new"] - o.cost_new) <= 1e-9 * o.cost_new
+        if abs(o.gain - opts.eta) > 1e-6:
+            assert g["accepted"] == int(o.accepted)
+        assert g["stop_order"] == o.stop_order
+    assert rel(cams, ref.cams) < 1e-8 and rel(lms, ref.lms) < 1e-8
+    assert trace[-1]["converged"] == int(ref.converged)
+
+
+def test_lm_f32_reaches_f64_optimum():
+    case = Case(synth.config("c1"))
+    s = case.scene
+    opts = olm.LMOptions(max_iters=50)
+    ref = olm.lm(s.cams0, s.lms0, s.obs_cam, s.obs_lm, case.obs, opts)
+    f_ref = min(it.cost_new for it in ref.iterations if it.accepted)
+    trace, _, _ = _run_gpu(case, "f32", opts, 50)
+    f32 = min(t["cost"] for t in trace)
+    log(f"f32 final {f32} vs f64 oracle {f_ref}")
+    assert abs(f32 - f_ref) <= 1e-6 * f_ref
+    # accepted costs decrease
+    acc = [t["cost"] for t in trace if t["accepted"]]
+    assert all(b < a for a, b in zip(acc, acc[1:]))
+
+
+def test_lm_done_state_is_sticky():
+    case = Case(synth.ring_scene(8, 200, (2, 4), seed=1, name="tiny"))
+    from paper_2204_12834_amd.solver import LMOptions, read_lm_state
+    prob = case.problem("f64")
+    cams, lms = case.state()
+    o = LMOptions(max_iters=3)
+    st = prob.lm_init(o)
+    for _ in range(3):
+        prob.lm_step(cams, lms, st, o)
+    before = (np_(cams).copy(), read_lm_state(st))
+    prob.lm_step(cams, lms, st, o)
+    after = (np_(cams), read_lm_state(st))
+    assert before[1]["done"] == 1 and after[1]["iteration"] == 3
+    assert np.array_equal(before[0], after[0])
