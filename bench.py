@@ -1,0 +1,359 @@
+#!/usr/bin/env python3
+"""Benchmark of the power-series bundle-adjustment hot path on one MI355X.
+
+Workload (default): the city-shaped synthetic problem - 1,100 cameras,
+780,000 landmarks, ~4.94M observations with heavy-tailed tracks (mean 6.3,
+max 200), 1 px noise, 2% outliers at 20 px, Huber loss (delta 3 px); series
+order m = 32; float32 storage.  Observations are produced on the GPU by the
+library's own projection of the ground truth plus the generator's noise.
+
+A step is one full LM iteration from the initial state (linearise both
+orders, assemble, damped inverses, reduced right-hand side, 32 series
+orders, back-substitution, trial cost and model decrease, accept / reject);
+the state is reset to the initial one before each step so all steps do the
+same work.  Per-kernel times come from HIP events that the library records
+around every launch inside the timed region.
+
+Printed JSON line: `value` is the series throughput in GB/s (algorithmic
+bytes of the m series orders divided by their kernel time); `roofline`
+refers to the dominant kernel; `cpu_baseline` is the float64 oracle's series
+on a bounded sample, single-threaded; extra keys give the LM iteration time
+and the time to the 1% cost tolerance in float64, float32 and bf16 storage.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "power-series RCS solve GB/s & LM iteration time to 1% cost tol, FP32 vs FP64, 1 GPU"
+SJ = {"f64": 8, "f32": 4, "bf16": 2}
+SX = {"f64": 8, "f32": 4, "bf16": 4}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c3.json")
+KERNEL_SOURCES = ["paper_2204_12834_amd/csrc/solve.hip", "paper_2204_12834_amd/csrc/device_ops.hpp",
+                  "paper_2204_12834_amd/csrc/common.hpp"]
+
+
+def series_bytes(n_obs, n_lms, prec):
+    """Algorithmic bytes of one series order, per pass (dual-order design):
+    landmark pass reads each Jacobian record and camera index once and each
+    V^-1 once, writes s; camera pass reads each record, landmark index and the
+    gathered s once per observation."""
+    sj, sx = SJ[prec], SX[prec]
+    lm = n_obs * (24 * sj + 4) + n_lms * (6 * sx + 3 * sx)
+    cam = n_obs * (24 * sj + 4 + 3 * sx)
+    return lm, cam
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_scene(workload):
+    from paper_2204_12834_amd import synth
+    if workload == "c3":
+        return synth.config("c3"), 3.0
+    if workload == "c3s":  # reduced city for quick checks
+        return synth.city_scene(n_cams=300, n_lms=60000, seed=0, name="c3s"), 3.0
+    if workload == "c2":
+        return synth.config("c2"), None
+    raise SystemExit(f"unknown workload {workload}")
+
+
+# --------------------------------------------------------------- CPU leg ----
+
+def cpu_baseline_child(workload, m, sample_lms):
+    """Oracle (float64 NumPy) series on a landmark subset, single thread."""
+    import numpy as np
+    import oracle
+    from oracle import camera, lm as olm, schur
+    scene, delta = make_scene(workload)
+    keep = scene.obs_lm < sample_lms
+    oc, ol = scene.obs_cam[keep], scene.obs_lm[keep]
+    cams0, lms0 = scene.cams0, scene.lms0[:sample_lms]
+    obs = camera.project(scene.cams_gt, scene.lms_gt[:sample_lms], oc, ol) + scene.noise[keep]
+    F, r, Jp, Jl = olm.linearize(cams0, lms0, oc, ol, obs, delta)
+    from oracle import normal
+    U, V, bp, bl = normal.assemble(Jp, Jl, r, oc, ol, scene.n_cams, sample_lms)
+    dp, dl = normal.damping_diagonals(U, V)
+    Ul, Vl = normal.damp(U, V, 1e-4, dp, dl)
+    Uinv, Vinv = normal.block_inverse(Ul), normal.block_inverse(Vl)
+    bt = schur.reduced_rhs(Jp, Jl, oc, ol, bp, bl, Vinv)
+    t0 = time.perf_counter()
+    schur.power_series(Jp, Jl, oc, ol, Uinv, Vinv, bt, m, 0.0)
+    dt = time.perf_counter() - t0
+    lmb, camb = series_bytes(int(keep.sum()), sample_lms, "f64")
+    out = {"value": m * (lmb + camb) / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+           "sample": f"{workload}: landmarks 0..{sample_lms - 1} ({int(keep.sum())} observations, all "
+                     f"{scene.n_cams} cameras), oracle power series m={m}, float64, "
+                     f"{dt:.1f} s single-threaded; bytes counted with the float64 dual-order formula",
+           "seconds": dt}
+    try:
+        model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
+    except Exception:
+        model = "unknown"
+    out["host"] = f"1 of {os.cpu_count()} cores, {model}"
+    print(json.dumps(out))
+
+
+def run_cpu_baseline(workload, m, sample_lms):
+    env = dict(os.environ, OMP_NUM_THREADS="1", MKL_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
+               HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", "--workload", workload, "--m", str(m),
+           "--sample-lms", str(sample_lms)]
+    res = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=900)
+    if res.returncode != 0:
+        print(res.stderr[-2000:], file=sys.stderr)
+        return None
+    return json.loads(res.stdout.strip().splitlines()[-1])
+
+
+# --------------------------------------------------------------- GPU leg ----
+
+def gpu_setup(scene, delta, precision, dev):
+    import torch
+    from paper_2204_12834_amd.solver import Problem, project
+    obs = project(scene.obs_cam, scene.obs_lm, scene.cams_gt, scene.lms_gt, device=dev)
+    obs += torch.as_tensor(scene.noise, device=dev)
+    prob = Problem(scene.obs_cam, scene.obs_lm, obs, scene.n_cams, scene.n_lms, precision=precision,
+                   loss="huber" if delta else "l2", huber_delta=delta or 0.0, device=dev)
+    cams0 = torch.as_tensor(scene.cams0, dtype=torch.float64, device=dev)
+    lms0 = torch.as_tensor(scene.lms0, dtype=torch.float64, device=dev)
+    return prob, cams0, lms0, obs
+
+
+def lm_run(prob, cams0, lms0, opts, max_iters):
+    """LM loop to termination with one event after every iteration; returns
+    [(cost after the iteration, seconds since the start, state)]."""
+    import torch
+    from paper_2204_12834_amd._lib import PobaLMState
+    from paper_2204_12834_amd.solver import read_lm_state
+    dev = cams0.device
+    cams, lms = cams0.clone(), lms0.clone()
+    st = prob.lm_init(opts)
+    size = st.numel()
+    hist = torch.zeros(max_iters, size, dtype=torch.uint8, device=dev)
+    start = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(max_iters)]
+    torch.cuda.synchronize()
+    start.record()
+    for i in range(max_iters):
+        prob.lm_step(cams, lms, st, opts)
+        hist[i].copy_(st)
+        evs[i].record()
+    torch.cuda.synchronize()
+    states = [read_lm_state(hist[i]) for i in range(max_iters)]
+    times = [start.elapsed_time(e) / 1e3 for e in evs]
+    out = []
+    for s, t in zip(states, times):
+        if s["iteration"] == 0:
+            break
+        out.append((s["cost"], t, s))
+        if s["done"]:
+            break
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--precision", default="f32", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--m", type=int, default=32)
+    ap.add_argument("--sample-lms", type=int, default=40000)
+    ap.add_argument("--tpw", type=int, default=0, help="landmark tiles per wavefront (0: library default)")
+    ap.add_argument("--sweep-tpw", default="", help="comma list: time the series for each and exit")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tau", action="store_true", help="skip the time-to-tolerance LM runs")
+    ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
+    args = ap.parse_args()
+
+    if args.cpu_baseline_child:
+        cpu_baseline_child(args.workload, args.m, args.sample_lms)
+        return 0
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2204_12834_amd.solver import LMOptions
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_gen = time.perf_counter()
+    scene, delta = make_scene(args.workload)
+    print(f"[bench] scene {scene.name}: {scene.n_cams} cams, {scene.n_lms} lms, {scene.n_obs} obs "
+          f"({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
+
+    prob, cams0, lms0, obs = gpu_setup(scene, delta, args.precision, dev)
+    if args.tpw:
+        prob.set_tuning("tiles_per_wave", args.tpw)
+    cams, lms = cams0.clone(), lms0.clone()
+    if args.sweep_tpw:
+        prob.linearize(cams0, lms0)
+        for tpw in [int(x) for x in args.sweep_tpw.split(",")]:
+            prob.set_tuning("tiles_per_wave", tpw)
+            prob.power_solve(1e-4, args.m, 0.0)
+            torch.cuda.synchronize()
+            prob.profile(True)
+            prob.profile_read()
+            for _ in range(3):
+                prob.power_solve(1e-4, args.m, 0.0)
+            torch.cuda.synchronize()
+            pr = prob.profile_read()
+            prob.profile(False)
+            print(f"[sweep] tpw={tpw}: " + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f} us x{v[1] // 3}"
+                                                    for k, v in pr.items() if v[1]), file=sys.stderr, flush=True)
+        return 0
+    opts = LMOptions(m=args.m, eps=0.0, func_tol=0.0, max_iters=1 << 30)
+    st = prob.lm_init(opts)
+
+    def step():
+        cams.copy_(cams0)
+        lms.copy_(lms0)
+        prob.lm_init(opts, state=st)
+        prob.lm_step(cams, lms, st, opts)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    prob.profile(True)
+    prob.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = prob.profile_read()
+    prob.profile(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    print(f"[bench] {args.steps} steps, {ms_per_step:.3f} ms/step; per step: "
+          + ", ".join(f"{k} {v[0] / args.steps:.3f} ms ({v[1] // args.steps})" for k, v in prof.items()),
+          file=sys.stderr, flush=True)
+
+    N, nl, nc = scene.n_obs, scene.n_lms, scene.n_cams
+    lmb, camb = series_bytes(N, nl, args.precision)
+    k = args.steps
+    t_lm = prof["landmark_pass"][0] / 1e3
+    t_cam = prof["camera_pass"][0] / 1e3
+    t_fin = prof["camera_finish"][0] / 1e3
+    n_lm = prof["landmark_pass"][1]
+    n_cam = prof["camera_pass"][1]
+    # one landmark pass per order; camera pass and finish run m + 1 times
+    # (the extra one forms the reduced right-hand side)
+    avg_lm = t_lm / n_lm
+    avg_cam = t_cam / n_cam
+    n_fin = prof["camera_finish"][1]
+    avg_fin = t_fin / n_fin if n_fin else 0.0
+    series_time = k * args.m * (avg_lm + avg_cam + avg_fin)
+    value = k * args.m * (lmb + camb) / series_time / 1e9
+    dom = "landmark_pass" if t_lm >= t_cam else "camera_pass"
+    dom_bytes = lmb if dom == "landmark_pass" else camb
+    dom_avg = avg_lm if dom == "landmark_pass" else avg_cam
+    achieved = dom_bytes / dom_avg / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        key = f"{args.workload}_{args.precision}_{dom}"
+        if tr.get("source_hash") == kernel_source_hash() and key in tr.get("bytes_per_launch", {}):
+            traffic = tr["bytes_per_launch"][key]
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_avg * 1e3, 4)}
+    phases = {name: round(v[0] / k, 4) for name, v in prof.items()}
+
+    # stream-copy probe: achievable HBM bandwidth (4 GiB, well beyond the caches)
+    a = torch.empty(1 << 29, dtype=torch.float64, device=dev)
+    bbuf = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(2):
+        bbuf.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        bbuf.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * a.numel() * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, bbuf
+
+    extra = {}
+    if not args.no_tau:
+        del prob
+        torch.cuda.empty_cache()
+        runs = {}
+        for prec in ["f64", "f32", "bf16"]:
+            p2, c0, l0, _ = gpu_setup(scene, delta, prec, dev)
+            o2 = LMOptions(m=args.m)  # Sec. 5.1 settings, series order m
+            runs[prec] = lm_run(p2, c0, l0, o2, 50)
+            print(f"[bench] LM {prec}: {len(runs[prec])} iterations, final cost {runs[prec][-1][0]:.6e}",
+                  file=sys.stderr, flush=True)
+            del p2
+            torch.cuda.empty_cache()
+        # F(x0) from a plain linearisation
+        p3, c0, l0, _ = gpu_setup(scene, delta, "f64", dev)
+        f0 = p3.linearize(c0, l0).item()
+        del p3
+        fstar = min(min(c for c, _, _ in out) for out in runs.values())
+        ftau = fstar + 0.01 * (f0 - fstar)
+        tau = {}
+        for prec, out in runs.items():
+            hit = [t for c, t, _ in out if c <= ftau]
+            tau[prec] = {"t_1pct_s": round(hit[0], 4) if hit else None, "iterations": len(out),
+                         "final_cost": out[-1][0], "lm_iter_ms": round(1e3 * out[-1][1] / len(out), 3),
+                         "iters_to_1pct": next((i + 1 for i, (c, _, _) in enumerate(out) if c <= ftau), None)}
+        extra = {"f0": f0, "f_star": fstar, "f_tau": ftau, "time_to_1pct": tau}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = run_cpu_baseline(args.workload, args.m, args.sample_lms)
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"{scene.name}: {nc} cameras, {nl} landmarks, {N} observations, "
+                               f"{'Huber delta 3 px, 2% outliers, ' if delta else ''}m={args.m}, "
+                               f"{args.precision} Jacobian storage, one LM iteration per step",
+                   "n_cams": nc, "n_lms": nl, "n_obs": N, "m": args.m, "precision": args.precision},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "phase_ms_per_step": phases,
+        "measured_copy_GBps": round(copy_gbs, 1),
+        "series_GBps_vs_copy": round(value / copy_gbs, 4),
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -226,6 +226,21 @@ poba_status poba_get_orders(poba_problem p, int32_t *perm_lm, int32_t *perm_cam,
  * [n_cams][9]. */
 poba_status poba_apply_P(poba_problem p, const double *v_in, double *v_out, poba_stream stream);
 
+/* ---- launch tuning ------------------------------------------------------ */
+
+enum {
+    POBA_TUNE_TILES_PER_WAVE = 0 /* 64-observation landmark tiles per wavefront in the
+                                    landmark pass (1..64, default 4)            */
+};
+
+/* Sets a launch parameter of the handle's kernels (results do not depend on
+ * it beyond floating-point summation order).  Returns POBA_ERR_INVALID_ARG for
+ * an unknown key or a value out of range. */
+poba_status poba_set_tuning(poba_problem p, int32_t key, int32_t value);
+
+/* Reads a launch parameter into *value [host]. */
+poba_status poba_get_tuning(poba_problem p, int32_t key, int32_t *value);
+
 /* ---- timing (benchmarks) ---------------------------------------------- */
 
 /* Kernel classes timed with events when profiling is on. */

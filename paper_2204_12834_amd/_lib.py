@@ -23,6 +23,7 @@ STATUS_BITS = {
 PRECISION = {"f64": 0, "f32": 1, "bf16": 2}
 DAMPING = {"marquardt": 0, "identity": 1}
 LOSS = {"l2": 0, "huber": 1}
+TUNING = {"tiles_per_wave": 0}
 KERNEL_CLASSES = ["linearize", "inverse", "landmark_pass", "camera_pass", "camera_finish", "backsub", "eval", "other"]
 
 
@@ -104,6 +105,8 @@ SIGNATURES = {
     "poba_get_jacobians": (I32, [P, I32, P, P, P, P]),
     "poba_get_orders": (I32, [P, P, P, P, P, P]),
     "poba_apply_P": (I32, [P, P, P, P]),
+    "poba_set_tuning": (I32, [P, I32, I32]),
+    "poba_get_tuning": (I32, [P, I32, ctypes.POINTER(I32)]),
     "poba_profile_enable": (I32, [P, I32]),
     "poba_profile_read": (I32, [P, ctypes.POINTER(F64), ctypes.POINTER(I64)]),
 }

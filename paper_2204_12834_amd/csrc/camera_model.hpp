@@ -149,6 +149,99 @@ __device__ __forceinline__ void evaluate_obs(const double* cam, const double* X,
     }
 }
 
+// Per-camera data shared by all of its observations: the nine parameters,
+// the Rodrigues coefficients A, B, C, D and the rotation matrix R.
+// Layout: [0..8] parameters, [9..12] A B C D, [13..21] R row-major, 2 pad.
+constexpr int kCamRec = 24;  // doubles per record
+
+__device__ __forceinline__ void make_cam_record(const double* cam, double* rec) {
+#pragma clang fp contract(off)
+    const double* w = cam;
+    const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    double A, B, C, D;
+    rodrigues_coeffs(th2, A, B, C, D);
+    for (int k = 0; k < 9; ++k) rec[k] = cam[k];
+    rec[9] = A;
+    rec[10] = B;
+    rec[11] = C;
+    rec[12] = D;
+    double* R = rec + 13;
+    R[0] = 1.0 + B * (w[0] * w[0] - th2);
+    R[4] = 1.0 + B * (w[1] * w[1] - th2);
+    R[8] = 1.0 + B * (w[2] * w[2] - th2);
+    R[1] = -A * w[2] + B * w[0] * w[1];
+    R[3] = A * w[2] + B * w[0] * w[1];
+    R[2] = A * w[1] + B * w[0] * w[2];
+    R[6] = -A * w[1] + B * w[0] * w[2];
+    R[5] = -A * w[0] + B * w[1] * w[2];
+    R[7] = A * w[0] + B * w[1] * w[2];
+    rec[22] = rec[23] = 0.0;
+}
+
+// Model pixel of X from a camera record: P = R X + t.
+__device__ __forceinline__ void project_rec(const double* rec, const double* X, double* px) {
+#pragma clang fp contract(off)
+    const double* R = rec + 13;
+    double P[3];
+    for (int k = 0; k < 3; ++k) P[k] = R[3 * k] * X[0] + R[3 * k + 1] * X[1] + R[3 * k + 2] * X[2] + rec[3 + k];
+    const double iz = 1.0 / P[2];
+    const double p0 = -P[0] * iz, p1 = -P[1] * iz;
+    const double r2 = p0 * p0 + p1 * p1;
+    const double d = 1.0 + rec[7] * r2 + rec[8] * r2 * r2;
+    px[0] = rec[6] * d * p0;
+    px[1] = rec[6] * d * p1;
+}
+
+// Residual and Jacobian blocks from a camera record (same formulas as
+// evaluate_obs with the per-camera factors hoisted).
+__device__ __forceinline__ void evaluate_obs_rec(const double* rec, const double* X, double ox, double oy, ObsEval& e) {
+#pragma clang fp contract(off)
+    const double* w = rec;
+    const double A = rec[9], B = rec[10], C = rec[11], D = rec[12];
+    const double* Rm = rec + 13;
+    double wx[3], wwx[3];
+    cross3(w, X, wx);
+    cross3(w, wx, wwx);
+    double P[3];
+    for (int k = 0; k < 3; ++k) P[k] = Rm[3 * k] * X[0] + Rm[3 * k + 1] * X[1] + Rm[3 * k + 2] * X[2] + rec[3 + k];
+    double dRX[3][3];
+    for (int j = 0; j < 3; ++j) {
+        double ej[3] = {0.0, 0.0, 0.0};
+        ej[j] = 1.0;
+        double ejX[3], ejwx[3], wejX[3];
+        cross3(ej, X, ejX);
+        cross3(ej, wx, ejwx);
+        cross3(w, ejX, wejX);
+        for (int k = 0; k < 3; ++k)
+            dRX[k][j] = C * w[j] * wx[k] + A * ejX[k] + D * w[j] * wwx[k] + B * (ejwx[k] + wejX[k]);
+    }
+    const double iz = 1.0 / P[2];
+    const double p[2] = {-P[0] * iz, -P[1] * iz};
+    const double r2 = p[0] * p[0] + p[1] * p[1];
+    const double f = rec[6], k1 = rec[7], k2 = rec[8];
+    const double d = 1.0 + k1 * r2 + k2 * r2 * r2;
+    const double dd = 2.0 * (k1 + 2.0 * k2 * r2);
+    e.r[0] = f * d * p[0] - ox;
+    e.r[1] = f * d * p[1] - oy;
+    double dpi_dp[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) dpi_dp[a][b] = f * ((a == b ? d : 0.0) + p[a] * dd * p[b]);
+    const double dp_dP[2][3] = {{-iz, 0.0, P[0] * iz * iz}, {0.0, -iz, P[1] * iz * iz}};
+    double JP[2][3];
+    for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 3; ++c) JP[a][c] = dpi_dp[a][0] * dp_dP[0][c] + dpi_dp[a][1] * dp_dP[1][c];
+    for (int a = 0; a < 2; ++a) {
+        double* Jp = e.J + 9 * a;
+        for (int j = 0; j < 3; ++j) Jp[j] = JP[a][0] * dRX[0][j] + JP[a][1] * dRX[1][j] + JP[a][2] * dRX[2][j];
+        for (int j = 0; j < 3; ++j) Jp[3 + j] = JP[a][j];
+        Jp[6] = d * p[a];
+        Jp[7] = f * r2 * p[a];
+        Jp[8] = f * r2 * r2 * p[a];
+        double* Jl = e.J + 18 + 3 * a;
+        for (int j = 0; j < 3; ++j) Jl[j] = JP[a][0] * Rm[j] + JP[a][1] * Rm[3 + j] + JP[a][2] * Rm[6 + j];
+    }
+}
+
 // Huber on s = |r|^2: rho(s) = s (s <= delta^2), 2 delta sqrt(s) - delta^2 otherwise;
 // IRLS weight w = rho'(s) = min(1, delta / sqrt(s)).
 __device__ __forceinline__ void huber(double s, double delta, double& rho, double& w) {

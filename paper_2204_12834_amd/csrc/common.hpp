@@ -20,7 +20,6 @@ constexpr int kDefaultPiece = 2048;
 constexpr uint32_t kHeadBit = 0x80000000u;
 constexpr uint32_t kIndexMask = 0x7fffffffu;
 constexpr int kMaxProfiled = 65536;
-constexpr int kTickets = 8;
 
 // ---------------------------------------------------------------- storage --
 
@@ -220,10 +219,7 @@ struct Ctrl {
     int32_t stop_order;  // last order summed
     int32_t status;      // OR of POBA_ERR_* bits
     int32_t accepted;    // last lm step accepted
-    uint32_t ticket[kTickets];
 };
-
-enum Ticket { kTicketCost = 0, kTicketNorm = 1, kTicketEval = 2, kTicketSpare = 3 };
 
 // ---------------------------------------------------------------- handle --
 
@@ -262,10 +258,11 @@ struct Buffers {
     double* part;         // [npieces_max][54] per-piece partial sums
     double* dxl;          // [nl][3] landmark step (lm step)
     double* dxp;          // [nc][9] camera step (lm step)
+    double* cam_rec;      // [nc][24] per-camera rotation data of the state being evaluated
     double* cams_new;     // [nc][9]
     double* lms_new;      // [nl][3]
     double* red_part;     // [kRedParts][4] grid-reduction partials
-    double* cam_norm;     // [nc][2] per-camera norm partials
+
     Ctrl* ctrl;
     void* sort_tmp;       // radix-sort scratch
     size_t sort_tmp_bytes;
@@ -298,6 +295,7 @@ struct poba_problem_s {
     poba::Buffers b;
     int64_t npieces = 0;
     int64_t nnel = 0;
+    int tiles_per_wave = 4;     // landmark-tile groups handled by one wavefront
     hipStream_t last_stream = nullptr;
     // profiling
     bool profiling = false;

@@ -83,33 +83,29 @@ __device__ __forceinline__ void block_sum(double* v, double* lds) {
     __syncthreads();
 }
 
-// Deterministic grid-wide sum: every block passes its block total (thread 0's
-// v); the last block to arrive sums all block totals in block order with
-// compensated (TwoSum) accumulation and returns true in all its threads with
-// the totals in thread 0's out[].  The ticket is reset for the next use.
+// Block totals (thread 0's v) to the block's slot of a partials array; a
+// later single-block kernel combines them (kernel boundaries order the
+// writes, so no device-scope fence is needed inside the producing kernel).
 template <int K>
-__device__ __forceinline__ bool grid_sum_last(const double* v, double* partials, uint32_t* ticket, uint32_t nblocks,
-                                              double* out, double* lds) {
-    __shared__ int is_last;
+__device__ __forceinline__ void store_block_partial(const double* v, double* partials) {
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) partials[size_t(blockIdx.x) * K + k] = v[k];
-        __threadfence();
-        const uint32_t t = atomicAdd(ticket, 1u);
-        is_last = (t == nblocks - 1) ? 1 : 0;
     }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
+}
+
+// Single-block sum of n block partials in block order with compensated
+// (TwoSum) per-thread accumulation; the totals are valid in thread 0.
+template <int K>
+__device__ __forceinline__ void sum_partials(const double* partials, uint32_t n, double* out, double* lds) {
     double s[K], e[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) s[k] = e[k] = 0.0;
-    for (uint32_t bI = threadIdx.x; bI < nblocks; bI += blockDim.x) {
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const volatile double* pp = partials;
             double t, err;
-            two_sum(s[k], pp[size_t(bI) * K + k], t, err);
+            two_sum(s[k], partials[size_t(i) * K + k], t, err);
             s[k] = t;
             e[k] += err;
         }
@@ -117,13 +113,11 @@ __device__ __forceinline__ bool grid_sum_last(const double* v, double* partials,
 #pragma unroll
     for (int k = 0; k < K; ++k) s[k] += e[k];
     block_sum<K>(s, lds);
-    if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) out[k] = s[k];
-        atomicExch(ticket, 0u);
-    }
-    return true;
+    for (int k = 0; k < K; ++k) out[k] = s[k];
 }
+
+constexpr int kReduceBlock = 1024;
 
 // -------------------------------------------------------- small inverses --
 

@@ -9,6 +9,9 @@ namespace poba {
 poba_status launch_linearize(Problem* p, const double* cams, const double* lms, const int32_t* gate,
                              double* cost_out, double* cost_out2, hipStream_t s);
 
+// Per-camera rotation records of cams into the handle's camera-record buffer.
+poba_status launch_cam_prep(Problem* p, const double* cams, const int32_t* gate, hipStream_t s);
+
 // Damped inverses, reduced right-hand side, power series and
 // back-substitution with the damping in ctrl->lambda; skipped unless
 // ctrl->active.  Writes dx_cams / dx_lms; info (device, may be null).

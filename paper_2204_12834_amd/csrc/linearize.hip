@@ -14,11 +14,24 @@
 
 namespace poba {
 
+// Rotation data of every camera (the only transcendental work per camera).
+__global__ __launch_bounds__(kBlock) void k_cam_prep(Buffers b, Sizes z, const double* __restrict__ cams,
+                                                     const int32_t* gate) {
+    if (gate && !*gate) return;
+    const int32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= z.nc) return;
+    double cam[9], rec[kCamRec];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) cam[k] = cams[9 * int64_t(c) + k];
+    make_cam_record(cam, rec);
+#pragma unroll
+    for (int k = 0; k < kCamRec; ++k) b.cam_rec[kCamRec * int64_t(c) + k] = rec[k];
+}
+
 template <typename TJ>
 __global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const double* __restrict__ cams,
                                                    const double* __restrict__ lms, int loss, double delta,
-                                                   const int32_t* gate, double* cost_out, double* cost_out2,
-                                                   Ctrl* ctrl) {
+                                                   const int32_t* gate) {
     __shared__ double lds[kWavesPerBlock * 2];
     if (gate && !*gate) return;
     const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
@@ -31,13 +44,12 @@ __global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const dou
                 for (int k = 0; k < 9; ++k) v[k] = 0.0;
                 if (!valid) return;
                 const int32_t l = b.nel[seg];
-                double C[9], X[3];
-#pragma unroll
-                for (int k = 0; k < 9; ++k) C[k] = cams[9 * int64_t(cam) + k];
+                double X[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) X[k] = lms[3 * int64_t(l) + k];
                 ObsEval e;
-                evaluate_obs(C, X, b.obs_lo[2 * int64_t(i)], b.obs_lo[2 * int64_t(i) + 1], e);
+                evaluate_obs_rec(b.cam_rec + kCamRec * int64_t(cam), X, b.obs_lo[2 * int64_t(i)],
+                                 b.obs_lo[2 * int64_t(i) + 1], e);
                 const double s2 = e.r[0] * e.r[0] + e.r[1] * e.r[1];
                 double rho = s2, w = 1.0;
                 if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, w);
@@ -75,12 +87,21 @@ __global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const dou
     }
     double tot[2] = {cost, bad};
     block_sum<2>(tot, lds);
+    store_block_partial<2>(tot, b.red_part);
+}
+
+// F = sum of the landmark-major pass's block partials.
+__global__ __launch_bounds__(kReduceBlock) void k_cost_final(Buffers b, uint32_t nblocks, const int32_t* gate,
+                                                             double* cost_out, double* cost_out2, Ctrl* ctrl) {
+    __shared__ double lds[(kReduceBlock / kWave) * 2];
+    if (gate && !*gate) return;
     double out[2];
-    if (grid_sum_last<2>(tot, b.red_part, &ctrl->ticket[kTicketCost], gridDim.x, out, lds) && threadIdx.x == 0) {
+    sum_partials<2>(b.red_part, nblocks, out, lds);
+    if (threadIdx.x == 0) {
         ctrl->red[0] = out[0];
         if (cost_out) *cost_out = out[0];
         if (cost_out2) *cost_out2 = out[0];
-        if (out[1] != 0.0 || !isfinite(out[0])) atomicOr(&ctrl->status, POBA_ERR_NONFINITE);
+        if (out[1] != 0.0 || !isfinite(out[0])) ctrl->status |= POBA_ERR_NONFINITE;
     }
 }
 
@@ -95,9 +116,9 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const do
     const int32_t p = blockIdx.x;
     const int32_t cam = b.piece_cam[p];
     const int32_t a = b.piece_begin[p], e = b.piece_end[p];
-    double C[9];
+    double C[kCamRec];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) C[k] = cams[9 * int64_t(cam) + k];
+    for (int k = 0; k < kCamRec; ++k) C[k] = b.cam_rec[kCamRec * int64_t(cam) + k];
     double acc[54];
 #pragma unroll
     for (int k = 0; k < 54; ++k) acc[k] = 0.0;
@@ -107,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const do
 #pragma unroll
         for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
         ObsEval ev;
-        evaluate_obs(C, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], ev);
+        evaluate_obs_rec(C, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], ev);
         double w = 1.0;
         if (loss == POBA_LOSS_HUBER) {
             double rho;
@@ -172,12 +193,20 @@ poba_status launch_linearize_t(Problem* p, const double* cams, const double* lms
     const double delta = p->d.huber_delta;
     const int loss = p->d.loss;
     ProfScope prof(p, POBA_K_LINEARIZE, s);
-    hipLaunchKernelGGL(k_lin_lm<TJ>, dim3(unsigned(ceil_div(z.ntiles, kWavesPerBlock))), dim3(kBlock), 0, s, b, z,
-                       cams, lms, loss, delta, gate, cost_out, cost_out2, b.ctrl);
+    hipLaunchKernelGGL(k_cam_prep, dim3(unsigned(ceil_div(z.nc, kBlock))), dim3(kBlock), 0, s, b, z, cams, gate);
+    const unsigned nblk = unsigned(ceil_div(z.ntiles, kWavesPerBlock));
+    hipLaunchKernelGGL(k_lin_lm<TJ>, dim3(nblk), dim3(kBlock), 0, s, b, z, cams, lms, loss, delta, gate);
+    hipLaunchKernelGGL(k_cost_final, dim3(1), dim3(kReduceBlock), 0, s, b, nblk, gate, cost_out, cost_out2, b.ctrl);
     if (p->npieces > 0)
         hipLaunchKernelGGL(k_lin_cam<TJ>, dim3(unsigned(p->npieces)), dim3(kBlock), 0, s, b, z, cams, lms, loss, delta,
                            gate);
     hipLaunchKernelGGL(k_lin_cam_fin, dim3(unsigned(ceil_div(z.nc, kBlock))), dim3(kBlock), 0, s, b, z, gate);
+    return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
+}
+
+poba_status launch_cam_prep(Problem* p, const double* cams, const int32_t* gate, hipStream_t s) {
+    hipLaunchKernelGGL(k_cam_prep, dim3(unsigned(ceil_div(p->z.nc, kBlock))), dim3(kBlock), 0, s, p->b, p->z, cams,
+                       gate);
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }
 

@@ -74,12 +74,10 @@ __global__ __launch_bounds__(kBlock) void k_eval(Buffers b, Sizes z, int loss, d
             if (!valid) continue;
             const int64_t c = w & kIndexMask;
             const int64_t l = b.nel[my_seg];
-            double C[9], X[3], px[2];
-#pragma unroll
-            for (int k = 0; k < 9; ++k) C[k] = b.cams_new[9 * c + k];
+            double X[3], px[2];
 #pragma unroll
             for (int k = 0; k < 3; ++k) X[k] = b.lms_new[3 * l + k];
-            project_point(C, X, px);
+            project_rec(b.cam_rec + kCamRec * c, X, px);
             const double e0 = px[0] - b.obs_lo[2 * int64_t(i)], e1 = px[1] - b.obs_lo[2 * int64_t(i) + 1];
             const double s2 = e0 * e0 + e1 * e1;
             double rho = s2, wgt;
@@ -103,8 +101,15 @@ __global__ __launch_bounds__(kBlock) void k_eval(Buffers b, Sizes z, int loss, d
     }
     double tot[3] = {cost, model, bad};
     block_sum<3>(tot, lds);
+    store_block_partial<3>(tot, b.red_part);
+}
+
+__global__ __launch_bounds__(kReduceBlock) void k_eval_final(Buffers b, uint32_t nblocks, Ctrl* ctrl) {
+    __shared__ double lds[(kReduceBlock / kWave) * 3];
+    if (!ctrl->active) return;
     double out[3];
-    if (grid_sum_last<3>(tot, b.red_part, &ctrl->ticket[kTicketEval], gridDim.x, out, lds) && threadIdx.x == 0) {
+    sum_partials<3>(b.red_part, nblocks, out, lds);
+    if (threadIdx.x == 0) {
         ctrl->red[1] = out[2] != 0.0 ? __builtin_nan("") : out[0];
         ctrl->red[2] = out[1];
     }
@@ -193,12 +198,15 @@ poba_status poba_lm_step(poba_problem p, double* cams, double* lms, poba_lm_stat
     {
         ProfScope pr(p, POBA_K_EVAL, s);
         hipLaunchKernelGGL(k_trial, g_state, dim3(kBlock), 0, s, b, z, cams, lms, b.ctrl);
+        rc = launch_cam_prep(p, b.cams_new, &b.ctrl->active, s);
+        if (rc) return rc;
         const dim3 g_tiles(unsigned(ceil_div(z.ntiles, kWavesPerBlock)));
         switch (p->d.precision) {
             case POBA_F64: hipLaunchKernelGGL(k_eval<double>, g_tiles, dim3(kBlock), 0, s, b, z, p->d.loss, p->d.huber_delta, b.ctrl); break;
             case POBA_F32: hipLaunchKernelGGL(k_eval<float>, g_tiles, dim3(kBlock), 0, s, b, z, p->d.loss, p->d.huber_delta, b.ctrl); break;
             default: hipLaunchKernelGGL(k_eval<bf16_t>, g_tiles, dim3(kBlock), 0, s, b, z, p->d.loss, p->d.huber_delta, b.ctrl); break;
         }
+        hipLaunchKernelGGL(k_eval_final, dim3(1), dim3(kReduceBlock), 0, s, b, unsigned(g_tiles.x), b.ctrl);
     }
     LMParams prm{o->func_tol, o->eta, o->lambda_min, o->lambda_max, o->max_iters};
     hipLaunchKernelGGL(k_control, dim3(1), dim3(64), 0, s, b.ctrl, st, prm);

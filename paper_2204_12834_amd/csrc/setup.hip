@@ -36,7 +36,7 @@ bool compute_sizes(const poba_desc* d, Sizes* z) {
     z->npieces_max = z->N / z->piece + z->nc + 1;
     z->jbytes = d->precision == POBA_F64 ? 8 : (d->precision == POBA_F32 ? 4 : 2);
     z->sbytes = d->precision == POBA_F64 ? 8 : 4;
-    z->red_parts = std::max<int64_t>(ceil_div(z->ntiles, kWavesPerBlock), ceil_div(z->nc, kBlock)) + 1;
+    z->red_parts = std::max<int64_t>(ceil_div(z->ntiles, kWavesPerBlock), ceil_div(z->nc, kBlock / 9)) + 1;
     return true;
 }
 
@@ -89,10 +89,11 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.part = (double*)take(size_t(z.npieces_max) * 54 * 8);
     t.dxl = (double*)take(nl * 3 * 8);
     t.dxp = (double*)take(nc * 9 * 8);
+    t.cam_rec = (double*)take(nc * 24 * 8);
     t.cams_new = (double*)take(nc * 9 * 8);
     t.lms_new = (double*)take(nl * 3 * 8);
     t.red_part = (double*)take(size_t(z.red_parts) * 4 * 8);
-    t.cam_norm = (double*)take(nc * 2 * 8);
+
     t.ctrl = (Ctrl*)take(sizeof(Ctrl));
     t.keys_tmp = (int32_t*)take(N * 4);
     t.vals_tmp = (int32_t*)take(N * 4);
@@ -215,7 +216,6 @@ __global__ void k_init_ctrl(Ctrl* ctrl) {
         ctrl->stop_order = 0;
         ctrl->status = 0;
         ctrl->accepted = 0;
-        for (int k = 0; k < kTickets; ++k) ctrl->ticket[k] = 0u;
     }
 }
 
@@ -425,6 +425,11 @@ poba_status poba_create(const poba_desc* d, const int32_t* obs_cam, const int32_
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nl) * 6)), dim3(kBlock), 0, s, b.V, int64_t(z.nl) * 6);
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nl) * 3)), dim3(kBlock), 0, s, b.bl, int64_t(z.nl) * 3);
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nl) * 4)), dim3(kBlock), 0, s, (double*)b.s, int64_t(z.nl) * 4);
+    // camera vectors of cameras without observations stay zero
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nc) * 9)), dim3(kBlock), 0, s, b.x, int64_t(z.nc) * 9);
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nc) * 9)), dim3(kBlock), 0, s, b.v, int64_t(z.nc) * 9);
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nc) * 12)), dim3(kBlock), 0, s, (double*)b.vq, int64_t(z.nc) * 12);
+
     if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
     if (hipGetLastError() != hipSuccess) return fail(POBA_ERR_HIP);
     *out = p;
@@ -464,6 +469,25 @@ poba_status poba_get_orders(poba_problem p, int32_t* perm_lm, int32_t* perm_cam,
     if (cam_off && hipMemcpyAsync(cam_off, b.cam_off, (p->z.nc + 1) * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return POBA_ERR_HIP;
     return POBA_OK;
+}
+
+poba_status poba_set_tuning(poba_problem p, int32_t key, int32_t value) {
+    if (!p) return POBA_ERR_INVALID_ARG;
+    switch (key) {
+        case POBA_TUNE_TILES_PER_WAVE:
+            if (value < 1 || value > 64) return POBA_ERR_INVALID_ARG;
+            p->tiles_per_wave = value;
+            return POBA_OK;
+        default: return POBA_ERR_INVALID_ARG;
+    }
+}
+
+poba_status poba_get_tuning(poba_problem p, int32_t key, int32_t* value) {
+    if (!p || !value) return POBA_ERR_INVALID_ARG;
+    switch (key) {
+        case POBA_TUNE_TILES_PER_WAVE: *value = p->tiles_per_wave; return POBA_OK;
+        default: return POBA_ERR_INVALID_ARG;
+    }
 }
 
 poba_status poba_profile_enable(poba_problem p, int32_t enable) {

@@ -12,6 +12,8 @@
 //   camera finish (per camera):      v_c = U_c^-1 u_c,  x_c += v_c,  norms
 // Both passes are segmented reductions inside a wavefront or block; camera
 // pieces are combined in a fixed order; no floating-point atomics are used.
+#include <type_traits>
+
 #include "device_ops.hpp"
 #include "kernels.hpp"
 
@@ -140,46 +142,131 @@ __global__ __launch_bounds__(kBlock) void k_rhs_lm(Buffers b, Sizes z, int dampi
 
 // ------------------------------------------------------------ landmark pass --
 
-// s_l = V_l^-1 sum_{i in l} J_l^T (J_p v_c(i)) for every non-empty landmark.
-// TJ: Jacobian storage, TC: arithmetic, TV: camera-vector type (stride vstride),
-// TS: landmark storage (V^-1 in, s out).
-template <typename TJ, typename TC, typename TV, typename TS>
-__global__ __launch_bounds__(kBlock) void k_lm_pass(Buffers b, Sizes z, const TV* __restrict__ vin, int vstride,
-                                                    TS* __restrict__ sout, const Ctrl* ctrl) {
+// Camera vector (stride 12, storage type) for one observation.
+__device__ __forceinline__ void load_cam_vec(const float* vq, int64_t cam, float* x) {
+    const float4* p = reinterpret_cast<const float4*>(vq + 12 * cam);
+    const float4 a = p[0], b = p[1], c = p[2];
+    x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+    x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+    x[8] = c.x;
+}
+__device__ __forceinline__ void load_cam_vec(const double* vq, int64_t cam, double* x) {
+    const double2* p = reinterpret_cast<const double2*>(vq + 12 * cam);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double2 a = p[k];
+        x[2 * k] = a.x;
+        x[2 * k + 1] = a.y;
+    }
+    x[8] = vq[12 * cam + 8];
+}
+
+// Packed symmetric V^-1 of one landmark (6 entries, storage type).
+__device__ __forceinline__ void load_vinv(const float* V, int64_t l, float* A) {
+    const float2* p = reinterpret_cast<const float2*>(V + 6 * l);
+    const float2 a = p[0], b = p[1], c = p[2];
+    A[0] = a.x; A[1] = a.y; A[2] = b.x; A[3] = b.y; A[4] = c.x; A[5] = c.y;
+}
+__device__ __forceinline__ void load_vinv(const double* V, int64_t l, double* A) {
+    const double2* p = reinterpret_cast<const double2*>(V + 6 * l);
+    const double2 a = p[0], b = p[1], c = p[2];
+    A[0] = a.x; A[1] = a.y; A[2] = b.x; A[3] = b.y; A[4] = c.x; A[5] = c.y;
+}
+
+__device__ __forceinline__ void store_s(float* s, int64_t l, const float* y) {
+    reinterpret_cast<float4*>(s)[l] = make_float4(y[0], y[1], y[2], 0.f);
+}
+__device__ __forceinline__ void store_s(double* s, int64_t l, const double* y) {
+    double2* p = reinterpret_cast<double2*>(s + 4 * l);
+    p[0] = make_double2(y[0], y[1]);
+    p[1] = make_double2(y[2], 0.0);
+}
+
+// Landmark pass: s_l = V_l^-1 sum_{i in l} J_l^T (J_p v_c(i)) for every
+// non-empty landmark.  One wavefront walks `tpw` consecutive 64-tiles as one
+// range, in chunks of 64 positions, loading the next chunk's records while it
+// reduces the current one.  TJ: record storage, TC: arithmetic, TS: landmark
+// storage (V^-1 in, s out) and camera-vector copy.
+template <typename TJ, typename TC, typename TS>
+__global__ __launch_bounds__(kBlock) void k_lm_pass(Buffers b, Sizes z, int tpw, TS* __restrict__ sout,
+                                                    const Ctrl* ctrl) {
     if (ctrl->stopped || !ctrl->active) return;
-    const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
-    if (tile >= z.ntiles) return;
+    const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t t0 = wave * tpw;
+    if (t0 >= z.ntiles) return;
+    const int64_t t1 = min(t0 + int64_t(tpw), z.ntiles);
+    const TS* __restrict__ vq = reinterpret_cast<const TS*>(b.vq);
     const TS* __restrict__ Vinv = reinterpret_cast<const TS*>(b.Vinv);
-    tile_landmarks<TC, 3>(
-        b.lo_cam, b.tile_start, b.seg_base, tile,
-        [&](int32_t i, bool valid, int32_t cam, int32_t, TC* v) {
-            v[0] = v[1] = v[2] = TC(0);
-            if (!valid) return;
-            TC J[24];
-            load_J<TJ, TC>(b.J_lo, z.npad, i, J);
-            const TV* vc = vin + int64_t(cam) * vstride;
+    const uint32_t* __restrict__ lo_cam = b.lo_cam;
+    const int lane = lane_id();
+    const int32_t start = b.tile_start[t0];
+    const int32_t end = b.tile_start[t1];
+    int32_t seg = b.seg_base[t0] - 1;
+    TC carry[3] = {TC(0), TC(0), TC(0)};
+    uint32_t w_nx = 0u;
+    TC J_nx[24];
+    if (start + lane < end) {
+        w_nx = lo_cam[start + lane];
+        load_J<TJ, TC>(b.J_lo, z.npad, start + lane, J_nx);
+    }
+    for (int32_t base = start; base < end; base += kWave) {
+        const int32_t i = base + lane;
+        const bool valid = i < end;
+        const uint32_t w = valid ? w_nx : 0u;
+        TC J[24];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) J[k] = J_nx[k];
+        const int32_t ni = i + kWave;
+        if (ni < end) {
+            w_nx = lo_cam[ni];
+            load_J<TJ, TC>(b.J_lo, z.npad, ni, J_nx);
+        }
+        const bool head = w & kHeadBit;
+        const uint64_t hm = ballot64(head);
+        const uint64_t hu = hm & mask_upto(lane);
+        const int seg_start = hu ? 63 - __builtin_clzll(hu) : 0;
+        const int32_t my_seg = seg + __popcll(hu);
+        TC v[3] = {TC(0), TC(0), TC(0)};
+        if (valid) {
+            TS xs[9];
+            load_cam_vec(vq, int64_t(w & kIndexMask), xs);
             TC q0 = TC(0), q1 = TC(0);
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
-                const TC xk = TC(vc[k]);
+                const TC xk = TC(xs[k]);
                 q0 += J[k] * xk;
                 q1 += J[9 + k] * xk;
             }
             v[0] = J[18] * q0 + J[21] * q1;
             v[1] = J[19] * q0 + J[22] * q1;
             v[2] = J[20] * q0 + J[23] * q1;
-        },
-        [&](int32_t seg, const TC* t) {
-            const int64_t l = b.nel[seg];
+        }
+        if (lane == 0 && !head) {
+            v[0] += carry[0];
+            v[1] += carry[1];
+            v[2] += carry[2];
+        }
+        segmented_scan<TC, 3>(v, lane, seg_start);
+        const int last = min(end - base, kWave) - 1;
+        bool is_tail;
+        if (lane < last) is_tail = (hm >> (lane + 1)) & 1ull;
+        else if (lane == last) is_tail = (i + 1 == end) || (lo_cam[i + 1] & kHeadBit);
+        else is_tail = false;
+        if (is_tail) {
+            const int64_t l = b.nel[my_seg];
+            TS Ad[6];
+            load_vinv(Vinv, l, Ad);
             TC A[6], y[3];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) A[k] = TC(Vinv[6 * l + k]);
-            sym3_apply(A, t, y);
-            TS* o = sout + 4 * l;
-            o[0] = TS(y[0]);
-            o[1] = TS(y[1]);
-            o[2] = TS(y[2]);
-        });
+            for (int k = 0; k < 6; ++k) A[k] = TC(Ad[k]);
+            sym3_apply(A, v, y);
+            TS ys[3] = {TS(y[0]), TS(y[1]), TS(y[2])};
+            store_s(sout, l, ys);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) carry[k] = __shfl(v[k], last, kWave);
+        seg += __popcll(hm);
+    }
 }
 
 // Back-substitution dx_l = -V_lambda^-1 (b_l + sum_{i in l} J_l^T J_p x_c) in
@@ -237,7 +324,18 @@ __global__ __launch_bounds__(kBlock) void k_zero_empty(Buffers b, Sizes z, doubl
 
 // -------------------------------------------------------------- camera pass --
 
-// Partial W s of one camera piece: sum_i J_p^T (J_l s_l(i)), float64 arithmetic.
+__device__ __forceinline__ void load_s3(const float* s, int64_t l, double* o) {
+    const float4 a = reinterpret_cast<const float4*>(s)[l];
+    o[0] = a.x; o[1] = a.y; o[2] = a.z;
+}
+__device__ __forceinline__ void load_s3(const double* s, int64_t l, double* o) {
+    const double2* p = reinterpret_cast<const double2*>(s + 4 * l);
+    const double2 a = p[0];
+    o[0] = a.x; o[1] = a.y; o[2] = s[4 * l + 2];
+}
+
+// Camera pass, one block per camera piece: u = sum_i J_p^T (J_l s_l(i)) over
+// the piece in float64, written to the piece's partial slot.
 template <typename TJ, typename TSin>
 __global__ __launch_bounds__(kBlock) void k_cam_pass(Buffers b, Sizes z, const TSin* __restrict__ sin,
                                                      const Ctrl* ctrl) {
@@ -248,16 +346,36 @@ __global__ __launch_bounds__(kBlock) void k_cam_pass(Buffers b, Sizes z, const T
     double acc[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc[k] = 0.0;
-    for (int32_t i = a + threadIdx.x; i < e; i += kBlock) {
-        const int64_t l = b.co_lm[i];
-        const TSin* sl = sin + 4 * l;
-        const double s0 = double(sl[0]), s1 = double(sl[1]), s2 = double(sl[2]);
-        double J[24];
-        load_J<TJ, double>(b.J_co, z.npad, i, J);
-        const double z0 = J[18] * s0 + J[19] * s1 + J[20] * s2;
-        const double z1 = J[21] * s0 + J[22] * s1 + J[23] * s2;
+    // records stay in their storage width (float for float32 and bfloat16
+    // storage) and are widened to float64 at use
+    using TL = typename std::conditional<std::is_same<TJ, double>::value, double, float>::type;
+    int32_t i = a + threadIdx.x;
+    for (; i + kBlock < e; i += 2 * kBlock) {
+        const int64_t l0 = b.co_lm[i], l1 = b.co_lm[i + kBlock];
+        TL J0[24], J1[24];
+        double s0[3], s1[3];
+        load_J<TJ, TL>(b.J_co, z.npad, i, J0);
+        load_J<TJ, TL>(b.J_co, z.npad, i + kBlock, J1);
+        load_s3(sin, l0, s0);
+        load_s3(sin, l1, s1);
+        const double z00 = double(J0[18]) * s0[0] + double(J0[19]) * s0[1] + double(J0[20]) * s0[2];
+        const double z01 = double(J0[21]) * s0[0] + double(J0[22]) * s0[1] + double(J0[23]) * s0[2];
+        const double z10 = double(J1[18]) * s1[0] + double(J1[19]) * s1[1] + double(J1[20]) * s1[2];
+        const double z11 = double(J1[21]) * s1[0] + double(J1[22]) * s1[1] + double(J1[23]) * s1[2];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) acc[k] += J[k] * z0 + J[9 + k] * z1;
+        for (int k = 0; k < 9; ++k)
+            acc[k] += (double(J0[k]) * z00 + double(J0[9 + k]) * z01) + (double(J1[k]) * z10 + double(J1[9 + k]) * z11);
+    }
+    if (i < e) {
+        const int64_t l0 = b.co_lm[i];
+        TL J0[24];
+        double s0[3];
+        load_J<TJ, TL>(b.J_co, z.npad, i, J0);
+        load_s3(sin, l0, s0);
+        const double z00 = double(J0[18]) * s0[0] + double(J0[19]) * s0[1] + double(J0[20]) * s0[2];
+        const double z01 = double(J0[21]) * s0[0] + double(J0[22]) * s0[1] + double(J0[23]) * s0[2];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[k] += double(J0[k]) * z00 + double(J0[9 + k]) * z01;
     }
     block_sum<9>(acc, lds);
     if (threadIdx.x == 0) {
@@ -266,69 +384,77 @@ __global__ __launch_bounds__(kBlock) void k_cam_pass(Buffers b, Sizes z, const T
     }
 }
 
-// Per camera: u_c = sum of its pieces, then
+// Camera finish: nine threads per camera, one per row of U^-1.  u_c is the
+// sum of the camera's pieces in piece order, then
 //   rhs:    b~_c = b_p - u_c,  v_c = -U^-1 b~_c,  x_c = v_c
 //   series: v_c = U^-1 u_c,    x_c += v_c
 //   apply:  vout_c = U^-1 u_c
-// and the squared norms of v and x over all cameras (stop rule).
+// Each block stores its partial squared norms of v and x; k_norm_stop sums
+// them in block order and applies the stop rule of eq. qcriterion.
+constexpr int kFinCams = kBlock / 9;  // cameras per block (28)
+
 template <typename TS>
-__global__ __launch_bounds__(kBlock) void k_cam_fin(Buffers b, Sizes z, int mode, int order, double eps,
-                                                    double* vout, Ctrl* ctrl) {
+__global__ __launch_bounds__(kBlock) void k_cam_fin(Buffers b, Sizes z, int mode, double* vout, const Ctrl* ctrl) {
     __shared__ double lds[kWavesPerBlock * 2];
+    __shared__ double us[kFinCams][9];
     if (ctrl->stopped || !ctrl->active) return;
-    const int32_t c = blockIdx.x * kBlock + threadIdx.x;
+    const int lc = threadIdx.x / 9, r = threadIdx.x % 9;
+    const int32_t c = blockIdx.x * kFinCams + lc;
+    const bool own = lc < kFinCams && c < z.nc;
+    if (own) {
+        double u = 0.0;
+        for (int32_t q = b.cam_piece[c]; q < b.cam_piece[c + 1]; ++q) u += b.part[9 * int64_t(q) + r];
+        if (mode == kFinRhs) u = b.bp[9 * int64_t(c) + r] - u;
+        us[lc][r] = u;
+    }
+    __syncthreads();
     double nv2 = 0.0, nx2 = 0.0;
-    if (c < z.nc) {
-        double u[9];
+    if (own) {
+        const double* Ui = b.Uinv + 81 * int64_t(c) + 9 * r;
+        double sacc = 0.0;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) u[k] = 0.0;
-        for (int32_t p = b.cam_piece[c]; p < b.cam_piece[c + 1]; ++p) {
-#pragma unroll
-            for (int k = 0; k < 9; ++k) u[k] += b.part[9 * int64_t(p) + k];
-        }
-        const double* Ui = b.Uinv + 81 * int64_t(c);
-        if (mode == kFinRhs) {
-#pragma unroll
-            for (int k = 0; k < 9; ++k) u[k] = b.bp[9 * int64_t(c) + k] - u[k];
-        }
-        double v[9];
-#pragma unroll
-        for (int r = 0; r < 9; ++r) {
-            double sacc = 0.0;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) sacc += Ui[9 * r + k] * u[k];
-            v[r] = mode == kFinRhs ? -sacc : sacc;
-        }
-        double* xc = b.x + 9 * int64_t(c);
+        for (int k = 0; k < 9; ++k) sacc += Ui[k] * us[lc][k];
+        const double v = mode == kFinRhs ? -sacc : sacc;
         if (mode == kFinApply) {
-#pragma unroll
-            for (int k = 0; k < 9; ++k) vout[9 * int64_t(c) + k] = v[k];
+            vout[9 * int64_t(c) + r] = v;
         } else {
-            TS* vq = reinterpret_cast<TS*>(b.vq) + 12 * int64_t(c);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const double xn = mode == kFinRhs ? v[k] : xc[k] + v[k];
-                xc[k] = xn;
-                b.v[9 * int64_t(c) + k] = v[k];
-                vq[k] = TS(v[k]);
-                nv2 += v[k] * v[k];
-                nx2 += xn * xn;
-            }
+            double* xc = b.x + 9 * int64_t(c) + r;
+            const double xn = mode == kFinRhs ? v : *xc + v;
+            *xc = xn;
+            b.v[9 * int64_t(c) + r] = v;
+            reinterpret_cast<TS*>(b.vq)[12 * int64_t(c) + r] = TS(v);
+            nv2 = v * v;
+            nx2 = xn * xn;
         }
     }
     double tot[2] = {nv2, nx2};
     block_sum<2>(tot, lds);
-    double out[2];
-    if (grid_sum_last<2>(tot, b.red_part, &ctrl->ticket[kTicketNorm], gridDim.x, out, lds) && threadIdx.x == 0) {
-        if (mode != kFinApply) {
-            ctrl->norm_v2 = out[0];
-            ctrl->norm_x2 = out[1];
-            ctrl->stop_order = order;
-            if (mode == kFinSeries && eps > 0.0 &&
-                (out[1] == 0.0 || double(order + 1) * sqrt(out[0]) < eps * sqrt(out[1])))
-                ctrl->stopped = 1;
-        }
+    store_block_partial<2>(tot, b.red_part);
+}
+
+// Norms of v and x over all cameras (block partials in block order) and the
+// stop rule of eq. qcriterion for series order `order`.
+__global__ __launch_bounds__(kReduceBlock) void k_norm_stop(Buffers b, uint32_t nblocks, int mode, int order,
+                                                            double eps, Ctrl* ctrl) {
+    __shared__ double lds[(kReduceBlock / kWave) * 2];
+    if (ctrl->stopped || !ctrl->active) return;
+    double tot[2];
+    sum_partials<2>(b.red_part, nblocks, tot, lds);
+    if (threadIdx.x == 0) {
+        ctrl->norm_v2 = tot[0];
+        ctrl->norm_x2 = tot[1];
+        ctrl->stop_order = order;
+        if (mode == kFinSeries && eps > 0.0 && (tot[1] == 0.0 || double(order + 1) * sqrt(tot[0]) < eps * sqrt(tot[1])))
+            ctrl->stopped = 1;
     }
+}
+
+template <typename TS>
+void launch_cam_fin(Problem* p, int mode, int order, double eps, double* vout, hipStream_t s) {
+    const unsigned nblk = unsigned(ceil_div(p->z.nc, kFinCams));
+    hipLaunchKernelGGL(k_cam_fin<TS>, dim3(nblk), dim3(kBlock), 0, s, p->b, p->z, mode, vout, p->b.ctrl);
+    if (mode != kFinApply)
+        hipLaunchKernelGGL(k_norm_stop, dim3(1), dim3(kReduceBlock), 0, s, p->b, nblk, mode, order, eps, p->b.ctrl);
 }
 
 // Copies x into the caller's camera step and fills the solve info.
@@ -345,6 +471,11 @@ __global__ __launch_bounds__(kBlock) void k_finish(Buffers b, Sizes z, double* d
         info->norm_x = sqrt(ctrl->norm_x2);
         info->norm_v = sqrt(ctrl->norm_v2);
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_f64v(double* p, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0.0;
 }
 
 // Camera vector into the gather copy (stride 12, storage type).
@@ -369,6 +500,8 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
     const dim3 blk(kBlock);
     const dim3 g_cam(unsigned(ceil_div(z.nc, kBlock)));
     const dim3 g_lm(unsigned(ceil_div(z.nl, kBlock)));
+    const int tpw = p->tiles_per_wave;
+    const dim3 g_waves(unsigned(ceil_div(ceil_div(z.ntiles, tpw), kWavesPerBlock)));
     const dim3 g_tiles(unsigned(ceil_div(z.ntiles, kWavesPerBlock)));
     const dim3 g_pieces(unsigned(std::max<int64_t>(p->npieces, 1)));
     const bool pieces = p->npieces > 0;
@@ -382,29 +515,30 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
         hipLaunchKernelGGL(k_rhs_lm, g_lm, blk, 0, s, b, z, damping, b.ctrl);
     }
     if (pieces) {
-        ProfScope pr(p, POBA_K_CAM_PASS, s);
-        hipLaunchKernelGGL((k_cam_pass<TJ, double>), g_pieces, blk, 0, s, b, z,
-                           reinterpret_cast<const double*>(b.s), b.ctrl);
-    }
-    {
-        ProfScope pr(p, POBA_K_CAM_FIN, s);
-        hipLaunchKernelGGL(k_cam_fin<TS>, g_cam, blk, 0, s, b, z, int(kFinRhs), 0, eps, (double*)nullptr, b.ctrl);
-    }
-    for (int i = 1; i <= m; ++i) {
         {
-            ProfScope pr(p, POBA_K_LM_PASS, s);
-            hipLaunchKernelGGL((k_lm_pass<TJ, TCL, TS, TS>), g_tiles, blk, 0, s, b, z,
-                               reinterpret_cast<const TS*>(b.vq), 12, reinterpret_cast<TS*>(b.s), b.ctrl);
-        }
-        if (pieces) {
             ProfScope pr(p, POBA_K_CAM_PASS, s);
-            hipLaunchKernelGGL((k_cam_pass<TJ, TS>), g_pieces, blk, 0, s, b, z, reinterpret_cast<const TS*>(b.s),
-                               b.ctrl);
+            hipLaunchKernelGGL((k_cam_pass<TJ, double>), g_pieces, blk, 0, s, b, z,
+                               reinterpret_cast<const double*>(b.s), b.ctrl);
         }
         {
             ProfScope pr(p, POBA_K_CAM_FIN, s);
-            hipLaunchKernelGGL(k_cam_fin<TS>, g_cam, blk, 0, s, b, z, int(kFinSeries), i, eps, (double*)nullptr,
-                               b.ctrl);
+            launch_cam_fin<TS>(p, kFinRhs, 0, eps, nullptr, s);
+        }
+        for (int i = 1; i <= m; ++i) {
+            {
+                ProfScope pr(p, POBA_K_LM_PASS, s);
+                hipLaunchKernelGGL((k_lm_pass<TJ, TCL, TS>), g_waves, blk, 0, s, b, z, tpw,
+                                   reinterpret_cast<TS*>(b.s), b.ctrl);
+            }
+            {
+                ProfScope pr(p, POBA_K_CAM_PASS, s);
+                hipLaunchKernelGGL((k_cam_pass<TJ, TS>), g_pieces, blk, 0, s, b, z,
+                                   reinterpret_cast<const TS*>(b.s), b.ctrl);
+            }
+            {
+                ProfScope pr(p, POBA_K_CAM_FIN, s);
+                launch_cam_fin<TS>(p, kFinSeries, i, eps, nullptr, s);
+            }
         }
     }
     {
@@ -437,13 +571,17 @@ poba_status run_apply_P(Problem* p, const double* vin, double* vout, hipStream_t
     const Sizes& z = p->z;
     const dim3 blk(kBlock);
     const dim3 g_cam(unsigned(ceil_div(z.nc, kBlock)));
+    const int tpw = p->tiles_per_wave;
     hipLaunchKernelGGL(k_load_v<TS>, g_cam, blk, 0, s, b, z, vin, b.ctrl);
-    hipLaunchKernelGGL((k_lm_pass<TJ, TCL, TS, TS>), dim3(unsigned(ceil_div(z.ntiles, kWavesPerBlock))), blk, 0, s, b,
-                       z, reinterpret_cast<const TS*>(b.vq), 12, reinterpret_cast<TS*>(b.s), b.ctrl);
-    if (p->npieces > 0)
+    hipLaunchKernelGGL(k_zero_f64v, dim3(unsigned(ceil_div(int64_t(z.nc) * 9, kBlock))), blk, 0, s, vout,
+                       int64_t(z.nc) * 9);
+    hipLaunchKernelGGL((k_lm_pass<TJ, TCL, TS>), dim3(unsigned(ceil_div(ceil_div(z.ntiles, tpw), kWavesPerBlock))), blk,
+                       0, s, b, z, tpw, reinterpret_cast<TS*>(b.s), b.ctrl);
+    if (p->npieces > 0) {
         hipLaunchKernelGGL((k_cam_pass<TJ, TS>), dim3(unsigned(p->npieces)), blk, 0, s, b, z,
                            reinterpret_cast<const TS*>(b.s), b.ctrl);
-    hipLaunchKernelGGL(k_cam_fin<TS>, g_cam, blk, 0, s, b, z, int(kFinApply), 0, 0.0, vout, b.ctrl);
+        launch_cam_fin<TS>(p, kFinApply, 0, 0.0, vout, s);
+    }
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }
 

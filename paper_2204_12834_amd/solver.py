@@ -200,6 +200,16 @@ class Problem:
         _lib.check("poba_apply_P", self.lib.poba_apply_P(self.handle, _ptr(v), _ptr(out), _stream(stream)))
         return out
 
+    # -- tuning ------------------------------------------------------------
+
+    def set_tuning(self, key: str, value: int):
+        _lib.check("poba_set_tuning", self.lib.poba_set_tuning(self.handle, _lib.TUNING[key], int(value)))
+
+    def get_tuning(self, key: str) -> int:
+        v = ctypes.c_int32()
+        _lib.check("poba_get_tuning", self.lib.poba_get_tuning(self.handle, _lib.TUNING[key], ctypes.byref(v)))
+        return int(v.value)
+
     # -- timing ------------------------------------------------------------
 
     def profile(self, enable: bool = True):
