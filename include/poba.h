@@ -266,6 +266,16 @@ poba_status poba_profile_enable(poba_problem p, int32_t enable);
  * [host] since the last read; then clears them. */
 poba_status poba_profile_read(poba_problem p, double *ms, int64_t *n);
 
+/* ---- bandwidth probe ---------------------------------------------------- */
+
+/* Streams `bytes` (a multiple of 16; src 16-byte aligned) from src [dev].
+ * kind 0 only reads (dst [dev]: `blocks` floats of sink, written only for a
+ * value that ordinary data never sums to); kind 1 copies src to dst [dev].
+ * blocks <= 0 selects 4096 blocks.  Used to measure the achievable HBM
+ * bandwidth and to calibrate byte counters with a transfer of known size. */
+poba_status poba_probe(int32_t kind, const void *src, void *dst, size_t bytes, int32_t blocks,
+                       poba_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

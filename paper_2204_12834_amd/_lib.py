@@ -107,6 +107,7 @@ SIGNATURES = {
     "poba_apply_P": (I32, [P, P, P, P]),
     "poba_set_tuning": (I32, [P, I32, I32]),
     "poba_get_tuning": (I32, [P, I32, ctypes.POINTER(I32)]),
+    "poba_probe": (I32, [I32, P, P, ctypes.c_size_t, I32, P]),
     "poba_profile_enable": (I32, [P, I32]),
     "poba_profile_read": (I32, [P, ctypes.POINTER(F64), ctypes.POINTER(I64)]),
 }
@@ -119,6 +120,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch supplies device memory and streams; importing it first makes the
+    # library bind to the HIP runtime torch already loaded (two runtimes in one
+    # process do not share devices).
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError(f"libpoba.so not found at {path}: build it with paper_2204_12834_amd/build.py "
                            "(there is no fallback implementation)")

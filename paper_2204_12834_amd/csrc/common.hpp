@@ -17,8 +17,9 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kDefaultPiece = 2048;
-constexpr uint32_t kHeadBit = 0x80000000u;
-constexpr uint32_t kIndexMask = 0x7fffffffu;
+constexpr uint32_t kHeadBit = 0x80000000u;  // first observation of its landmark
+constexpr uint32_t kTailBit = 0x40000000u;  // last observation of its landmark
+constexpr uint32_t kIndexMask = 0x3fffffffu;
 constexpr int kMaxProfiled = 65536;
 
 // ---------------------------------------------------------------- storage --
@@ -227,8 +228,9 @@ struct Buffers {
     // observation orders
     int32_t* perm_l;      // [N] original index at each landmark-major position
     int32_t* perm_c;      // [N] original index at each camera-major position
-    uint32_t* lo_cam;     // [N] camera at each landmark-major position | head bit
+    uint32_t* lo_cam;     // [N] camera at each landmark-major position | head bit | tail bit
     int32_t* co_lm;       // [N] landmark at each camera-major position
+    int32_t* co_seg;      // [N] segment (rank among non-empty landmarks) at each camera-major position
     int32_t* lm_off;      // [nl+1]
     int32_t* cam_off;     // [nc+1]
     int32_t* nel;         // [nl] non-empty landmarks in order
@@ -250,8 +252,8 @@ struct Buffers {
     double* bl;           // [nl][3]
     // solve
     double* Uinv;         // [nc][81]
-    void* Vinv;           // [nl][6] storage type
-    void* s;              // [nl][4] storage type (landmark vector of the series)
+    void* Vinv;           // [nseg][6] storage type, indexed by segment
+    void* s;              // [nseg][4] storage type (landmark vector of the series), by segment
     double* v;            // [nc][9] current series term
     void* vq;             // [nc][12] current term in storage type (gather copy)
     double* x;            // [nc][9] series sum

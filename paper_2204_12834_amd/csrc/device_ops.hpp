@@ -43,15 +43,7 @@ __device__ __forceinline__ void tile_landmarks(const uint32_t* __restrict__ lo_c
         }
         segmented_scan<T, K>(v, lane, seg_start);
         const int last = min(end - base, kWave) - 1;
-        bool is_tail;
-        if (lane < last) {
-            is_tail = (hm >> (lane + 1)) & 1ull;
-        } else if (lane == last) {
-            is_tail = (i + 1 == end) || (lo_cam[i + 1] & kHeadBit);
-        } else {
-            is_tail = false;
-        }
-        if (is_tail) tail(my_seg, v);
+        if (w & kTailBit) tail(my_seg, v);
 #pragma unroll
         for (int k = 0; k < K; ++k) carry[k] = __shfl(v[k], last, kWave);
         seg += __popcll(hm);

@@ -225,6 +225,7 @@ using namespace poba;
 
 extern "C" poba_status poba_linearize(poba_problem p, const double* cams, const double* lms, double* cost,
                                       poba_stream stream) {
+    (void)hipGetLastError();  // report only this call's launch errors
     if (!p || !cams || !lms) return POBA_ERR_INVALID_ARG;
     return launch_linearize(p, cams, lms, nullptr, cost, nullptr, reinterpret_cast<hipStream_t>(stream));
 }

@@ -173,6 +173,7 @@ using namespace poba;
 extern "C" {
 
 poba_status poba_lm_init(poba_problem p, poba_lm_state* st, const poba_lm_options* o, poba_stream stream) {
+    (void)hipGetLastError();  // report only this call's launch errors
     if (!p || !st || !o) return POBA_ERR_INVALID_ARG;
     if (!(o->lambda0 > 0.0)) return POBA_ERR_INVALID_ARG;
     hipLaunchKernelGGL(k_lm_init, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), st, o->lambda0);
@@ -181,6 +182,7 @@ poba_status poba_lm_init(poba_problem p, poba_lm_state* st, const poba_lm_option
 
 poba_status poba_lm_step(poba_problem p, double* cams, double* lms, poba_lm_state* st, const poba_lm_options* o,
                          poba_stream stream) {
+    (void)hipGetLastError();  // report only this call's launch errors
     if (!p || !cams || !lms || !st || !o) return POBA_ERR_INVALID_ARG;
     if (o->m < 0 || o->m > 100000 || !(o->eps >= 0.0) || o->max_iters < 1 || !(o->lambda_min > 0.0) ||
         !(o->lambda_max >= o->lambda_min))

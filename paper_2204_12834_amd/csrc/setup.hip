@@ -20,7 +20,8 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 bool compute_sizes(const poba_desc* d, Sizes* z) {
     if (!d) return false;
-    if (d->n_cams < 1 || d->n_lms < 1 || d->n_obs < 0 || d->n_obs >= (int64_t(1) << 31)) return false;
+    if (d->n_cams < 1 || d->n_cams >= (1 << 30) || d->n_lms < 1 || d->n_obs < 0 || d->n_obs >= (int64_t(1) << 31))
+        return false;
     if (d->precision < POBA_F64 || d->precision > POBA_F32_BF16J) return false;
     if (d->damping != POBA_DAMP_MARQUARDT && d->damping != POBA_DAMP_IDENTITY) return false;
     if (d->loss != POBA_LOSS_L2 && d->loss != POBA_LOSS_HUBER) return false;
@@ -62,6 +63,7 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.perm_c = (int32_t*)take(N * 4);
     t.lo_cam = (uint32_t*)take(N * 4);
     t.co_lm = (int32_t*)take(N * 4);
+    t.co_seg = (int32_t*)take(N * 4);
     t.lm_off = (int32_t*)take((nl + 1) * 4);
     t.cam_off = (int32_t*)take((nc + 1) * 4);
     t.nel = (int32_t*)take(nl * 4);
@@ -128,18 +130,21 @@ __global__ void k_segment_offsets(const int32_t* keys, int64_t N, int32_t n, int
 
 __global__ void k_gather_orders(const int32_t* perm_l, const int32_t* perm_c, const int32_t* obs_cam,
                                 const int32_t* obs_lm, const double* obs_xy, const int32_t* lm_off,
-                                const int32_t* sorted_lm, int64_t N, uint32_t* lo_cam, int32_t* co_lm,
-                                double* obs_lo, double* obs_co) {
+                                const int32_t* sorted_lm, const int32_t* rank, int64_t N, uint32_t* lo_cam,
+                                int32_t* co_lm, int32_t* co_seg, double* obs_lo, double* obs_co) {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const int32_t ol = perm_l[i];
     const int32_t l = sorted_lm[i];
     const bool head = lm_off[l] == int32_t(i);
-    lo_cam[i] = uint32_t(obs_cam[ol]) | (head ? kHeadBit : 0u);
+    const bool tail = lm_off[l + 1] == int32_t(i + 1);
+    lo_cam[i] = uint32_t(obs_cam[ol]) | (head ? kHeadBit : 0u) | (tail ? kTailBit : 0u);
     obs_lo[2 * i] = obs_xy[2 * ol];
     obs_lo[2 * i + 1] = obs_xy[2 * ol + 1];
     const int32_t oc = perm_c[i];
-    co_lm[i] = obs_lm[oc];
+    const int32_t lc = obs_lm[oc];
+    co_lm[i] = lc;
+    co_seg[i] = rank[lc];
     obs_co[2 * i] = obs_xy[2 * oc];
     obs_co[2 * i + 1] = obs_xy[2 * oc + 1];
 }
@@ -301,6 +306,7 @@ size_t poba_workspace_bytes(const poba_desc* d) {
 
 poba_status poba_create(const poba_desc* d, const int32_t* obs_cam, const int32_t* obs_lm, const double* obs_xy,
                         void* workspace, size_t workspace_bytes, poba_stream stream, poba_problem* out) {
+    (void)hipGetLastError();  // report only this call's launch errors
     if (!out) return POBA_ERR_INVALID_ARG;
     *out = nullptr;
     Sizes z;
@@ -373,10 +379,8 @@ poba_status poba_create(const poba_desc* d, const int32_t* obs_cam, const int32_
         if (vc.Current() != b.perm_c)
             if (hipMemcpyAsync(b.perm_c, vc.Current(), N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
         hipLaunchKernelGGL(k_segment_offsets, dim3(grid_for(N + 1)), dim3(kBlock), 0, s, b.keys_out, N, z.nc, b.cam_off);
-        // sorted landmark keys move to keys_tmp before co_lm is overwritten
+        // sorted landmark keys move to keys_tmp (gathered below, once the ranks exist)
         if (hipMemcpyAsync(b.keys_tmp, b.co_lm, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
-        hipLaunchKernelGGL(k_gather_orders, dim3(grid_for(N)), dim3(kBlock), 0, s, b.perm_l, b.perm_c, obs_cam, obs_lm,
-                           obs_xy, b.lm_off, b.keys_tmp, N, b.lo_cam, b.co_lm, b.obs_lo, b.obs_co);
     } else {
         hipLaunchKernelGGL(k_segment_offsets, dim3(1), dim3(kBlock), 0, s, b.keys_out, int64_t(0), z.nl, b.lm_off);
         hipLaunchKernelGGL(k_segment_offsets, dim3(1), dim3(kBlock), 0, s, b.keys_out, int64_t(0), z.nc, b.cam_off);
@@ -397,6 +401,10 @@ poba_status poba_create(const poba_desc* d, const int32_t* obs_cam, const int32_
         hipLaunchKernelGGL(k_compact_nonempty, dim3(grid_for(z.nl)), dim3(kBlock), 0, s, b.lm_off, rank, z.nl, b.nel);
         hipLaunchKernelGGL(k_tiles, dim3(grid_for(z.ntiles + 1)), dim3(kBlock), 0, s, b.lm_off, rank, z.nl, N, z.ntiles,
                            b.tile_start, b.seg_base);
+        if (N > 0)
+            hipLaunchKernelGGL(k_gather_orders, dim3(grid_for(N)), dim3(kBlock), 0, s, b.perm_l, b.perm_c, obs_cam,
+                               obs_lm, obs_xy, b.lm_off, b.keys_tmp, rank, N, b.lo_cam, b.co_lm, b.co_seg, b.obs_lo,
+                               b.obs_co);
         int32_t nnel = 0;
         if (hipMemcpyAsync(&nnel, rank + z.nl, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return fail(POBA_ERR_HIP);
         if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
@@ -448,6 +456,7 @@ poba_status poba_destroy(poba_problem p) {
 
 poba_status poba_project(int64_t n_obs, const int32_t* obs_cam, const int32_t* obs_lm, const double* cams,
                          const double* lms, double* out_xy, poba_stream stream) {
+    (void)hipGetLastError();  // report only this call's launch errors
     if (n_obs < 0) return POBA_ERR_INVALID_ARG;
     if (n_obs == 0) return POBA_OK;
     if (!obs_cam || !obs_lm || !cams || !lms || !out_xy) return POBA_ERR_INVALID_ARG;

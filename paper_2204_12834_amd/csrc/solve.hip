@@ -105,39 +105,41 @@ __global__ __launch_bounds__(kBlock) void k_inv_cam(Buffers b, Sizes z, int damp
     }
 }
 
-// V_lambda^-1 per landmark in float64, stored in the landmark storage type.
+// V_lambda^-1 of every non-empty landmark in float64, stored in the landmark
+// storage type at the landmark's segment index.
 template <typename TS>
-__global__ __launch_bounds__(kBlock) void k_inv_lm(Buffers b, Sizes z, int damping, Ctrl* ctrl) {
+__global__ __launch_bounds__(kBlock) void k_inv_lm(Buffers b, int32_t nseg, int damping, Ctrl* ctrl) {
     if (!ctrl->active) return;
-    const int32_t l = blockIdx.x * kBlock + threadIdx.x;
-    if (l >= z.nl) return;
+    const int32_t g = blockIdx.x * kBlock + threadIdx.x;
+    if (g >= nseg) return;
+    const int64_t l = b.nel[g];
     double Vd[6], inv[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) Vd[k] = b.V[6 * int64_t(l) + k];
+    for (int k = 0; k < 6; ++k) Vd[k] = b.V[6 * l + k];
     const bool ok = inv3_damped(Vd, ctrl->lambda, damping, inv);
-    TS* o = reinterpret_cast<TS*>(b.Vinv) + 6 * int64_t(l);
+    TS* o = reinterpret_cast<TS*>(b.Vinv) + 6 * int64_t(g);
 #pragma unroll
     for (int k = 0; k < 6; ++k) o[k] = TS(inv[k]);
     if (!ok) atomicOr(&ctrl->status, POBA_ERR_NOT_SPD);
 }
 
-// y_l = V_lambda^-1 b_l in float64 (first half of b~), into the float64 view of s.
-__global__ __launch_bounds__(kBlock) void k_rhs_lm(Buffers b, Sizes z, int damping, const Ctrl* ctrl) {
+// y = V_lambda^-1 b_l in float64 (first half of b~) for every non-empty
+// landmark, into the float64 view of s at its segment index.
+__global__ __launch_bounds__(kBlock) void k_rhs_lm(Buffers b, int32_t nseg, int damping, const Ctrl* ctrl) {
     if (!ctrl->active) return;
-    const int32_t l = blockIdx.x * kBlock + threadIdx.x;
-    if (l >= z.nl) return;
+    const int32_t g = blockIdx.x * kBlock + threadIdx.x;
+    if (g >= nseg) return;
+    const int64_t l = b.nel[g];
     double Vd[6], inv[6], bl[3], y[3];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) Vd[k] = b.V[6 * int64_t(l) + k];
+    for (int k = 0; k < 6; ++k) Vd[k] = b.V[6 * l + k];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) bl[k] = b.bl[3 * int64_t(l) + k];
+    for (int k = 0; k < 3; ++k) bl[k] = b.bl[3 * l + k];
     inv3_damped(Vd, ctrl->lambda, damping, inv);
     sym3_apply(inv, bl, y);
-    double* o = reinterpret_cast<double*>(b.s) + 4 * int64_t(l);
-    o[0] = y[0];
-    o[1] = y[1];
-    o[2] = y[2];
-    o[3] = 0.0;
+    double2* o = reinterpret_cast<double2*>(reinterpret_cast<double*>(b.s) + 4 * int64_t(g));
+    o[0] = make_double2(y[0], y[1]);
+    o[1] = make_double2(y[2], 0.0);
 }
 
 // ------------------------------------------------------------ landmark pass --
@@ -182,11 +184,13 @@ __device__ __forceinline__ void store_s(double* s, int64_t l, const double* y) {
     p[1] = make_double2(y[2], 0.0);
 }
 
-// Landmark pass: s_l = V_l^-1 sum_{i in l} J_l^T (J_p v_c(i)) for every
-// non-empty landmark.  One wavefront walks `tpw` consecutive 64-tiles as one
-// range, in chunks of 64 positions, loading the next chunk's records while it
-// reduces the current one.  TJ: record storage, TC: arithmetic, TS: landmark
-// storage (V^-1 in, s out) and camera-vector copy.
+// Landmark pass: s_g = V_g^-1 sum_{i in g} J_l^T (J_p v_c(i)) for every
+// non-empty landmark (segment g).  One wavefront walks `tpw` consecutive
+// 64-tiles as one range, in chunks of 64 positions, as a two-stage pipeline:
+// while chunk k is reduced, the records of chunk k+1 are in flight, and the
+// gathers of chunk k+1 (camera vector per observation, V^-1 per landmark end)
+// are issued after them, so no wait ever covers a younger load.
+// TJ: record storage, TC: arithmetic, TS: landmark storage and camera copy.
 template <typename TJ, typename TC, typename TS>
 __global__ __launch_bounds__(kBlock) void k_lm_pass(Buffers b, Sizes z, int tpw, TS* __restrict__ sout,
                                                     const Ctrl* ctrl) {
@@ -201,35 +205,40 @@ __global__ __launch_bounds__(kBlock) void k_lm_pass(Buffers b, Sizes z, int tpw,
     const int lane = lane_id();
     const int32_t start = b.tile_start[t0];
     const int32_t end = b.tile_start[t1];
+    if (start >= end) return;
     int32_t seg = b.seg_base[t0] - 1;
-    TC carry[3] = {TC(0), TC(0), TC(0)};
-    uint32_t w_nx = 0u;
-    TC J_nx[24];
-    if (start + lane < end) {
-        w_nx = lo_cam[start + lane];
-        load_J<TJ, TC>(b.J_lo, z.npad, start + lane, J_nx);
+
+    // stage: chunk k (current)
+    uint32_t w = 0u;
+    TC J[24];
+    TS xs[9], A[6];
+    uint64_t hm;
+    int32_t my_seg;
+    {
+        const int32_t i = start + lane;
+        if (i < end) {
+            w = lo_cam[i];
+            load_J<TJ, TC>(b.J_lo, z.npad, i, J);
+        }
+        hm = ballot64(w & kHeadBit);
+        my_seg = seg + __popcll(hm & mask_upto(lane));
+        if (i < end) load_cam_vec(vq, int64_t(w & kIndexMask), xs);
+        if (w & kTailBit) load_vinv(Vinv, my_seg, A);
     }
+    TC carry[3] = {TC(0), TC(0), TC(0)};
     for (int32_t base = start; base < end; base += kWave) {
         const int32_t i = base + lane;
         const bool valid = i < end;
-        const uint32_t w = valid ? w_nx : 0u;
-        TC J[24];
-#pragma unroll
-        for (int k = 0; k < 24; ++k) J[k] = J_nx[k];
+        // chunk k+1: records in flight while chunk k is reduced
         const int32_t ni = i + kWave;
+        uint32_t wn = 0u;
+        TC Jn[24];
         if (ni < end) {
-            w_nx = lo_cam[ni];
-            load_J<TJ, TC>(b.J_lo, z.npad, ni, J_nx);
+            wn = lo_cam[ni];
+            load_J<TJ, TC>(b.J_lo, z.npad, ni, Jn);
         }
-        const bool head = w & kHeadBit;
-        const uint64_t hm = ballot64(head);
-        const uint64_t hu = hm & mask_upto(lane);
-        const int seg_start = hu ? 63 - __builtin_clzll(hu) : 0;
-        const int32_t my_seg = seg + __popcll(hu);
         TC v[3] = {TC(0), TC(0), TC(0)};
         if (valid) {
-            TS xs[9];
-            load_cam_vec(vq, int64_t(w & kIndexMask), xs);
             TC q0 = TC(0), q1 = TC(0);
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
@@ -241,31 +250,35 @@ __global__ __launch_bounds__(kBlock) void k_lm_pass(Buffers b, Sizes z, int tpw,
             v[1] = J[19] * q0 + J[22] * q1;
             v[2] = J[20] * q0 + J[23] * q1;
         }
+        const bool head = w & kHeadBit;
         if (lane == 0 && !head) {
             v[0] += carry[0];
             v[1] += carry[1];
             v[2] += carry[2];
         }
+        const uint64_t hu = hm & mask_upto(lane);
+        const int seg_start = hu ? 63 - __builtin_clzll(hu) : 0;
         segmented_scan<TC, 3>(v, lane, seg_start);
-        const int last = min(end - base, kWave) - 1;
-        bool is_tail;
-        if (lane < last) is_tail = (hm >> (lane + 1)) & 1ull;
-        else if (lane == last) is_tail = (i + 1 == end) || (lo_cam[i + 1] & kHeadBit);
-        else is_tail = false;
-        if (is_tail) {
-            const int64_t l = b.nel[my_seg];
-            TS Ad[6];
-            load_vinv(Vinv, l, Ad);
-            TC A[6], y[3];
+        if (w & kTailBit) {
+            TC Ac[6], y[3];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) A[k] = TC(Ad[k]);
-            sym3_apply(A, v, y);
+            for (int k = 0; k < 6; ++k) Ac[k] = TC(A[k]);
+            sym3_apply(Ac, v, y);
             TS ys[3] = {TS(y[0]), TS(y[1]), TS(y[2])};
-            store_s(sout, l, ys);
+            store_s(sout, my_seg, ys);
         }
+        const int last = min(end - base, kWave) - 1;
 #pragma unroll
         for (int k = 0; k < 3; ++k) carry[k] = __shfl(v[k], last, kWave);
         seg += __popcll(hm);
+        // advance: chunk k+1 becomes current, its gathers are issued now
+        w = wn;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) J[k] = Jn[k];
+        hm = ballot64(w & kHeadBit);
+        my_seg = seg + __popcll(hm & mask_upto(lane));
+        if (ni < end) load_cam_vec(vq, int64_t(w & kIndexMask), xs);
+        if (w & kTailBit) load_vinv(Vinv, my_seg, A);
     }
 }
 
@@ -334,8 +347,10 @@ __device__ __forceinline__ void load_s3(const double* s, int64_t l, double* o) {
     o[0] = a.x; o[1] = a.y; o[2] = s[4 * l + 2];
 }
 
-// Camera pass, one block per camera piece: u = sum_i J_p^T (J_l s_l(i)) over
-// the piece in float64, written to the piece's partial slot.
+// Camera pass, one block per camera piece: u = sum_i J_p^T (J_l s_g(i)) over
+// the piece in float64, written to the piece's partial slot.  Two-stage
+// pipeline per thread: the next observation's record and segment index are in
+// flight while the current one is accumulated; its s gather is issued after.
 template <typename TJ, typename TSin>
 __global__ __launch_bounds__(kBlock) void k_cam_pass(Buffers b, Sizes z, const TSin* __restrict__ sin,
                                                      const Ctrl* ctrl) {
@@ -343,6 +358,7 @@ __global__ __launch_bounds__(kBlock) void k_cam_pass(Buffers b, Sizes z, const T
     if (ctrl->stopped || !ctrl->active) return;
     const int32_t p = blockIdx.x;
     const int32_t a = b.piece_begin[p], e = b.piece_end[p];
+    const int32_t* __restrict__ co_seg = b.co_seg;
     double acc[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc[k] = 0.0;
@@ -350,32 +366,28 @@ __global__ __launch_bounds__(kBlock) void k_cam_pass(Buffers b, Sizes z, const T
     // storage) and are widened to float64 at use
     using TL = typename std::conditional<std::is_same<TJ, double>::value, double, float>::type;
     int32_t i = a + threadIdx.x;
-    for (; i + kBlock < e; i += 2 * kBlock) {
-        const int64_t l0 = b.co_lm[i], l1 = b.co_lm[i + kBlock];
-        TL J0[24], J1[24];
-        double s0[3], s1[3];
-        load_J<TJ, TL>(b.J_co, z.npad, i, J0);
-        load_J<TJ, TL>(b.J_co, z.npad, i + kBlock, J1);
-        load_s3(sin, l0, s0);
-        load_s3(sin, l1, s1);
-        const double z00 = double(J0[18]) * s0[0] + double(J0[19]) * s0[1] + double(J0[20]) * s0[2];
-        const double z01 = double(J0[21]) * s0[0] + double(J0[22]) * s0[1] + double(J0[23]) * s0[2];
-        const double z10 = double(J1[18]) * s1[0] + double(J1[19]) * s1[1] + double(J1[20]) * s1[2];
-        const double z11 = double(J1[21]) * s1[0] + double(J1[22]) * s1[1] + double(J1[23]) * s1[2];
-#pragma unroll
-        for (int k = 0; k < 9; ++k)
-            acc[k] += (double(J0[k]) * z00 + double(J0[9 + k]) * z01) + (double(J1[k]) * z10 + double(J1[9 + k]) * z11);
-    }
+    TL J[24];
+    double sv[3];
     if (i < e) {
-        const int64_t l0 = b.co_lm[i];
-        TL J0[24];
-        double s0[3];
-        load_J<TJ, TL>(b.J_co, z.npad, i, J0);
-        load_s3(sin, l0, s0);
-        const double z00 = double(J0[18]) * s0[0] + double(J0[19]) * s0[1] + double(J0[20]) * s0[2];
-        const double z01 = double(J0[21]) * s0[0] + double(J0[22]) * s0[1] + double(J0[23]) * s0[2];
+        const int64_t g = co_seg[i];
+        load_J<TJ, TL>(b.J_co, z.npad, i, J);
+        load_s3(sin, g, sv);
+    }
+    for (; i < e; i += kBlock) {
+        const int32_t ni = i + kBlock;
+        int64_t gn = 0;
+        TL Jn[24];
+        if (ni < e) {
+            gn = co_seg[ni];
+            load_J<TJ, TL>(b.J_co, z.npad, ni, Jn);
+        }
+        const double z0 = double(J[18]) * sv[0] + double(J[19]) * sv[1] + double(J[20]) * sv[2];
+        const double z1 = double(J[21]) * sv[0] + double(J[22]) * sv[1] + double(J[23]) * sv[2];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) acc[k] += double(J0[k]) * z00 + double(J0[9 + k]) * z01;
+        for (int k = 0; k < 9; ++k) acc[k] += double(J[k]) * z0 + double(J[9 + k]) * z1;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) J[k] = Jn[k];
+        if (ni < e) load_s3(sin, gn, sv);
     }
     block_sum<9>(acc, lds);
     if (threadIdx.x == 0) {
@@ -500,6 +512,8 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
     const dim3 blk(kBlock);
     const dim3 g_cam(unsigned(ceil_div(z.nc, kBlock)));
     const dim3 g_lm(unsigned(ceil_div(z.nl, kBlock)));
+    const int32_t nseg = int32_t(p->nnel);
+    const dim3 g_seg(unsigned(std::max<int64_t>(ceil_div(nseg, kBlock), 1)));
     const int tpw = p->tiles_per_wave;
     const dim3 g_waves(unsigned(ceil_div(ceil_div(z.ntiles, tpw), kWavesPerBlock)));
     const dim3 g_tiles(unsigned(ceil_div(z.ntiles, kWavesPerBlock)));
@@ -508,11 +522,11 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
     {
         ProfScope pr(p, POBA_K_INVERSE, s);
         hipLaunchKernelGGL(k_inv_cam, g_cam, blk, 0, s, b, z, damping, b.ctrl);
-        hipLaunchKernelGGL(k_inv_lm<TS>, g_lm, blk, 0, s, b, z, damping, b.ctrl);
+        hipLaunchKernelGGL(k_inv_lm<TS>, g_seg, blk, 0, s, b, nseg, damping, b.ctrl);
     }
     {
         ProfScope pr(p, POBA_K_OTHER, s);
-        hipLaunchKernelGGL(k_rhs_lm, g_lm, blk, 0, s, b, z, damping, b.ctrl);
+        hipLaunchKernelGGL(k_rhs_lm, g_seg, blk, 0, s, b, nseg, damping, b.ctrl);
     }
     if (pieces) {
         {
@@ -626,6 +640,7 @@ extern "C" {
 
 poba_status poba_power_solve(poba_problem p, double lambda, int32_t m, double eps, double* dx_cams, double* dx_lms,
                              poba_solve_info* info, poba_stream stream) {
+    (void)hipGetLastError();  // report only this call's launch errors
     if (!p || !dx_cams || !dx_lms) return POBA_ERR_INVALID_ARG;
     if (!(lambda > 0.0) || m < 0 || m > 100000 || !(eps >= 0.0)) return POBA_ERR_INVALID_ARG;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -635,6 +650,7 @@ poba_status poba_power_solve(poba_problem p, double lambda, int32_t m, double ep
 }
 
 poba_status poba_apply_P(poba_problem p, const double* v_in, double* v_out, poba_stream stream) {
+    (void)hipGetLastError();  // report only this call's launch errors
     if (!p || !v_in || !v_out) return POBA_ERR_INVALID_ARG;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_begin_solve, dim3(1), dim3(64), 0, s, p->b.ctrl, 0.0);
@@ -648,6 +664,7 @@ poba_status poba_apply_P(poba_problem p, const double* v_in, double* v_out, poba
 }
 
 poba_status poba_get_jacobians(poba_problem p, int32_t order, double* Jp, double* Jl, double* r, poba_stream stream) {
+    (void)hipGetLastError();  // report only this call's launch errors
     if (!p || !Jp || !Jl || (order != 0 && order != 1)) return POBA_ERR_INVALID_ARG;
     if (p->z.N == 0) return POBA_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -661,6 +678,7 @@ poba_status poba_get_jacobians(poba_problem p, int32_t order, double* Jp, double
 }
 
 poba_status poba_get_blocks(poba_problem p, double* U, double* V, double* bp, double* bl, poba_stream stream) {
+    (void)hipGetLastError();  // report only this call's launch errors
     if (!p) return POBA_ERR_INVALID_ARG;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int64_t n = std::max<int64_t>(int64_t(p->z.nc) * 81, int64_t(p->z.nl) * 3);
