@@ -78,7 +78,10 @@ typedef struct {
     int32_t precision;  /* POBA_F64 / POBA_F32 / POBA_F32_BF16J */
     int32_t damping;    /* POBA_DAMP_* */
     int32_t loss;       /* POBA_LOSS_* */
-    int32_t piece_size; /* observations per camera-pass work item; 0 = default (2048) */
+    int32_t piece_size; /* observations per camera-pass work item; 0 = default (1024) */
+    int32_t lm_ranges;  /* landmark ranges of the camera-major order (XCD-local gathers);
+                           0 = automatic, 1 = none, else a multiple of 8            */
+    int32_t reserved;   /* must be 0 */
     double huber_delta; /* pixels; used when loss == POBA_LOSS_HUBER, must be > 0 */
 } poba_desc;
 
@@ -139,8 +142,10 @@ void poba_lm_default_options(poba_lm_options *o);
 size_t poba_workspace_bytes(const poba_desc *d);
 
 /* Builds a problem: validates the indices, sorts the observations into a
- * landmark-major and a camera-major order (stable, by original index), and
- * lays out the work tiles of both passes.  obs_cam, obs_lm [dev] int32
+ * landmark-major order (stable by landmark) and a camera-major order (stable
+ * by camera, then by landmark range: the observed landmarks are cut into
+ * lm_ranges contiguous ranges so that each of the GPU's eight dies gathers
+ * from a slice that fits its L2), and lays out the work tiles of both passes.  obs_cam, obs_lm [dev] int32
  * [n_obs]; obs_xy [dev] float64 [n_obs][2]; workspace [dev], 256-byte
  * aligned, at least poba_workspace_bytes(d) bytes, owned by the caller and
  * used by the handle until poba_destroy.  The inputs are copied and may be
@@ -229,8 +234,9 @@ poba_status poba_apply_P(poba_problem p, const double *v_in, double *v_out, poba
 /* ---- launch tuning ------------------------------------------------------ */
 
 enum {
-    POBA_TUNE_TILES_PER_WAVE = 0 /* 64-observation landmark tiles per wavefront in the
-                                    landmark pass (1..64, default 4)            */
+    POBA_TUNE_TILES_PER_WAVE = 0, /* 64-observation landmark tiles per wavefront in the
+                                     landmark pass (1..64, default 4)            */
+    POBA_TUNE_LM_RANGES = 1       /* landmark ranges chosen at creation (read only) */
 };
 
 /* Sets a launch parameter of the handle's kernels (results do not depend on

@@ -23,7 +23,7 @@ STATUS_BITS = {
 PRECISION = {"f64": 0, "f32": 1, "bf16": 2}
 DAMPING = {"marquardt": 0, "identity": 1}
 LOSS = {"l2": 0, "huber": 1}
-TUNING = {"tiles_per_wave": 0}
+TUNING = {"tiles_per_wave": 0, "lm_ranges": 1}
 KERNEL_CLASSES = ["linearize", "inverse", "landmark_pass", "camera_pass", "camera_finish", "backsub", "eval", "other"]
 
 
@@ -36,6 +36,8 @@ class PobaDesc(ctypes.Structure):
         ("damping", ctypes.c_int32),
         ("loss", ctypes.c_int32),
         ("piece_size", ctypes.c_int32),
+        ("lm_ranges", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("huber_delta", ctypes.c_double),
     ]
 

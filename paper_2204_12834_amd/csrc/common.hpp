@@ -16,7 +16,9 @@ using Problem = ::poba_problem_s;
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kDefaultPiece = 2048;
+constexpr int kDefaultPiece = 1024;
+constexpr int kXcds = 8;                      // dies of an MI355X; workgroups are dealt to them in turn
+constexpr int64_t kRangeBytes = 2ll << 20;   // landmark-vector slice gathered by one die
 constexpr uint32_t kHeadBit = 0x80000000u;  // first observation of its landmark
 constexpr uint32_t kTailBit = 0x40000000u;  // last observation of its landmark
 constexpr uint32_t kIndexMask = 0x3fffffffu;
@@ -239,7 +241,11 @@ struct Buffers {
     int32_t* piece_cam;   // [npieces_max]
     int32_t* piece_begin; // [npieces_max]
     int32_t* piece_end;   // [npieces_max]
-    int32_t* cam_piece;   // [nc+1]
+    int32_t* piece_grp;   // [npieces_max] (camera, range) group of each piece
+    int32_t* cam_piece;   // [nc+1] first piece of each camera
+    int32_t* grp_off;     // [nc*R+1] camera-major offsets of the (camera, range) groups
+    int32_t* grp_piece;   // [nc*R+1] first piece of each group
+    int32_t* sched;       // [kXcds*npieces_max] camera-pass block -> piece (-1: idle)
     double* obs_lo;       // [N][2] observations, landmark-major
     double* obs_co;       // [N][2] observations, camera-major
     // linearisation
@@ -277,7 +283,7 @@ struct Buffers {
 
 struct Sizes {
     int32_t nc, nl;
-    int64_t N, npad, ntiles, npieces_max;
+    int64_t N, npad, ntiles, npieces_max, ranges_max;
     int piece;
     int jbytes;  // bytes per stored Jacobian scalar
     int sbytes;  // bytes per stored landmark-side scalar
@@ -298,6 +304,8 @@ struct poba_problem_s {
     int64_t npieces = 0;
     int64_t nnel = 0;
     int tiles_per_wave = 4;     // landmark-tile groups handled by one wavefront
+    int32_t lm_ranges = 1;      // landmark ranges of the camera-major order
+    int64_t sched_len = 0;      // camera-pass grid size
     hipStream_t last_stream = nullptr;
     // profiling
     bool profiling = false;

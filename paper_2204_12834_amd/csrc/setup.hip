@@ -26,7 +26,8 @@ bool compute_sizes(const poba_desc* d, Sizes* z) {
     if (d->damping != POBA_DAMP_MARQUARDT && d->damping != POBA_DAMP_IDENTITY) return false;
     if (d->loss != POBA_LOSS_L2 && d->loss != POBA_LOSS_HUBER) return false;
     if (d->loss == POBA_LOSS_HUBER && !(d->huber_delta > 0.0)) return false;
-    if (d->piece_size < 0) return false;
+    if (d->piece_size < 0 || d->reserved != 0) return false;
+    if (d->lm_ranges < 0 || (d->lm_ranges > 1 && d->lm_ranges % kXcds != 0) || d->lm_ranges > 4096) return false;
     z->nc = d->n_cams;
     z->nl = d->n_lms;
     z->N = d->n_obs;
@@ -34,7 +35,12 @@ bool compute_sizes(const poba_desc* d, Sizes* z) {
     z->ntiles = z->N / kWave + 1;
     z->piece = d->piece_size ? d->piece_size : kDefaultPiece;
     z->piece = std::max(64, std::min(z->piece, 1 << 20));
-    z->npieces_max = z->N / z->piece + z->nc + 1;
+    // automatic choice: one range per die when the landmark vector exceeds the
+    // slice size, more when a slice per die would still be larger
+    const int64_t s_bytes_max = int64_t(z->nl) * 32;
+    const int64_t auto_max = s_bytes_max > kRangeBytes ? kXcds * ceil_div(s_bytes_max, kXcds * kRangeBytes) : 1;
+    z->ranges_max = d->lm_ranges ? d->lm_ranges : auto_max;
+    z->npieces_max = z->N / z->piece + int64_t(z->nc) * z->ranges_max + 1;
     z->jbytes = d->precision == POBA_F64 ? 8 : (d->precision == POBA_F32 ? 4 : 2);
     z->sbytes = d->precision == POBA_F64 ? 8 : 4;
     z->red_parts = std::max<int64_t>(ceil_div(z->ntiles, kWavesPerBlock), ceil_div(z->nc, kBlock / 9)) + 1;
@@ -72,7 +78,11 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.piece_cam = (int32_t*)take(size_t(z.npieces_max) * 4);
     t.piece_begin = (int32_t*)take(size_t(z.npieces_max) * 4);
     t.piece_end = (int32_t*)take(size_t(z.npieces_max) * 4);
+    t.piece_grp = (int32_t*)take(size_t(z.npieces_max) * 4);
     t.cam_piece = (int32_t*)take((nc + 1) * 4);
+    t.grp_off = (int32_t*)take((nc * size_t(z.ranges_max) + 1) * 4);
+    t.grp_piece = (int32_t*)take((nc * size_t(z.ranges_max) + 1) * 4);
+    t.sched = (int32_t*)take(size_t(kXcds) * size_t(z.npieces_max) * 4);
     t.obs_lo = (double*)take(N * 16);
     t.obs_co = (double*)take(N * 16);
     t.J_lo = take(jrec);
@@ -186,28 +196,51 @@ __global__ void k_tiles(const int32_t* lm_off, const int32_t* rank, int32_t nl, 
     seg_base[t] = rank[lo];
 }
 
-__global__ void k_piece_counts(const int32_t* cam_off, int32_t nc, int32_t piece, int32_t* counts) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c > nc) return;
-    if (c == nc) {
-        counts[c] = 0;
-        return;
-    }
-    const int32_t len = cam_off[c + 1] - cam_off[c];
-    counts[c] = (len + piece - 1) / piece;
+// Camera-major sort key of each observation: camera * R + landmark range.
+__global__ void k_cam_keys(const int32_t* obs_cam, const int32_t* obs_lm, const int32_t* rank, int64_t N,
+                           int32_t R, int32_t seg_per_range, int32_t* keys) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    keys[i] = obs_cam[i] * R + rank[obs_lm[i]] / seg_per_range;
 }
 
-__global__ void k_piece_fill(const int32_t* cam_off, const int32_t* cam_piece, int32_t nc, int32_t piece,
-                             int32_t* piece_cam, int32_t* piece_begin, int32_t* piece_end) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
-    const int32_t a = cam_off[c], b = cam_off[c + 1];
-    int32_t p = cam_piece[c];
+__global__ void k_piece_counts(const int32_t* grp_off, int32_t ngrp, int32_t piece, int32_t* counts) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g > ngrp) return;
+    if (g == ngrp) {
+        counts[g] = 0;
+        return;
+    }
+    const int32_t len = grp_off[g + 1] - grp_off[g];
+    counts[g] = (len + piece - 1) / piece;
+}
+
+__global__ void k_piece_fill(const int32_t* grp_off, const int32_t* grp_piece, int32_t ngrp, int32_t R, int32_t piece,
+                             int32_t* piece_cam, int32_t* piece_begin, int32_t* piece_end, int32_t* piece_grp) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ngrp) return;
+    const int32_t a = grp_off[g], b = grp_off[g + 1];
+    int32_t p = grp_piece[g];
     for (int32_t s = a; s < b; s += piece, ++p) {
-        piece_cam[p] = c;
+        piece_cam[p] = g / R;
         piece_begin[p] = s;
         piece_end[p] = min(s + piece, b);
+        piece_grp[p] = g;
     }
+}
+
+// cam_piece[c] = first piece of camera c (pieces are ordered by camera, range).
+__global__ void k_cam_piece(const int32_t* grp_piece, int32_t nc, int32_t R, int32_t* cam_piece) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > nc) return;
+    cam_piece[c] = grp_piece[int64_t(c) * R];
+}
+
+// cam_off[c] = first camera-major position of camera c.
+__global__ void k_cam_off(const int32_t* grp_off, int32_t nc, int32_t R, int32_t* cam_off) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > nc) return;
+    cam_off[c] = grp_off[int64_t(c) * R];
 }
 
 __global__ void k_init_ctrl(Ctrl* ctrl) {
@@ -343,13 +376,12 @@ poba_status poba_create(const poba_desc* d, const int32_t* obs_cam, const int32_
     if (herr) return fail(POBA_ERR_INDEX_RANGE);
 
     if (N > 0) {
-        // stable radix sorts: (landmark, original index) and (camera, original index)
+        // landmark-major: stable radix sort by landmark
         size_t tmp = 0;
         hipcub::DoubleBuffer<int32_t> kb(b.keys_out, b.keys_tmp), vb(b.perm_l, b.vals_tmp);
         if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, kb, vb, int(N), 0, key_bits(z.nl), s) != hipSuccess)
             return fail(POBA_ERR_HIP);
         if (tmp > b.sort_tmp_bytes) return fail(POBA_ERR_WORKSPACE);
-        // landmark-major
         if (hipMemcpyAsync(b.keys_out, obs_lm, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
         if (hipMemcpyAsync(b.perm_l, b.iota, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
         tmp = b.sort_tmp_bytes;
@@ -360,37 +392,17 @@ poba_status poba_create(const poba_desc* d, const int32_t* obs_cam, const int32_
         if (vb.Current() != b.perm_l)
             if (hipMemcpyAsync(b.perm_l, vb.Current(), N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
         hipLaunchKernelGGL(k_segment_offsets, dim3(grid_for(N + 1)), dim3(kBlock), 0, s, b.keys_out, N, z.nl, b.lm_off);
-        // keep the sorted landmark keys for the head flags: stash in co_lm for now
+        // sorted landmark keys (head and tail flags) wait in co_lm until the gather
         if (hipMemcpyAsync(b.co_lm, b.keys_out, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
-
-        // camera-major
-        size_t tmp2 = 0;
-        hipcub::DoubleBuffer<int32_t> kc(b.keys_out, b.keys_tmp), vc(b.perm_c, b.vals_tmp);
-        if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp2, kc, vc, int(N), 0, key_bits(z.nc), s) != hipSuccess)
-            return fail(POBA_ERR_HIP);
-        if (tmp2 > b.sort_tmp_bytes) return fail(POBA_ERR_WORKSPACE);
-        if (hipMemcpyAsync(b.keys_out, obs_cam, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
-        if (hipMemcpyAsync(b.perm_c, b.iota, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
-        tmp2 = b.sort_tmp_bytes;
-        if (hipcub::DeviceRadixSort::SortPairs(b.sort_tmp, tmp2, kc, vc, int(N), 0, key_bits(z.nc), s) != hipSuccess)
-            return fail(POBA_ERR_HIP);
-        if (kc.Current() != b.keys_out)
-            if (hipMemcpyAsync(b.keys_out, kc.Current(), N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
-        if (vc.Current() != b.perm_c)
-            if (hipMemcpyAsync(b.perm_c, vc.Current(), N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
-        hipLaunchKernelGGL(k_segment_offsets, dim3(grid_for(N + 1)), dim3(kBlock), 0, s, b.keys_out, N, z.nc, b.cam_off);
-        // sorted landmark keys move to keys_tmp (gathered below, once the ranks exist)
-        if (hipMemcpyAsync(b.keys_tmp, b.co_lm, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
     } else {
         hipLaunchKernelGGL(k_segment_offsets, dim3(1), dim3(kBlock), 0, s, b.keys_out, int64_t(0), z.nl, b.lm_off);
-        hipLaunchKernelGGL(k_segment_offsets, dim3(1), dim3(kBlock), 0, s, b.keys_out, int64_t(0), z.nc, b.cam_off);
     }
 
-    // non-empty landmark list and tiles
+    // non-empty landmark list (segments) and landmark tiles
+    const int64_t half = std::max<int64_t>(z.nc, z.nl) + 2;
+    int32_t* rank = b.scratch_i + half;
     {
-        const int64_t half = std::max<int64_t>(z.nc, z.nl) + 2;
         int32_t* flags = b.scratch_i;
-        int32_t* rank = b.scratch_i + half;
         hipLaunchKernelGGL(k_nonempty_flags, dim3(grid_for(z.nl)), dim3(kBlock), 0, s, b.lm_off, z.nl, flags);
         if (hipMemsetAsync(flags + z.nl, 0, 4, s) != hipSuccess) return fail(POBA_ERR_HIP);
         size_t tmp = 0;
@@ -401,33 +413,101 @@ poba_status poba_create(const poba_desc* d, const int32_t* obs_cam, const int32_
         hipLaunchKernelGGL(k_compact_nonempty, dim3(grid_for(z.nl)), dim3(kBlock), 0, s, b.lm_off, rank, z.nl, b.nel);
         hipLaunchKernelGGL(k_tiles, dim3(grid_for(z.ntiles + 1)), dim3(kBlock), 0, s, b.lm_off, rank, z.nl, N, z.ntiles,
                            b.tile_start, b.seg_base);
-        if (N > 0)
-            hipLaunchKernelGGL(k_gather_orders, dim3(grid_for(N)), dim3(kBlock), 0, s, b.perm_l, b.perm_c, obs_cam,
-                               obs_lm, obs_xy, b.lm_off, b.keys_tmp, rank, N, b.lo_cam, b.co_lm, b.co_seg, b.obs_lo,
-                               b.obs_co);
         int32_t nnel = 0;
         if (hipMemcpyAsync(&nnel, rank + z.nl, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return fail(POBA_ERR_HIP);
         if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
         p->nnel = nnel;
     }
-    // camera pieces
+
+    // landmark ranges of the camera-major order: each die of the GPU gathers
+    // the landmark vector from one slice small enough for its L2
+    int32_t R = d->lm_ranges;
+    if (R == 0) {
+        const int64_t s_bytes = p->nnel * (d->precision == POBA_F64 ? 32 : 16);
+        R = s_bytes > kRangeBytes ? int32_t(kXcds * ceil_div(s_bytes, kXcds * kRangeBytes)) : 1;
+    }
+    if (R > z.ranges_max) return fail(POBA_ERR_STATE);
+    p->lm_ranges = R;
+    const int32_t spr = int32_t(std::max<int64_t>(1, ceil_div(std::max<int64_t>(p->nnel, 1), R)));
+    const int64_t ngrp = int64_t(z.nc) * R;
+
+    if (N > 0) {
+        // camera-major: stable radix sort by (camera, landmark range)
+        hipLaunchKernelGGL(k_cam_keys, dim3(grid_for(N)), dim3(kBlock), 0, s, obs_cam, obs_lm, rank, N, R, spr,
+                           b.keys_out);
+        size_t tmp2 = 0;
+        const int bits = key_bits(int32_t(std::min<int64_t>(ngrp, int64_t(1) << 30)));
+        hipcub::DoubleBuffer<int32_t> kc(b.keys_out, b.keys_tmp), vc(b.perm_c, b.vals_tmp);
+        if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp2, kc, vc, int(N), 0, bits, s) != hipSuccess)
+            return fail(POBA_ERR_HIP);
+        if (tmp2 > b.sort_tmp_bytes) return fail(POBA_ERR_WORKSPACE);
+        if (hipMemcpyAsync(b.perm_c, b.iota, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        tmp2 = b.sort_tmp_bytes;
+        if (hipcub::DeviceRadixSort::SortPairs(b.sort_tmp, tmp2, kc, vc, int(N), 0, bits, s) != hipSuccess)
+            return fail(POBA_ERR_HIP);
+        if (kc.Current() != b.keys_out)
+            if (hipMemcpyAsync(b.keys_out, kc.Current(), N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        if (vc.Current() != b.perm_c)
+            if (hipMemcpyAsync(b.perm_c, vc.Current(), N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        hipLaunchKernelGGL(k_segment_offsets, dim3(grid_for(N + 1)), dim3(kBlock), 0, s, b.keys_out, N, int32_t(ngrp),
+                           b.grp_off);
+        if (hipMemcpyAsync(b.keys_tmp, b.co_lm, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        hipLaunchKernelGGL(k_gather_orders, dim3(grid_for(N)), dim3(kBlock), 0, s, b.perm_l, b.perm_c, obs_cam, obs_lm,
+                           obs_xy, b.lm_off, b.keys_tmp, rank, N, b.lo_cam, b.co_lm, b.co_seg, b.obs_lo, b.obs_co);
+    } else {
+        hipLaunchKernelGGL(k_segment_offsets, dim3(grid_for(ngrp + 1)), dim3(kBlock), 0, s, b.keys_out, int64_t(0),
+                           int32_t(ngrp), b.grp_off);
+    }
+    hipLaunchKernelGGL(k_cam_off, dim3(grid_for(z.nc + 1)), dim3(kBlock), 0, s, b.grp_off, z.nc, R, b.cam_off);
+
+    // camera pieces: at most `piece` observations of one (camera, range) group
     {
-        int32_t* counts = b.scratch_i;
-        hipLaunchKernelGGL(k_piece_counts, dim3(grid_for(z.nc + 1)), dim3(kBlock), 0, s, b.cam_off, z.nc, z.piece, counts);
+        int32_t* counts = b.sched;  // scratch until the schedule is written
+        hipLaunchKernelGGL(k_piece_counts, dim3(grid_for(ngrp + 1)), dim3(kBlock), 0, s, b.grp_off, int32_t(ngrp),
+                           z.piece, counts);
         size_t tmp = 0;
-        if (hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, counts, b.cam_piece, z.nc + 1, s) != hipSuccess)
+        if (hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, counts, b.grp_piece, int(ngrp + 1), s) != hipSuccess)
             return fail(POBA_ERR_HIP);
         if (tmp > b.sort_tmp_bytes) return fail(POBA_ERR_WORKSPACE);
         tmp = b.sort_tmp_bytes;
-        if (hipcub::DeviceScan::ExclusiveSum(b.sort_tmp, tmp, counts, b.cam_piece, z.nc + 1, s) != hipSuccess)
+        if (hipcub::DeviceScan::ExclusiveSum(b.sort_tmp, tmp, counts, b.grp_piece, int(ngrp + 1), s) != hipSuccess)
             return fail(POBA_ERR_HIP);
-        hipLaunchKernelGGL(k_piece_fill, dim3(grid_for(z.nc)), dim3(kBlock), 0, s, b.cam_off, b.cam_piece, z.nc, z.piece,
-                           b.piece_cam, b.piece_begin, b.piece_end);
+        hipLaunchKernelGGL(k_piece_fill, dim3(grid_for(ngrp)), dim3(kBlock), 0, s, b.grp_off, b.grp_piece,
+                           int32_t(ngrp), R, z.piece, b.piece_cam, b.piece_begin, b.piece_end, b.piece_grp);
+        hipLaunchKernelGGL(k_cam_piece, dim3(grid_for(z.nc + 1)), dim3(kBlock), 0, s, b.grp_piece, z.nc, R, b.cam_piece);
         int32_t np = 0;
-        if (hipMemcpyAsync(&np, b.cam_piece + z.nc, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        if (hipMemcpyAsync(&np, b.grp_piece + ngrp, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return fail(POBA_ERR_HIP);
         if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
         if (np > z.npieces_max) return fail(POBA_ERR_STATE);
         p->npieces = np;
+    }
+    // camera-pass schedule: workgroups are dealt to the dies in turn, so block
+    // b runs on die b % 8; with ranges it takes a piece of a range r with
+    // r % 8 == b % 8, otherwise piece b
+    {
+        std::vector<int32_t> sched;
+        if (R > 1 && p->npieces > 0) {
+            std::vector<int32_t> pgrp(size_t(p->npieces));
+            if (hipMemcpyAsync(pgrp.data(), b.piece_grp, pgrp.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+                return fail(POBA_ERR_HIP);
+            if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
+            std::vector<std::vector<int32_t>> lists(kXcds);
+            for (int32_t q = 0; q < int32_t(pgrp.size()); ++q) lists[(pgrp[q] % R) % kXcds].push_back(q);
+            size_t maxlen = 0;
+            for (auto& l : lists) maxlen = std::max(maxlen, l.size());
+            sched.assign(maxlen * kXcds, -1);
+            for (int x = 0; x < kXcds; ++x)
+                for (size_t j = 0; j < lists[x].size(); ++j) sched[j * kXcds + x] = lists[x][j];
+        } else {
+            sched.resize(size_t(p->npieces));
+            for (int32_t q = 0; q < int32_t(sched.size()); ++q) sched[q] = q;
+        }
+        if (int64_t(sched.size()) > int64_t(kXcds) * z.npieces_max) return fail(POBA_ERR_STATE);
+        p->sched_len = int64_t(sched.size());
+        if (!sched.empty() &&
+            hipMemcpyAsync(b.sched, sched.data(), sched.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(POBA_ERR_HIP);
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
     }
     // blocks of landmarks without observations are never written by a pass
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nl) * 6)), dim3(kBlock), 0, s, b.V, int64_t(z.nl) * 6);
@@ -495,6 +575,7 @@ poba_status poba_get_tuning(poba_problem p, int32_t key, int32_t* value) {
     if (!p || !value) return POBA_ERR_INVALID_ARG;
     switch (key) {
         case POBA_TUNE_TILES_PER_WAVE: *value = p->tiles_per_wave; return POBA_OK;
+        case POBA_TUNE_LM_RANGES: *value = p->lm_ranges; return POBA_OK;
         default: return POBA_ERR_INVALID_ARG;
     }
 }

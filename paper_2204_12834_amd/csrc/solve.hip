@@ -356,7 +356,8 @@ __global__ __launch_bounds__(kBlock) void k_cam_pass(Buffers b, Sizes z, const T
                                                      const Ctrl* ctrl) {
     __shared__ double lds[kWavesPerBlock * 9];
     if (ctrl->stopped || !ctrl->active) return;
-    const int32_t p = blockIdx.x;
+    const int32_t p = b.sched[blockIdx.x];
+    if (p < 0) return;
     const int32_t a = b.piece_begin[p], e = b.piece_end[p];
     const int32_t* __restrict__ co_seg = b.co_seg;
     double acc[9];
@@ -517,7 +518,7 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
     const int tpw = p->tiles_per_wave;
     const dim3 g_waves(unsigned(ceil_div(ceil_div(z.ntiles, tpw), kWavesPerBlock)));
     const dim3 g_tiles(unsigned(ceil_div(z.ntiles, kWavesPerBlock)));
-    const dim3 g_pieces(unsigned(std::max<int64_t>(p->npieces, 1)));
+    const dim3 g_pieces(unsigned(std::max<int64_t>(p->sched_len, 1)));
     const bool pieces = p->npieces > 0;
     {
         ProfScope pr(p, POBA_K_INVERSE, s);
@@ -592,7 +593,7 @@ poba_status run_apply_P(Problem* p, const double* vin, double* vout, hipStream_t
     hipLaunchKernelGGL((k_lm_pass<TJ, TCL, TS>), dim3(unsigned(ceil_div(ceil_div(z.ntiles, tpw), kWavesPerBlock))), blk,
                        0, s, b, z, tpw, reinterpret_cast<TS*>(b.s), b.ctrl);
     if (p->npieces > 0) {
-        hipLaunchKernelGGL((k_cam_pass<TJ, TS>), dim3(unsigned(p->npieces)), blk, 0, s, b, z,
+        hipLaunchKernelGGL((k_cam_pass<TJ, TS>), dim3(unsigned(p->sched_len)), blk, 0, s, b, z,
                            reinterpret_cast<const TS*>(b.s), b.ctrl);
         launch_cam_fin<TS>(p, kFinApply, 0, 0.0, vout, s);
     }

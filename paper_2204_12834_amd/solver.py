@@ -75,7 +75,7 @@ def workspace_bytes(n_cams, n_lms, n_obs, precision="f64", damping="marquardt", 
                     piece_size=0) -> int:
     lib = _lib.load()
     d = _lib.PobaDesc(int(n_cams), int(n_lms), int(n_obs), _lib.PRECISION[precision], _lib.DAMPING[damping],
-                      _lib.LOSS[loss], int(piece_size), float(huber_delta))
+                      _lib.LOSS[loss], int(piece_size), 0, 0, float(huber_delta))
     return int(lib.poba_workspace_bytes(ctypes.byref(d)))
 
 
@@ -84,7 +84,7 @@ class Problem:
 
     def __init__(self, obs_cam, obs_lm, obs_xy, n_cams: int, n_lms: int, precision: str = "f64",
                  damping: str = "marquardt", loss: str = "l2", huber_delta: float = 0.0, piece_size: int = 0,
-                 device="cuda", stream=None):
+                 lm_ranges: int = 0, device="cuda", stream=None):
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.precision = precision
@@ -94,7 +94,8 @@ class Problem:
         self.n_obs = int(obs_cam.numel())
         obs_xy = _dev(obs_xy, torch.float64, self.device, (self.n_obs, 2))
         self.desc = _lib.PobaDesc(self.n_cams, self.n_lms, self.n_obs, _lib.PRECISION[precision],
-                                  _lib.DAMPING[damping], _lib.LOSS[loss], int(piece_size), float(huber_delta))
+                                  _lib.DAMPING[damping], _lib.LOSS[loss], int(piece_size), int(lm_ranges), 0,
+                                  float(huber_delta))
         nbytes = int(self.lib.poba_workspace_bytes(ctypes.byref(self.desc)))
         if nbytes == 0:
             raise _lib.PobaError("poba_workspace_bytes", 1)

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(_lib.PobaDesc) == 40
+    assert ctypes.sizeof(_lib.PobaDesc) == 48
     assert ctypes.sizeof(_lib.PobaSolveInfo) == 32
     assert ctypes.sizeof(_lib.PobaLMState) == 80
     assert ctypes.sizeof(_lib.PobaLMOptions) == 56
@@ -44,14 +44,16 @@ def test_pure_host_calls():
     o = _lib.PobaLMOptions()
     lib.poba_lm_default_options(ctypes.byref(o))
     assert (o.lambda0, o.func_tol, o.eps, o.m, o.max_iters) == (1e-4, 1e-6, 0.01, 20, 50)
-    d = _lib.PobaDesc(16, 1000, 4000, 0, 0, 0, 0, 0.0)
+    d = _lib.PobaDesc(16, 1000, 4000, 0, 0, 0, 0, 0, 0, 0.0)
     small = lib.poba_workspace_bytes(ctypes.byref(d))
-    d32 = _lib.PobaDesc(16, 1000, 4000, 1, 0, 0, 0, 0.0)
+    d32 = _lib.PobaDesc(16, 1000, 4000, 1, 0, 0, 0, 0, 0, 0.0)
     assert small > lib.poba_workspace_bytes(ctypes.byref(d32)) > 0
-    bad = _lib.PobaDesc(0, 1000, 4000, 0, 0, 0, 0, 0.0)
+    bad = _lib.PobaDesc(0, 1000, 4000, 0, 0, 0, 0, 0, 0, 0.0)
     assert lib.poba_workspace_bytes(ctypes.byref(bad)) == 0
-    huber_no_delta = _lib.PobaDesc(16, 1000, 4000, 0, 0, 1, 0, 0.0)
+    huber_no_delta = _lib.PobaDesc(16, 1000, 4000, 0, 0, 1, 0, 0, 0, 0.0)
     assert lib.poba_workspace_bytes(ctypes.byref(huber_no_delta)) == 0
+    bad_ranges = _lib.PobaDesc(16, 1000, 4000, 0, 0, 0, 0, 12, 0, 0.0)
+    assert lib.poba_workspace_bytes(ctypes.byref(bad_ranges)) == 0
     assert lib.poba_status_string(0) == b"ok"
     assert lib.poba_status_string(2) == b"observation index out of range"
     # host-detected argument errors return at once, before any device work

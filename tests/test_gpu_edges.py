@@ -33,13 +33,13 @@ def _ragged_scene():
     return dataclasses.replace(base, obs_cam=oc, obs_lm=ol, noise=noise, outlier=np.zeros(oc.size, bool))
 
 
-@pytest.mark.parametrize("piece", [0, 64, 100])
+@pytest.mark.parametrize("piece,ranges", [(0, 0), (64, 0), (100, 0), (64, 8)])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_ragged_segments_and_empty_entities(piece, precision):
-    log(f"ragged piece={piece} {precision}")
+def test_ragged_segments_and_empty_entities(piece, ranges, precision):
+    log(f"ragged piece={piece} ranges={ranges} {precision}")
     case = Case(_ragged_scene())
     s = case.scene
-    prob = case.problem(precision, piece_size=piece)
+    prob = case.problem(precision, piece_size=piece, lm_ranges=ranges)
     cams, lms = case.state()
     cost = prob.linearize(cams, lms)
     assert abs(cost.item() - case.F) <= 1e-12 * case.F

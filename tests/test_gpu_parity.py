@@ -46,18 +46,52 @@ def test_project_matches_oracle():
         assert rel(out, ref) < 1e-13, name
 
 
+def expected_camera_order(s, R):
+    """Stable order by (camera, landmark range); ranges cut the observed
+    landmarks, in landmark order, into R equal runs."""
+    observed = np.bincount(s.obs_lm, minlength=s.n_lms) > 0
+    rank = np.cumsum(observed) - observed
+    nseg = int(observed.sum())
+    spr = max(1, -(-max(nseg, 1) // R))
+    key = s.obs_cam.astype(np.int64) * R + rank[s.obs_lm] // spr
+    return np.argsort(key, kind="stable")
+
+
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("piece", [0, 64])
-def test_orders_are_stable_sorts(name, piece):
-    log(f"orders {name} piece={piece}")
+@pytest.mark.parametrize("piece,ranges", [(0, 0), (64, 0), (0, 8), (100, 16)])
+def test_orders_are_stable_sorts(name, piece, ranges):
+    log(f"orders {name} piece={piece} ranges={ranges}")
     case = CASES[name]()
     s = case.scene
-    prob = case.problem(piece_size=piece)
+    prob = case.problem(piece_size=piece, lm_ranges=ranges)
+    R = prob.get_tuning("lm_ranges")
+    assert R == (ranges or 1)
     pl, pc, lo, co = (np_(t) for t in prob.get_orders())
     np.testing.assert_array_equal(pl, np.argsort(s.obs_lm, kind="stable"))
-    np.testing.assert_array_equal(pc, np.argsort(s.obs_cam, kind="stable"))
+    np.testing.assert_array_equal(pc, expected_camera_order(s, R))
     np.testing.assert_array_equal(lo, np.concatenate([[0], np.cumsum(np.bincount(s.obs_lm, minlength=s.n_lms))]))
     np.testing.assert_array_equal(co, np.concatenate([[0], np.cumsum(np.bincount(s.obs_cam, minlength=s.n_cams))]))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("ranges", [8, 16])
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_power_solve_with_landmark_ranges(name, ranges, precision, tol):
+    """Camera-major order split by landmark range (die-local gathers) gives the
+    same step up to summation order."""
+    case = CASES[name]()
+    prob = case.problem(precision, piece_size=128, lm_ranges=ranges)
+    cams, lms = case.state()
+    prob.linearize(cams, lms)
+    U, V, bp, bl = (np_(t) for t in prob.get_blocks())
+    s = case.scene
+    Jp0, Jl0, r0 = (np_(t) for t in prob.get_jacobians(0))
+    Ur, _, bpr, _ = normal.assemble(Jp0, Jl0, r0, s.obs_cam, s.obs_lm, s.n_cams, s.n_lms)
+    assert rel(U, Ur) < 1e-13 and rel(bp, bpr) < 1e-12
+    for lam in [1e-4, 1.0]:
+        dxp, dxl, _ = prob.power_solve(lam, 20, 0.0)
+        ref = case.solve(lam, 20)
+        assert rel(np_(dxp), ref.dxp) <= tol and rel(np_(dxl), ref.dxl) <= tol
 
 
 @pytest.mark.parametrize("name", list(CASES))
