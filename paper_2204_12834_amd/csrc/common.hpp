@@ -306,6 +306,8 @@ struct poba_problem_s {
     int tiles_per_wave = 4;     // landmark-tile groups handled by one wavefront
     int32_t lm_ranges = 1;      // landmark ranges of the camera-major order
     int64_t sched_len = 0;      // camera-pass grid size
+    int64_t n_cus = 256;        // compute units of the device
+    int lds_cam = 1;            // stage the camera vector in LDS when it fits
     hipStream_t last_stream = nullptr;
     // profiling
     bool profiling = false;

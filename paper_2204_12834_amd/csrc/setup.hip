@@ -363,6 +363,12 @@ poba_status poba_create(const poba_desc* d, const int32_t* obs_cam, const int32_
         return e;
     };
 
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            p->n_cus = cus;
+    }
     hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, s, b.ctrl);
     int32_t* err = b.scratch_i;  // reuse scratch for the error flag, cleared below
     if (hipMemsetAsync(err, 0, sizeof(int32_t), s) != hipSuccess) return fail(POBA_ERR_HIP);
@@ -567,6 +573,10 @@ poba_status poba_set_tuning(poba_problem p, int32_t key, int32_t value) {
             if (value < 1 || value > 64) return POBA_ERR_INVALID_ARG;
             p->tiles_per_wave = value;
             return POBA_OK;
+        case POBA_TUNE_LDS_CAMERA:
+            if (value != 0 && value != 1) return POBA_ERR_INVALID_ARG;
+            p->lds_cam = value;
+            return POBA_OK;
         default: return POBA_ERR_INVALID_ARG;
     }
 }
@@ -576,6 +586,7 @@ poba_status poba_get_tuning(poba_problem p, int32_t key, int32_t* value) {
     switch (key) {
         case POBA_TUNE_TILES_PER_WAVE: *value = p->tiles_per_wave; return POBA_OK;
         case POBA_TUNE_LM_RANGES: *value = p->lm_ranges; return POBA_OK;
+        case POBA_TUNE_LDS_CAMERA: *value = p->lds_cam; return POBA_OK;
         default: return POBA_ERR_INVALID_ARG;
     }
 }

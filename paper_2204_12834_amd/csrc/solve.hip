@@ -19,6 +19,8 @@
 
 namespace poba {
 
+__device__ __forceinline__ int64_t ceil_div_d(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
 enum FinMode { kFinRhs = 0, kFinSeries = 1, kFinApply = 2 };
 
 // ---------------------------------------------------------------- control --
@@ -191,6 +193,19 @@ __device__ __forceinline__ void store_s(double* s, int64_t l, const double* y) {
 // gathers of chunk k+1 (camera vector per observation, V^-1 per landmark end)
 // are issued after them, so no wait ever covers a younger load.
 // TJ: record storage, TC: arithmetic, TS: landmark storage and camera copy.
+template <typename TJ, typename TC, typename TS, bool LDS_CAM>
+__device__ __forceinline__ void lm_pass_range(const Buffers& b, const Sizes& z, int64_t t0, int64_t t1,
+                                              const TS* __restrict__ vq, TS* __restrict__ sout);
+
+// Camera vector of one observation from the LDS copy (stride 9).
+template <typename TS>
+__device__ __forceinline__ void load_cam_vec_lds(const TS* cv, int64_t cam, TS* x) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) x[k] = cv[9 * cam + k];
+}
+
+// Landmark pass over global memory: each wavefront takes `tpw` consecutive
+// tiles; the camera vector is gathered from the L2-resident copy.
 template <typename TJ, typename TC, typename TS>
 __global__ __launch_bounds__(kBlock) void k_lm_pass(Buffers b, Sizes z, int tpw, TS* __restrict__ sout,
                                                     const Ctrl* ctrl) {
@@ -199,7 +214,32 @@ __global__ __launch_bounds__(kBlock) void k_lm_pass(Buffers b, Sizes z, int tpw,
     const int64_t t0 = wave * tpw;
     if (t0 >= z.ntiles) return;
     const int64_t t1 = min(t0 + int64_t(tpw), z.ntiles);
+    lm_pass_range<TJ, TC, TS, false>(b, z, t0, t1, reinterpret_cast<const TS*>(b.vq), sout);
+}
+
+// Landmark pass with the camera vector staged in LDS: persistent blocks copy
+// the n_c x 9 vector once, then their wavefronts take tile groups in turn.
+template <typename TJ, typename TC, typename TS>
+__global__ __launch_bounds__(kBlock) void k_lm_pass_lds(Buffers b, Sizes z, int tpw, TS* __restrict__ sout,
+                                                        const Ctrl* ctrl) {
+    extern __shared__ unsigned char lds_raw[];
+    if (ctrl->stopped || !ctrl->active) return;
+    TS* cv = reinterpret_cast<TS*>(lds_raw);
     const TS* __restrict__ vq = reinterpret_cast<const TS*>(b.vq);
+    for (int64_t k = threadIdx.x; k < int64_t(z.nc) * 9; k += kBlock) cv[k] = vq[12 * (k / 9) + k % 9];
+    __syncthreads();
+    const int64_t ngroups = ceil_div_d(z.ntiles, tpw);
+    const int64_t nwaves = int64_t(gridDim.x) * kWavesPerBlock;
+    for (int64_t g = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave; g < ngroups; g += nwaves) {
+        const int64_t t0 = g * tpw;
+        const int64_t t1 = min(t0 + int64_t(tpw), z.ntiles);
+        lm_pass_range<TJ, TC, TS, true>(b, z, t0, t1, cv, sout);
+    }
+}
+
+template <typename TJ, typename TC, typename TS, bool LDS_CAM>
+__device__ __forceinline__ void lm_pass_range(const Buffers& b, const Sizes& z, int64_t t0, int64_t t1,
+                                              const TS* __restrict__ vq, TS* __restrict__ sout) {
     const TS* __restrict__ Vinv = reinterpret_cast<const TS*>(b.Vinv);
     const uint32_t* __restrict__ lo_cam = b.lo_cam;
     const int lane = lane_id();
@@ -207,6 +247,10 @@ __global__ __launch_bounds__(kBlock) void k_lm_pass(Buffers b, Sizes z, int tpw,
     const int32_t end = b.tile_start[t1];
     if (start >= end) return;
     int32_t seg = b.seg_base[t0] - 1;
+    auto cam_vec = [&](int64_t cam, TS* x) {
+        if (LDS_CAM) load_cam_vec_lds(vq, cam, x);
+        else load_cam_vec(vq, cam, x);
+    };
 
     // stage: chunk k (current)
     uint32_t w = 0u;
@@ -222,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_lm_pass(Buffers b, Sizes z, int tpw,
         }
         hm = ballot64(w & kHeadBit);
         my_seg = seg + __popcll(hm & mask_upto(lane));
-        if (i < end) load_cam_vec(vq, int64_t(w & kIndexMask), xs);
+        if (i < end) cam_vec(int64_t(w & kIndexMask), xs);
         if (w & kTailBit) load_vinv(Vinv, my_seg, A);
     }
     TC carry[3] = {TC(0), TC(0), TC(0)};
@@ -277,8 +321,31 @@ __global__ __launch_bounds__(kBlock) void k_lm_pass(Buffers b, Sizes z, int tpw,
         for (int k = 0; k < 24; ++k) J[k] = Jn[k];
         hm = ballot64(w & kHeadBit);
         my_seg = seg + __popcll(hm & mask_upto(lane));
-        if (ni < end) load_cam_vec(vq, int64_t(w & kIndexMask), xs);
+        if (ni < end) cam_vec(int64_t(w & kIndexMask), xs);
         if (w & kTailBit) load_vinv(Vinv, my_seg, A);
+    }
+}
+
+// Launches the landmark pass: with the camera vector in LDS when it fits
+// (persistent blocks, a few per compute unit), else gathering it from L2.
+constexpr size_t kLdsCamMax = 64 << 10;
+
+template <typename TJ, typename TC, typename TS>
+void launch_lm_pass(Problem* p, hipStream_t s) {
+    const Buffers& b = p->b;
+    const Sizes& z = p->z;
+    const int tpw = p->tiles_per_wave;
+    const int64_t ngroups = ceil_div(z.ntiles, tpw);
+    const size_t lds = size_t(z.nc) * 9 * sizeof(TS);
+    TS* sout = reinterpret_cast<TS*>(b.s);
+    if (p->lds_cam && lds <= kLdsCamMax) {
+        const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(4, (160 << 10) / int64_t(lds)));
+        const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(p->n_cus * per_cu, ceil_div(ngroups, kWavesPerBlock)));
+        hipLaunchKernelGGL((k_lm_pass_lds<TJ, TC, TS>), dim3(unsigned(nblk)), dim3(kBlock), lds, s, b, z, tpw, sout,
+                           b.ctrl);
+    } else {
+        hipLaunchKernelGGL((k_lm_pass<TJ, TC, TS>), dim3(unsigned(ceil_div(ngroups, kWavesPerBlock))), dim3(kBlock), 0,
+                           s, b, z, tpw, sout, b.ctrl);
     }
 }
 
@@ -542,8 +609,7 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
         for (int i = 1; i <= m; ++i) {
             {
                 ProfScope pr(p, POBA_K_LM_PASS, s);
-                hipLaunchKernelGGL((k_lm_pass<TJ, TCL, TS>), g_waves, blk, 0, s, b, z, tpw,
-                                   reinterpret_cast<TS*>(b.s), b.ctrl);
+                launch_lm_pass<TJ, TCL, TS>(p, s);
             }
             {
                 ProfScope pr(p, POBA_K_CAM_PASS, s);
@@ -590,8 +656,7 @@ poba_status run_apply_P(Problem* p, const double* vin, double* vout, hipStream_t
     hipLaunchKernelGGL(k_load_v<TS>, g_cam, blk, 0, s, b, z, vin, b.ctrl);
     hipLaunchKernelGGL(k_zero_f64v, dim3(unsigned(ceil_div(int64_t(z.nc) * 9, kBlock))), blk, 0, s, vout,
                        int64_t(z.nc) * 9);
-    hipLaunchKernelGGL((k_lm_pass<TJ, TCL, TS>), dim3(unsigned(ceil_div(ceil_div(z.ntiles, tpw), kWavesPerBlock))), blk,
-                       0, s, b, z, tpw, reinterpret_cast<TS*>(b.s), b.ctrl);
+    launch_lm_pass<TJ, TCL, TS>(p, s);
     if (p->npieces > 0) {
         hipLaunchKernelGGL((k_cam_pass<TJ, TS>), dim3(unsigned(p->sched_len)), blk, 0, s, b, z,
                            reinterpret_cast<const TS*>(b.s), b.ctrl);
