@@ -2,12 +2,14 @@
 // undamped normal-equation blocks U = J_p^T J_p, V = J_l^T J_l, b_p = J_p^T r,
 // b_l = J_l^T r, plus the cost F = 1/2 sum rho(|r_i|^2).
 //
-// Two passes evaluate every observation once per order: the landmark-major
-// pass stores the landmark-major Jacobian records and residuals and reduces V
-// and b_l per landmark segment; the camera-major pass stores the camera-major
-// records and reduces U and b_p per camera piece.  Both passes accumulate the
-// blocks in float64 from the Jacobian values rounded to the storage precision,
-// so U, V and W are built from one and the same J.
+// The camera-major pass evaluates every observation once (camera data is the
+// same for the whole block), stores the camera-major records and residuals and
+// reduces U and b_p per camera piece; the landmark-major pass copies the
+// records into landmark-major order and reduces V and b_l per landmark
+// segment.  Both accumulate in float64 from the Jacobian values rounded to the
+// storage precision, so U, V and W are built from one and the same J.
+#include <type_traits>
+
 #include "camera_model.hpp"
 #include "device_ops.hpp"
 #include "kernels.hpp"
@@ -28,29 +30,52 @@ __global__ __launch_bounds__(kBlock) void k_cam_prep(Buffers b, Sizes z, const d
     for (int k = 0; k < kCamRec; ++k) b.cam_rec[kCamRec * int64_t(c) + k] = rec[k];
 }
 
+// Camera-major pass, one block per camera piece (blocks dealt to the dies as
+// in the camera pass of the series, so the landmark gathers stay die-local).
+// Each observation is evaluated once here: residual, Huber weight, Jacobian
+// blocks; the records and the reweighted residual are stored camera-major and
+// the block's rounded J_p rows go through LDS, where 216 threads (54 entries
+// x 4 groups) accumulate the upper triangle of J_p^T J_p (45) and J_p^T r (9)
+// in float64.  Block partials of the cost go to the reduction slots.
 template <typename TJ>
-__global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const double* __restrict__ cams,
-                                                   const double* __restrict__ lms, int loss, double delta,
-                                                   const int32_t* gate) {
+__global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
+                                                    double delta, const int32_t* gate) {
+    using TL = typename std::conditional<std::is_same<TJ, double>::value, double, float>::type;
+    __shared__ TL js[kBlock][18];
+    __shared__ double rs[kBlock][2];
+    __shared__ double red[4][54];
     __shared__ double lds[kWavesPerBlock * 2];
     if (gate && !*gate) return;
-    const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
-    double cost = 0.0, bad = 0.0;
-    if (tile < z.ntiles) {
-        tile_landmarks<double, 9>(
-            b.lo_cam, b.tile_start, b.seg_base, tile,
-            [&](int32_t i, bool valid, int32_t cam, int32_t seg, double* v) {
-#pragma unroll
-                for (int k = 0; k < 9; ++k) v[k] = 0.0;
-                if (!valid) return;
-                const int32_t l = b.nel[seg];
+    const int t = threadIdx.x;
+    const int ent = t % 54, grp = t / 54;  // grp 4 (t >= 216) only evaluates
+    int ea = 0, eb = 0;
+    if (ent < 45) {
+        int e = ent, row = 0;
+        while (e >= 9 - row) {
+            e -= 9 - row;
+            ++row;
+        }
+        ea = row;
+        eb = row + e;
+    } else {
+        ea = ent - 45;
+    }
+    double acc = 0.0, cost = 0.0, bad = 0.0;
+    const int32_t p = b.sched[blockIdx.x];
+    if (p >= 0) {
+        const int32_t cam = b.piece_cam[p];
+        const int32_t a = b.piece_begin[p], e = b.piece_end[p];
+        const double* rec = b.cam_rec + kCamRec * int64_t(cam);
+        for (int32_t base = a; base < e; base += kBlock) {
+            const int32_t i = base + t;
+            if (i < e) {
+                const int64_t l = b.co_lm[i];
                 double X[3];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) X[k] = lms[3 * int64_t(l) + k];
-                ObsEval e;
-                evaluate_obs_rec(b.cam_rec + kCamRec * int64_t(cam), X, b.obs_lo[2 * int64_t(i)],
-                                 b.obs_lo[2 * int64_t(i) + 1], e);
-                const double s2 = e.r[0] * e.r[0] + e.r[1] * e.r[1];
+                for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
+                ObsEval ev;
+                evaluate_obs_rec(rec, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], ev);
+                const double s2 = ev.r[0] * ev.r[0] + ev.r[1] * ev.r[1];
                 double rho = s2, w = 1.0;
                 if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, w);
                 cost += 0.5 * rho;
@@ -58,39 +83,79 @@ __global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const dou
                 const double sw = sqrt(w);
                 double J[24];
 #pragma unroll
-                for (int k = 0; k < 24; ++k) J[k] = sw * e.J[k];
-                store_J<TJ>(b.J_lo, z.npad, i, J);
+                for (int k = 0; k < 24; ++k) J[k] = sw * ev.J[k];
+                store_J<TJ>(b.J_co, z.npad, i, J);
+                const double r0 = sw * ev.r[0], r1 = sw * ev.r[1];
+                b.r_co[2 * int64_t(i)] = r0;
+                b.r_co[2 * int64_t(i) + 1] = r1;
 #pragma unroll
-                for (int k = 0; k < 24; ++k) J[k] = round_to_storage<TJ>(J[k]);
-                const double r0 = sw * e.r[0], r1 = sw * e.r[1];
-                b.r_lo[2 * int64_t(i)] = r0;
-                b.r_lo[2 * int64_t(i) + 1] = r1;
-                const double* a = J + 18;  // J_l row 0
-                const double* c = J + 21;  // J_l row 1
-                v[0] = a[0] * a[0] + c[0] * c[0];
-                v[1] = a[0] * a[1] + c[0] * c[1];
-                v[2] = a[0] * a[2] + c[0] * c[2];
-                v[3] = a[1] * a[1] + c[1] * c[1];
-                v[4] = a[1] * a[2] + c[1] * c[2];
-                v[5] = a[2] * a[2] + c[2] * c[2];
-                v[6] = a[0] * r0 + c[0] * r1;
-                v[7] = a[1] * r0 + c[1] * r1;
-                v[8] = a[2] * r0 + c[2] * r1;
-            },
-            [&](int32_t seg, const double* v) {
-                const int64_t l = b.nel[seg];
-#pragma unroll
-                for (int k = 0; k < 6; ++k) b.V[6 * l + k] = v[k];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) b.bl[3 * l + k] = v[6 + k];
-            });
+                for (int k = 0; k < 18; ++k) js[t][k] = TL(round_to_storage<TJ>(J[k]));
+                rs[t][0] = r0;
+                rs[t][1] = r1;
+            }
+            __syncthreads();
+            const int cnt = min(kBlock, e - base);
+            if (grp < 4) {
+                if (ent < 45) {
+                    for (int j = grp; j < cnt; j += 4)
+                        acc += double(js[j][ea]) * double(js[j][eb]) + double(js[j][9 + ea]) * double(js[j][9 + eb]);
+                } else {
+                    for (int j = grp; j < cnt; j += 4)
+                        acc += double(js[j][ea]) * rs[j][0] + double(js[j][9 + ea]) * rs[j][1];
+                }
+            }
+            __syncthreads();
+        }
     }
+    if (grp < 4) red[grp][ent] = acc;
     double tot[2] = {cost, bad};
-    block_sum<2>(tot, lds);
+    block_sum<2>(tot, lds);  // contains barriers (also publishes red)
+    if (p >= 0 && t < 54)
+        b.part[54 * int64_t(p) + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
     store_block_partial<2>(tot, b.red_part);
 }
 
-// F = sum of the landmark-major pass's block partials.
+// Landmark-major pass: copies every observation's record and residual from
+// its camera-major position (bit-identical blocks in both orders) and reduces
+// V = J_l^T J_l (6) and b_l = J_l^T r (3) per landmark segment in float64.
+template <typename TJ>
+__global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const int32_t* gate) {
+    if (gate && !*gate) return;
+    const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+    if (tile >= z.ntiles) return;
+    tile_landmarks<double, 9>(
+        b.lo_cam, b.tile_start, b.seg_base, tile,
+        [&](int32_t i, bool valid, int32_t, int32_t, double* v) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) v[k] = 0.0;
+            if (!valid) return;
+            const int64_t j = b.l2c[i];
+            double J[24];
+            load_J<TJ, double>(b.J_co, z.npad, j, J);
+            store_J<TJ>(b.J_lo, z.npad, i, J);
+            const double r0 = b.r_co[2 * j], r1 = b.r_co[2 * j + 1];
+            const double* a = J + 18;  // J_l row 0
+            const double* c = J + 21;  // J_l row 1
+            v[0] = a[0] * a[0] + c[0] * c[0];
+            v[1] = a[0] * a[1] + c[0] * c[1];
+            v[2] = a[0] * a[2] + c[0] * c[2];
+            v[3] = a[1] * a[1] + c[1] * c[1];
+            v[4] = a[1] * a[2] + c[1] * c[2];
+            v[5] = a[2] * a[2] + c[2] * c[2];
+            v[6] = a[0] * r0 + c[0] * r1;
+            v[7] = a[1] * r0 + c[1] * r1;
+            v[8] = a[2] * r0 + c[2] * r1;
+        },
+        [&](int32_t seg, const double* v) {
+            const int64_t l = b.nel[seg];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) b.V[6 * l + k] = v[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) b.bl[3 * l + k] = v[6 + k];
+        });
+}
+
+// F = sum of the camera-major pass's block partials.
 __global__ __launch_bounds__(kReduceBlock) void k_cost_final(Buffers b, uint32_t nblocks, const int32_t* gate,
                                                              double* cost_out, double* cost_out2, Ctrl* ctrl) {
     __shared__ double lds[(kReduceBlock / kWave) * 2];
@@ -105,57 +170,10 @@ __global__ __launch_bounds__(kReduceBlock) void k_cost_final(Buffers b, uint32_t
     }
 }
 
-// Camera-major pass: one block per camera piece.  Accumulates the upper
-// triangle of J_p^T J_p (45 values) and J_p^T r (9) in float64.
-template <typename TJ>
-__global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const double* __restrict__ cams,
-                                                    const double* __restrict__ lms, int loss, double delta,
-                                                    const int32_t* gate) {
-    __shared__ double lds[kWavesPerBlock * 54];
+// Zero cost partial when there is no camera piece (no observations).
+__global__ void k_zero_partials(Buffers b, const int32_t* gate) {
     if (gate && !*gate) return;
-    const int32_t p = blockIdx.x;
-    const int32_t cam = b.piece_cam[p];
-    const int32_t a = b.piece_begin[p], e = b.piece_end[p];
-    double C[kCamRec];
-#pragma unroll
-    for (int k = 0; k < kCamRec; ++k) C[k] = b.cam_rec[kCamRec * int64_t(cam) + k];
-    double acc[54];
-#pragma unroll
-    for (int k = 0; k < 54; ++k) acc[k] = 0.0;
-    for (int32_t i = a + threadIdx.x; i < e; i += kBlock) {
-        const int64_t l = b.co_lm[i];
-        double X[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
-        ObsEval ev;
-        evaluate_obs_rec(C, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], ev);
-        double w = 1.0;
-        if (loss == POBA_LOSS_HUBER) {
-            double rho;
-            huber(ev.r[0] * ev.r[0] + ev.r[1] * ev.r[1], delta, rho, w);
-        }
-        const double sw = sqrt(w);
-        double J[24];
-#pragma unroll
-        for (int k = 0; k < 24; ++k) J[k] = sw * ev.J[k];
-        store_J<TJ>(b.J_co, z.npad, i, J);
-#pragma unroll
-        for (int k = 0; k < 18; ++k) J[k] = round_to_storage<TJ>(J[k]);
-        const double r0 = sw * ev.r[0], r1 = sw * ev.r[1];
-        int idx = 0;
-#pragma unroll
-        for (int r = 0; r < 9; ++r) {
-#pragma unroll
-            for (int c = r; c < 9; ++c) acc[idx++] += J[r] * J[c] + J[9 + r] * J[9 + c];
-        }
-#pragma unroll
-        for (int r = 0; r < 9; ++r) acc[45 + r] += J[r] * r0 + J[9 + r] * r1;
-    }
-    block_sum<54>(acc, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < 54; ++k) b.part[54 * int64_t(p) + k] = acc[k];
-    }
+    if (threadIdx.x < 2) b.red_part[threadIdx.x] = 0.0;
 }
 
 // Sums each camera's pieces into the full symmetric U (81) and b_p (9).
@@ -194,12 +212,14 @@ poba_status launch_linearize_t(Problem* p, const double* cams, const double* lms
     const int loss = p->d.loss;
     ProfScope prof(p, POBA_K_LINEARIZE, s);
     hipLaunchKernelGGL(k_cam_prep, dim3(unsigned(ceil_div(z.nc, kBlock))), dim3(kBlock), 0, s, b, z, cams, gate);
-    const unsigned nblk = unsigned(ceil_div(z.ntiles, kWavesPerBlock));
-    hipLaunchKernelGGL(k_lin_lm<TJ>, dim3(nblk), dim3(kBlock), 0, s, b, z, cams, lms, loss, delta, gate);
-    hipLaunchKernelGGL(k_cost_final, dim3(1), dim3(kReduceBlock), 0, s, b, nblk, gate, cost_out, cost_out2, b.ctrl);
-    if (p->npieces > 0)
-        hipLaunchKernelGGL(k_lin_cam<TJ>, dim3(unsigned(p->npieces)), dim3(kBlock), 0, s, b, z, cams, lms, loss, delta,
-                           gate);
+    const unsigned ncb = unsigned(std::max<int64_t>(p->sched_len, 1));
+    if (p->sched_len > 0)
+        hipLaunchKernelGGL(k_lin_cam<TJ>, dim3(ncb), dim3(kBlock), 0, s, b, z, lms, loss, delta, gate);
+    else
+        hipLaunchKernelGGL(k_zero_partials, dim3(1), dim3(64), 0, s, b, gate);
+    hipLaunchKernelGGL(k_cost_final, dim3(1), dim3(kReduceBlock), 0, s, b, ncb, gate, cost_out, cost_out2, b.ctrl);
+    hipLaunchKernelGGL(k_lin_lm<TJ>, dim3(unsigned(ceil_div(z.ntiles, kWavesPerBlock))), dim3(kBlock), 0, s, b, z,
+                       gate);
     hipLaunchKernelGGL(k_lin_cam_fin, dim3(unsigned(ceil_div(z.nc, kBlock))), dim3(kBlock), 0, s, b, z, gate);
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }

@@ -53,40 +53,33 @@ __global__ __launch_bounds__(kBlock) void k_trial(Buffers b, Sizes z, const doub
     if (i < int64_t(z.nl) * 3) b.lms_new[i] = lms[i] + b.dxl[i];
 }
 
-// F(x + dx) and L(0) - L(dx) over all observations (landmark-major).
+// F(x + dx) and L(0) - L(dx) over all observations, camera-major: one block
+// per camera piece (the camera's record and step are the same for the block).
 template <typename TJ>
 __global__ __launch_bounds__(kBlock) void k_eval(Buffers b, Sizes z, int loss, double delta, Ctrl* ctrl) {
     __shared__ double lds[kWavesPerBlock * 3];
     if (!ctrl->active) return;
-    const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
     double cost = 0.0, model = 0.0, bad = 0.0;
-    if (tile < z.ntiles) {
-        const int lane = lane_id();
-        const int32_t start = b.tile_start[tile], end = b.tile_start[tile + 1];
-        int32_t seg = b.seg_base[tile] - 1;
-        for (int32_t base = start; base < end; base += kWave) {
-            const int32_t i = base + lane;
-            const bool valid = i < end;
-            const uint32_t w = valid ? b.lo_cam[i] : 0u;
-            const uint64_t hm = ballot64(valid && (w & kHeadBit));
-            const int32_t my_seg = seg + __popcll(hm & mask_upto(lane));
-            seg += __popcll(hm);
-            if (!valid) continue;
-            const int64_t c = w & kIndexMask;
-            const int64_t l = b.nel[my_seg];
+    const int32_t p = b.sched[blockIdx.x];
+    if (p >= 0) {
+        const int64_t c = b.piece_cam[p];
+        const int32_t a = b.piece_begin[p], e = b.piece_end[p];
+        const double* rec = b.cam_rec + kCamRec * c;
+        const double* dp = b.dxp + 9 * c;
+        for (int32_t i = a + threadIdx.x; i < e; i += kBlock) {
+            const int64_t l = b.co_lm[i];
             double X[3], px[2];
 #pragma unroll
             for (int k = 0; k < 3; ++k) X[k] = b.lms_new[3 * l + k];
-            project_rec(b.cam_rec + kCamRec * c, X, px);
-            const double e0 = px[0] - b.obs_lo[2 * int64_t(i)], e1 = px[1] - b.obs_lo[2 * int64_t(i) + 1];
+            project_rec(rec, X, px);
+            const double e0 = px[0] - b.obs_co[2 * int64_t(i)], e1 = px[1] - b.obs_co[2 * int64_t(i) + 1];
             const double s2 = e0 * e0 + e1 * e1;
             double rho = s2, wgt;
             if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, wgt);
             cost += 0.5 * rho;
             if (!isfinite(rho)) bad = 1.0;
             double J[24];
-            load_J<TJ, double>(b.J_lo, z.npad, i, J);
-            const double* dp = b.dxp + 9 * c;
+            load_J<TJ, double>(b.J_co, z.npad, i, J);
             const double* dl = b.dxl + 3 * l;
             double m0 = J[18] * dl[0] + J[19] * dl[1] + J[20] * dl[2];
             double m1 = J[21] * dl[0] + J[22] * dl[1] + J[23] * dl[2];
@@ -95,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(Buffers b, Sizes z, int loss, d
                 m0 += J[k] * dp[k];
                 m1 += J[9 + k] * dp[k];
             }
-            const double r0 = b.r_lo[2 * int64_t(i)], r1 = b.r_lo[2 * int64_t(i) + 1];
+            const double r0 = b.r_co[2 * int64_t(i)], r1 = b.r_co[2 * int64_t(i) + 1];
             model -= r0 * m0 + r1 * m1 + 0.5 * (m0 * m0 + m1 * m1);
         }
     }
@@ -202,7 +195,7 @@ poba_status poba_lm_step(poba_problem p, double* cams, double* lms, poba_lm_stat
         hipLaunchKernelGGL(k_trial, g_state, dim3(kBlock), 0, s, b, z, cams, lms, b.ctrl);
         rc = launch_cam_prep(p, b.cams_new, &b.ctrl->active, s);
         if (rc) return rc;
-        const dim3 g_tiles(unsigned(ceil_div(z.ntiles, kWavesPerBlock)));
+        const dim3 g_tiles(unsigned(std::max<int64_t>(p->sched_len, 1)));
         switch (p->d.precision) {
             case POBA_F64: hipLaunchKernelGGL(k_eval<double>, g_tiles, dim3(kBlock), 0, s, b, z, p->d.loss, p->d.huber_delta, b.ctrl); break;
             case POBA_F32: hipLaunchKernelGGL(k_eval<float>, g_tiles, dim3(kBlock), 0, s, b, z, p->d.loss, p->d.huber_delta, b.ctrl); break;

@@ -677,9 +677,10 @@ __global__ __launch_bounds__(kBlock) void k_get_jac(Buffers b, Sizes z, int orde
     for (int k = 0; k < 18; ++k) Jp[18 * o + k] = J[k];
 #pragma unroll
     for (int k = 0; k < 6; ++k) Jl[6 * o + k] = J[18 + k];
-    if (r && order == 0) {
-        r[2 * o] = b.r_lo[2 * i];
-        r[2 * o + 1] = b.r_lo[2 * i + 1];
+    if (r) {  // residuals live camera-major
+        const int64_t oc = b.perm_c[i];
+        r[2 * oc] = b.r_co[2 * i];
+        r[2 * oc + 1] = b.r_co[2 * i + 1];
     }
 }
 
