@@ -252,7 +252,6 @@ struct Buffers {
     void* J_lo;           // Jacobian records, landmark-major
     void* J_co;           // Jacobian records, camera-major
     double* r_co;         // [N][2] reweighted residual, camera-major
-    int32_t* l2c;         // [N] camera-major position of each landmark-major position
     double* U;            // [nc][81] undamped
     double* bp;           // [nc][9]
     double* V;            // [nl][6] undamped, packed (00 01 02 11 12 22)

@@ -2,11 +2,11 @@
 // undamped normal-equation blocks U = J_p^T J_p, V = J_l^T J_l, b_p = J_p^T r,
 // b_l = J_l^T r, plus the cost F = 1/2 sum rho(|r_i|^2).
 //
-// The camera-major pass evaluates every observation once (camera data is the
-// same for the whole block), stores the camera-major records and residuals and
-// reduces U and b_p per camera piece; the landmark-major pass copies the
-// records into landmark-major order and reduces V and b_l per landmark
-// segment.  Both accumulate in float64 from the Jacobian values rounded to the
+// The camera-major pass evaluates every observation (camera data is the same
+// for the whole block), stores the camera-major records and residuals, sums
+// the cost and reduces U and b_p per camera piece; the landmark-major pass
+// evaluates the observations again, stores the landmark-major records and
+// reduces V and b_l per landmark segment.  Both accumulate in float64 from the Jacobian values rounded to the
 // storage precision, so U, V and W are built from one and the same J.
 #include <type_traits>
 
@@ -115,25 +115,44 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const do
     store_block_partial<2>(tot, b.red_part);
 }
 
-// Landmark-major pass: copies every observation's record and residual from
-// its camera-major position (bit-identical blocks in both orders) and reduces
-// V = J_l^T J_l (6) and b_l = J_l^T r (3) per landmark segment in float64.
+// Landmark-major pass: evaluates every observation again from the per-camera
+// records (these stay in L2; gathering the camera-major records through the
+// permutation would read a whole line per 16 bytes), stores the landmark-major
+// records and reduces V = J_l^T J_l (6) and b_l = J_l^T r (3) per landmark
+// segment in float64.  The same contraction-free arithmetic as the
+// camera-major pass gives bit-identical blocks.
 template <typename TJ>
-__global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const int32_t* gate) {
+__global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
+                                                   double delta, const int32_t* gate) {
     if (gate && !*gate) return;
     const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
     if (tile >= z.ntiles) return;
     tile_landmarks<double, 9>(
         b.lo_cam, b.tile_start, b.seg_base, tile,
-        [&](int32_t i, bool valid, int32_t, int32_t, double* v) {
+        [&](int32_t i, bool valid, int32_t cam, int32_t seg, double* v) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) v[k] = 0.0;
             if (!valid) return;
-            const int64_t j = b.l2c[i];
+            const int64_t l = b.nel[seg];
+            double X[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
+            ObsEval ev;
+            evaluate_obs_rec(b.cam_rec + kCamRec * int64_t(cam), X, b.obs_lo[2 * int64_t(i)],
+                             b.obs_lo[2 * int64_t(i) + 1], ev);
+            double w = 1.0;
+            if (loss == POBA_LOSS_HUBER) {
+                double rho;
+                huber(ev.r[0] * ev.r[0] + ev.r[1] * ev.r[1], delta, rho, w);
+            }
+            const double sw = sqrt(w);
             double J[24];
-            load_J<TJ, double>(b.J_co, z.npad, j, J);
+#pragma unroll
+            for (int k = 0; k < 24; ++k) J[k] = sw * ev.J[k];
             store_J<TJ>(b.J_lo, z.npad, i, J);
-            const double r0 = b.r_co[2 * j], r1 = b.r_co[2 * j + 1];
+#pragma unroll
+            for (int k = 18; k < 24; ++k) J[k] = round_to_storage<TJ>(J[k]);
+            const double r0 = sw * ev.r[0], r1 = sw * ev.r[1];
             const double* a = J + 18;  // J_l row 0
             const double* c = J + 21;  // J_l row 1
             v[0] = a[0] * a[0] + c[0] * c[0];
@@ -219,7 +238,7 @@ poba_status launch_linearize_t(Problem* p, const double* cams, const double* lms
         hipLaunchKernelGGL(k_zero_partials, dim3(1), dim3(64), 0, s, b, gate);
     hipLaunchKernelGGL(k_cost_final, dim3(1), dim3(kReduceBlock), 0, s, b, ncb, gate, cost_out, cost_out2, b.ctrl);
     hipLaunchKernelGGL(k_lin_lm<TJ>, dim3(unsigned(ceil_div(z.ntiles, kWavesPerBlock))), dim3(kBlock), 0, s, b, z,
-                       gate);
+                       lms, loss, delta, gate);
     hipLaunchKernelGGL(k_lin_cam_fin, dim3(unsigned(ceil_div(z.nc, kBlock))), dim3(kBlock), 0, s, b, z, gate);
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }

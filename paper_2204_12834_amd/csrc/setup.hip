@@ -89,7 +89,6 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.J_lo = take(jrec);
     t.J_co = take(jrec);
     t.r_co = (double*)take(N * 16);
-    t.l2c = (int32_t*)take(N * 4);
     t.U = (double*)take(nc * 81 * 8);
     t.bp = (double*)take(nc * 9 * 8);
     t.V = (double*)take(nl * 6 * 8);
@@ -162,17 +161,6 @@ __global__ void k_gather_orders(const int32_t* perm_l, const int32_t* perm_c, co
 }
 
 // flags[l] = 1 if landmark l has an observation.
-// l2c[i] = camera-major position of landmark-major position i
-// (inv_c[perm_c[j]] = j, then l2c[i] = inv_c[perm_l[i]]).
-__global__ void k_invert(const int32_t* perm, int64_t N, int32_t* inv) {
-    int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (j < N) inv[perm[j]] = int32_t(j);
-}
-__global__ void k_compose(const int32_t* inv_c, const int32_t* perm_l, int64_t N, int32_t* l2c) {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < N) l2c[i] = inv_c[perm_l[i]];
-}
-
 __global__ void k_nonempty_flags(const int32_t* lm_off, int32_t nl, int32_t* flags) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nl) return;
@@ -473,8 +461,6 @@ poba_status poba_create(const poba_desc* d, const int32_t* obs_cam, const int32_
         if (hipMemcpyAsync(b.keys_tmp, b.co_lm, N * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(POBA_ERR_HIP);
         hipLaunchKernelGGL(k_gather_orders, dim3(grid_for(N)), dim3(kBlock), 0, s, b.perm_l, b.perm_c, obs_cam, obs_lm,
                            obs_xy, b.lm_off, b.keys_tmp, rank, N, b.lo_cam, b.co_lm, b.co_seg, b.obs_lo, b.obs_co);
-        hipLaunchKernelGGL(k_invert, dim3(grid_for(N)), dim3(kBlock), 0, s, b.perm_c, N, b.vals_tmp);
-        hipLaunchKernelGGL(k_compose, dim3(grid_for(N)), dim3(kBlock), 0, s, b.vals_tmp, b.perm_l, N, b.l2c);
     } else {
         hipLaunchKernelGGL(k_segment_offsets, dim3(grid_for(ngrp + 1)), dim3(kBlock), 0, s, b.keys_out, int64_t(0),
                            int32_t(ngrp), b.grp_off);
