@@ -24,4 +24,4 @@ the hot path computes, one module per stage of a Levenberg-Marquardt iteration:
 Readings taken where the paper is silent or garbled are listed in each
 function's docstring.
 """
-from . import camera, robust, normal, schur, dense, lm  # noqa: F401
+from . import camera, robust, normal, schur, dense, lm, adjoint  # noqa: F401

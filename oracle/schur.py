@@ -111,18 +111,20 @@ class Solve:
 
 
 def solve(Jp, Jl, r, obs_cam, obs_lm, n_cams, n_lms, lam, m, eps=0.0,
-          damping="marquardt", rhs=None):
+          damping="marquardt", rhs=None, diagonals=None):
     """One damped step: blocks, damped inverses, b~, series, back-substitution.
 
     rhs: optional (g_p, g_l) replacing (b_p, b_l) (the right-hand side of
-    eq. normal is then -(g_p, g_l)); the blocks and damping always come from J.
+    eq. normal is then -(g_p, g_l)); the blocks always come from J.
+    diagonals: optional fixed damping diagonals (d_p [n_c,9], d_l [n_l,3])
+    replacing those taken from the blocks.
     """
     from . import normal
 
     U, V, bp, bl = normal.assemble(Jp, Jl, r, obs_cam, obs_lm, n_cams, n_lms)
     if rhs is not None:
         bp, bl = rhs
-    dp, dl = normal.damping_diagonals(U, V, damping)
+    dp, dl = normal.damping_diagonals(U, V, damping) if diagonals is None else diagonals
     Ul, Vl = normal.damp(U, V, lam, dp, dl)
     Uinv = normal.block_inverse(Ul)
     Vinv = normal.block_inverse(Vl)
