@@ -198,6 +198,45 @@ poba_status poba_lm_init(poba_problem p, poba_lm_state *st, const poba_lm_option
 poba_status poba_lm_step(poba_problem p, double *cams, double *lms, poba_lm_state *st,
                          const poba_lm_options *o, poba_stream stream);
 
+/* ---- differentiation of the damped step (an extension) ------------------ */
+
+/* Replaces the observed pixel positions of the handle: obs_xy [dev] float64
+ * [n_obs][2] in the original observation order (as given to poba_create).
+ * Takes effect at the next poba_linearize. */
+poba_status poba_set_observations(poba_problem p, const double *obs_xy, poba_stream stream);
+
+/* frozen = 1: later solves reuse the damping diagonal D (Sec. 4.1 D^T D) of
+ * the last solve made with frozen = 0 instead of taking it from the current
+ * blocks, so D is a constant of the step (the setting in which
+ * poba_step_adjoint differentiates it).  frozen = 0 (default) restores the
+ * normal behaviour.  D is zero until a first unfrozen solve has run. */
+poba_status poba_set_damping_frozen(poba_problem p, int32_t frozen);
+
+/* Adjoint of the damped step dx = -H^-1 g of eq. normal (Sec. 4.1) at fixed
+ * lambda and fixed D, H = J^T J + lambda D, g = J^T r, r = pi - o, by implicit
+ * differentiation.  The handle must hold the linearisation at cams, lms [dev]
+ * (poba_linearize at that state, squared loss only), and dx_cams, dx_lms
+ * [dev] must be the step that poba_power_solve(lambda, m, eps = 0) returned
+ * there.  For the upstream gradient grad_dx_cams [dev] [n_cams][9],
+ * grad_dx_lms [dev] [n_lms][3]:
+ *   z = H~^-1 gbar, the same power solve of order m run on gbar (the
+ *       truncated inverse H~ of eqs. S_approx, x_approx is symmetric), into
+ *       z_cams [n_cams][9], z_lms [n_lms][3] [dev];
+ *   grad_obs [dev] [n_obs][2], original observation order: J_i z_i, the
+ *       exact gradient of <gbar, dx> with respect to o_i for the step as
+ *       computed (dx is linear in o);
+ *   grad_intrinsics [dev] [n_cams][3] (f, k1, k2): -z^T d(H dx + g)/d theta
+ *       at fixed dx, from the mixed second derivatives of the projection.
+ * All float64.  Overwrites the series work buffers (the state used by
+ * poba_lm_step is not kept across this call: call poba_lm_init again before
+ * further LM iterations).  info [dev] may be NULL.  Returns
+ * POBA_ERR_INVALID_ARG for the Huber loss (its weights depend on o). */
+poba_status poba_step_adjoint(poba_problem p, double lambda, int32_t m, const double *cams,
+                              const double *lms, const double *dx_cams, const double *dx_lms,
+                              const double *grad_dx_cams, const double *grad_dx_lms, double *z_cams,
+                              double *z_lms, double *grad_obs, double *grad_intrinsics,
+                              poba_solve_info *info, poba_stream stream);
+
 /* Model pixel positions out_xy [dev] float64 [n_obs][2] of observations
  * (obs_cam, obs_lm [dev] int32 [n_obs]) at cams, lms [dev].  Needs no handle;
  * indices must be in range (they are not checked). */

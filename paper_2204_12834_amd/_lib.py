@@ -107,6 +107,9 @@ SIGNATURES = {
     "poba_get_jacobians": (I32, [P, I32, P, P, P, P]),
     "poba_get_orders": (I32, [P, P, P, P, P, P]),
     "poba_apply_P": (I32, [P, P, P, P]),
+    "poba_set_observations": (I32, [P, P, P]),
+    "poba_set_damping_frozen": (I32, [P, I32]),
+    "poba_step_adjoint": (I32, [P, F64, I32, P, P, P, P, P, P, P, P, P, P, P, P]),
     "poba_set_tuning": (I32, [P, I32, I32]),
     "poba_get_tuning": (I32, [P, I32, ctypes.POINTER(I32)]),
     "poba_probe": (I32, [I32, P, P, ctypes.c_size_t, I32, P]),

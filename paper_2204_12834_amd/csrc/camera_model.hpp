@@ -54,6 +54,25 @@ __device__ __forceinline__ void cross3(const double* a, const double* b, double*
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// dRX[k][j] = d(R X)_k / d omega_j
+//   = C w_j (w x X)_k + A (e_j x X)_k + D w_j (w x (w x X))_k
+//     + B ( (e_j x (w x X))_k + (w x (e_j x X))_k )
+__device__ __forceinline__ void rotation_derivative(const double* w, const double* X, const double* wx,
+                                                    const double* wwx, double A, double B, double C, double D,
+                                                    double (*dRX)[3]) {
+#pragma clang fp contract(off)
+    for (int j = 0; j < 3; ++j) {
+        double ej[3] = {0.0, 0.0, 0.0};
+        ej[j] = 1.0;
+        double ejX[3], ejwx[3], wejX[3];
+        cross3(ej, X, ejX);
+        cross3(ej, wx, ejwx);
+        cross3(w, ejX, wejX);
+        for (int k = 0; k < 3; ++k)
+            dRX[k][j] = C * w[j] * wx[k] + A * ejX[k] + D * w[j] * wwx[k] + B * (ejwx[k] + wejX[k]);
+    }
+}
+
 // Camera-frame point of landmark X (no derivatives).
 __device__ __forceinline__ void transform_point(const double* cam, const double* X, double* P) {
 #pragma clang fp contract(off)
@@ -103,20 +122,8 @@ __device__ __forceinline__ void evaluate_obs(const double* cam, const double* X,
     R[1][2] = -A * w[0] + B * w[1] * w[2];
     R[2][1] = A * w[0] + B * w[1] * w[2];
 
-    // dRX[k][j] = d(R X)_k / d omega_j
-    //   = C w_j (w x X)_k + A (e_j x X)_k + D w_j (w x (w x X))_k
-    //     + B ( (e_j x (w x X))_k + (w x (e_j x X))_k )
     double dRX[3][3];
-    for (int j = 0; j < 3; ++j) {
-        double ej[3] = {0.0, 0.0, 0.0};
-        ej[j] = 1.0;
-        double ejX[3], ejwx[3], wejX[3];
-        cross3(ej, X, ejX);
-        cross3(ej, wx, ejwx);
-        cross3(w, ejX, wejX);
-        for (int k = 0; k < 3; ++k)
-            dRX[k][j] = C * w[j] * wx[k] + A * ejX[k] + D * w[j] * wwx[k] + B * (ejwx[k] + wejX[k]);
-    }
+    rotation_derivative(w, X, wx, wwx, A, B, C, D, dRX);
 
     const double iz = 1.0 / P[2];
     const double p[2] = {-P[0] * iz, -P[1] * iz};
@@ -205,16 +212,7 @@ __device__ __forceinline__ void evaluate_obs_rec(const double* rec, const double
     double P[3];
     for (int k = 0; k < 3; ++k) P[k] = Rm[3 * k] * X[0] + Rm[3 * k + 1] * X[1] + Rm[3 * k + 2] * X[2] + rec[3 + k];
     double dRX[3][3];
-    for (int j = 0; j < 3; ++j) {
-        double ej[3] = {0.0, 0.0, 0.0};
-        ej[j] = 1.0;
-        double ejX[3], ejwx[3], wejX[3];
-        cross3(ej, X, ejX);
-        cross3(ej, wx, ejwx);
-        cross3(w, ejX, wejX);
-        for (int k = 0; k < 3; ++k)
-            dRX[k][j] = C * w[j] * wx[k] + A * ejX[k] + D * w[j] * wwx[k] + B * (ejwx[k] + wejX[k]);
-    }
+    rotation_derivative(w, X, wx, wwx, A, B, C, D, dRX);
     const double iz = 1.0 / P[2];
     const double p[2] = {-P[0] * iz, -P[1] * iz};
     const double r2 = p[0] * p[0] + p[1] * p[1];
@@ -239,6 +237,41 @@ __device__ __forceinline__ void evaluate_obs_rec(const double* rec, const double
         Jp[8] = f * r2 * r2 * p[a];
         double* Jl = e.J + 18 + 3 * a;
         for (int j = 0; j < 3; ++j) Jl[j] = JP[a][0] * Rm[j] + JP[a][1] * Rm[3 + j] + JP[a][2] * Rm[6 + j];
+    }
+}
+
+// Normalised image point of an observation and its derivatives, for the
+// second-order terms of the adjoint: p = -P_xy / P_z, n = |p|^2 and
+// dp[a][j] = d p_a / d y_j for y = (omega, t, X).  The intrinsics enter only
+// through pi = f (1 + k1 n + k2 n^2) p.
+struct ObsGeom {
+    double p[2];
+    double n;
+    double dp[2][9];
+};
+
+__device__ __forceinline__ void observation_geometry(const double* rec, const double* X, ObsGeom& g) {
+    const double* w = rec;
+    const double A = rec[9], B = rec[10], C = rec[11], D = rec[12];
+    const double* Rm = rec + 13;
+    double wx[3], wwx[3];
+    cross3(w, X, wx);
+    cross3(w, wx, wwx);
+    double P[3];
+    for (int k = 0; k < 3; ++k) P[k] = Rm[3 * k] * X[0] + Rm[3 * k + 1] * X[1] + Rm[3 * k + 2] * X[2] + rec[3 + k];
+    double dRX[3][3];
+    rotation_derivative(w, X, wx, wwx, A, B, C, D, dRX);
+    const double iz = 1.0 / P[2];
+    g.p[0] = -P[0] * iz;
+    g.p[1] = -P[1] * iz;
+    g.n = g.p[0] * g.p[0] + g.p[1] * g.p[1];
+    const double dp_dP[2][3] = {{-iz, 0.0, P[0] * iz * iz}, {0.0, -iz, P[1] * iz * iz}};
+    for (int a = 0; a < 2; ++a) {
+        for (int j = 0; j < 3; ++j) {
+            g.dp[a][j] = dp_dP[a][0] * dRX[0][j] + dp_dP[a][1] * dRX[1][j] + dp_dP[a][2] * dRX[2][j];
+            g.dp[a][3 + j] = dp_dP[a][j];
+            g.dp[a][6 + j] = dp_dP[a][0] * Rm[j] + dp_dP[a][1] * Rm[3 + j] + dp_dP[a][2] * Rm[6 + j];
+        }
     }
 }
 

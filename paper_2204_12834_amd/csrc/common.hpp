@@ -258,6 +258,8 @@ struct Buffers {
     double* bl;           // [nl][3]
     // solve
     double* Uinv;         // [nc][81]
+    double* Dp;           // [nc][9] damping diagonal of the last solve
+    double* Dl;           // [nseg][3] damping diagonal of the last solve, by segment
     void* Vinv;           // [nseg][6] storage type, indexed by segment
     void* s;              // [nseg][4] storage type (landmark vector of the series), by segment
     double* v;            // [nc][9] current series term
@@ -308,6 +310,7 @@ struct poba_problem_s {
     int64_t sched_len = 0;      // camera-pass grid size
     int64_t n_cus = 256;        // compute units of the device
     int lds_cam = 1;            // stage the camera vector in LDS when it fits
+    int damping_frozen = 0;     // solves reuse the damping diagonal of the last unfrozen solve
     hipStream_t last_stream = nullptr;
     // profiling
     bool profiling = false;

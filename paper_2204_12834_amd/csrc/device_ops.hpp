@@ -119,11 +119,18 @@ __device__ __forceinline__ double damp_diag(double diag, int damping) {
     return damping == POBA_DAMP_MARQUARDT ? fmin(fmax(diag, 1e-6), 1e32) : 1.0;
 }
 
-// Inverse of the damped 3x3 block V + lambda D (packed 00 01 02 11 12 22) by
-// Cholesky; returns false (and the inverse of the damping diagonal) if a pivot
-// is not positive.
-__device__ __forceinline__ bool inv3_damped(const double* V, double lam, int damping, double* out) {
-    const double d0 = damp_diag(V[0], damping), d1 = damp_diag(V[3], damping), d2 = damp_diag(V[5], damping);
+// Damping diagonal of a packed 3x3 block (entries 0, 3, 5 are the diagonal).
+__device__ __forceinline__ void damp_diag3(const double* V, int damping, double* dd) {
+    dd[0] = damp_diag(V[0], damping);
+    dd[1] = damp_diag(V[3], damping);
+    dd[2] = damp_diag(V[5], damping);
+}
+
+// Inverse of the damped 3x3 block V + lambda diag(dd) (packed 00 01 02 11 12
+// 22) by Cholesky; returns false (and the inverse of the damping diagonal) if
+// a pivot is not positive.
+__device__ __forceinline__ bool inv3_damped(const double* V, double lam, const double* dd, double* out) {
+    const double d0 = dd[0], d1 = dd[1], d2 = dd[2];
     const double a00 = V[0] + lam * d0, a01 = V[1], a02 = V[2];
     const double a11 = V[3] + lam * d1, a12 = V[4], a22 = V[5] + lam * d2;
     bool ok = a00 > 0.0;

@@ -15,8 +15,9 @@ poba_status launch_cam_prep(Problem* p, const double* cams, const int32_t* gate,
 // Damped inverses, reduced right-hand side, power series and
 // back-substitution with the damping in ctrl->lambda; skipped unless
 // ctrl->active.  Writes dx_cams / dx_lms; info (device, may be null).
+// rhs_p / rhs_l (device, may be null) replace b_p / b_l of the linearisation.
 poba_status launch_solve(Problem* p, int m, double eps, double* dx_cams, double* dx_lms, poba_solve_info* info,
-                         hipStream_t s);
+                         hipStream_t s, const double* rhs_p = nullptr, const double* rhs_l = nullptr);
 
 // Sets ctrl->lambda = lam, ctrl->active = 1 and clears the series flags.
 poba_status launch_begin_solve(Problem* p, double lam, hipStream_t s);

@@ -94,6 +94,8 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.V = (double*)take(nl * 6 * 8);
     t.bl = (double*)take(nl * 3 * 8);
     t.Uinv = (double*)take(nc * 81 * 8);
+    t.Dp = (double*)take(nc * 9 * 8);
+    t.Dl = (double*)take(nl * 3 * 8);
     t.Vinv = take(nl * 6 * z.sbytes);
     t.s = take(nl * 4 * 8);  // also holds float64 landmark vectors
     t.v = (double*)take(nc * 9 * 8);
@@ -523,6 +525,8 @@ poba_status poba_create(const poba_desc* d, const int32_t* obs_cam, const int32_
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nl) * 4)), dim3(kBlock), 0, s, (double*)b.s, int64_t(z.nl) * 4);
     // camera vectors of cameras without observations stay zero
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nc) * 9)), dim3(kBlock), 0, s, b.x, int64_t(z.nc) * 9);
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nc) * 9)), dim3(kBlock), 0, s, b.Dp, int64_t(z.nc) * 9);
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nl) * 3)), dim3(kBlock), 0, s, b.Dl, int64_t(z.nl) * 3);
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nc) * 9)), dim3(kBlock), 0, s, b.v, int64_t(z.nc) * 9);
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nc) * 12)), dim3(kBlock), 0, s, (double*)b.vq, int64_t(z.nc) * 12);
 

@@ -37,8 +37,10 @@ __global__ void k_begin_solve(Ctrl* ctrl, double lam) {
 
 // ---------------------------------------------------------------- inverses --
 
-// U_lambda^-1 per camera by a 9x9 Cholesky factorisation, in float64.
-__global__ __launch_bounds__(kBlock) void k_inv_cam(Buffers b, Sizes z, int damping, Ctrl* ctrl) {
+// U_lambda^-1 per camera by a 9x9 Cholesky factorisation, in float64.  The
+// damping diagonal is taken from U and kept in Dp, or, when `frozen`, read
+// from Dp as an earlier solve left it.
+__global__ __launch_bounds__(kBlock) void k_inv_cam(Buffers b, Sizes z, int damping, int frozen, Ctrl* ctrl) {
     if (!ctrl->active) return;
     const int32_t c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= z.nc) return;
@@ -50,7 +52,14 @@ __global__ __launch_bounds__(kBlock) void k_inv_cam(Buffers b, Sizes z, int damp
     double dg[9];
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
-        dg[j] = lam * damp_diag(U[10 * j], damping);
+        double dj;
+        if (frozen) {
+            dj = b.Dp[9 * int64_t(c) + j];
+        } else {
+            dj = damp_diag(U[10 * j], damping);
+            b.Dp[9 * int64_t(c) + j] = dj;
+        }
+        dg[j] = lam * dj;
         L[10 * j] += dg[j];
     }
     bool ok = true;
@@ -108,17 +117,26 @@ __global__ __launch_bounds__(kBlock) void k_inv_cam(Buffers b, Sizes z, int damp
 }
 
 // V_lambda^-1 of every non-empty landmark in float64, stored in the landmark
-// storage type at the landmark's segment index.
+// storage type at the landmark's segment index.  The damping diagonal goes to
+// (or, when `frozen`, comes from) Dl at the same index.
 template <typename TS>
-__global__ __launch_bounds__(kBlock) void k_inv_lm(Buffers b, int32_t nseg, int damping, Ctrl* ctrl) {
+__global__ __launch_bounds__(kBlock) void k_inv_lm(Buffers b, int32_t nseg, int damping, int frozen, Ctrl* ctrl) {
     if (!ctrl->active) return;
     const int32_t g = blockIdx.x * kBlock + threadIdx.x;
     if (g >= nseg) return;
     const int64_t l = b.nel[g];
-    double Vd[6], inv[6];
+    double Vd[6], inv[6], dd[3];
 #pragma unroll
     for (int k = 0; k < 6; ++k) Vd[k] = b.V[6 * l + k];
-    const bool ok = inv3_damped(Vd, ctrl->lambda, damping, inv);
+    if (frozen) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dd[k] = b.Dl[3 * int64_t(g) + k];
+    } else {
+        damp_diag3(Vd, damping, dd);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) b.Dl[3 * int64_t(g) + k] = dd[k];
+    }
+    const bool ok = inv3_damped(Vd, ctrl->lambda, dd, inv);
     TS* o = reinterpret_cast<TS*>(b.Vinv) + 6 * int64_t(g);
 #pragma unroll
     for (int k = 0; k < 6; ++k) o[k] = TS(inv[k]);
@@ -127,17 +145,20 @@ __global__ __launch_bounds__(kBlock) void k_inv_lm(Buffers b, int32_t nseg, int 
 
 // y = V_lambda^-1 b_l in float64 (first half of b~) for every non-empty
 // landmark, into the float64 view of s at its segment index.
-__global__ __launch_bounds__(kBlock) void k_rhs_lm(Buffers b, int32_t nseg, int damping, const Ctrl* ctrl) {
+__global__ __launch_bounds__(kBlock) void k_rhs_lm(Buffers b, int32_t nseg, const Ctrl* ctrl) {
     if (!ctrl->active) return;
     const int32_t g = blockIdx.x * kBlock + threadIdx.x;
     if (g >= nseg) return;
     const int64_t l = b.nel[g];
-    double Vd[6], inv[6], bl[3], y[3];
+    double Vd[6], inv[6], bl[3], y[3], dd[3];
 #pragma unroll
     for (int k = 0; k < 6; ++k) Vd[k] = b.V[6 * l + k];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) bl[k] = b.bl[3 * l + k];
-    inv3_damped(Vd, ctrl->lambda, damping, inv);
+    for (int k = 0; k < 3; ++k) {
+        bl[k] = b.bl[3 * l + k];
+        dd[k] = b.Dl[3 * int64_t(g) + k];
+    }
+    inv3_damped(Vd, ctrl->lambda, dd, inv);
     sym3_apply(inv, bl, y);
     double2* o = reinterpret_cast<double2*>(reinterpret_cast<double*>(b.s) + 4 * int64_t(g));
     o[0] = make_double2(y[0], y[1]);
@@ -352,7 +373,7 @@ void launch_lm_pass(Problem* p, hipStream_t s) {
 // Back-substitution dx_l = -V_lambda^-1 (b_l + sum_{i in l} J_l^T J_p x_c) in
 // float64 with V_lambda^-1 recomputed from the float64 V.
 template <typename TJ>
-__global__ __launch_bounds__(kBlock) void k_backsub(Buffers b, Sizes z, int damping, const double* __restrict__ x,
+__global__ __launch_bounds__(kBlock) void k_backsub(Buffers b, Sizes z, const double* __restrict__ x,
                                                     double* __restrict__ dxl, const Ctrl* ctrl) {
     if (!ctrl->active) return;
     const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
@@ -378,10 +399,12 @@ __global__ __launch_bounds__(kBlock) void k_backsub(Buffers b, Sizes z, int damp
         },
         [&](int32_t seg, const double* t) {
             const int64_t l = b.nel[seg];
-            double Vd[6], inv[6], rhs[3], y[3];
+            double Vd[6], inv[6], rhs[3], y[3], dd[3];
 #pragma unroll
             for (int k = 0; k < 6; ++k) Vd[k] = b.V[6 * l + k];
-            inv3_damped(Vd, lam, damping, inv);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) dd[k] = b.Dl[3 * int64_t(seg) + k];
+            inv3_damped(Vd, lam, dd, inv);
 #pragma unroll
             for (int k = 0; k < 3; ++k) rhs[k] = b.bl[3 * l + k] + t[k];
             sym3_apply(inv, rhs, y);
@@ -530,11 +553,11 @@ __global__ __launch_bounds__(kReduceBlock) void k_norm_stop(Buffers b, uint32_t 
 }
 
 template <typename TS>
-void launch_cam_fin(Problem* p, int mode, int order, double eps, double* vout, hipStream_t s) {
+void launch_cam_fin(Problem* p, const Buffers& b, int mode, int order, double eps, double* vout, hipStream_t s) {
     const unsigned nblk = unsigned(ceil_div(p->z.nc, kFinCams));
-    hipLaunchKernelGGL(k_cam_fin<TS>, dim3(nblk), dim3(kBlock), 0, s, p->b, p->z, mode, vout, p->b.ctrl);
+    hipLaunchKernelGGL(k_cam_fin<TS>, dim3(nblk), dim3(kBlock), 0, s, b, p->z, mode, vout, b.ctrl);
     if (mode != kFinApply)
-        hipLaunchKernelGGL(k_norm_stop, dim3(1), dim3(kReduceBlock), 0, s, p->b, nblk, mode, order, eps, p->b.ctrl);
+        hipLaunchKernelGGL(k_norm_stop, dim3(1), dim3(kReduceBlock), 0, s, b, nblk, mode, order, eps, b.ctrl);
 }
 
 // Copies x into the caller's camera step and fills the solve info.
@@ -573,8 +596,13 @@ __global__ __launch_bounds__(kBlock) void k_load_v(Buffers b, Sizes z, const dou
 
 template <typename TJ, typename TS, typename TCL>
 poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx_lms, poba_solve_info* info,
-                      hipStream_t s) {
-    const Buffers& b = p->b;
+                      const double* rhs_p, const double* rhs_l, hipStream_t s) {
+    // a replacement right-hand side stands in for (b_p, b_l) in every kernel
+    // of this solve (the buffers are passed by value)
+    Buffers b = p->b;
+    if (rhs_p) b.bp = const_cast<double*>(rhs_p);
+    if (rhs_l) b.bl = const_cast<double*>(rhs_l);
+    const int frozen = p->damping_frozen;
     const Sizes& z = p->z;
     const int damping = p->d.damping;
     const dim3 blk(kBlock);
@@ -589,12 +617,12 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
     const bool pieces = p->npieces > 0;
     {
         ProfScope pr(p, POBA_K_INVERSE, s);
-        hipLaunchKernelGGL(k_inv_cam, g_cam, blk, 0, s, b, z, damping, b.ctrl);
-        hipLaunchKernelGGL(k_inv_lm<TS>, g_seg, blk, 0, s, b, nseg, damping, b.ctrl);
+        hipLaunchKernelGGL(k_inv_cam, g_cam, blk, 0, s, b, z, damping, frozen, b.ctrl);
+        hipLaunchKernelGGL(k_inv_lm<TS>, g_seg, blk, 0, s, b, nseg, damping, frozen, b.ctrl);
     }
     {
         ProfScope pr(p, POBA_K_OTHER, s);
-        hipLaunchKernelGGL(k_rhs_lm, g_seg, blk, 0, s, b, nseg, damping, b.ctrl);
+        hipLaunchKernelGGL(k_rhs_lm, g_seg, blk, 0, s, b, nseg, b.ctrl);
     }
     if (pieces) {
         {
@@ -604,7 +632,7 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
         }
         {
             ProfScope pr(p, POBA_K_CAM_FIN, s);
-            launch_cam_fin<TS>(p, kFinRhs, 0, eps, nullptr, s);
+            launch_cam_fin<TS>(p, b, kFinRhs, 0, eps, nullptr, s);
         }
         for (int i = 1; i <= m; ++i) {
             {
@@ -618,13 +646,13 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
             }
             {
                 ProfScope pr(p, POBA_K_CAM_FIN, s);
-                launch_cam_fin<TS>(p, kFinSeries, i, eps, nullptr, s);
+                launch_cam_fin<TS>(p, b, kFinSeries, i, eps, nullptr, s);
             }
         }
     }
     {
         ProfScope pr(p, POBA_K_BACKSUB, s);
-        hipLaunchKernelGGL(k_backsub<TJ>, g_tiles, blk, 0, s, b, z, damping, b.x, dx_lms, b.ctrl);
+        hipLaunchKernelGGL(k_backsub<TJ>, g_tiles, blk, 0, s, b, z, b.x, dx_lms, b.ctrl);
         hipLaunchKernelGGL(k_zero_empty, g_lm, blk, 0, s, b, z, dx_lms, b.ctrl);
         hipLaunchKernelGGL(k_finish, dim3(unsigned(ceil_div(int64_t(z.nc) * 9, kBlock))), blk, 0, s, b, z, dx_cams,
                            info, b.ctrl);
@@ -633,11 +661,11 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
 }
 
 poba_status launch_solve(Problem* p, int m, double eps, double* dx_cams, double* dx_lms, poba_solve_info* info,
-                         hipStream_t s) {
+                         hipStream_t s, const double* rhs_p, const double* rhs_l) {
     switch (p->d.precision) {
-        case POBA_F64: return run_solve<double, double, double>(p, m, eps, dx_cams, dx_lms, info, s);
-        case POBA_F32: return run_solve<float, float, float>(p, m, eps, dx_cams, dx_lms, info, s);
-        default: return run_solve<bf16_t, float, float>(p, m, eps, dx_cams, dx_lms, info, s);
+        case POBA_F64: return run_solve<double, double, double>(p, m, eps, dx_cams, dx_lms, info, rhs_p, rhs_l, s);
+        case POBA_F32: return run_solve<float, float, float>(p, m, eps, dx_cams, dx_lms, info, rhs_p, rhs_l, s);
+        default: return run_solve<bf16_t, float, float>(p, m, eps, dx_cams, dx_lms, info, rhs_p, rhs_l, s);
     }
 }
 
@@ -660,7 +688,7 @@ poba_status run_apply_P(Problem* p, const double* vin, double* vout, hipStream_t
     if (p->npieces > 0) {
         hipLaunchKernelGGL((k_cam_pass<TJ, TS>), dim3(unsigned(p->sched_len)), blk, 0, s, b, z,
                            reinterpret_cast<const TS*>(b.s), b.ctrl);
-        launch_cam_fin<TS>(p, kFinApply, 0, 0.0, vout, s);
+        launch_cam_fin<TS>(p, b, kFinApply, 0, 0.0, vout, s);
     }
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }

@@ -167,6 +167,37 @@ class Problem:
         _lib.check("poba_lm_step", self.lib.poba_lm_step(self.handle, _ptr(cams), _ptr(lms), _ptr(state),
                                                          ctypes.byref(o), _stream(stream)))
 
+    # -- differentiation ---------------------------------------------------
+
+    def set_observations(self, obs_xy: torch.Tensor, stream=None):
+        """Replaces the observed pixels [n_obs, 2] (original order)."""
+        obs_xy = _dev(obs_xy, torch.float64, self.device, (self.n_obs, 2))
+        _lib.check("poba_set_observations", self.lib.poba_set_observations(self.handle, _ptr(obs_xy),
+                                                                           _stream(stream)))
+
+    def freeze_damping(self, frozen: bool = True):
+        """Later solves reuse the damping diagonal of the last unfrozen solve."""
+        _lib.check("poba_set_damping_frozen", self.lib.poba_set_damping_frozen(self.handle, 1 if frozen else 0))
+
+    def step_adjoint(self, lam: float, m: int, cams, lms, dx_cams, dx_lms, grad_dx_cams, grad_dx_lms, stream=None):
+        """Gradients of <gbar, dx> for the step dx of the last linearisation:
+        returns (grad_obs [n_obs, 2], grad_intrinsics [n_cams, 3], z_cams, z_lms)."""
+        d = self.device
+        cams = _dev(cams, torch.float64, d, (self.n_cams, 9))
+        lms = _dev(lms, torch.float64, d, (self.n_lms, 3))
+        dx_cams = _dev(dx_cams, torch.float64, d, (self.n_cams, 9))
+        dx_lms = _dev(dx_lms, torch.float64, d, (self.n_lms, 3))
+        gc = _dev(grad_dx_cams, torch.float64, d, (self.n_cams, 9))
+        gl = _dev(grad_dx_lms, torch.float64, d, (self.n_lms, 3))
+        zc = torch.empty(self.n_cams, 9, dtype=torch.float64, device=d)
+        zl = torch.empty(self.n_lms, 3, dtype=torch.float64, device=d)
+        go = torch.empty(self.n_obs, 2, dtype=torch.float64, device=d)
+        gi = torch.empty(self.n_cams, 3, dtype=torch.float64, device=d)
+        _lib.check("poba_step_adjoint", self.lib.poba_step_adjoint(
+            self.handle, float(lam), int(m), _ptr(cams), _ptr(lms), _ptr(dx_cams), _ptr(dx_lms), _ptr(gc), _ptr(gl),
+            _ptr(zc), _ptr(zl), _ptr(go), _ptr(gi), _ptr(self._info), _stream(stream)))
+        return go, gi, zc, zl
+
     # -- inspection --------------------------------------------------------
 
     def get_blocks(self, stream=None):

@@ -10,7 +10,6 @@ from paper_2204_12834_amd import synth
 from oracle import adjoint, camera, schur
 
 
-
 @functools.lru_cache(maxsize=None)
 def tiny():
     s = synth.ring_scene(6, 120, (2, 5), seed=3, name="adj_tiny")
