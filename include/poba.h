@@ -85,7 +85,7 @@ typedef struct {
     double huber_delta; /* pixels; used when loss == POBA_LOSS_HUBER, must be > 0 */
 } poba_desc;
 
-/* [dev] Written by poba_power_solve. */
+/* [dev] Written by poba_power_solve, one per problem of the handle. */
 typedef struct {
     int32_t stop_order; /* highest power of P in the result (Sec. 4.3, x(m))  */
     int32_t stopped;    /* 1 if the stop rule (eq. qcriterion) ended the series early */
@@ -95,7 +95,8 @@ typedef struct {
     double norm_v;      /* |x(stop_order) - x(stop_order - 1)|_2               */
 } poba_solve_info;
 
-/* [dev] LM state carried between poba_lm_step calls; set up by poba_lm_init. */
+/* [dev] LM state carried between poba_lm_step calls, one per problem of the
+ * handle; set up by poba_lm_init. */
 typedef struct {
     double lambda;         /* damping for the next step                          */
     double nu;             /* growth factor applied on the next rejection        */
@@ -155,6 +156,26 @@ poba_status poba_create(const poba_desc *d, const int32_t *obs_cam, const int32_
                         const double *obs_xy, void *workspace, size_t workspace_bytes,
                         poba_stream stream, poba_problem *out);
 
+/* Batched problems: n_problems independent bundle-adjustment problems held in
+ * one handle and solved together, every call covering all of them.  Problem j
+ * owns the cameras [prob_cam_off[j], prob_cam_off[j+1]) and the landmarks
+ * [prob_lm_off[j], prob_lm_off[j+1]) of the concatenated state (both [host]
+ * int32 [n_problems + 1], starting at 0, strictly increasing, ending at
+ * n_cams / n_lms); each observation must pair a camera and a landmark of the
+ * same problem (else POBA_ERR_INDEX_RANGE).  Each problem keeps its own
+ * damping, series stop rule and LM decision: poba_power_solve fills
+ * info[n_problems], poba_linearize cost[n_problems], and poba_lm_init /
+ * poba_lm_step take st[n_problems].  The kernels of every call cover all
+ * problems in one launch each (a landmark segment or camera piece never
+ * mixes two problems, so each problem's results match a handle of its own
+ * up to the floating-point summation order).  poba_create is the case
+ * n_problems = 1. */
+size_t poba_batch_workspace_bytes(const poba_desc *d, int32_t n_problems);
+poba_status poba_batch_create(const poba_desc *d, int32_t n_problems, const int32_t *prob_cam_off,
+                              const int32_t *prob_lm_off, const int32_t *obs_cam,
+                              const int32_t *obs_lm, const double *obs_xy, void *workspace,
+                              size_t workspace_bytes, poba_stream stream, poba_problem *out);
+
 /* Releases the host-side handle (the workspace stays the caller's). */
 poba_status poba_destroy(poba_problem p);
 
@@ -163,8 +184,8 @@ poba_status poba_destroy(poba_problem p);
  * applies the Huber reweighting if configured; stores the blocks (rounded to
  * the storage precision) in both observation orders; accumulates the
  * undamped blocks U = J_p^T J_p, V = J_l^T J_l and b_p = J_p^T r,
- * b_l = J_l^T r in float64 from the rounded blocks; writes F to cost [dev]
- * (one float64; may be NULL). */
+ * b_l = J_l^T r in float64 from the rounded blocks; writes F of every problem
+ * to cost [dev] (float64 [n_problems]; may be NULL). */
 poba_status poba_linearize(poba_problem p, const double *cams, const double *lms, double *cost,
                            poba_stream stream);
 
@@ -177,24 +198,28 @@ poba_status poba_linearize(poba_problem p, const double *cams, const double *lms
  * fixed order m), and back-substitutes dx_l = -V^-1 (b_l + W^T dx_p) (the
  * sign that solves eq. normal; the paper prints -b_l).
  * dx_cams [dev] float64 [n_cams][9], dx_lms [dev] float64 [n_lms][3],
- * info [dev] (may be NULL).  lambda > 0, 0 <= m <= 100000, eps >= 0. */
+ * info [dev] [n_problems] (may be NULL).  Every problem of a batch is
+ * solved with the same lambda and stops by its own rule.  lambda > 0,
+ * 0 <= m <= 100000, eps >= 0. */
 poba_status poba_power_solve(poba_problem p, double lambda, int32_t m, double eps, double *dx_cams,
                              double *dx_lms, poba_solve_info *info, poba_stream stream);
 
-/* Resets an LM state [dev]: lambda = lambda0, nu = 2, iteration 0, needs a
- * linearisation, not done. */
+/* Resets the LM states st [dev] [n_problems]: lambda = lambda0, nu = 2,
+ * iteration 0, needs a linearisation, not done. */
 poba_status poba_lm_init(poba_problem p, poba_lm_state *st, const poba_lm_options *o,
                          poba_stream stream);
 
-/* One LM iteration (Sec. 5.1 "LM loop") on the state cams, lms [dev] (updated
- * in place when the step is accepted) and st [dev]: linearises if the last
- * step was accepted (or on the first call), solves with st->lambda as
+/* One LM iteration (Sec. 5.1 "LM loop") of every problem that is not done,
+ * on the state cams, lms [dev] (a problem's part updated in place when its
+ * step is accepted) and st [dev] [n_problems]: linearises if a last step was
+ * accepted (or on the first call), solves with st[j].lambda as
  * poba_power_solve does (order o->m, threshold o->eps), evaluates F at the
  * trial state and the undamped linear-model decrease L(0) - L(dx), accepts
  * iff F_new is finite, L(0) - L(dx) > 0 and the gain ratio exceeds o->eta,
  * and updates lambda (success: lambda *= max(1/3, 1 - (2 rho - 1)^3), nu = 2;
- * failure: lambda *= nu, nu *= 2).  Once st->done is set, further calls do
- * nothing.  No host synchronisation: the call can be captured in a graph. */
+ * failure: lambda *= nu, nu *= 2).  Once st[j].done is set, further calls
+ * leave problem j alone.  No host synchronisation and no memory set or copy:
+ * the call can be captured in a graph (poba_lm_graph_create). */
 poba_status poba_lm_step(poba_problem p, double *cams, double *lms, poba_lm_state *st,
                          const poba_lm_options *o, poba_stream stream);
 
@@ -236,6 +261,19 @@ poba_status poba_step_adjoint(poba_problem p, double lambda, int32_t m, const do
                               const double *grad_dx_cams, const double *grad_dx_lms, double *z_cams,
                               double *z_lms, double *grad_obs, double *grad_intrinsics,
                               poba_solve_info *info, poba_stream stream);
+
+/* A HIP graph of n_steps consecutive poba_lm_step calls with these
+ * arguments (device pointers, options copied), captured on a private
+ * stream; one poba_lm_graph_launch then runs the n_steps iterations of every
+ * problem with a single launch on the caller's stream.  Steps after a
+ * problem is done leave it untouched, so a graph of max_iters steps runs an
+ * LM solve to its end.  Event timing (poba_profile_enable) is not recorded
+ * inside the graph.  1 <= n_steps <= 1000. */
+typedef struct poba_lm_graph_s *poba_lm_graph;
+poba_status poba_lm_graph_create(poba_problem p, double *cams, double *lms, poba_lm_state *st,
+                                 const poba_lm_options *o, int32_t n_steps, poba_lm_graph *out);
+poba_status poba_lm_graph_launch(poba_lm_graph g, poba_stream stream);
+poba_status poba_lm_graph_destroy(poba_lm_graph g);
 
 /* Model pixel positions out_xy [dev] float64 [n_obs][2] of observations
  * (obs_cam, obs_lm [dev] int32 [n_obs]) at cams, lms [dev].  Needs no handle;

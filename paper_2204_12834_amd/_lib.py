@@ -97,6 +97,12 @@ SIGNATURES = {
     "poba_lm_default_options": (None, [ctypes.POINTER(PobaLMOptions)]),
     "poba_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(PobaDesc)]),
     "poba_create": (I32, [ctypes.POINTER(PobaDesc), P, P, P, P, ctypes.c_size_t, P, ctypes.POINTER(P)]),
+    "poba_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(PobaDesc), I32]),
+    "poba_batch_create": (I32, [ctypes.POINTER(PobaDesc), I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P, P, P, P,
+                                ctypes.c_size_t, P, ctypes.POINTER(P)]),
+    "poba_lm_graph_create": (I32, [P, P, P, P, ctypes.POINTER(PobaLMOptions), I32, ctypes.POINTER(P)]),
+    "poba_lm_graph_launch": (I32, [P, P]),
+    "poba_lm_graph_destroy": (I32, [P]),
     "poba_destroy": (I32, [P]),
     "poba_linearize": (I32, [P, P, P, P, P]),
     "poba_power_solve": (I32, [P, F64, I32, F64, P, P, P, P]),

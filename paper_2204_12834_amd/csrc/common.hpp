@@ -211,17 +211,29 @@ __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e
 
 // ---------------------------------------------------------------- control --
 
-// Device control block of a handle.
+// Device control of a handle: flags over all of its problems.  Kernels that
+// cover every problem return early when no problem is active or when the
+// series of every active problem has stopped.
 struct Ctrl {
+    int32_t active;   // number of problems the current call works on
+    int32_t lin;      // 1 if the current lm step linearises
+    int32_t running;  // active problems whose series has not stopped
+    int32_t pad;
+};
+
+// Per-problem control (one per independent sub-problem of a batch).
+struct PCtrl {
     double lambda;       // damping of the current solve
-    double red[8];       // results of grid reductions
+    double cost;         // F of the last linearisation
+    double cost_new;     // F at the trial state
+    double model;        // L(0) - L(dx)
     double norm_x2, norm_v2;
-    int32_t active;      // 1 while the current call does work
-    int32_t lin;         // 1 if the current lm step linearises
+    int32_t active;      // 1 while the current call works on the problem
     int32_t stopped;     // series ended by the stop rule
     int32_t stop_order;  // last order summed
     int32_t status;      // OR of POBA_ERR_* bits
     int32_t accepted;    // last lm step accepted
+    int32_t pad;
 };
 
 // ---------------------------------------------------------------- handle --
@@ -271,7 +283,15 @@ struct Buffers {
     double* cam_rec;      // [nc][24] per-camera rotation data of the state being evaluated
     double* cams_new;     // [nc][9]
     double* lms_new;      // [nl][3]
-    double* red_part;     // [kRedParts][4] grid-reduction partials
+    double* piece_red;    // [npieces_max][3] per-piece partial sums (cost, model, flags)
+    double* cam_red;      // [nc][2] per-camera squared norms of v and x
+    // independent problems: contiguous camera and landmark ranges
+    int32_t* prob_cam_off;   // [np+1]
+    int32_t* prob_lm_off;    // [np+1]
+    int32_t* prob_piece_off; // [np+1] first camera piece of each problem
+    int32_t* cam_prob;       // [nc] problem of each camera
+    int32_t* lm_prob;        // [nl] problem of each landmark
+    PCtrl* pctl;             // [np]
 
     Ctrl* ctrl;
     void* sort_tmp;       // radix-sort scratch
@@ -285,11 +305,11 @@ struct Buffers {
 
 struct Sizes {
     int32_t nc, nl;
+    int32_t np;  // independent problems
     int64_t N, npad, ntiles, npieces_max, ranges_max;
     int piece;
     int jbytes;  // bytes per stored Jacobian scalar
     int sbytes;  // bytes per stored landmark-side scalar
-    int64_t red_parts;
 };
 
 struct ProfileSlot {
@@ -323,7 +343,7 @@ struct poba_problem_s {
 namespace poba {
 
 // Workspace layout (defined in setup.hip).
-bool compute_sizes(const poba_desc* d, Sizes* z);
+bool compute_sizes(const poba_desc* d, int32_t n_problems, Sizes* z);
 size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t sort_tmp_bytes);
 size_t sort_tmp_upper_bound(int64_t N);
 

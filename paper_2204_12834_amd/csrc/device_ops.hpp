@@ -86,10 +86,12 @@ __device__ __forceinline__ void store_block_partial(const double* v, double* par
     }
 }
 
-// Single-block sum of n block partials in block order with compensated
-// (TwoSum) per-thread accumulation; the totals are valid in thread 0.
+// Single-block sum of the first K entries of n partial records (record q at
+// partials[q * stride]) in record order, with compensated (TwoSum)
+// per-thread accumulation; the totals are valid in thread 0.
 template <int K>
-__device__ __forceinline__ void sum_partials(const double* partials, uint32_t n, double* out, double* lds) {
+__device__ __forceinline__ void sum_partials(const double* partials, uint32_t n, double* out, double* lds,
+                                             int stride = K) {
     double s[K], e[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) s[k] = e[k] = 0.0;
@@ -97,7 +99,7 @@ __device__ __forceinline__ void sum_partials(const double* partials, uint32_t n,
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             double t, err;
-            two_sum(s[k], partials[size_t(i) * K + k], t, err);
+            two_sum(s[k], partials[size_t(i) * stride + k], t, err);
             s[k] = t;
             e[k] += err;
         }

@@ -6,20 +6,23 @@
 namespace poba {
 
 // Linearisation passes; gate (device, may be null) skips the work when 0.
+// F of each problem goes to cost_out[j] and, for active problems, to st[j]
+// (either may be null).
 poba_status launch_linearize(Problem* p, const double* cams, const double* lms, const int32_t* gate,
-                             double* cost_out, double* cost_out2, hipStream_t s);
+                             double* cost_out, poba_lm_state* st, hipStream_t s);
 
 // Per-camera rotation records of cams into the handle's camera-record buffer.
 poba_status launch_cam_prep(Problem* p, const double* cams, const int32_t* gate, hipStream_t s);
 
 // Damped inverses, reduced right-hand side, power series and
-// back-substitution with the damping in ctrl->lambda; skipped unless
-// ctrl->active.  Writes dx_cams / dx_lms; info (device, may be null).
+// back-substitution, each problem with the damping in its pctl[j].lambda;
+// problems that are not active are skipped.  Writes dx_cams / dx_lms (active
+// problems) and info[j] (device, may be null).
 // rhs_p / rhs_l (device, may be null) replace b_p / b_l of the linearisation.
 poba_status launch_solve(Problem* p, int m, double eps, double* dx_cams, double* dx_lms, poba_solve_info* info,
                          hipStream_t s, const double* rhs_p = nullptr, const double* rhs_l = nullptr);
 
-// Sets ctrl->lambda = lam, ctrl->active = 1 and clears the series flags.
+// Makes every problem active with damping lam and clears the series flags.
 poba_status launch_begin_solve(Problem* p, double lam, hipStream_t s);
 
 }  // namespace poba

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kBlock) void k_cam_prep(Buffers b, Sizes z, const d
 // blocks; the records and the reweighted residual are stored camera-major and
 // the block's rounded J_p rows go through LDS, where 216 threads (54 entries
 // x 4 groups) accumulate the upper triangle of J_p^T J_p (45) and J_p^T r (9)
-// in float64.  Block partials of the cost go to the reduction slots.
+// in float64.  The piece's partial cost goes to its slot of piece_red.
 template <typename TJ>
 __global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
                                                     double delta, const int32_t* gate) {
@@ -112,7 +112,10 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const do
     block_sum<2>(tot, lds);  // contains barriers (also publishes red)
     if (p >= 0 && t < 54)
         b.part[54 * int64_t(p) + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
-    store_block_partial<2>(tot, b.red_part);
+    if (p >= 0 && t == 0) {
+        b.piece_red[3 * int64_t(p)] = tot[0];
+        b.piece_red[3 * int64_t(p) + 1] = tot[1];
+    }
 }
 
 // Landmark-major pass: evaluates every observation again from the per-camera
@@ -174,25 +177,24 @@ __global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const dou
         });
 }
 
-// F = sum of the camera-major pass's block partials.
-__global__ __launch_bounds__(kReduceBlock) void k_cost_final(Buffers b, uint32_t nblocks, const int32_t* gate,
-                                                             double* cost_out, double* cost_out2, Ctrl* ctrl) {
-    __shared__ double lds[(kReduceBlock / kWave) * 2];
+// F of every problem: its pieces' partial costs in piece order (one block per
+// problem).  Written to pctl, to cost_out[j] and, for active problems, to the
+// LM states st[j] (either pointer may be null).
+__global__ __launch_bounds__(kBlock) void k_cost_final(Buffers b, const int32_t* gate, double* cost_out,
+                                                       poba_lm_state* st) {
+    __shared__ double lds[kWavesPerBlock * 2];
     if (gate && !*gate) return;
+    const int32_t j = blockIdx.x;
+    const int32_t a = b.prob_piece_off[j], e = b.prob_piece_off[j + 1];
     double out[2];
-    sum_partials<2>(b.red_part, nblocks, out, lds);
+    sum_partials<2>(b.piece_red + 3 * int64_t(a), uint32_t(e - a), out, lds, 3);
     if (threadIdx.x == 0) {
-        ctrl->red[0] = out[0];
-        if (cost_out) *cost_out = out[0];
-        if (cost_out2) *cost_out2 = out[0];
-        if (out[1] != 0.0 || !isfinite(out[0])) ctrl->status |= POBA_ERR_NONFINITE;
+        PCtrl& q = b.pctl[j];
+        q.cost = out[0];
+        if (cost_out) cost_out[j] = out[0];
+        if (st && q.active) st[j].cost = out[0];
+        if (out[1] != 0.0 || !isfinite(out[0])) q.status |= POBA_ERR_NONFINITE;
     }
-}
-
-// Zero cost partial when there is no camera piece (no observations).
-__global__ void k_zero_partials(Buffers b, const int32_t* gate) {
-    if (gate && !*gate) return;
-    if (threadIdx.x < 2) b.red_part[threadIdx.x] = 0.0;
 }
 
 // Sums each camera's pieces into the full symmetric U (81) and b_p (9).
@@ -224,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam_fin(Buffers b, Sizes z, cons
 
 template <typename TJ>
 poba_status launch_linearize_t(Problem* p, const double* cams, const double* lms, const int32_t* gate,
-                               double* cost_out, double* cost_out2, hipStream_t s) {
+                               double* cost_out, poba_lm_state* st, hipStream_t s) {
     const Buffers& b = p->b;
     const Sizes& z = p->z;
     const double delta = p->d.huber_delta;
@@ -234,9 +236,7 @@ poba_status launch_linearize_t(Problem* p, const double* cams, const double* lms
     const unsigned ncb = unsigned(std::max<int64_t>(p->sched_len, 1));
     if (p->sched_len > 0)
         hipLaunchKernelGGL(k_lin_cam<TJ>, dim3(ncb), dim3(kBlock), 0, s, b, z, lms, loss, delta, gate);
-    else
-        hipLaunchKernelGGL(k_zero_partials, dim3(1), dim3(64), 0, s, b, gate);
-    hipLaunchKernelGGL(k_cost_final, dim3(1), dim3(kReduceBlock), 0, s, b, ncb, gate, cost_out, cost_out2, b.ctrl);
+    hipLaunchKernelGGL(k_cost_final, dim3(unsigned(z.np)), dim3(kBlock), 0, s, b, gate, cost_out, st);
     hipLaunchKernelGGL(k_lin_lm<TJ>, dim3(unsigned(ceil_div(z.ntiles, kWavesPerBlock))), dim3(kBlock), 0, s, b, z,
                        lms, loss, delta, gate);
     hipLaunchKernelGGL(k_lin_cam_fin, dim3(unsigned(ceil_div(z.nc, kBlock))), dim3(kBlock), 0, s, b, z, gate);
@@ -250,11 +250,11 @@ poba_status launch_cam_prep(Problem* p, const double* cams, const int32_t* gate,
 }
 
 poba_status launch_linearize(Problem* p, const double* cams, const double* lms, const int32_t* gate,
-                             double* cost_out, double* cost_out2, hipStream_t s) {
+                             double* cost_out, poba_lm_state* st, hipStream_t s) {
     switch (p->d.precision) {
-        case POBA_F64: return launch_linearize_t<double>(p, cams, lms, gate, cost_out, cost_out2, s);
-        case POBA_F32: return launch_linearize_t<float>(p, cams, lms, gate, cost_out, cost_out2, s);
-        default: return launch_linearize_t<bf16_t>(p, cams, lms, gate, cost_out, cost_out2, s);
+        case POBA_F64: return launch_linearize_t<double>(p, cams, lms, gate, cost_out, st, s);
+        case POBA_F32: return launch_linearize_t<float>(p, cams, lms, gate, cost_out, st, s);
+        default: return launch_linearize_t<bf16_t>(p, cams, lms, gate, cost_out, st, s);
     }
 }
 

@@ -1,19 +1,23 @@
-// One Levenberg-Marquardt iteration on the device (Sec. 5.1 "LM loop").
+// One Levenberg-Marquardt iteration on the device (Sec. 5.1 "LM loop") for
+// every problem of a handle at once.
 //
 // The accept/reject decision needs F at the trial state and the decrease of
 // the undamped linear model, L(0) - L(dx) = -sum_i (r_i . e_i + e_i . e_i / 2)
-// with e_i = J_p dx_c + J_l dx_l; both are float64 sums over all observations
-// computed in one landmark-major pass.  Every decision (gain ratio, damping
-// update, convergence) is taken by a single device thread, so a step needs no
-// host synchronisation and can be captured in a graph.
+// with e_i = J_p dx_c + J_l dx_l; both are float64 sums over the problem's
+// observations computed in one camera-major pass.  Every decision (gain
+// ratio, damping update, convergence) is taken on the device by one thread
+// per problem, so a step needs no host synchronisation and can be captured in
+// a graph.  A problem that is done leaves its state untouched.
 #include "camera_model.hpp"
 #include "device_ops.hpp"
 #include "kernels.hpp"
 
 namespace poba {
 
-__global__ void k_lm_init(poba_lm_state* st, double lambda0) {
-    if (threadIdx.x == 0) {
+__global__ void k_lm_init(poba_lm_state* states, int32_t np, double lambda0) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < np) {
+        poba_lm_state* st = states + j;
         st->lambda = lambda0;
         st->nu = 2.0;
         st->cost = 0.0;
@@ -31,16 +35,32 @@ __global__ void k_lm_init(poba_lm_state* st, double lambda0) {
     }
 }
 
-__global__ void k_begin_step(Ctrl* ctrl, const poba_lm_state* st) {
+// Per-problem flags from the LM states; one block counts the active problems
+// and whether any of them needs a new linearisation.
+__global__ __launch_bounds__(kReduceBlock) void k_begin_step(Ctrl* ctrl, PCtrl* pctl, const poba_lm_state* st,
+                                                             int32_t np) {
+    int n_active = 0, any_lin = 0;
+    for (int32_t base = 0; base < np; base += blockDim.x) {
+        const int32_t j = base + threadIdx.x;
+        int active = 0, lin = 0;
+        if (j < np) {
+            active = st[j].done ? 0 : 1;
+            lin = active && st[j].need_linearize;
+            PCtrl& q = pctl[j];
+            q.active = active;
+            q.lambda = st[j].lambda;
+            q.stopped = 0;
+            q.stop_order = 0;
+            q.status = 0;
+            q.accepted = 0;
+        }
+        n_active += __syncthreads_count(active);
+        any_lin |= __syncthreads_or(lin);
+    }
     if (threadIdx.x == 0) {
-        const int active = st->done ? 0 : 1;
-        ctrl->active = active;
-        ctrl->lin = active && st->need_linearize;
-        ctrl->lambda = st->lambda;
-        ctrl->stopped = 0;
-        ctrl->stop_order = 0;
-        ctrl->status = 0;
-        ctrl->accepted = 0;
+        ctrl->active = n_active;
+        ctrl->running = n_active;
+        ctrl->lin = any_lin ? 1 : 0;
     }
 }
 
@@ -54,14 +74,16 @@ __global__ __launch_bounds__(kBlock) void k_trial(Buffers b, Sizes z, const doub
 }
 
 // F(x + dx) and L(0) - L(dx) over all observations, camera-major: one block
-// per camera piece (the camera's record and step are the same for the block).
+// per camera piece (the camera's record and step are the same for the block);
+// the piece's partial sums go to its slot of piece_red.
 template <typename TJ>
-__global__ __launch_bounds__(kBlock) void k_eval(Buffers b, Sizes z, int loss, double delta, Ctrl* ctrl) {
+__global__ __launch_bounds__(kBlock) void k_eval(Buffers b, Sizes z, int loss, double delta, const Ctrl* ctrl) {
     __shared__ double lds[kWavesPerBlock * 3];
     if (!ctrl->active) return;
     double cost = 0.0, model = 0.0, bad = 0.0;
     const int32_t p = b.sched[blockIdx.x];
-    if (p >= 0) {
+    if (p < 0 || !b.pctl[b.cam_prob[b.piece_cam[p]]].active) return;
+    {
         const int64_t c = b.piece_cam[p];
         const int32_t a = b.piece_begin[p], e = b.piece_end[p];
         const double* rec = b.cam_rec + kCamRec * c;
@@ -94,17 +116,25 @@ __global__ __launch_bounds__(kBlock) void k_eval(Buffers b, Sizes z, int loss, d
     }
     double tot[3] = {cost, model, bad};
     block_sum<3>(tot, lds);
-    store_block_partial<3>(tot, b.red_part);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) b.piece_red[3 * int64_t(p) + k] = tot[k];
+    }
 }
 
-__global__ __launch_bounds__(kReduceBlock) void k_eval_final(Buffers b, uint32_t nblocks, Ctrl* ctrl) {
-    __shared__ double lds[(kReduceBlock / kWave) * 3];
+// Per problem (one block each): F(x + dx) and the model decrease from its
+// pieces in piece order.
+__global__ __launch_bounds__(kBlock) void k_eval_final(Buffers b, const Ctrl* ctrl) {
+    __shared__ double lds[kWavesPerBlock * 3];
     if (!ctrl->active) return;
+    PCtrl& q = b.pctl[blockIdx.x];
+    if (!q.active) return;
+    const int32_t a = b.prob_piece_off[blockIdx.x], e = b.prob_piece_off[blockIdx.x + 1];
     double out[3];
-    sum_partials<3>(b.red_part, nblocks, out, lds);
+    sum_partials<3>(b.piece_red + 3 * int64_t(a), uint32_t(e - a), out, lds);
     if (threadIdx.x == 0) {
-        ctrl->red[1] = out[2] != 0.0 ? __builtin_nan("") : out[0];
-        ctrl->red[2] = out[1];
+        q.cost_new = out[2] != 0.0 ? __builtin_nan("") : out[0];
+        q.model = out[1];
     }
 }
 
@@ -113,12 +143,17 @@ struct LMParams {
     int32_t max_iters;
 };
 
-// Gain ratio, accept / reject, damping update and termination.
-__global__ void k_control(Ctrl* ctrl, poba_lm_state* st, LMParams o) {
-    if (threadIdx.x != 0 || !ctrl->active) return;
+// Gain ratio, accept / reject, damping update and termination, one thread
+// per problem.
+__global__ void k_control(Buffers b, int32_t np, poba_lm_state* states, LMParams o) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= np) return;
+    PCtrl& q = b.pctl[j];
+    if (!q.active) return;
+    poba_lm_state* st = states + j;
     const double F = st->cost;
-    const double Fn = ctrl->red[1];
-    const double L = ctrl->red[2];
+    const double Fn = q.cost_new;
+    const double L = q.model;
     const double rho = (isfinite(Fn) && L > 0.0) ? (F - Fn) / L : -__builtin_inf();
     const int accepted = rho > o.eta ? 1 : 0;
     st->iteration += 1;
@@ -126,9 +161,9 @@ __global__ void k_control(Ctrl* ctrl, poba_lm_state* st, LMParams o) {
     st->gain = rho;
     st->cost_new = Fn;
     st->model_decrease = L;
-    st->stop_order = ctrl->stop_order;
-    st->status |= ctrl->status;
-    ctrl->accepted = accepted;
+    st->stop_order = q.stop_order;
+    st->status |= q.status;
+    q.accepted = accepted;
     double lam = st->lambda;
     if (accepted) {
         const double rel = F > 0.0 ? (F - Fn) / F : 0.0;
@@ -151,12 +186,18 @@ __global__ void k_control(Ctrl* ctrl, poba_lm_state* st, LMParams o) {
     if (st->iteration >= o.max_iters) st->done = 1;
 }
 
-// Accepted step: the trial state becomes the state.
+// Accepted step: the trial state becomes the state (problem by problem).
 __global__ __launch_bounds__(kBlock) void k_apply(Buffers b, Sizes z, double* cams, double* lms, const Ctrl* ctrl) {
-    if (!ctrl->active || !ctrl->accepted) return;
+    if (!ctrl->active) return;
     const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (i < int64_t(z.nc) * 9) cams[i] = b.cams_new[i];
-    if (i < int64_t(z.nl) * 3) lms[i] = b.lms_new[i];
+    if (i < int64_t(z.nc) * 9) {
+        const PCtrl& q = b.pctl[b.cam_prob[i / 9]];
+        if (q.active && q.accepted) cams[i] = b.cams_new[i];
+    }
+    if (i < int64_t(z.nl) * 3) {
+        const PCtrl& q = b.pctl[b.lm_prob[i / 3]];
+        if (q.active && q.accepted) lms[i] = b.lms_new[i];
+    }
 }
 
 }  // namespace poba
@@ -169,7 +210,8 @@ poba_status poba_lm_init(poba_problem p, poba_lm_state* st, const poba_lm_option
     (void)hipGetLastError();  // report only this call's launch errors
     if (!p || !st || !o) return POBA_ERR_INVALID_ARG;
     if (!(o->lambda0 > 0.0)) return POBA_ERR_INVALID_ARG;
-    hipLaunchKernelGGL(k_lm_init, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), st, o->lambda0);
+    hipLaunchKernelGGL(k_lm_init, dim3(unsigned(ceil_div(p->z.np, kBlock))), dim3(kBlock), 0,
+                       reinterpret_cast<hipStream_t>(stream), st, p->z.np, o->lambda0);
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }
 
@@ -183,8 +225,8 @@ poba_status poba_lm_step(poba_problem p, double* cams, double* lms, poba_lm_stat
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const Buffers& b = p->b;
     const Sizes& z = p->z;
-    hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(64), 0, s, b.ctrl, st);
-    poba_status rc = launch_linearize(p, cams, lms, &b.ctrl->lin, nullptr, &st->cost, s);
+    hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(kReduceBlock), 0, s, b.ctrl, b.pctl, st, z.np);
+    poba_status rc = launch_linearize(p, cams, lms, &b.ctrl->lin, nullptr, st, s);
     if (rc) return rc;
     rc = launch_solve(p, o->m, o->eps, b.dxp, b.dxl, nullptr, s);
     if (rc) return rc;
@@ -201,10 +243,10 @@ poba_status poba_lm_step(poba_problem p, double* cams, double* lms, poba_lm_stat
             case POBA_F32: hipLaunchKernelGGL(k_eval<float>, g_tiles, dim3(kBlock), 0, s, b, z, p->d.loss, p->d.huber_delta, b.ctrl); break;
             default: hipLaunchKernelGGL(k_eval<bf16_t>, g_tiles, dim3(kBlock), 0, s, b, z, p->d.loss, p->d.huber_delta, b.ctrl); break;
         }
-        hipLaunchKernelGGL(k_eval_final, dim3(1), dim3(kReduceBlock), 0, s, b, unsigned(g_tiles.x), b.ctrl);
+        hipLaunchKernelGGL(k_eval_final, dim3(unsigned(z.np)), dim3(kBlock), 0, s, b, b.ctrl);
     }
     LMParams prm{o->func_tol, o->eta, o->lambda_min, o->lambda_max, o->max_iters};
-    hipLaunchKernelGGL(k_control, dim3(1), dim3(64), 0, s, b.ctrl, st, prm);
+    hipLaunchKernelGGL(k_control, dim3(unsigned(ceil_div(z.np, kBlock))), dim3(kBlock), 0, s, b, z.np, st, prm);
     hipLaunchKernelGGL(k_apply, g_state, dim3(kBlock), 0, s, b, z, cams, lms, b.ctrl);
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }

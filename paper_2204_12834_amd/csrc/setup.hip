@@ -18,8 +18,9 @@ namespace poba {
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-bool compute_sizes(const poba_desc* d, Sizes* z) {
+bool compute_sizes(const poba_desc* d, int32_t n_problems, Sizes* z) {
     if (!d) return false;
+    if (n_problems < 1 || n_problems > d->n_cams || n_problems > d->n_lms) return false;
     if (d->n_cams < 1 || d->n_cams >= (1 << 30) || d->n_lms < 1 || d->n_obs < 0 || d->n_obs >= (int64_t(1) << 31))
         return false;
     if (d->precision < POBA_F64 || d->precision > POBA_F32_BF16J) return false;
@@ -30,6 +31,7 @@ bool compute_sizes(const poba_desc* d, Sizes* z) {
     if (d->lm_ranges < 0 || (d->lm_ranges > 1 && d->lm_ranges % kXcds != 0) || d->lm_ranges > 4096) return false;
     z->nc = d->n_cams;
     z->nl = d->n_lms;
+    z->np = n_problems;
     z->N = d->n_obs;
     z->npad = std::max<int64_t>(ceil_div(z->N, kWave) * kWave, kWave);
     z->ntiles = z->N / kWave + 1;
@@ -43,8 +45,6 @@ bool compute_sizes(const poba_desc* d, Sizes* z) {
     z->npieces_max = z->N / z->piece + int64_t(z->nc) * z->ranges_max + 1;
     z->jbytes = d->precision == POBA_F64 ? 8 : (d->precision == POBA_F32 ? 4 : 2);
     z->sbytes = d->precision == POBA_F64 ? 8 : 4;
-    z->red_parts = std::max<int64_t>(std::max<int64_t>(ceil_div(z->ntiles, kWavesPerBlock), ceil_div(z->nc, kBlock / 9)),
-                                     int64_t(kXcds) * z->npieces_max) + 1;
     return true;
 }
 
@@ -107,7 +107,15 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.cam_rec = (double*)take(nc * 24 * 8);
     t.cams_new = (double*)take(nc * 9 * 8);
     t.lms_new = (double*)take(nl * 3 * 8);
-    t.red_part = (double*)take(size_t(z.red_parts) * 4 * 8);
+    t.piece_red = (double*)take(size_t(z.npieces_max) * 3 * 8);
+    t.cam_red = (double*)take(nc * 2 * 8);
+    const size_t np1 = size_t(z.np) + 1;
+    t.prob_cam_off = (int32_t*)take(np1 * 4);
+    t.prob_lm_off = (int32_t*)take(np1 * 4);
+    t.prob_piece_off = (int32_t*)take(np1 * 4);
+    t.cam_prob = (int32_t*)take(nc * 4);
+    t.lm_prob = (int32_t*)take(nl * 4);
+    t.pctl = (PCtrl*)take(size_t(z.np) * sizeof(PCtrl));
 
     t.ctrl = (Ctrl*)take(sizeof(Ctrl));
     t.keys_tmp = (int32_t*)take(N * 4);
@@ -123,13 +131,40 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
 
 // ------------------------------------------------------------------ kernels --
 
+// Every index in range, and camera and landmark of one observation in the
+// same problem.
 __global__ void k_check_indices(const int32_t* obs_cam, const int32_t* obs_lm, int64_t N, int32_t nc,
-                                int32_t nl, int32_t* err, int32_t* iota) {
+                                int32_t nl, const int32_t* cam_prob, const int32_t* lm_prob, int32_t* err,
+                                int32_t* iota) {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= N) return;
     iota[i] = int32_t(i);
     const int32_t c = obs_cam[i], l = obs_lm[i];
-    if (c < 0 || c >= nc || l < 0 || l >= nl) atomicOr(err, 1);
+    if (c < 0 || c >= nc || l < 0 || l >= nl) {
+        atomicOr(err, 1);
+        return;
+    }
+    if (cam_prob[c] != lm_prob[l]) atomicOr(err, 2);
+}
+
+// prob[i] = the problem j with off[j] <= i < off[j+1] (off ascending).
+__global__ void k_fill_prob(const int32_t* off, int32_t np, int32_t n, int32_t* prob) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t lo = 0, hi = np - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    prob[i] = lo;
+}
+
+// First camera piece of every problem (pieces are ordered by camera).
+__global__ void k_prob_pieces(const int32_t* prob_cam_off, const int32_t* cam_piece, int32_t np,
+                              int32_t* prob_piece_off) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > np) return;
+    prob_piece_off[j] = cam_piece[prob_cam_off[j]];
 }
 
 // off[k] = first sorted position whose key is >= k (k = 0..n); keys sorted.
@@ -246,17 +281,18 @@ __global__ void k_cam_off(const int32_t* grp_off, int32_t nc, int32_t R, int32_t
     cam_off[c] = grp_off[int64_t(c) * R];
 }
 
-__global__ void k_init_ctrl(Ctrl* ctrl) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        ctrl->lambda = 0.0;
-        for (int k = 0; k < 8; ++k) ctrl->red[k] = 0.0;
-        ctrl->norm_x2 = ctrl->norm_v2 = 0.0;
+__global__ void k_init_ctrl(Ctrl* ctrl, PCtrl* pctl, int32_t np) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0) {
         ctrl->active = 0;
         ctrl->lin = 0;
-        ctrl->stopped = 0;
-        ctrl->stop_order = 0;
-        ctrl->status = 0;
-        ctrl->accepted = 0;
+        ctrl->running = 0;
+        ctrl->pad = 0;
+    }
+    if (j < np) {
+        PCtrl& q = pctl[j];
+        q.lambda = q.cost = q.cost_new = q.model = q.norm_x2 = q.norm_v2 = 0.0;
+        q.active = q.stopped = q.stop_order = q.status = q.accepted = q.pad = 0;
     }
 }
 
@@ -334,21 +370,38 @@ void poba_lm_default_options(poba_lm_options* o) {
     o->max_iters = 50;
 }
 
-size_t poba_workspace_bytes(const poba_desc* d) {
+size_t poba_batch_workspace_bytes(const poba_desc* d, int32_t n_problems) {
     Sizes z;
-    if (!compute_sizes(d, &z)) return 0;
+    if (!compute_sizes(d, n_problems, &z)) return 0;
     return layout(d, z, nullptr, nullptr, sort_tmp_upper_bound(z.N));
 }
 
+size_t poba_workspace_bytes(const poba_desc* d) { return poba_batch_workspace_bytes(d, 1); }
+
 poba_status poba_create(const poba_desc* d, const int32_t* obs_cam, const int32_t* obs_lm, const double* obs_xy,
                         void* workspace, size_t workspace_bytes, poba_stream stream, poba_problem* out) {
+    if (!d) return POBA_ERR_INVALID_ARG;
+    const int32_t cam_off[2] = {0, d->n_cams}, lm_off[2] = {0, d->n_lms};
+    return poba_batch_create(d, 1, cam_off, lm_off, obs_cam, obs_lm, obs_xy, workspace, workspace_bytes, stream, out);
+}
+
+poba_status poba_batch_create(const poba_desc* d, int32_t n_problems, const int32_t* prob_cam_off,
+                              const int32_t* prob_lm_off, const int32_t* obs_cam, const int32_t* obs_lm,
+                              const double* obs_xy, void* workspace, size_t workspace_bytes, poba_stream stream,
+                              poba_problem* out) {
     (void)hipGetLastError();  // report only this call's launch errors
     if (!out) return POBA_ERR_INVALID_ARG;
     *out = nullptr;
     Sizes z;
-    if (!compute_sizes(d, &z)) return POBA_ERR_INVALID_ARG;
+    if (!compute_sizes(d, n_problems, &z)) return POBA_ERR_INVALID_ARG;
     if (z.N > 0 && (!obs_cam || !obs_lm || !obs_xy)) return POBA_ERR_INVALID_ARG;
-    const size_t need = poba_workspace_bytes(d);
+    if (!prob_cam_off || !prob_lm_off) return POBA_ERR_INVALID_ARG;
+    if (prob_cam_off[0] != 0 || prob_lm_off[0] != 0 || prob_cam_off[n_problems] != z.nc ||
+        prob_lm_off[n_problems] != z.nl)
+        return POBA_ERR_INVALID_ARG;
+    for (int32_t j = 0; j < n_problems; ++j)
+        if (prob_cam_off[j + 1] <= prob_cam_off[j] || prob_lm_off[j + 1] <= prob_lm_off[j]) return POBA_ERR_INVALID_ARG;
+    const size_t need = poba_batch_workspace_bytes(d, n_problems);
     if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255u))
         return POBA_ERR_WORKSPACE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -372,17 +425,23 @@ poba_status poba_create(const poba_desc* d, const int32_t* obs_cam, const int32_
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
             p->n_cus = cus;
     }
-    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, s, b.ctrl);
+    hipLaunchKernelGGL(k_init_ctrl, dim3(grid_for(z.np)), dim3(kBlock), 0, s, b.ctrl, b.pctl, z.np);
+    const size_t np1 = size_t(z.np) + 1;
+    if (hipMemcpyAsync(b.prob_cam_off, prob_cam_off, np1 * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(b.prob_lm_off, prob_lm_off, np1 * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(POBA_ERR_HIP);
+    hipLaunchKernelGGL(k_fill_prob, dim3(grid_for(z.nc)), dim3(kBlock), 0, s, b.prob_cam_off, z.np, z.nc, b.cam_prob);
+    hipLaunchKernelGGL(k_fill_prob, dim3(grid_for(z.nl)), dim3(kBlock), 0, s, b.prob_lm_off, z.np, z.nl, b.lm_prob);
     int32_t* err = b.scratch_i;  // reuse scratch for the error flag, cleared below
     if (hipMemsetAsync(err, 0, sizeof(int32_t), s) != hipSuccess) return fail(POBA_ERR_HIP);
     if (N > 0) {
         hipLaunchKernelGGL(k_check_indices, dim3(grid_for(N)), dim3(kBlock), 0, s, obs_cam, obs_lm, N, z.nc, z.nl,
-                           err, b.iota);
+                           b.cam_prob, b.lm_prob, err, b.iota);
     }
     int32_t herr = 0;
     if (hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess) return fail(POBA_ERR_HIP);
     if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
-    if (herr) return fail(POBA_ERR_INDEX_RANGE);
+    if (herr) return fail(POBA_ERR_INDEX_RANGE);  // out of range, or across problems
 
     if (N > 0) {
         // landmark-major: stable radix sort by landmark
@@ -484,6 +543,8 @@ poba_status poba_create(const poba_desc* d, const int32_t* obs_cam, const int32_
         hipLaunchKernelGGL(k_piece_fill, dim3(grid_for(ngrp)), dim3(kBlock), 0, s, b.grp_off, b.grp_piece,
                            int32_t(ngrp), R, z.piece, b.piece_cam, b.piece_begin, b.piece_end, b.piece_grp);
         hipLaunchKernelGGL(k_cam_piece, dim3(grid_for(z.nc + 1)), dim3(kBlock), 0, s, b.grp_piece, z.nc, R, b.cam_piece);
+        hipLaunchKernelGGL(k_prob_pieces, dim3(grid_for(z.np + 1)), dim3(kBlock), 0, s, b.prob_cam_off, b.cam_piece,
+                           z.np, b.prob_piece_off);
         int32_t np = 0;
         if (hipMemcpyAsync(&np, b.grp_piece + ngrp, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return fail(POBA_ERR_HIP);
         if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);

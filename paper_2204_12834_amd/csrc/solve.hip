@@ -25,13 +25,19 @@ enum FinMode { kFinRhs = 0, kFinSeries = 1, kFinApply = 2 };
 
 // ---------------------------------------------------------------- control --
 
-__global__ void k_begin_solve(Ctrl* ctrl, double lam) {
+// Every problem active with damping lam; series flags cleared.
+__global__ void k_begin_solve(Ctrl* ctrl, PCtrl* pctl, int32_t np, double lam) {
+    for (int32_t j = threadIdx.x; j < np; j += blockDim.x) {
+        PCtrl& q = pctl[j];
+        q.lambda = lam;
+        q.active = 1;
+        q.stopped = 0;
+        q.stop_order = 0;
+        q.status = 0;
+    }
     if (threadIdx.x == 0) {
-        ctrl->lambda = lam;
-        ctrl->active = 1;
-        ctrl->stopped = 0;
-        ctrl->stop_order = 0;
-        ctrl->status = 0;
+        ctrl->active = np;
+        ctrl->running = np;
     }
 }
 
@@ -40,11 +46,13 @@ __global__ void k_begin_solve(Ctrl* ctrl, double lam) {
 // U_lambda^-1 per camera by a 9x9 Cholesky factorisation, in float64.  The
 // damping diagonal is taken from U and kept in Dp, or, when `frozen`, read
 // from Dp as an earlier solve left it.
-__global__ __launch_bounds__(kBlock) void k_inv_cam(Buffers b, Sizes z, int damping, int frozen, Ctrl* ctrl) {
+__global__ __launch_bounds__(kBlock) void k_inv_cam(Buffers b, Sizes z, int damping, int frozen, const Ctrl* ctrl) {
     if (!ctrl->active) return;
     const int32_t c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= z.nc) return;
-    const double lam = ctrl->lambda;
+    PCtrl& q = b.pctl[b.cam_prob[c]];
+    if (!q.active) return;
+    const double lam = q.lambda;
     const double* U = b.U + 81 * int64_t(c);
     double L[81];
 #pragma unroll
@@ -112,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_inv_cam(Buffers b, Sizes z, int damp
         for (int i = 0; i < 9; ++i)
 #pragma unroll
             for (int j = 0; j < 9; ++j) out[9 * i + j] = (i == j && dg[i] > 0.0) ? 1.0 / dg[i] : 0.0;
-        atomicOr(&ctrl->status, POBA_ERR_NOT_SPD);
+        atomicOr(&q.status, POBA_ERR_NOT_SPD);
     }
 }
 
@@ -120,11 +128,14 @@ __global__ __launch_bounds__(kBlock) void k_inv_cam(Buffers b, Sizes z, int damp
 // storage type at the landmark's segment index.  The damping diagonal goes to
 // (or, when `frozen`, comes from) Dl at the same index.
 template <typename TS>
-__global__ __launch_bounds__(kBlock) void k_inv_lm(Buffers b, int32_t nseg, int damping, int frozen, Ctrl* ctrl) {
+__global__ __launch_bounds__(kBlock) void k_inv_lm(Buffers b, int32_t nseg, int damping, int frozen,
+                                                   const Ctrl* ctrl) {
     if (!ctrl->active) return;
     const int32_t g = blockIdx.x * kBlock + threadIdx.x;
     if (g >= nseg) return;
     const int64_t l = b.nel[g];
+    PCtrl& q = b.pctl[b.lm_prob[l]];
+    if (!q.active) return;
     double Vd[6], inv[6], dd[3];
 #pragma unroll
     for (int k = 0; k < 6; ++k) Vd[k] = b.V[6 * l + k];
@@ -136,11 +147,11 @@ __global__ __launch_bounds__(kBlock) void k_inv_lm(Buffers b, int32_t nseg, int 
 #pragma unroll
         for (int k = 0; k < 3; ++k) b.Dl[3 * int64_t(g) + k] = dd[k];
     }
-    const bool ok = inv3_damped(Vd, ctrl->lambda, dd, inv);
+    const bool ok = inv3_damped(Vd, q.lambda, dd, inv);
     TS* o = reinterpret_cast<TS*>(b.Vinv) + 6 * int64_t(g);
 #pragma unroll
     for (int k = 0; k < 6; ++k) o[k] = TS(inv[k]);
-    if (!ok) atomicOr(&ctrl->status, POBA_ERR_NOT_SPD);
+    if (!ok) atomicOr(&q.status, POBA_ERR_NOT_SPD);
 }
 
 // y = V_lambda^-1 b_l in float64 (first half of b~) for every non-empty
@@ -150,6 +161,8 @@ __global__ __launch_bounds__(kBlock) void k_rhs_lm(Buffers b, int32_t nseg, cons
     const int32_t g = blockIdx.x * kBlock + threadIdx.x;
     if (g >= nseg) return;
     const int64_t l = b.nel[g];
+    const PCtrl& q = b.pctl[b.lm_prob[l]];
+    if (!q.active) return;
     double Vd[6], inv[6], bl[3], y[3], dd[3];
 #pragma unroll
     for (int k = 0; k < 6; ++k) Vd[k] = b.V[6 * l + k];
@@ -158,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs_lm(Buffers b, int32_t nseg, cons
         bl[k] = b.bl[3 * l + k];
         dd[k] = b.Dl[3 * int64_t(g) + k];
     }
-    inv3_damped(Vd, ctrl->lambda, dd, inv);
+    inv3_damped(Vd, q.lambda, dd, inv);
     sym3_apply(inv, bl, y);
     double2* o = reinterpret_cast<double2*>(reinterpret_cast<double*>(b.s) + 4 * int64_t(g));
     o[0] = make_double2(y[0], y[1]);
@@ -230,7 +243,7 @@ __device__ __forceinline__ void load_cam_vec_lds(const TS* cv, int64_t cam, TS* 
 template <typename TJ, typename TC, typename TS>
 __global__ __launch_bounds__(kBlock) void k_lm_pass(Buffers b, Sizes z, int tpw, TS* __restrict__ sout,
                                                     const Ctrl* ctrl) {
-    if (ctrl->stopped || !ctrl->active) return;
+    if (ctrl->running == 0) return;
     const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
     const int64_t t0 = wave * tpw;
     if (t0 >= z.ntiles) return;
@@ -244,7 +257,7 @@ template <typename TJ, typename TC, typename TS>
 __global__ __launch_bounds__(kBlock) void k_lm_pass_lds(Buffers b, Sizes z, int tpw, TS* __restrict__ sout,
                                                         const Ctrl* ctrl) {
     extern __shared__ unsigned char lds_raw[];
-    if (ctrl->stopped || !ctrl->active) return;
+    if (ctrl->running == 0) return;
     TS* cv = reinterpret_cast<TS*>(lds_raw);
     const TS* __restrict__ vq = reinterpret_cast<const TS*>(b.vq);
     for (int64_t k = threadIdx.x; k < int64_t(z.nc) * 9; k += kBlock) cv[k] = vq[12 * (k / 9) + k % 9];
@@ -378,7 +391,6 @@ __global__ __launch_bounds__(kBlock) void k_backsub(Buffers b, Sizes z, const do
     if (!ctrl->active) return;
     const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
     if (tile >= z.ntiles) return;
-    const double lam = ctrl->lambda;
     tile_landmarks<double, 3>(
         b.lo_cam, b.tile_start, b.seg_base, tile,
         [&](int32_t i, bool valid, int32_t cam, int32_t, double* v) {
@@ -399,12 +411,14 @@ __global__ __launch_bounds__(kBlock) void k_backsub(Buffers b, Sizes z, const do
         },
         [&](int32_t seg, const double* t) {
             const int64_t l = b.nel[seg];
+            const PCtrl& q = b.pctl[b.lm_prob[l]];
+            if (!q.active) return;
             double Vd[6], inv[6], rhs[3], y[3], dd[3];
 #pragma unroll
             for (int k = 0; k < 6; ++k) Vd[k] = b.V[6 * l + k];
 #pragma unroll
             for (int k = 0; k < 3; ++k) dd[k] = b.Dl[3 * int64_t(seg) + k];
-            inv3_damped(Vd, lam, dd, inv);
+            inv3_damped(Vd, q.lambda, dd, inv);
 #pragma unroll
             for (int k = 0; k < 3; ++k) rhs[k] = b.bl[3 * l + k] + t[k];
             sym3_apply(inv, rhs, y);
@@ -418,7 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_zero_empty(Buffers b, Sizes z, doubl
     if (!ctrl->active) return;
     const int32_t l = blockIdx.x * kBlock + threadIdx.x;
     if (l >= z.nl) return;
-    if (b.lm_off[l + 1] == b.lm_off[l]) {
+    if (b.lm_off[l + 1] == b.lm_off[l] && b.pctl[b.lm_prob[l]].active) {
         dxl[3 * int64_t(l)] = 0.0;
         dxl[3 * int64_t(l) + 1] = 0.0;
         dxl[3 * int64_t(l) + 2] = 0.0;
@@ -445,9 +459,13 @@ template <typename TJ, typename TSin>
 __global__ __launch_bounds__(kBlock) void k_cam_pass(Buffers b, Sizes z, const TSin* __restrict__ sin,
                                                      const Ctrl* ctrl) {
     __shared__ double lds[kWavesPerBlock * 9];
-    if (ctrl->stopped || !ctrl->active) return;
+    if (ctrl->running == 0) return;
     const int32_t p = b.sched[blockIdx.x];
     if (p < 0) return;
+    {
+        const PCtrl& q = b.pctl[b.cam_prob[b.piece_cam[p]]];
+        if (!q.active || q.stopped) return;
+    }
     const int32_t a = b.piece_begin[p], e = b.piece_end[p];
     const int32_t* __restrict__ co_seg = b.co_seg;
     double acc[9];
@@ -492,18 +510,23 @@ __global__ __launch_bounds__(kBlock) void k_cam_pass(Buffers b, Sizes z, const T
 //   rhs:    b~_c = b_p - u_c,  v_c = -U^-1 b~_c,  x_c = v_c
 //   series: v_c = U^-1 u_c,    x_c += v_c
 //   apply:  vout_c = U^-1 u_c
-// Each block stores its partial squared norms of v and x; k_norm_stop sums
-// them in block order and applies the stop rule of eq. qcriterion.
+// Cameras of problems that are inactive or stopped are left alone.  The
+// camera's squared norms of v and x go to cam_red; k_norm_stop sums them per
+// problem and applies the stop rule of eq. qcriterion.
 constexpr int kFinCams = kBlock / 9;  // cameras per block (28)
 
 template <typename TS>
 __global__ __launch_bounds__(kBlock) void k_cam_fin(Buffers b, Sizes z, int mode, double* vout, const Ctrl* ctrl) {
-    __shared__ double lds[kWavesPerBlock * 2];
     __shared__ double us[kFinCams][9];
-    if (ctrl->stopped || !ctrl->active) return;
+    __shared__ double n2[kFinCams][9][2];
+    if (ctrl->running == 0) return;
     const int lc = threadIdx.x / 9, r = threadIdx.x % 9;
     const int32_t c = blockIdx.x * kFinCams + lc;
-    const bool own = lc < kFinCams && c < z.nc;
+    bool own = lc < kFinCams && c < z.nc;
+    if (own) {
+        const PCtrl& q = b.pctl[b.cam_prob[c]];
+        own = q.active && !q.stopped;
+    }
     if (own) {
         double u = 0.0;
         for (int32_t q = b.cam_piece[c]; q < b.cam_piece[c + 1]; ++q) u += b.part[9 * int64_t(q) + r];
@@ -511,7 +534,6 @@ __global__ __launch_bounds__(kBlock) void k_cam_fin(Buffers b, Sizes z, int mode
         us[lc][r] = u;
     }
     __syncthreads();
-    double nv2 = 0.0, nx2 = 0.0;
     if (own) {
         const double* Ui = b.Uinv + 81 * int64_t(c) + 9 * r;
         double sacc = 0.0;
@@ -526,29 +548,43 @@ __global__ __launch_bounds__(kBlock) void k_cam_fin(Buffers b, Sizes z, int mode
             *xc = xn;
             b.v[9 * int64_t(c) + r] = v;
             reinterpret_cast<TS*>(b.vq)[12 * int64_t(c) + r] = TS(v);
-            nv2 = v * v;
-            nx2 = xn * xn;
+            n2[lc][r][0] = v * v;
+            n2[lc][r][1] = xn * xn;
         }
     }
-    double tot[2] = {nv2, nx2};
-    block_sum<2>(tot, lds);
-    store_block_partial<2>(tot, b.red_part);
+    if (mode == kFinApply) return;
+    __syncthreads();
+    if (own && r == 0) {
+        double sv = 0.0, sx = 0.0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            sv += n2[lc][k][0];
+            sx += n2[lc][k][1];
+        }
+        b.cam_red[2 * int64_t(c)] = sv;
+        b.cam_red[2 * int64_t(c) + 1] = sx;
+    }
 }
 
-// Norms of v and x over all cameras (block partials in block order) and the
-// stop rule of eq. qcriterion for series order `order`.
-__global__ __launch_bounds__(kReduceBlock) void k_norm_stop(Buffers b, uint32_t nblocks, int mode, int order,
-                                                            double eps, Ctrl* ctrl) {
-    __shared__ double lds[(kReduceBlock / kWave) * 2];
-    if (ctrl->stopped || !ctrl->active) return;
+// Norms of v and x of one problem (its cameras in order, one block per
+// problem) and the stop rule of eq. qcriterion for series order `order`.
+__global__ __launch_bounds__(kBlock) void k_norm_stop(Buffers b, int mode, int order, double eps, Ctrl* ctrl) {
+    __shared__ double lds[kWavesPerBlock * 2];
+    if (ctrl->running == 0) return;
+    PCtrl& q = b.pctl[blockIdx.x];
+    if (!q.active || q.stopped) return;
+    const int32_t c0 = b.prob_cam_off[blockIdx.x], c1 = b.prob_cam_off[blockIdx.x + 1];
     double tot[2];
-    sum_partials<2>(b.red_part, nblocks, tot, lds);
+    sum_partials<2>(b.cam_red + 2 * int64_t(c0), uint32_t(c1 - c0), tot, lds);
     if (threadIdx.x == 0) {
-        ctrl->norm_v2 = tot[0];
-        ctrl->norm_x2 = tot[1];
-        ctrl->stop_order = order;
-        if (mode == kFinSeries && eps > 0.0 && (tot[1] == 0.0 || double(order + 1) * sqrt(tot[0]) < eps * sqrt(tot[1])))
-            ctrl->stopped = 1;
+        q.norm_v2 = tot[0];
+        q.norm_x2 = tot[1];
+        q.stop_order = order;
+        if (mode == kFinSeries && eps > 0.0 &&
+            (tot[1] == 0.0 || double(order + 1) * sqrt(tot[0]) < eps * sqrt(tot[1]))) {
+            q.stopped = 1;
+            atomicSub(&ctrl->running, 1);
+        }
     }
 }
 
@@ -557,22 +593,26 @@ void launch_cam_fin(Problem* p, const Buffers& b, int mode, int order, double ep
     const unsigned nblk = unsigned(ceil_div(p->z.nc, kFinCams));
     hipLaunchKernelGGL(k_cam_fin<TS>, dim3(nblk), dim3(kBlock), 0, s, b, p->z, mode, vout, b.ctrl);
     if (mode != kFinApply)
-        hipLaunchKernelGGL(k_norm_stop, dim3(1), dim3(kReduceBlock), 0, s, b, nblk, mode, order, eps, b.ctrl);
+        hipLaunchKernelGGL(k_norm_stop, dim3(unsigned(p->z.np)), dim3(kBlock), 0, s, b, mode, order, eps, b.ctrl);
 }
 
-// Copies x into the caller's camera step and fills the solve info.
+// Copies x into the caller's camera step (cameras of active problems) and
+// fills the per-problem solve info.
 __global__ __launch_bounds__(kBlock) void k_finish(Buffers b, Sizes z, double* dx_cams, poba_solve_info* info,
                                                    const Ctrl* ctrl) {
     if (!ctrl->active) return;
     const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (i < int64_t(z.nc) * 9) dx_cams[i] = b.x[i];
-    if (i == 0 && info) {
-        info->stop_order = ctrl->stop_order;
-        info->stopped = ctrl->stopped;
-        info->status = ctrl->status;
-        info->reserved = 0;
-        info->norm_x = sqrt(ctrl->norm_x2);
-        info->norm_v = sqrt(ctrl->norm_v2);
+    if (i < int64_t(z.nc) * 9 && b.pctl[b.cam_prob[i / 9]].active) dx_cams[i] = b.x[i];
+    if (info && i < z.np) {
+        const PCtrl& q = b.pctl[i];
+        if (!q.active) return;
+        poba_solve_info& o = info[i];
+        o.stop_order = q.stop_order;
+        o.stopped = q.stopped;
+        o.status = q.status;
+        o.reserved = 0;
+        o.norm_x = sqrt(q.norm_x2);
+        o.norm_v = sqrt(q.norm_v2);
     }
 }
 
@@ -654,8 +694,8 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
         ProfScope pr(p, POBA_K_BACKSUB, s);
         hipLaunchKernelGGL(k_backsub<TJ>, g_tiles, blk, 0, s, b, z, b.x, dx_lms, b.ctrl);
         hipLaunchKernelGGL(k_zero_empty, g_lm, blk, 0, s, b, z, dx_lms, b.ctrl);
-        hipLaunchKernelGGL(k_finish, dim3(unsigned(ceil_div(int64_t(z.nc) * 9, kBlock))), blk, 0, s, b, z, dx_cams,
-                           info, b.ctrl);
+        const int64_t nfin = std::max<int64_t>(int64_t(z.nc) * 9, z.np);
+        hipLaunchKernelGGL(k_finish, dim3(unsigned(ceil_div(nfin, kBlock))), blk, 0, s, b, z, dx_cams, info, b.ctrl);
     }
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }
@@ -670,7 +710,7 @@ poba_status launch_solve(Problem* p, int m, double eps, double* dx_cams, double*
 }
 
 poba_status launch_begin_solve(Problem* p, double lam, hipStream_t s) {
-    hipLaunchKernelGGL(k_begin_solve, dim3(1), dim3(64), 0, s, p->b.ctrl, lam);
+    hipLaunchKernelGGL(k_begin_solve, dim3(1), dim3(kReduceBlock), 0, s, p->b.ctrl, p->b.pctl, p->z.np, lam);
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }
 
@@ -748,7 +788,7 @@ poba_status poba_apply_P(poba_problem p, const double* v_in, double* v_out, poba
     (void)hipGetLastError();  // report only this call's launch errors
     if (!p || !v_in || !v_out) return POBA_ERR_INVALID_ARG;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(k_begin_solve, dim3(1), dim3(64), 0, s, p->b.ctrl, 0.0);
+    hipLaunchKernelGGL(k_begin_solve, dim3(1), dim3(kReduceBlock), 0, s, p->b.ctrl, p->b.pctl, p->z.np, 0.0);
     // k_begin_solve overwrote lambda; the inverses of the last solve are kept,
     // and apply-P does not read lambda.
     switch (p->d.precision) {

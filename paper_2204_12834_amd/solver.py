@@ -57,18 +57,27 @@ def default_options() -> LMOptions:
     return LMOptions(o.lambda0, o.func_tol, o.eps, o.eta, o.lambda_min, o.lambda_max, o.m, o.max_iters)
 
 
-def read_solve_info(t: torch.Tensor) -> dict:
-    raw = bytes(t.cpu().numpy().tobytes())
+def read_solve_info(t: torch.Tensor, index: int = 0) -> dict:
+    """Solve info of problem `index` from the info buffer."""
+    n = ctypes.sizeof(_lib.PobaSolveInfo)
+    raw = bytes(t.cpu().numpy().tobytes())[index * n:(index + 1) * n]
     info = _lib.PobaSolveInfo.from_buffer_copy(raw)
     return {f: getattr(info, f) for f, _ in _lib.PobaSolveInfo._fields_}
 
 
-def read_lm_state(t: torch.Tensor) -> dict:
-    raw = bytes(t.cpu().numpy().tobytes())
+def read_lm_state(t: torch.Tensor, index: int = 0) -> dict:
+    """LM state of problem `index` from the state buffer."""
+    n = ctypes.sizeof(_lib.PobaLMState)
+    raw = bytes(t.cpu().numpy().tobytes())[index * n:(index + 1) * n]
     st = _lib.PobaLMState.from_buffer_copy(raw)
     out = {f: getattr(st, f) for f, _ in _lib.PobaLMState._fields_}
     out["lambda"] = out.pop("lambda_")
     return out
+
+
+def read_lm_states(t: torch.Tensor) -> list:
+    n = t.numel() // ctypes.sizeof(_lib.PobaLMState)
+    return [read_lm_state(t, j) for j in range(n)]
 
 
 def workspace_bytes(n_cams, n_lms, n_obs, precision="f64", damping="marquardt", loss="l2", huber_delta=0.0,
@@ -80,11 +89,14 @@ def workspace_bytes(n_cams, n_lms, n_obs, precision="f64", damping="marquardt", 
 
 
 class Problem:
-    """A bundle-adjustment problem held on one GPU (poba_create ... poba_destroy)."""
+    """A bundle-adjustment problem held on one GPU (poba_batch_create ...
+    poba_destroy).  With prob_cam_off / prob_lm_off (host sequences of
+    n_problems + 1 offsets) it holds that many independent problems over the
+    concatenated cameras and landmarks, solved together."""
 
     def __init__(self, obs_cam, obs_lm, obs_xy, n_cams: int, n_lms: int, precision: str = "f64",
                  damping: str = "marquardt", loss: str = "l2", huber_delta: float = 0.0, piece_size: int = 0,
-                 lm_ranges: int = 0, device="cuda", stream=None):
+                 lm_ranges: int = 0, device="cuda", stream=None, prob_cam_off=None, prob_lm_off=None):
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.precision = precision
@@ -96,21 +108,31 @@ class Problem:
         self.desc = _lib.PobaDesc(self.n_cams, self.n_lms, self.n_obs, _lib.PRECISION[precision],
                                   _lib.DAMPING[damping], _lib.LOSS[loss], int(piece_size), int(lm_ranges), 0,
                                   float(huber_delta))
-        nbytes = int(self.lib.poba_workspace_bytes(ctypes.byref(self.desc)))
+        if prob_cam_off is None:
+            prob_cam_off, prob_lm_off = [0, self.n_cams], [0, self.n_lms]
+        self.prob_cam_off = [int(v) for v in prob_cam_off]
+        self.prob_lm_off = [int(v) for v in prob_lm_off]
+        if len(self.prob_cam_off) != len(self.prob_lm_off) or len(self.prob_cam_off) < 2:
+            raise ValueError("prob_cam_off and prob_lm_off need n_problems + 1 entries each")
+        self.n_problems = len(self.prob_cam_off) - 1
+        nbytes = int(self.lib.poba_batch_workspace_bytes(ctypes.byref(self.desc), self.n_problems))
         if nbytes == 0:
-            raise _lib.PobaError("poba_workspace_bytes", 1)
+            raise _lib.PobaError("poba_batch_workspace_bytes", 1)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self.workspace.data_ptr()) % 256
         self._ws_ptr = self.workspace.data_ptr() + off
         self._ws_bytes = nbytes
         h = ctypes.c_void_p()
+        co = (ctypes.c_int32 * (self.n_problems + 1))(*self.prob_cam_off)
+        lo = (ctypes.c_int32 * (self.n_problems + 1))(*self.prob_lm_off)
         with torch.cuda.device(self.device):
-            rc = self.lib.poba_create(ctypes.byref(self.desc), _ptr(obs_cam), _ptr(obs_lm), _ptr(obs_xy),
-                                      ctypes.c_void_p(self._ws_ptr), ctypes.c_size_t(nbytes), _stream(stream),
-                                      ctypes.byref(h))
-        _lib.check("poba_create", rc)
+            rc = self.lib.poba_batch_create(ctypes.byref(self.desc), self.n_problems, co, lo, _ptr(obs_cam),
+                                            _ptr(obs_lm), _ptr(obs_xy), ctypes.c_void_p(self._ws_ptr),
+                                            ctypes.c_size_t(nbytes), _stream(stream), ctypes.byref(h))
+        _lib.check("poba_batch_create", rc)
         self.handle = h
-        self._info = torch.zeros(32, dtype=torch.uint8, device=self.device)
+        self._info = torch.zeros(ctypes.sizeof(_lib.PobaSolveInfo) * self.n_problems, dtype=torch.uint8,
+                                 device=self.device)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -129,7 +151,7 @@ class Problem:
         cams = _dev(cams, torch.float64, self.device, (self.n_cams, 9))
         lms = _dev(lms, torch.float64, self.device, (self.n_lms, 3))
         if cost is None:
-            cost = torch.zeros(1, dtype=torch.float64, device=self.device)
+            cost = torch.zeros(self.n_problems, dtype=torch.float64, device=self.device)
         _lib.check("poba_linearize", self.lib.poba_linearize(self.handle, _ptr(cams), _ptr(lms), _ptr(cost),
                                                              _stream(stream)))
         return cost
@@ -149,7 +171,8 @@ class Problem:
     def lm_init(self, opts: LMOptions | None = None, state: torch.Tensor | None = None, stream=None):
         opts = opts or LMOptions()
         if state is None:
-            state = torch.zeros(ctypes.sizeof(_lib.PobaLMState), dtype=torch.uint8, device=self.device)
+            state = torch.zeros(ctypes.sizeof(_lib.PobaLMState) * self.n_problems, dtype=torch.uint8,
+                                device=self.device)
         o = opts.c()
         _lib.check("poba_lm_init", self.lib.poba_lm_init(self.handle, _ptr(state), ctypes.byref(o),
                                                          _stream(stream)))
@@ -166,6 +189,20 @@ class Problem:
         o = opts.c()
         _lib.check("poba_lm_step", self.lib.poba_lm_step(self.handle, _ptr(cams), _ptr(lms), _ptr(state),
                                                          ctypes.byref(o), _stream(stream)))
+
+    def lm_graph(self, cams: torch.Tensor, lms: torch.Tensor, state: torch.Tensor, n_steps: int,
+                 opts: LMOptions | None = None) -> "LMGraph":
+        """n_steps LM iterations captured in one HIP graph (poba_lm_graph_create)."""
+        opts = opts or LMOptions()
+        for t, shape in [(cams, (self.n_cams, 9)), (lms, (self.n_lms, 3))]:
+            if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != shape:
+                raise ValueError(f"expected a contiguous float64 {shape} device tensor")
+        g = ctypes.c_void_p()
+        o = opts.c()
+        with torch.cuda.device(self.device):
+            _lib.check("poba_lm_graph_create", self.lib.poba_lm_graph_create(
+                self.handle, _ptr(cams), _ptr(lms), _ptr(state), ctypes.byref(o), int(n_steps), ctypes.byref(g)))
+        return LMGraph(self, g, (cams, lms, state))
 
     # -- differentiation ---------------------------------------------------
 
@@ -252,6 +289,27 @@ class Problem:
         n = (ctypes.c_int64 * 8)()
         _lib.check("poba_profile_read", self.lib.poba_profile_read(self.handle, ms, n))
         return {k: (ms[i], n[i]) for i, k in enumerate(_lib.KERNEL_CLASSES)}
+
+
+class LMGraph:
+    """A captured run of LM iterations; launch() replays it on a stream."""
+
+    def __init__(self, problem: Problem, handle: ctypes.c_void_p, keep):
+        self.problem, self.handle, self._keep = problem, handle, keep
+
+    def launch(self, stream=None):
+        _lib.check("poba_lm_graph_launch", self.problem.lib.poba_lm_graph_launch(self.handle, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.problem.lib.poba_lm_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def project(obs_cam, obs_lm, cams, lms, device="cuda", stream=None) -> torch.Tensor:

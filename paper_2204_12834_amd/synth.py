@@ -30,6 +30,7 @@ __all__ = [
     "ladybug_scene",
     "city_scene",
     "batched_scenes",
+    "concat_scenes",
     "config",
 ]
 
@@ -386,6 +387,20 @@ def batched_scenes(n_problems: int = 256, base_seed: int = 1000, cams_range=(20,
         nl = int(round(math.exp(rng.uniform(math.log(lms_range[0]), math.log(lms_range[1])))))
         out.append(ring_scene(nc, nl, track=track, seed=base_seed + b, name=f"batch{b}"))
     return out
+
+
+def concat_scenes(scenes: list, name: str = "batch"):
+    """Independent scenes as one scene over concatenated cameras and landmarks
+    (observation indices shifted), plus the per-problem camera and landmark
+    offsets [n + 1] each."""
+    cam_off = np.cumsum([0] + [s.n_cams for s in scenes])
+    lm_off = np.cumsum([0] + [s.n_lms for s in scenes])
+    cat = lambda f: np.concatenate([getattr(s, f) for s in scenes])
+    obs_cam = np.concatenate([s.obs_cam + cam_off[k] for k, s in enumerate(scenes)]).astype(np.int32)
+    obs_lm = np.concatenate([s.obs_lm + lm_off[k] for k, s in enumerate(scenes)]).astype(np.int32)
+    scene = Scene(name, cat("cams_gt"), cat("lms_gt"), obs_cam, obs_lm, cat("noise"), cat("outlier"), cat("cams0"),
+                  cat("lms0"))
+    return scene, cam_off.astype(np.int32), lm_off.astype(np.int32)
 
 
 def config(name: str, **kw):
