@@ -200,6 +200,194 @@ def lm_run(prob, cams0, lms0, opts, max_iters):
     return out
 
 
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def bench_batched(args, dev):
+    """256 independent ring problems of uneven size (20-200 cameras,
+    2k-40k landmarks, log-uniform; tracks 2-8), float32, m = 16: one LM
+    iteration of all problems per step, as (a) the batched handle with the
+    autotuned launch shape, eagerly and (b) as one captured graph launch,
+    against (c) the batched handle with the default shape and (d) one handle
+    and launch sequence per problem.  Tuning and capture are outside the
+    timed regions."""
+    import numpy as np
+    import torch
+    from paper_2204_12834_amd import autotune, synth
+    from paper_2204_12834_amd.solver import LMOptions, Problem, project
+    m = 16 if args.m == 32 else args.m
+    prec = args.precision
+    t_gen = time.perf_counter()
+    scenes = synth.config("c4")
+    cat, co, lo = synth.concat_scenes(scenes, name="c4")
+    print(f"[bench] c4: {len(scenes)} problems, {cat.n_cams} cams, {cat.n_lms} lms, {cat.n_obs} obs "
+          f"({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
+    obs = project(cat.obs_cam, cat.obs_lm, cat.cams_gt, cat.lms_gt, device=dev)
+    obs += torch.as_tensor(cat.noise, device=dev)
+    oc = torch.as_tensor(cat.obs_cam, device=dev)
+    ol = torch.as_tensor(cat.obs_lm, device=dev)
+    cams0 = torch.as_tensor(cat.cams0, dtype=torch.float64, device=dev)
+    lms0 = torch.as_tensor(cat.lms0, dtype=torch.float64, device=dev)
+    opts = LMOptions(m=m, eps=0.0, func_tol=0.0, max_iters=1 << 30)
+
+    def make(ps):
+        return Problem(oc, ol, obs, cat.n_cams, cat.n_lms, precision=prec, piece_size=ps, device=dev,
+                       prob_cam_off=co, prob_lm_off=lo)
+
+    t_tune = time.perf_counter()
+    cfg, prob = autotune.tune(make, prec, cat.n_obs, cat.n_lms, cams0, lms0,
+                              log=lambda s: print(s, file=sys.stderr, flush=True))
+    t_tune = time.perf_counter() - t_tune
+    print(f"[bench] tuned in {t_tune:.1f} s: {cfg.get('piece_size')}/{cfg.get('tiles_per_wave')}/"
+          f"{cfg.get('lds_camera')}", file=sys.stderr, flush=True)
+    cams, lms = cams0.clone(), lms0.clone()
+    st = prob.lm_init(opts)
+
+    def reset(pr, c, l, s_):
+        c.copy_(cams0)
+        l.copy_(lms0)
+        pr.lm_init(opts, state=s_)
+
+    def timed(fn, pre, k):
+        for _ in range(args.warmup):
+            pre()
+            fn()
+        tot = 0.0
+        for _ in range(k):
+            pre()
+            e0, e1 = _events()
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            tot += e0.elapsed_time(e1)
+        return tot / k
+
+    k = args.steps
+    eager_ms = timed(lambda: prob.lm_step(cams, lms, st, opts), lambda: reset(prob, cams, lms, st), k)
+    # series bytes and kernel times of the tuned batched step
+    reset(prob, cams, lms, st)
+    prob.profile(True)
+    prob.profile_read()
+    prob.lm_step(cams, lms, st, opts)
+    prof = prob.profile_read()
+    prob.profile(False)
+    graph = prob.lm_graph(cams, lms, st, 1, opts)
+    graph_ms = timed(graph.launch, lambda: reset(prob, cams, lms, st), k)
+    graph.close()
+    del prob
+    torch.cuda.empty_cache()
+    plain = make(autotune.DEFAULT["piece_size"])
+    plain.linearize(cams0, lms0)
+    autotune.apply(plain, autotune.DEFAULT)
+    pst = plain.lm_init(opts)
+    default_ms = timed(lambda: plain.lm_step(cams, lms, pst, opts), lambda: reset(plain, cams, lms, pst), k)
+    del plain
+    torch.cuda.empty_cache()
+    # one handle and one launch sequence per problem
+    solo = []
+    for j, sc in enumerate(scenes):
+        a, b_ = int(co[j]), int(co[j + 1])
+        la, lb = int(lo[j]), int(lo[j + 1])
+        sel = (oc >= a) & (oc < b_)
+        pj = Problem(oc[sel] - a, ol[sel] - la, obs[sel], b_ - a, lb - la, precision=prec, device=dev)
+        cj, lj = cams0[a:b_].clone(), lms0[la:lb].clone()
+        solo.append((pj, cj, lj, pj.lm_init(opts), a, b_, la, lb))
+
+    def solo_reset():
+        for pj, cj, lj, sj, a, b_, la, lb in solo:
+            cj.copy_(cams0[a:b_])
+            lj.copy_(lms0[la:lb])
+            pj.lm_init(opts, state=sj)
+
+    def solo_step():
+        for pj, cj, lj, sj, *_ in solo:
+            pj.lm_step(cj, lj, sj, opts)
+
+    solo_ms = timed(solo_step, solo_reset, max(2, k // 2))
+    lmb = camb = 0
+    for sc in scenes:
+        a_, b2 = series_bytes(sc.n_obs, sc.n_lms, prec)
+        lmb += a_
+        camb += b2
+    t_series = (prof["landmark_pass"][0] + prof["camera_pass"][0] + prof["camera_finish"][0]) / 1e3
+    n_ord = max(prof["landmark_pass"][1], 1)
+    value = n_ord * (lmb + camb) / t_series / 1e9
+    line = {
+        "metric": "batched LM iteration time and series GB/s, 256 sub-problems, 1 GPU",
+        "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": k, "warmup": args.warmup,
+        "ms_per_step": round(graph_ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": prec, "data": "synthetic",
+        "config": {"workload": f"c4: {len(scenes)} ring problems, {cat.n_cams} cameras, {cat.n_lms} landmarks, "
+                               f"{cat.n_obs} observations, m={m}, {prec}, one LM iteration of every problem per step",
+                   "n_problems": len(scenes), "n_obs": cat.n_obs, "m": m, "precision": prec},
+        "lm_step_ms": {"batched_graph_tuned": round(graph_ms, 3), "batched_eager_tuned": round(eager_ms, 3),
+                       "batched_eager_default_shape": round(default_ms, 3),
+                       "one_handle_per_problem": round(solo_ms, 3)},
+        "speedup_graph_vs_per_problem": round(solo_ms / graph_ms, 2),
+        "tuned": {kk: cfg[kk] for kk in ("piece_size", "tiles_per_wave", "lds_camera", "us_per_order") if kk in cfg},
+        "tune_seconds": round(t_tune, 1),
+        "phase_ms_per_step": {name: round(v[0], 4) for name, v in prof.items()},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_adjoint(args, dev):
+    """Differentiable damped step: 200 cameras, 50,000 landmarks (ring, tracks
+    2-8), float32, lambda = 1, m = 32: forward (linearise + power solve) and
+    backward (adjoint power solve + gradients of the observations and
+    intrinsics) through the autograd Function."""
+    import numpy as np
+    import torch
+    from paper_2204_12834_amd import synth
+    from paper_2204_12834_amd.autograd import damped_step
+    from paper_2204_12834_amd.solver import Problem, project
+    s = synth.config("c5")
+    obs = project(s.obs_cam, s.obs_lm, s.cams_gt, s.lms_gt, device=dev) + torch.as_tensor(s.noise, device=dev)
+    prob = Problem(s.obs_cam, s.obs_lm, obs, s.n_cams, s.n_lms, precision=args.precision, device=dev)
+    rng = np.random.default_rng(1)
+    gp = torch.as_tensor(rng.normal(size=(s.n_cams, 9)), device=dev)
+    gl = torch.as_tensor(rng.normal(size=(s.n_lms, 3)), device=dev)
+    extr = torch.as_tensor(s.cams0[:, :6].copy(), device=dev)
+    lms = torch.as_tensor(s.lms0, device=dev)
+    intr0 = torch.as_tensor(s.cams0[:, 6:9].copy(), device=dev)
+
+    def run():
+        o = obs.clone().requires_grad_(True)
+        intr = intr0.clone().requires_grad_(True)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        dxc, dxl = damped_step(prob, o, intr, extr, lms, 1.0, 32)
+        e1.record()
+        loss = (dxc * gp).sum() + (dxl * gl).sum()
+        g_o, g_i = torch.autograd.grad(loss, [o, intr])
+        e2.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), e1.elapsed_time(e2)
+
+    for _ in range(args.warmup):
+        run()
+    f = b = 0.0
+    for _ in range(args.steps):
+        tf, tb = run()
+        f += tf
+        b += tb
+    f /= args.steps
+    b /= args.steps
+    line = {"metric": "differentiable damped step: forward + backward time, 1 GPU", "value": round(f + b, 4),
+            "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(f + b, 4),
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
+            "data": "synthetic",
+            "config": {"workload": f"c5: {s.n_cams} cameras, {s.n_lms} landmarks, {s.n_obs} observations, "
+                                   f"lambda=1, m=32, {args.precision}", "n_obs": s.n_obs},
+            "forward_ms": round(f, 4), "backward_ms": round(b, 4)}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,7 +396,8 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--precision", default="f32", choices=["f64", "f32", "bf16"])
     ap.add_argument("--m", type=int, default=32)
-    ap.add_argument("--sample-lms", type=int, default=40000)
+    ap.add_argument("--sample-lms", type=int, default=600000,
+                    help="landmarks of the scene the CPU oracle's series runs on (about 10-20 s of CPU work)")
     ap.add_argument("--tpw", type=int, default=0, help="landmark tiles per wavefront (0: library default)")
     ap.add_argument("--sweep-tpw", default="", help="comma list: time the series for each and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -231,6 +420,10 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "c4":
+        return bench_batched(args, dev)
+    if args.workload == "c5":
+        return bench_adjoint(args, dev)
     t_gen = time.perf_counter()
     scene, delta = make_scene(args.workload)
     print(f"[bench] scene {scene.name}: {scene.n_cams} cams, {scene.n_lms} lms, {scene.n_obs} obs "
@@ -322,8 +515,13 @@ def main():
         del prob
         torch.cuda.empty_cache()
         runs = {}
+        steps_at_x0 = {}
         for prec in ["f64", "f32", "bf16"]:
             p2, c0, l0, _ = gpu_setup(scene, delta, prec, dev)
+            # the damped step at x0 (lambda0, fixed order) for the precision comparison
+            p2.linearize(c0, l0)
+            dxc, dxl, _ = p2.power_solve(1e-4, args.m, 0.0)
+            steps_at_x0[prec] = (dxc.cpu().numpy(), dxl.cpu().numpy())
             o2 = LMOptions(m=args.m)  # Sec. 5.1 settings, series order m
             runs[prec] = lm_run(p2, c0, l0, o2, 50)
             print(f"[bench] LM {prec}: {len(runs[prec])} iterations, final cost {runs[prec][-1][0]:.6e}",
@@ -342,7 +540,14 @@ def main():
             tau[prec] = {"t_1pct_s": round(hit[0], 4) if hit else None, "iterations": len(out),
                          "final_cost": out[-1][0], "lm_iter_ms": round(1e3 * out[-1][1] / len(out), 3),
                          "iters_to_1pct": next((i + 1 for i, (c, _, _) in enumerate(out) if c <= ftau), None)}
-        extra = {"f0": f0, "f_star": fstar, "f_tau": ftau, "time_to_1pct": tau}
+        ref_c, ref_l = steps_at_x0["f64"]
+        prec_err = {}
+        for prec in ["f32", "bf16"]:
+            c_, l_ = steps_at_x0[prec]
+            prec_err[prec] = {"dx_cams": float(np.linalg.norm(c_ - ref_c) / np.linalg.norm(ref_c)),
+                              "dx_lms": float(np.linalg.norm(l_ - ref_l) / np.linalg.norm(ref_l))}
+        extra = {"f0": f0, "f_star": fstar, "f_tau": ftau, "time_to_1pct": tau,
+                 "step_error_vs_f64_at_x0": prec_err}
 
     cpu = None
     if not args.no_cpu_baseline:
