@@ -100,6 +100,16 @@ def back_substitute(Jp, Jl, obs_cam, obs_lm, bl, Vinv, dxp):
     return -block_matvec(Vinv, bl + t)
 
 
+def reduced_residual(Jp, Jl, obs_cam, obs_lm, Ul, Vinv, btilde, x):
+    """|S x + b~|_2 / |b~|_2 with S x = U_lambda x - W V^-1 W^T x (eq. Schur),
+    matrix-free: how far a camera step is from solving the reduced camera
+    system."""
+    t = apply_Wt(Jp, Jl, obs_cam, obs_lm, x, Vinv.shape[0])
+    u = apply_W(Jp, Jl, obs_cam, obs_lm, block_matvec(Vinv, t), Ul.shape[0])
+    res = block_matvec(Ul, x) - u + btilde
+    return float(np.linalg.norm(res.ravel()) / np.linalg.norm(btilde.ravel()))
+
+
 @dataclasses.dataclass
 class Solve:
     dxp: np.ndarray
@@ -108,6 +118,7 @@ class Solve:
     Uinv: np.ndarray
     Vinv: np.ndarray
     series: SeriesResult
+    Ul: np.ndarray = None    # damped camera blocks
 
 
 def solve(Jp, Jl, r, obs_cam, obs_lm, n_cams, n_lms, lam, m, eps=0.0,
@@ -131,4 +142,4 @@ def solve(Jp, Jl, r, obs_cam, obs_lm, n_cams, n_lms, lam, m, eps=0.0,
     bt = reduced_rhs(Jp, Jl, obs_cam, obs_lm, bp, bl, Vinv)
     ser = power_series(Jp, Jl, obs_cam, obs_lm, Uinv, Vinv, bt, m, eps)
     dxl = back_substitute(Jp, Jl, obs_cam, obs_lm, bl, Vinv, ser.x)
-    return Solve(ser.x, dxl, bt, Uinv, Vinv, ser)
+    return Solve(ser.x, dxl, bt, Uinv, Vinv, ser, Ul)

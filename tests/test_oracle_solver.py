@@ -108,6 +108,25 @@ def test_series_error_closed_form(lam, m):
         assert rel(sol.dxp.ravel(), -Uinv @ bt) < 1e-12
 
 
+@pytest.mark.parametrize("lam,m", [(1e-2, 0), (1e-2, 5), (1.0, 3), (1.0, 40)])
+def test_reduced_residual_closed_form(lam, m):
+    """S x(m) + b~ = U P^{m+1} U^-1 b~ (the series sums the first m+1 terms of
+    (I - P)^-1, Sec. 3 Prop. 1), evaluated with dense matrices."""
+    P = c1()
+    J = dense.dense_jacobian(P.Jp, P.Jl, P.obs_cam, P.obs_lm, P.n_cams, P.n_lms)
+    Pm, U, S, bt = dense.P_matrix(J, P.r, lam, P.n_cams)
+    sol = schur.solve(P.Jp, P.Jl, P.r, P.obs_cam, P.obs_lm, P.n_cams, P.n_lms, lam, m, 0.0)
+    got = schur.reduced_residual(P.Jp, P.Jl, P.obs_cam, P.obs_lm, sol.Ul, sol.Vinv, sol.btilde, sol.dxp)
+    pred = U @ np.linalg.matrix_power(Pm, m + 1) @ np.linalg.solve(U, bt)
+    want = np.linalg.norm(pred) / np.linalg.norm(bt)
+    assert abs(got - want) <= 1e-8 * want + 1e-14, (got, want)
+    # the dense solution of the reduced system has no residual
+    exact = -np.linalg.solve(S, bt)
+    zero = schur.reduced_residual(P.Jp, P.Jl, P.obs_cam, P.obs_lm, sol.Ul, sol.Vinv, sol.btilde,
+                                  exact.reshape(P.n_cams, 9))
+    assert zero < 1e-9
+
+
 @pytest.mark.parametrize("lam", [1e-4, 1e-2, 1.0, 100.0])
 @pytest.mark.parametrize("mode", ["marquardt", "identity"])
 def test_lemma1_eigenvalues_in_unit_interval(lam, mode):
