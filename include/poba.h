@@ -282,6 +282,16 @@ poba_status poba_project(int64_t n_obs, const int32_t *obs_cam, const int32_t *o
                          const double *cams, const double *lms, double *out_xy,
                          poba_stream stream);
 
+/* Residual check of the reduced camera system (Sec. 4.2, eq. Schur) for a
+ * camera step dx_cams [dev] float64 [n_cams][9] of the last poba_power_solve
+ * (its lambda, damping diagonal and b~): rel_residual[j] = |S x + b~|_2 /
+ * |b~|_2 per problem [dev] float64 [n_problems], with S x = U_lambda x -
+ * W V_lambda^-1 W^T x evaluated in float64 (V^-1 recomputed in float64, the
+ * stored Jacobian blocks widened, norms summed with TwoSum compensation).
+ * For the series x(m) it equals |U P^{m+1} U^-1 b~| / |b~|. */
+poba_status poba_solve_residual(poba_problem p, const double *dx_cams, double *rel_residual,
+                                poba_stream stream);
+
 /* ---- inspection (tests, diagnostics) ---------------------------------- */
 
 /* Copies the undamped blocks of the last linearisation: U [dev] float64

@@ -113,6 +113,7 @@ SIGNATURES = {
     "poba_get_jacobians": (I32, [P, I32, P, P, P, P]),
     "poba_get_orders": (I32, [P, P, P, P, P, P]),
     "poba_apply_P": (I32, [P, P, P, P]),
+    "poba_solve_residual": (I32, [P, P, P, P]),
     "poba_set_observations": (I32, [P, P, P]),
     "poba_set_damping_frozen": (I32, [P, I32]),
     "poba_step_adjoint": (I32, [P, F64, I32, P, P, P, P, P, P, P, P, P, P, P, P]),

@@ -277,6 +277,7 @@ struct Buffers {
     double* v;            // [nc][9] current series term
     void* vq;             // [nc][12] current term in storage type (gather copy)
     double* x;            // [nc][9] series sum
+    double* bt;           // [nc][9] reduced right-hand side b~ of the last solve
     double* part;         // [npieces_max][54] per-piece partial sums
     double* dxl;          // [nl][3] landmark step (lm step)
     double* dxp;          // [nc][9] camera step (lm step)

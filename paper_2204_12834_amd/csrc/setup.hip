@@ -101,6 +101,7 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.v = (double*)take(nc * 9 * 8);
     t.vq = take(nc * 12 * 8);
     t.x = (double*)take(nc * 9 * 8);
+    t.bt = (double*)take(nc * 9 * 8);
     t.part = (double*)take(size_t(z.npieces_max) * 54 * 8);
     t.dxl = (double*)take(nl * 3 * 8);
     t.dxp = (double*)take(nc * 9 * 8);

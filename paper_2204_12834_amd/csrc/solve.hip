@@ -530,7 +530,10 @@ __global__ __launch_bounds__(kBlock) void k_cam_fin(Buffers b, Sizes z, int mode
     if (own) {
         double u = 0.0;
         for (int32_t q = b.cam_piece[c]; q < b.cam_piece[c + 1]; ++q) u += b.part[9 * int64_t(q) + r];
-        if (mode == kFinRhs) u = b.bp[9 * int64_t(c) + r] - u;
+        if (mode == kFinRhs) {
+            u = b.bp[9 * int64_t(c) + r] - u;
+            b.bt[9 * int64_t(c) + r] = u;
+        }
         us[lc][r] = u;
     }
     __syncthreads();
@@ -733,6 +736,133 @@ poba_status run_apply_P(Problem* p, const double* vin, double* vout, hipStream_t
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }
 
+// ------------------------------------------------ reduced-system residual --
+//
+// |S x + b~| / |b~| for a camera step x, S x = U_lambda x - W V^-1 W^T x
+// (eq. Schur), in float64 with V^-1 recomputed in float64, for every problem
+// of the last solve (its damping, D and b~).
+
+// Series flags cleared so that the camera pass covers every active problem.
+__global__ __launch_bounds__(kReduceBlock) void k_begin_residual(Ctrl* ctrl, PCtrl* pctl, int32_t np) {
+    int n = 0;
+    for (int32_t base = 0; base < np; base += blockDim.x) {
+        const int32_t j = base + threadIdx.x;
+        int a = 0;
+        if (j < np) {
+            pctl[j].stopped = 0;
+            a = pctl[j].active;
+        }
+        n += __syncthreads_count(a);
+    }
+    if (threadIdx.x == 0) ctrl->running = n;
+}
+
+// s_l = V_lambda^-1 sum_{i in l} J_l^T J_p x_c in float64 (float64 view of s).
+template <typename TJ>
+__global__ __launch_bounds__(kBlock) void k_lm_apply64(Buffers b, Sizes z, const double* __restrict__ x,
+                                                       const Ctrl* ctrl) {
+    if (!ctrl->active) return;
+    const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+    if (tile >= z.ntiles) return;
+    tile_landmarks<double, 3>(
+        b.lo_cam, b.tile_start, b.seg_base, tile,
+        [&](int32_t i, bool valid, int32_t cam, int32_t, double* v) {
+            v[0] = v[1] = v[2] = 0.0;
+            if (!valid) return;
+            double J[24];
+            load_J<TJ, double>(b.J_lo, z.npad, i, J);
+            const double* vc = x + 9 * int64_t(cam);
+            double q0 = 0.0, q1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                q0 += J[k] * vc[k];
+                q1 += J[9 + k] * vc[k];
+            }
+            v[0] = J[18] * q0 + J[21] * q1;
+            v[1] = J[19] * q0 + J[22] * q1;
+            v[2] = J[20] * q0 + J[23] * q1;
+        },
+        [&](int32_t seg, const double* t) {
+            const int64_t l = b.nel[seg];
+            const PCtrl& q = b.pctl[b.lm_prob[l]];
+            if (!q.active) return;
+            double Vd[6], inv[6], y[3], dd[3];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Vd[k] = b.V[6 * l + k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) dd[k] = b.Dl[3 * int64_t(seg) + k];
+            inv3_damped(Vd, q.lambda, dd, inv);
+            sym3_apply(inv, t, y);
+            double* o = reinterpret_cast<double*>(b.s) + 4 * int64_t(seg);
+            o[0] = y[0];
+            o[1] = y[1];
+            o[2] = y[2];
+            o[3] = 0.0;
+        });
+}
+
+// Per camera: r_c = U_lambda x_c - (W s)_c + b~_c; squared norms of r_c and
+// b~_c to cam_red.
+__global__ __launch_bounds__(kBlock) void k_residual_cam(Buffers b, Sizes z, const double* __restrict__ x,
+                                                         const Ctrl* ctrl) {
+    if (!ctrl->active) return;
+    const int32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= z.nc) return;
+    const PCtrl& q = b.pctl[b.cam_prob[c]];
+    if (!q.active) return;
+    double u[9], xc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        u[k] = 0.0;
+        xc[k] = x[9 * int64_t(c) + k];
+    }
+    for (int32_t p = b.cam_piece[c]; p < b.cam_piece[c + 1]; ++p) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) u[k] += b.part[9 * int64_t(p) + k];
+    }
+    const double* U = b.U + 81 * int64_t(c);
+    double r2 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        double acc = q.lambda * b.Dp[9 * int64_t(c) + k] * xc[k];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) acc += U[9 * k + j] * xc[j];
+        const double btk = b.bt[9 * int64_t(c) + k];
+        const double r = acc - u[k] + btk;
+        r2 += r * r;
+        b2 += btk * btk;
+    }
+    b.cam_red[2 * int64_t(c)] = r2;
+    b.cam_red[2 * int64_t(c) + 1] = b2;
+}
+
+// Per problem: |r| / |b~| from its cameras' squared norms (compensated sums).
+__global__ __launch_bounds__(kBlock) void k_residual_norm(Buffers b, double* out, const Ctrl* ctrl) {
+    __shared__ double lds[kWavesPerBlock * 2];
+    if (!ctrl->active) return;
+    const PCtrl& q = b.pctl[blockIdx.x];
+    if (!q.active) return;
+    const int32_t c0 = b.prob_cam_off[blockIdx.x], c1 = b.prob_cam_off[blockIdx.x + 1];
+    double tot[2];
+    sum_partials<2>(b.cam_red + 2 * int64_t(c0), uint32_t(c1 - c0), tot, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = tot[1] > 0.0 ? sqrt(tot[0]) / sqrt(tot[1]) : 0.0;
+}
+
+template <typename TJ>
+poba_status run_residual(Problem* p, const double* x, double* out, hipStream_t s) {
+    const Buffers& b = p->b;
+    const Sizes& z = p->z;
+    hipLaunchKernelGGL(k_begin_residual, dim3(1), dim3(kReduceBlock), 0, s, b.ctrl, b.pctl, z.np);
+    hipLaunchKernelGGL(k_lm_apply64<TJ>, dim3(unsigned(ceil_div(z.ntiles, kWavesPerBlock))), dim3(kBlock), 0, s, b,
+                       z, x, b.ctrl);
+    if (p->npieces > 0)
+        hipLaunchKernelGGL((k_cam_pass<TJ, double>), dim3(unsigned(p->sched_len)), dim3(kBlock), 0, s, b, z,
+                           reinterpret_cast<const double*>(b.s), b.ctrl);
+    hipLaunchKernelGGL(k_residual_cam, dim3(unsigned(ceil_div(z.nc, kBlock))), dim3(kBlock), 0, s, b, z, x, b.ctrl);
+    hipLaunchKernelGGL(k_residual_norm, dim3(unsigned(z.np)), dim3(kBlock), 0, s, b, out, b.ctrl);
+    return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
+}
+
 // Widens the stored records of one order to float64 in original order.
 template <typename TJ>
 __global__ __launch_bounds__(kBlock) void k_get_jac(Buffers b, Sizes z, int order, double* Jp, double* Jl, double* r) {
@@ -782,6 +912,17 @@ poba_status poba_power_solve(poba_problem p, double lambda, int32_t m, double ep
     poba_status st = launch_begin_solve(p, lambda, s);
     if (st) return st;
     return launch_solve(p, m, eps, dx_cams, dx_lms, info, s);
+}
+
+poba_status poba_solve_residual(poba_problem p, const double* dx_cams, double* rel_residual, poba_stream stream) {
+    (void)hipGetLastError();  // report only this call's launch errors
+    if (!p || !dx_cams || !rel_residual) return POBA_ERR_INVALID_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    switch (p->d.precision) {
+        case POBA_F64: return run_residual<double>(p, dx_cams, rel_residual, s);
+        case POBA_F32: return run_residual<float>(p, dx_cams, rel_residual, s);
+        default: return run_residual<bf16_t>(p, dx_cams, rel_residual, s);
+    }
 }
 
 poba_status poba_apply_P(poba_problem p, const double* v_in, double* v_out, poba_stream stream) {

@@ -168,6 +168,14 @@ class Problem:
                                                                  _stream(stream)))
         return dx_cams, dx_lms, info
 
+    def solve_residual(self, dx_cams: torch.Tensor, stream=None) -> torch.Tensor:
+        """|S x + b~| / |b~| per problem for a camera step of the last power_solve."""
+        dx_cams = _dev(dx_cams, torch.float64, self.device, (self.n_cams, 9))
+        out = torch.empty(self.n_problems, dtype=torch.float64, device=self.device)
+        _lib.check("poba_solve_residual", self.lib.poba_solve_residual(self.handle, _ptr(dx_cams), _ptr(out),
+                                                                       _stream(stream)))
+        return out
+
     def lm_init(self, opts: LMOptions | None = None, state: torch.Tensor | None = None, stream=None):
         opts = opts or LMOptions()
         if state is None:

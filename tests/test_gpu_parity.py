@@ -214,3 +214,23 @@ def test_bitwise_determinism():
         dxp, dxl, _ = prob.power_solve(1e-3, 16, 0.0)
         outs.append((np_(dxp).copy(), np_(dxl).copy()))
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("name", ["c1", "city_small"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_solve_residual_matches_oracle(name, precision):
+    """|S x + b~| / |b~| on the GPU against the oracle's matrix-free residual
+    of the same step, built from the stored (rounded) Jacobian blocks."""
+    case = CASES[name]()
+    s = case.scene
+    prob = case.problem(precision)
+    cams, lms = case.state()
+    prob.linearize(cams, lms)
+    Jp, Jl, r = (np_(t) for t in prob.get_jacobians(0))
+    for lam, m in [(1e-2, 0), (1e-2, 5), (1.0, 20)]:
+        dxp, _, _ = prob.power_solve(lam, m, 0.0)
+        got = np_(prob.solve_residual(dxp))[0]
+        ref = schur.solve(Jp, Jl, r, s.obs_cam, s.obs_lm, s.n_cams, s.n_lms, lam, m)
+        want = schur.reduced_residual(Jp, Jl, s.obs_cam, s.obs_lm, ref.Ul, ref.Vinv, ref.btilde, np_(dxp))
+        log(f"residual {name} {precision} lam={lam} m={m}: gpu {got:.3e} oracle {want:.3e}")
+        assert abs(got - want) <= 1e-6 * want + 1e-12, (got, want)
