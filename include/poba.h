@@ -61,6 +61,15 @@ enum {
  * cost and the LM decision are float64 in every mode. */
 enum { POBA_F64 = 0, POBA_F32 = 1, POBA_F32_BF16J = 2 };
 
+/* What the passes read per observation (both orders).  JACOBIAN: the 24
+ * scalars of J_p (2x9) and J_l (2x3) in the storage precision.  POINT: the
+ * camera-frame point P = R X + t and the square root of the IRLS weight
+ * (4 scalars, float32 or float64); every pass rebuilds the blocks from them
+ * and the camera's parameters (Sec. 4: J depends on the observation only
+ * through P), moving about a sixth of the bytes.  POINT is available with
+ * POBA_F64 and POBA_F32. */
+enum { POBA_RECORDS_JACOBIAN = 0, POBA_RECORDS_POINT = 1 };
+
 /* D^T D of Sec. 4.1: Marquardt = diag(J^T J) clamped to [1e-6, 1e32]; identity = I. */
 enum { POBA_DAMP_MARQUARDT = 0, POBA_DAMP_IDENTITY = 1 };
 
@@ -81,7 +90,7 @@ typedef struct {
     int32_t piece_size; /* observations per camera-pass work item; 0 = default (1024) */
     int32_t lm_ranges;  /* landmark ranges of the camera-major order (XCD-local gathers);
                            0 = automatic, 1 = none, else a multiple of 8            */
-    int32_t reserved;   /* must be 0 */
+    int32_t records;    /* POBA_RECORDS_*: what is stored per observation      */
     double huber_delta; /* pixels; used when loss == POBA_LOSS_HUBER, must be > 0 */
 } poba_desc;
 

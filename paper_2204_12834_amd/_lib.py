@@ -22,6 +22,7 @@ STATUS_BITS = {
 }
 PRECISION = {"f64": 0, "f32": 1, "bf16": 2}
 DAMPING = {"marquardt": 0, "identity": 1}
+RECORDS = {"jacobian": 0, "point": 1}
 LOSS = {"l2": 0, "huber": 1}
 TUNING = {"tiles_per_wave": 0, "lm_ranges": 1, "lds_camera": 2}
 KERNEL_CLASSES = ["linearize", "inverse", "landmark_pass", "camera_pass", "camera_finish", "backsub", "eval", "other"]
@@ -37,7 +38,7 @@ class PobaDesc(ctypes.Structure):
         ("loss", ctypes.c_int32),
         ("piece_size", ctypes.c_int32),
         ("lm_ranges", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("records", ctypes.c_int32),
         ("huber_delta", ctypes.c_double),
     ]
 

@@ -64,7 +64,7 @@ __device__ __forceinline__ void intrinsic_mixed(const ObsGeom& g, const double* 
 // One block per camera piece (camera-major order).  Writes obar of every
 // observation of the piece at its original index and the piece's partial
 // intrinsic gradient (3 values) to its slot of `part`.
-template <typename TJ>
+template <typename TJ, bool PT>
 __global__ __launch_bounds__(kBlock) void k_adjoint(Buffers b, Sizes z, const double* __restrict__ lms,
                                                     const double* __restrict__ zc, const double* __restrict__ zl,
                                                     const double* __restrict__ dxc, const double* __restrict__ dxl,
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(Buffers b, Sizes z, const do
     if (p < 0) return;
     const int32_t a0 = b.piece_begin[p], e0 = b.piece_end[p];
     const int64_t c = b.piece_cam[p];
-    const double* rec = b.cam_rec + kCamRec * c;
+    const double* rec = b.lin_rec + kCamRec * c;
     double zcam[9], dcam[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(Buffers b, Sizes z, const do
         const double zlm[3] = {zl[3 * l], zl[3 * l + 1], zl[3 * l + 2]};
         const double dlm[3] = {dxl[3 * l], dxl[3 * l + 1], dxl[3 * l + 2]};
         double J[24];
-        load_J<TJ, double>(b.J_co, z.npad, i, J);
+        Rec<TJ, PT>::template jac<double>(b, z, b.J_co, i, c, J);
         double av[2], ev[2];
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
@@ -185,24 +185,23 @@ poba_status poba_step_adjoint(poba_problem p, double lambda, int32_t m, const do
     if (z.nl > 0)
         hipLaunchKernelGGL(k_negate, dim3(unsigned(ceil_div(int64_t(z.nl) * 3, kBlock))), blk, 0, s, z_lms,
                            int64_t(z.nl) * 3);
-    st = launch_cam_prep(p, cams, nullptr, s);
+    st = launch_cam_prep(p, cams, nullptr, p->b.lin_rec, s);
     if (st) return st;
     if (p->npieces > 0) {
         const dim3 g(unsigned(p->sched_len));
-        switch (p->d.precision) {
-            case POBA_F64:
-                hipLaunchKernelGGL(k_adjoint<double>, g, blk, 0, s, p->b, z, lms, z_cams, z_lms, dx_cams, dx_lms,
-                                   grad_obs);
-                break;
-            case POBA_F32:
-                hipLaunchKernelGGL(k_adjoint<float>, g, blk, 0, s, p->b, z, lms, z_cams, z_lms, dx_cams, dx_lms,
-                                   grad_obs);
-                break;
-            default:
-                hipLaunchKernelGGL(k_adjoint<bf16_t>, g, blk, 0, s, p->b, z, lms, z_cams, z_lms, dx_cams, dx_lms,
-                                   grad_obs);
-                break;
+#define POBA_ADJ(TJ_, PT_)                                                                                      \
+    hipLaunchKernelGGL((k_adjoint<TJ_, PT_>), g, blk, 0, s, p->b, z, lms, z_cams, z_lms, dx_cams, dx_lms, grad_obs)
+        if (z.point) {
+            if (p->d.precision == POBA_F64) POBA_ADJ(double, true);
+            else POBA_ADJ(float, true);
+        } else if (p->d.precision == POBA_F64) {
+            POBA_ADJ(double, false);
+        } else if (p->d.precision == POBA_F32) {
+            POBA_ADJ(float, false);
+        } else {
+            POBA_ADJ(bf16_t, false);
         }
+#undef POBA_ADJ
     }
     hipLaunchKernelGGL(k_adjoint_fin, dim3(unsigned(ceil_div(z.nc, kBlock))), blk, 0, s, p->b, z, grad_intrinsics);
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;

@@ -156,9 +156,21 @@ __device__ __forceinline__ void evaluate_obs(const double* cam, const double* X,
     }
 }
 
+// Coefficient of [w]x^2 in the left Jacobian of SO(3),
+// E = (1 - sin(theta)/theta) / theta^2 (Taylor series below theta^2 = 1e-3).
+__device__ __forceinline__ double left_jacobian_coeff(double th2, double A) {
+#pragma clang fp contract(off)
+    if (th2 < 1e-3) {
+        const double t4 = th2 * th2;
+        return 1.0 / 6.0 - th2 / 120.0 + t4 / 5040.0 - t4 * th2 / 362880.0;
+    }
+    return (1.0 - A) / th2;
+}
+
 // Per-camera data shared by all of its observations: the nine parameters,
-// the Rodrigues coefficients A, B, C, D and the rotation matrix R.
-// Layout: [0..8] parameters, [9..12] A B C D, [13..21] R row-major, 2 pad.
+// the Rodrigues coefficients A, B, C, D, the rotation matrix R and the
+// coefficient E of the left Jacobian J_l(w) = I + B [w]x + E [w]x^2.
+// Layout: [0..8] parameters, [9..12] A B C D, [13..21] R row-major, [22] E, 1 pad.
 constexpr int kCamRec = 24;  // doubles per record
 
 __device__ __forceinline__ void make_cam_record(const double* cam, double* rec) {
@@ -182,7 +194,8 @@ __device__ __forceinline__ void make_cam_record(const double* cam, double* rec) 
     R[6] = -A * w[1] + B * w[0] * w[2];
     R[5] = -A * w[0] + B * w[1] * w[2];
     R[7] = A * w[0] + B * w[1] * w[2];
-    rec[22] = rec[23] = 0.0;
+    rec[22] = left_jacobian_coeff(th2, A);
+    rec[23] = 0.0;
 }
 
 // Model pixel of X from a camera record: P = R X + t.
@@ -272,6 +285,81 @@ __device__ __forceinline__ void observation_geometry(const double* rec, const do
             g.dp[a][3 + j] = dp_dP[a][j];
             g.dp[a][6 + j] = dp_dP[a][0] * Rm[j] + dp_dP[a][1] * Rm[3 + j] + dp_dP[a][2] * Rm[6 + j];
         }
+    }
+}
+
+// ------------------------------------------------------------ point records --
+//
+// The blocks of an observation depend on it only through its camera-frame
+// point P = R X + t: with p = -P_xy / P_z, n = |p|^2, d = 1 + k1 n + k2 n^2,
+// A = dpi/dp = f (d I + 2 (k1 + 2 k2 n) p p^T) (symmetric 2x2) and
+// dp/dP = -1/P_z [[1, 0, p_0], [0, 1, p_1]],
+//   J_P   = dpi/dP = -1/P_z [A_0, A_1, A p]            (2x3)
+//   J_p   = [J_P dRX, J_P, d p, f n p, f n^2 p]      dRX = -[P - t]x J_l(w)
+//   J_l   = J_P R
+// A point record keeps (P, sqrt(w)); the blocks are rebuilt from it and the
+// camera record, scaled by sqrt(w) like the stored blocks of the IRLS step.
+
+// Camera-frame point and residual of an observation from the camera record.
+__device__ __forceinline__ void camera_point(const double* rec, const double* X, double ox, double oy, double* P,
+                                             double* r) {
+#pragma clang fp contract(off)
+    const double* Rm = rec + 13;
+    for (int k = 0; k < 3; ++k) P[k] = Rm[3 * k] * X[0] + Rm[3 * k + 1] * X[1] + Rm[3 * k + 2] * X[2] + rec[3 + k];
+    const double iz = 1.0 / P[2];
+    const double p0 = -P[0] * iz, p1 = -P[1] * iz;
+    const double n = p0 * p0 + p1 * p1;
+    const double d = 1.0 + rec[7] * n + rec[8] * n * n;
+    r[0] = rec[6] * d * p0 - ox;
+    r[1] = rec[6] * d * p1 - oy;
+}
+
+// The 24 block scalars (J_p row 0, row 1, J_l row 0, row 1) of a point record,
+// times sw, in arithmetic T.
+template <typename T>
+__device__ __forceinline__ void point_jacobian(const double* rec, const T* P, T sw, T* J) {
+#pragma clang fp contract(off)
+    const T f = T(rec[6]), k1 = T(rec[7]), k2 = T(rec[8]);
+    const T iz = T(1) / P[2];
+    const T p0 = -P[0] * iz, p1 = -P[1] * iz;
+    const T n = p0 * p0 + p1 * p1;
+    const T d = T(1) + k1 * n + k2 * n * n;
+    const T dd = T(2) * (k1 + T(2) * k2 * n);
+    const T A00 = f * (d + dd * p0 * p0), A01 = f * dd * p0 * p1, A11 = f * (d + dd * p1 * p1);
+    T JP[2][3];
+    JP[0][0] = -iz * A00;
+    JP[0][1] = -iz * A01;
+    JP[0][2] = -iz * (A00 * p0 + A01 * p1);
+    JP[1][0] = -iz * A01;
+    JP[1][1] = -iz * A11;
+    JP[1][2] = -iz * (A01 * p0 + A11 * p1);
+    // dRX = -[RX]x J_l(w), RX = P - t
+    const T w0 = T(rec[0]), w1 = T(rec[1]), w2 = T(rec[2]);
+    const T B = T(rec[10]), E = T(rec[22]);
+    const T th2 = w0 * w0 + w1 * w1 + w2 * w2;
+    const T W[3][3] = {{T(0), -w2, w1}, {w2, T(0), -w0}, {-w1, w0, T(0)}};
+    T Jl[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const T ww = (i == j ? -th2 : T(0)) + (i == 0 ? w0 : (i == 1 ? w1 : w2)) * (j == 0 ? w0 : (j == 1 ? w1 : w2));
+            Jl[i][j] = (i == j ? T(1) : T(0)) + B * W[i][j] + E * ww;
+        }
+    const T X0 = P[0] - T(rec[3]), X1 = P[1] - T(rec[4]), X2 = P[2] - T(rec[5]);
+    const T S[3][3] = {{T(0), X2, -X1}, {-X2, T(0), X0}, {X1, -X0, T(0)}};  // -[RX]x
+    T dRX[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) dRX[i][j] = S[i][0] * Jl[0][j] + S[i][1] * Jl[1][j] + S[i][2] * Jl[2][j];
+    const T pp[2] = {p0, p1};
+    for (int a = 0; a < 2; ++a) {
+        T* Jp = J + 9 * a;
+        for (int j = 0; j < 3; ++j) Jp[j] = sw * (JP[a][0] * dRX[0][j] + JP[a][1] * dRX[1][j] + JP[a][2] * dRX[2][j]);
+        for (int j = 0; j < 3; ++j) Jp[3 + j] = sw * JP[a][j];
+        Jp[6] = sw * (d * pp[a]);
+        Jp[7] = sw * (f * n * pp[a]);
+        Jp[8] = sw * (f * n * n * pp[a]);
+        T* Jl_ = J + 18 + 3 * a;
+        for (int j = 0; j < 3; ++j)
+            Jl_[j] = sw * (JP[a][0] * T(rec[13 + j]) + JP[a][1] * T(rec[16 + j]) + JP[a][2] * T(rec[19 + j]));
     }
 }
 

@@ -165,6 +165,48 @@ __device__ __forceinline__ void load_J<bf16_t, float>(const void* b, int64_t n, 
 template <>
 __device__ __forceinline__ void load_J<bf16_t, double>(const void* b, int64_t n, int64_t i, double* v) { load_J_b(b, n, i, v); }
 
+// Point record of an observation: (P_x, P_y, P_z, sqrt(w)).  float32: one
+// 16-byte group at byte i * 16; float64: two groups (P_x, P_y), (P_z, sqrt(w))
+// at (g * npad + i) * 16.
+template <typename TP>
+__device__ __forceinline__ void store_point(void* base, int64_t npad, int64_t i, const double* P, double sw);
+template <>
+__device__ __forceinline__ void store_point<float>(void* base, int64_t, int64_t i, const double* P, double sw) {
+    reinterpret_cast<float4*>(base)[i] = make_float4(float(P[0]), float(P[1]), float(P[2]), float(sw));
+}
+template <>
+__device__ __forceinline__ void store_point<double>(void* base, int64_t npad, int64_t i, const double* P, double sw) {
+    double2* b = reinterpret_cast<double2*>(base);
+    b[i] = make_double2(P[0], P[1]);
+    b[npad + i] = make_double2(P[2], sw);
+}
+
+template <typename TP, typename TC>
+__device__ __forceinline__ void load_point(const void* base, int64_t npad, int64_t i, TC* P, TC& sw);
+template <>
+__device__ __forceinline__ void load_point<float, float>(const void* base, int64_t, int64_t i, float* P, float& sw) {
+    const f4v x = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(base) + i);
+    P[0] = x.x; P[1] = x.y; P[2] = x.z; sw = x.w;
+}
+template <>
+__device__ __forceinline__ void load_point<float, double>(const void* base, int64_t, int64_t i, double* P,
+                                                          double& sw) {
+    const f4v x = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(base) + i);
+    P[0] = x.x; P[1] = x.y; P[2] = x.z; sw = x.w;
+}
+template <>
+__device__ __forceinline__ void load_point<double, double>(const void* base, int64_t npad, int64_t i, double* P,
+                                                           double& sw) {
+    const d2v* b = reinterpret_cast<const d2v*>(base);
+    const d2v a = __builtin_nontemporal_load(b + i);
+    const d2v c = __builtin_nontemporal_load(b + npad + i);
+    P[0] = a.x; P[1] = a.y; P[2] = c.x; sw = c.y;
+}
+
+// Rounds a value to the point-record type and back.
+template <typename TP>
+__device__ __forceinline__ double round_point(double v) { return double(TP(v)); }
+
 // ------------------------------------------------------------ wave helpers --
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -281,7 +323,8 @@ struct Buffers {
     double* part;         // [npieces_max][54] per-piece partial sums
     double* dxl;          // [nl][3] landmark step (lm step)
     double* dxp;          // [nc][9] camera step (lm step)
-    double* cam_rec;      // [nc][24] per-camera rotation data of the state being evaluated
+    double* cam_rec;      // [nc][24] camera records of the state being evaluated (trial state)
+    double* lin_rec;      // [nc][24] camera records of the last linearisation
     double* cams_new;     // [nc][9]
     double* lms_new;      // [nl][3]
     double* piece_red;    // [npieces_max][3] per-piece partial sums (cost, model, flags)
@@ -311,6 +354,8 @@ struct Sizes {
     int piece;
     int jbytes;  // bytes per stored Jacobian scalar
     int sbytes;  // bytes per stored landmark-side scalar
+    int point;   // 1: point records (P, sqrt(w)) instead of Jacobian blocks
+    int rbytes;  // bytes of one observation's record
 };
 
 struct ProfileSlot {
@@ -331,6 +376,7 @@ struct poba_problem_s {
     int64_t sched_len = 0;      // camera-pass grid size
     int64_t n_cus = 256;        // compute units of the device
     int lds_cam = 1;            // stage the camera vector in LDS when it fits
+    int64_t lds_max = 65536;    // bytes of LDS one workgroup may allocate
     int damping_frozen = 0;     // solves reuse the damping diagonal of the last unfrozen solve
     hipStream_t last_stream = nullptr;
     // profiling

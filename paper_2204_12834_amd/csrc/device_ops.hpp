@@ -3,9 +3,98 @@
 // small symmetric block inverses.
 #pragma once
 
+#include "camera_model.hpp"
 #include "common.hpp"
 
 namespace poba {
+
+// ------------------------------------------------------ observation blocks --
+
+// The 24 block scalars of observation i of one order in arithmetic TC: the
+// stored blocks (POINT = false, storage TJ), or the blocks rebuilt from the
+// point record (storage TJ) and the camera record of the linearisation.
+template <typename TJ, bool POINT>
+struct Rec {
+    template <typename TC>
+    __device__ __forceinline__ static void jac(const Buffers& b, const Sizes& z, const void* base, int64_t i,
+                                               int64_t cam, TC* J) {
+        if constexpr (POINT) {
+            TC P[3], sw;
+            load_point<TJ, TC>(base, z.npad, i, P, sw);
+            point_jacobian<TC>(b.lin_rec + kCamRec * cam, P, sw, J);
+        } else {
+            load_J<TJ, TC>(base, z.npad, i, J);
+        }
+    }
+};
+
+// Per-camera data of the point-record landmark pass for the camera vector v
+// (24 slots): a = J_l(w) v_w, e = v_t - a x t, v_intrinsics, f, k1, k2, R.
+// With them J_p v = J_P (a x P + e) + p (d v_f + f n v_k1 + f n^2 v_k2).
+template <typename TS>
+__device__ __forceinline__ void fold_camera(const double* rec, const double* v, TS* out) {
+    const double w0 = rec[0], w1 = rec[1], w2 = rec[2];
+    const double B = rec[10], E = rec[22];
+    const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
+    const double ww[3] = {w0, w1, w2};
+    const double W[3][3] = {{0.0, -w2, w1}, {w2, 0.0, -w0}, {-w1, w0, 0.0}};
+    double a[3];
+    for (int i = 0; i < 3; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            const double jl = (i == j ? 1.0 - E * th2 : 0.0) + B * W[i][j] + E * ww[i] * ww[j];
+            s += jl * v[j];
+        }
+        a[i] = s;
+    }
+    const double t0 = rec[3], t1 = rec[4], t2 = rec[5];
+    out[0] = TS(a[0]);
+    out[1] = TS(a[1]);
+    out[2] = TS(a[2]);
+    out[3] = TS(v[3] - (a[1] * t2 - a[2] * t1));
+    out[4] = TS(v[4] - (a[2] * t0 - a[0] * t2));
+    out[5] = TS(v[5] - (a[0] * t1 - a[1] * t0));
+    out[6] = TS(v[6]);
+    out[7] = TS(v[7]);
+    out[8] = TS(v[8]);
+    out[9] = TS(rec[6]);
+    out[10] = TS(rec[7]);
+    out[11] = TS(rec[8]);
+    for (int k = 0; k < 9; ++k) out[12 + k] = TS(rec[13 + k]);
+    out[21] = out[22] = out[23] = TS(0);
+}
+
+// Shape factors of a camera-frame point shared by the point-record passes:
+// iz = 1 / P_z, p = -P_xy iz, n = |p|^2, d = 1 + k1 n + k2 n^2 and
+// A = dpi/dp = f (d I + 2 (k1 + 2 k2 n) p p^T).
+template <typename T>
+struct PointShape {
+    T iz, p0, p1, n, d, A00, A01, A11;
+    __device__ __forceinline__ PointShape(const T* P, T f, T k1, T k2) {
+        iz = T(1) / P[2];
+        p0 = -P[0] * iz;
+        p1 = -P[1] * iz;
+        n = p0 * p0 + p1 * p1;
+        d = T(1) + k1 * n + k2 * n * n;
+        const T dd = T(2) * (k1 + T(2) * k2 * n);
+        A00 = f * (d + dd * p0 * p0);
+        A01 = f * dd * p0 * p1;
+        A11 = f * (d + dd * p1 * p1);
+    }
+    // J_P y (2) for a camera-frame vector y (3)
+    __device__ __forceinline__ void JP(const T* y, T& z0, T& z1) const {
+        const T u0 = y[0] + p0 * y[2], u1 = y[1] + p1 * y[2];
+        z0 = -iz * (A00 * u0 + A01 * u1);
+        z1 = -iz * (A01 * u0 + A11 * u1);
+    }
+    // J_P^T z (3)
+    __device__ __forceinline__ void JPt(T z0, T z1, T* h) const {
+        const T y0 = A00 * z0 + A01 * z1, y1 = A01 * z0 + A11 * z1;
+        h[0] = -iz * y0;
+        h[1] = -iz * y1;
+        h[2] = -iz * (p0 * y0 + p1 * y1);
+    }
+};
 
 // ------------------------------------------------------ landmark-tile loop --
 //

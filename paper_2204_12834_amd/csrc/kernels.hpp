@@ -11,8 +11,9 @@ namespace poba {
 poba_status launch_linearize(Problem* p, const double* cams, const double* lms, const int32_t* gate,
                              double* cost_out, poba_lm_state* st, hipStream_t s);
 
-// Per-camera rotation records of cams into the handle's camera-record buffer.
-poba_status launch_cam_prep(Problem* p, const double* cams, const int32_t* gate, hipStream_t s);
+// Per-camera records of cams (rotation data) into out (b.cam_rec for a trial
+// state, b.lin_rec for the linearisation).
+poba_status launch_cam_prep(Problem* p, const double* cams, const int32_t* gate, double* out, hipStream_t s);
 
 // Damped inverses, reduced right-hand side, power series and
 // back-substitution, each problem with the damping in its pctl[j].lambda;

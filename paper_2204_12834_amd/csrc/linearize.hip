@@ -17,8 +17,8 @@
 namespace poba {
 
 // Rotation data of every camera (the only transcendental work per camera).
-__global__ __launch_bounds__(kBlock) void k_cam_prep(Buffers b, Sizes z, const double* __restrict__ cams,
-                                                     const int32_t* gate) {
+__global__ __launch_bounds__(kBlock) void k_cam_prep(Sizes z, const double* __restrict__ cams, const int32_t* gate,
+                                                     double* __restrict__ out) {
     if (gate && !*gate) return;
     const int32_t c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= z.nc) return;
@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kBlock) void k_cam_prep(Buffers b, Sizes z, const d
     for (int k = 0; k < 9; ++k) cam[k] = cams[9 * int64_t(c) + k];
     make_cam_record(cam, rec);
 #pragma unroll
-    for (int k = 0; k < kCamRec; ++k) b.cam_rec[kCamRec * int64_t(c) + k] = rec[k];
+    for (int k = 0; k < kCamRec; ++k) out[kCamRec * int64_t(c) + k] = rec[k];
 }
 
 // Camera-major pass, one block per camera piece (blocks dealt to the dies as
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const do
     if (p >= 0) {
         const int32_t cam = b.piece_cam[p];
         const int32_t a = b.piece_begin[p], e = b.piece_end[p];
-        const double* rec = b.cam_rec + kCamRec * int64_t(cam);
+        const double* rec = b.lin_rec + kCamRec * int64_t(cam);
         for (int32_t base = a; base < e; base += kBlock) {
             const int32_t i = base + t;
             if (i < e) {
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const dou
 #pragma unroll
             for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
             ObsEval ev;
-            evaluate_obs_rec(b.cam_rec + kCamRec * int64_t(cam), X, b.obs_lo[2 * int64_t(i)],
+            evaluate_obs_rec(b.lin_rec + kCamRec * int64_t(cam), X, b.obs_lo[2 * int64_t(i)],
                              b.obs_lo[2 * int64_t(i) + 1], ev);
             double w = 1.0;
             if (loss == POBA_LOSS_HUBER) {
@@ -158,6 +158,140 @@ __global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const dou
             const double r0 = sw * ev.r[0], r1 = sw * ev.r[1];
             const double* a = J + 18;  // J_l row 0
             const double* c = J + 21;  // J_l row 1
+            v[0] = a[0] * a[0] + c[0] * c[0];
+            v[1] = a[0] * a[1] + c[0] * c[1];
+            v[2] = a[0] * a[2] + c[0] * c[2];
+            v[3] = a[1] * a[1] + c[1] * c[1];
+            v[4] = a[1] * a[2] + c[1] * c[2];
+            v[5] = a[2] * a[2] + c[2] * c[2];
+            v[6] = a[0] * r0 + c[0] * r1;
+            v[7] = a[1] * r0 + c[1] * r1;
+            v[8] = a[2] * r0 + c[2] * r1;
+        },
+        [&](int32_t seg, const double* v) {
+            const int64_t l = b.nel[seg];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) b.V[6 * l + k] = v[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) b.bl[3 * l + k] = v[6 + k];
+        });
+}
+
+// Point records (camera-major pass): stores (P, sqrt(w)) rounded to TP and the
+// reweighted residual, and accumulates U and b_p from the blocks rebuilt in
+// float64 from the rounded record, the blocks every later pass sees.
+template <typename TP>
+__global__ __launch_bounds__(kBlock) void k_lin_cam_pt(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
+                                                       double delta, const int32_t* gate) {
+    __shared__ double js[kBlock][18];
+    __shared__ double rs[kBlock][2];
+    __shared__ double red[4][54];
+    __shared__ double lds[kWavesPerBlock * 2];
+    if (gate && !*gate) return;
+    const int t = threadIdx.x;
+    const int ent = t % 54, grp = t / 54;
+    int ea = 0, eb = 0;
+    if (ent < 45) {
+        int e = ent, row = 0;
+        while (e >= 9 - row) {
+            e -= 9 - row;
+            ++row;
+        }
+        ea = row;
+        eb = row + e;
+    } else {
+        ea = ent - 45;
+    }
+    double acc = 0.0, cost = 0.0, bad = 0.0;
+    const int32_t p = b.sched[blockIdx.x];
+    if (p >= 0) {
+        const int32_t cam = b.piece_cam[p];
+        const int32_t a = b.piece_begin[p], e = b.piece_end[p];
+        const double* rec = b.lin_rec + kCamRec * int64_t(cam);
+        for (int32_t base = a; base < e; base += kBlock) {
+            const int32_t i = base + t;
+            if (i < e) {
+                const int64_t l = b.co_lm[i];
+                double X[3], P[3], r[2];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
+                camera_point(rec, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], P, r);
+                const double s2 = r[0] * r[0] + r[1] * r[1];
+                double rho = s2, w = 1.0;
+                if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, w);
+                cost += 0.5 * rho;
+                if (!isfinite(rho)) bad = 1.0;
+                store_point<TP>(b.J_co, z.npad, i, P, sqrt(w));
+                double Pr[3] = {round_point<TP>(P[0]), round_point<TP>(P[1]), round_point<TP>(P[2])};
+                const double swr = round_point<TP>(sqrt(w));
+                double J[24];
+                point_jacobian<double>(rec, Pr, swr, J);
+                const double r0 = swr * r[0], r1 = swr * r[1];
+                b.r_co[2 * int64_t(i)] = r0;
+                b.r_co[2 * int64_t(i) + 1] = r1;
+#pragma unroll
+                for (int k = 0; k < 18; ++k) js[t][k] = J[k];
+                rs[t][0] = r0;
+                rs[t][1] = r1;
+            }
+            __syncthreads();
+            const int cnt = min(kBlock, e - base);
+            if (grp < 4) {
+                if (ent < 45) {
+                    for (int j = grp; j < cnt; j += 4)
+                        acc += js[j][ea] * js[j][eb] + js[j][9 + ea] * js[j][9 + eb];
+                } else {
+                    for (int j = grp; j < cnt; j += 4) acc += js[j][ea] * rs[j][0] + js[j][9 + ea] * rs[j][1];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (grp < 4) red[grp][ent] = acc;
+    double tot[2] = {cost, bad};
+    block_sum<2>(tot, lds);
+    if (p >= 0 && t < 54)
+        b.part[54 * int64_t(p) + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+    if (p >= 0 && t == 0) {
+        b.piece_red[3 * int64_t(p)] = tot[0];
+        b.piece_red[3 * int64_t(p) + 1] = tot[1];
+    }
+}
+
+// Point records (landmark-major pass): the same records in landmark-major
+// order (bit-identical to the camera-major ones) and V, b_l per landmark from
+// the rebuilt blocks.
+template <typename TP>
+__global__ __launch_bounds__(kBlock) void k_lin_lm_pt(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
+                                                      double delta, const int32_t* gate) {
+    if (gate && !*gate) return;
+    const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+    if (tile >= z.ntiles) return;
+    tile_landmarks<double, 9>(
+        b.lo_cam, b.tile_start, b.seg_base, tile,
+        [&](int32_t i, bool valid, int32_t cam, int32_t seg, double* v) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) v[k] = 0.0;
+            if (!valid) return;
+            const int64_t l = b.nel[seg];
+            const double* rec = b.lin_rec + kCamRec * int64_t(cam);
+            double X[3], P[3], r[2];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
+            camera_point(rec, X, b.obs_lo[2 * int64_t(i)], b.obs_lo[2 * int64_t(i) + 1], P, r);
+            double w = 1.0;
+            if (loss == POBA_LOSS_HUBER) {
+                double rho;
+                huber(r[0] * r[0] + r[1] * r[1], delta, rho, w);
+            }
+            store_point<TP>(b.J_lo, z.npad, i, P, sqrt(w));
+            double Pr[3] = {round_point<TP>(P[0]), round_point<TP>(P[1]), round_point<TP>(P[2])};
+            const double swr = round_point<TP>(sqrt(w));
+            double J[24];
+            point_jacobian<double>(rec, Pr, swr, J);
+            const double r0 = swr * r[0], r1 = swr * r[1];
+            const double* a = J + 18;
+            const double* c = J + 21;
             v[0] = a[0] * a[0] + c[0] * c[0];
             v[1] = a[0] * a[1] + c[0] * c[1];
             v[2] = a[0] * a[2] + c[0] * c[2];
@@ -232,20 +366,34 @@ poba_status launch_linearize_t(Problem* p, const double* cams, const double* lms
     const double delta = p->d.huber_delta;
     const int loss = p->d.loss;
     ProfScope prof(p, POBA_K_LINEARIZE, s);
-    hipLaunchKernelGGL(k_cam_prep, dim3(unsigned(ceil_div(z.nc, kBlock))), dim3(kBlock), 0, s, b, z, cams, gate);
+    hipLaunchKernelGGL(k_cam_prep, dim3(unsigned(ceil_div(z.nc, kBlock))), dim3(kBlock), 0, s, z, cams, gate,
+                       b.lin_rec);
     const unsigned ncb = unsigned(std::max<int64_t>(p->sched_len, 1));
-    if (p->sched_len > 0)
-        hipLaunchKernelGGL(k_lin_cam<TJ>, dim3(ncb), dim3(kBlock), 0, s, b, z, lms, loss, delta, gate);
-    hipLaunchKernelGGL(k_cost_final, dim3(unsigned(z.np)), dim3(kBlock), 0, s, b, gate, cost_out, st);
-    hipLaunchKernelGGL(k_lin_lm<TJ>, dim3(unsigned(ceil_div(z.ntiles, kWavesPerBlock))), dim3(kBlock), 0, s, b, z,
-                       lms, loss, delta, gate);
+    const dim3 g_tiles(unsigned(ceil_div(z.ntiles, kWavesPerBlock)));
+    bool done = false;
+    if constexpr (!std::is_same<TJ, bf16_t>::value) {
+        if (z.point) {
+            // point records in the precision of TJ (double or float)
+            if (p->sched_len > 0)
+                hipLaunchKernelGGL(k_lin_cam_pt<TJ>, dim3(ncb), dim3(kBlock), 0, s, b, z, lms, loss, delta, gate);
+            hipLaunchKernelGGL(k_cost_final, dim3(unsigned(z.np)), dim3(kBlock), 0, s, b, gate, cost_out, st);
+            hipLaunchKernelGGL(k_lin_lm_pt<TJ>, g_tiles, dim3(kBlock), 0, s, b, z, lms, loss, delta, gate);
+            done = true;
+        }
+    }
+    if (!done) {
+        if (p->sched_len > 0)
+            hipLaunchKernelGGL(k_lin_cam<TJ>, dim3(ncb), dim3(kBlock), 0, s, b, z, lms, loss, delta, gate);
+        hipLaunchKernelGGL(k_cost_final, dim3(unsigned(z.np)), dim3(kBlock), 0, s, b, gate, cost_out, st);
+        hipLaunchKernelGGL(k_lin_lm<TJ>, g_tiles, dim3(kBlock), 0, s, b, z, lms, loss, delta, gate);
+    }
     hipLaunchKernelGGL(k_lin_cam_fin, dim3(unsigned(ceil_div(z.nc, kBlock))), dim3(kBlock), 0, s, b, z, gate);
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }
 
-poba_status launch_cam_prep(Problem* p, const double* cams, const int32_t* gate, hipStream_t s) {
-    hipLaunchKernelGGL(k_cam_prep, dim3(unsigned(ceil_div(p->z.nc, kBlock))), dim3(kBlock), 0, s, p->b, p->z, cams,
-                       gate);
+poba_status launch_cam_prep(Problem* p, const double* cams, const int32_t* gate, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_cam_prep, dim3(unsigned(ceil_div(p->z.nc, kBlock))), dim3(kBlock), 0, s, p->z, cams, gate,
+                       out);
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }
 

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_trial(Buffers b, Sizes z, const doub
 // F(x + dx) and L(0) - L(dx) over all observations, camera-major: one block
 // per camera piece (the camera's record and step are the same for the block);
 // the piece's partial sums go to its slot of piece_red.
-template <typename TJ>
+template <typename TJ, bool PT>
 __global__ __launch_bounds__(kBlock) void k_eval(Buffers b, Sizes z, int loss, double delta, const Ctrl* ctrl) {
     __shared__ double lds[kWavesPerBlock * 3];
     if (!ctrl->active) return;
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(Buffers b, Sizes z, int loss, d
             cost += 0.5 * rho;
             if (!isfinite(rho)) bad = 1.0;
             double J[24];
-            load_J<TJ, double>(b.J_co, z.npad, i, J);
+            Rec<TJ, PT>::template jac<double>(b, z, b.J_co, i, c, J);
             const double* dl = b.dxl + 3 * l;
             double m0 = J[18] * dl[0] + J[19] * dl[1] + J[20] * dl[2];
             double m1 = J[21] * dl[0] + J[22] * dl[1] + J[23] * dl[2];
@@ -235,13 +235,22 @@ poba_status poba_lm_step(poba_problem p, double* cams, double* lms, poba_lm_stat
     {
         ProfScope pr(p, POBA_K_EVAL, s);
         hipLaunchKernelGGL(k_trial, g_state, dim3(kBlock), 0, s, b, z, cams, lms, b.ctrl);
-        rc = launch_cam_prep(p, b.cams_new, &b.ctrl->active, s);
+        rc = launch_cam_prep(p, b.cams_new, &b.ctrl->active, b.cam_rec, s);
         if (rc) return rc;
         const dim3 g_tiles(unsigned(std::max<int64_t>(p->sched_len, 1)));
-        switch (p->d.precision) {
-            case POBA_F64: hipLaunchKernelGGL(k_eval<double>, g_tiles, dim3(kBlock), 0, s, b, z, p->d.loss, p->d.huber_delta, b.ctrl); break;
-            case POBA_F32: hipLaunchKernelGGL(k_eval<float>, g_tiles, dim3(kBlock), 0, s, b, z, p->d.loss, p->d.huber_delta, b.ctrl); break;
-            default: hipLaunchKernelGGL(k_eval<bf16_t>, g_tiles, dim3(kBlock), 0, s, b, z, p->d.loss, p->d.huber_delta, b.ctrl); break;
+        const int loss = p->d.loss;
+        const double delta = p->d.huber_delta;
+        if (z.point) {
+            if (p->d.precision == POBA_F64)
+                hipLaunchKernelGGL((k_eval<double, true>), g_tiles, dim3(kBlock), 0, s, b, z, loss, delta, b.ctrl);
+            else
+                hipLaunchKernelGGL((k_eval<float, true>), g_tiles, dim3(kBlock), 0, s, b, z, loss, delta, b.ctrl);
+        } else {
+            switch (p->d.precision) {
+                case POBA_F64: hipLaunchKernelGGL((k_eval<double, false>), g_tiles, dim3(kBlock), 0, s, b, z, loss, delta, b.ctrl); break;
+                case POBA_F32: hipLaunchKernelGGL((k_eval<float, false>), g_tiles, dim3(kBlock), 0, s, b, z, loss, delta, b.ctrl); break;
+                default: hipLaunchKernelGGL((k_eval<bf16_t, false>), g_tiles, dim3(kBlock), 0, s, b, z, loss, delta, b.ctrl); break;
+            }
         }
         hipLaunchKernelGGL(k_eval_final, dim3(unsigned(z.np)), dim3(kBlock), 0, s, b, b.ctrl);
     }

@@ -27,7 +27,9 @@ bool compute_sizes(const poba_desc* d, int32_t n_problems, Sizes* z) {
     if (d->damping != POBA_DAMP_MARQUARDT && d->damping != POBA_DAMP_IDENTITY) return false;
     if (d->loss != POBA_LOSS_L2 && d->loss != POBA_LOSS_HUBER) return false;
     if (d->loss == POBA_LOSS_HUBER && !(d->huber_delta > 0.0)) return false;
-    if (d->piece_size < 0 || d->reserved != 0) return false;
+    if (d->piece_size < 0) return false;
+    if (d->records != POBA_RECORDS_JACOBIAN && d->records != POBA_RECORDS_POINT) return false;
+    if (d->records == POBA_RECORDS_POINT && d->precision == POBA_F32_BF16J) return false;
     if (d->lm_ranges < 0 || (d->lm_ranges > 1 && d->lm_ranges % kXcds != 0) || d->lm_ranges > 4096) return false;
     z->nc = d->n_cams;
     z->nl = d->n_lms;
@@ -45,6 +47,8 @@ bool compute_sizes(const poba_desc* d, int32_t n_problems, Sizes* z) {
     z->npieces_max = z->N / z->piece + int64_t(z->nc) * z->ranges_max + 1;
     z->jbytes = d->precision == POBA_F64 ? 8 : (d->precision == POBA_F32 ? 4 : 2);
     z->sbytes = d->precision == POBA_F64 ? 8 : 4;
+    z->point = d->records == POBA_RECORDS_POINT ? 1 : 0;
+    z->rbytes = z->point ? 4 * z->sbytes : 24 * z->jbytes;
     return true;
 }
 
@@ -64,7 +68,7 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
         return p;
     };
     const size_t N = size_t(z.N), nc = size_t(z.nc), nl = size_t(z.nl);
-    const size_t jrec = size_t(z.npad) * 24 * z.jbytes;
+    const size_t jrec = size_t(z.npad) * size_t(z.rbytes);
     Buffers t{};
     t.perm_l = (int32_t*)take(N * 4);
     t.perm_c = (int32_t*)take(N * 4);
@@ -99,13 +103,14 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.Vinv = take(nl * 6 * z.sbytes);
     t.s = take(nl * 4 * 8);  // also holds float64 landmark vectors
     t.v = (double*)take(nc * 9 * 8);
-    t.vq = take(nc * 12 * 8);
+    t.vq = take(nc * 24 * 8);  // camera vector (stride 12), or folded camera records (stride 24)
     t.x = (double*)take(nc * 9 * 8);
     t.bt = (double*)take(nc * 9 * 8);
     t.part = (double*)take(size_t(z.npieces_max) * 54 * 8);
     t.dxl = (double*)take(nl * 3 * 8);
     t.dxp = (double*)take(nc * 9 * 8);
     t.cam_rec = (double*)take(nc * 24 * 8);
+    t.lin_rec = (double*)take(nc * 24 * 8);
     t.cams_new = (double*)take(nc * 9 * 8);
     t.lms_new = (double*)take(nl * 3 * 8);
     t.piece_red = (double*)take(size_t(z.npieces_max) * 3 * 8);
@@ -425,6 +430,9 @@ poba_status poba_batch_create(const poba_desc* d, int32_t n_problems, const int3
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
             p->n_cus = cus;
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+            p->lds_max = lds;
     }
     hipLaunchKernelGGL(k_init_ctrl, dim3(grid_for(z.np)), dim3(kBlock), 0, s, b.ctrl, b.pctl, z.np);
     const size_t np1 = size_t(z.np) + 1;

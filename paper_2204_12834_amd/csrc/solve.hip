@@ -385,7 +385,7 @@ void launch_lm_pass(Problem* p, hipStream_t s) {
 
 // Back-substitution dx_l = -V_lambda^-1 (b_l + sum_{i in l} J_l^T J_p x_c) in
 // float64 with V_lambda^-1 recomputed from the float64 V.
-template <typename TJ>
+template <typename TJ, bool PT>
 __global__ __launch_bounds__(kBlock) void k_backsub(Buffers b, Sizes z, const double* __restrict__ x,
                                                     double* __restrict__ dxl, const Ctrl* ctrl) {
     if (!ctrl->active) return;
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_backsub(Buffers b, Sizes z, const do
             v[0] = v[1] = v[2] = 0.0;
             if (!valid) return;
             double J[24];
-            load_J<TJ, double>(b.J_lo, z.npad, i, J);
+            Rec<TJ, PT>::template jac<double>(b, z, b.J_lo, i, cam, J);
             const double* vc = x + 9 * int64_t(cam);
             double q0 = 0.0, q1 = 0.0;
 #pragma unroll
@@ -515,9 +515,10 @@ __global__ __launch_bounds__(kBlock) void k_cam_pass(Buffers b, Sizes z, const T
 // problem and applies the stop rule of eq. qcriterion.
 constexpr int kFinCams = kBlock / 9;  // cameras per block (28)
 
-template <typename TS>
+template <typename TS, bool FOLD>
 __global__ __launch_bounds__(kBlock) void k_cam_fin(Buffers b, Sizes z, int mode, double* vout, const Ctrl* ctrl) {
     __shared__ double us[kFinCams][9];
+    __shared__ double vs[kFinCams][9];
     __shared__ double n2[kFinCams][9][2];
     if (ctrl->running == 0) return;
     const int lc = threadIdx.x / 9, r = threadIdx.x % 9;
@@ -550,7 +551,8 @@ __global__ __launch_bounds__(kBlock) void k_cam_fin(Buffers b, Sizes z, int mode
             const double xn = mode == kFinRhs ? v : *xc + v;
             *xc = xn;
             b.v[9 * int64_t(c) + r] = v;
-            reinterpret_cast<TS*>(b.vq)[12 * int64_t(c) + r] = TS(v);
+            if (FOLD) vs[lc][r] = v;
+            else reinterpret_cast<TS*>(b.vq)[12 * int64_t(c) + r] = TS(v);
             n2[lc][r][0] = v * v;
             n2[lc][r][1] = xn * xn;
         }
@@ -566,6 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_cam_fin(Buffers b, Sizes z, int mode
         }
         b.cam_red[2 * int64_t(c)] = sv;
         b.cam_red[2 * int64_t(c) + 1] = sx;
+        if (FOLD) fold_camera<TS>(b.lin_rec + kCamRec * int64_t(c), vs[lc], reinterpret_cast<TS*>(b.vq) + 24 * int64_t(c));
     }
 }
 
@@ -594,7 +597,10 @@ __global__ __launch_bounds__(kBlock) void k_norm_stop(Buffers b, int mode, int o
 template <typename TS>
 void launch_cam_fin(Problem* p, const Buffers& b, int mode, int order, double eps, double* vout, hipStream_t s) {
     const unsigned nblk = unsigned(ceil_div(p->z.nc, kFinCams));
-    hipLaunchKernelGGL(k_cam_fin<TS>, dim3(nblk), dim3(kBlock), 0, s, b, p->z, mode, vout, b.ctrl);
+    if (p->z.point)
+        hipLaunchKernelGGL((k_cam_fin<TS, true>), dim3(nblk), dim3(kBlock), 0, s, b, p->z, mode, vout, b.ctrl);
+    else
+        hipLaunchKernelGGL((k_cam_fin<TS, false>), dim3(nblk), dim3(kBlock), 0, s, b, p->z, mode, vout, b.ctrl);
     if (mode != kFinApply)
         hipLaunchKernelGGL(k_norm_stop, dim3(unsigned(p->z.np)), dim3(kBlock), 0, s, b, mode, order, eps, b.ctrl);
 }
@@ -624,20 +630,324 @@ __global__ __launch_bounds__(kBlock) void k_zero_f64v(double* p, int64_t n) {
     if (i < n) p[i] = 0.0;
 }
 
-// Camera vector into the gather copy (stride 12, storage type).
-template <typename TS>
+// Camera vector into the gather copy (stride 12, storage type), or folded
+// into the point-record camera data (stride 24).
+template <typename TS, bool FOLD>
 __global__ __launch_bounds__(kBlock) void k_load_v(Buffers b, Sizes z, const double* vin, const Ctrl* ctrl) {
     if (!ctrl->active) return;
     const int32_t c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= z.nc) return;
+    if (FOLD) {
+        double v[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v[k] = vin[9 * int64_t(c) + k];
+        fold_camera<TS>(b.lin_rec + kCamRec * int64_t(c), v, reinterpret_cast<TS*>(b.vq) + 24 * int64_t(c));
+        return;
+    }
     TS* vq = reinterpret_cast<TS*>(b.vq) + 12 * int64_t(c);
 #pragma unroll
     for (int k = 0; k < 9; ++k) vq[k] = TS(vin[9 * int64_t(c) + k]);
 }
 
+// ---------------------------------------------------- point-record passes --
+//
+// The same two products of P as above with the blocks rebuilt in registers
+// from the 4-scalar point records (J depends on an observation only through
+// its camera-frame point):
+//   landmark pass: J_p v = J_P (a x P + e) + p (d v_f + f n v_k1 + f n^2 v_k2)
+//                  with the camera's folded data (a, e, v_i, f, k1, k2, R),
+//                  J_l^T q = R^T J_P^T q, times the IRLS weight sw^2;
+//   camera pass:   J_l s = J_P (R s); J_p^T z = (J_l(w)^T ((P - t) x h), h,
+//                  (d, f n, f n^2) p.z) with h = J_P^T z, the rotation part
+//                  multiplied by J_l(w)^T once per piece.
+
+// Folded camera data (24 slots) of camera `cam` from LDS or global memory.
+template <typename TS, typename TC>
+__device__ __forceinline__ void load_fold(const TS* src, int64_t cam, TC* c) {
+    if constexpr (std::is_same<TS, float>::value) {
+        const float4* q = reinterpret_cast<const float4*>(src + 24 * cam);
+#pragma unroll
+        for (int g = 0; g < 6; ++g) {
+            const float4 x = q[g];
+            c[4 * g] = TC(x.x);
+            c[4 * g + 1] = TC(x.y);
+            c[4 * g + 2] = TC(x.z);
+            c[4 * g + 3] = TC(x.w);
+        }
+    } else {
+        const double2* q = reinterpret_cast<const double2*>(src + 24 * cam);
+#pragma unroll
+        for (int g = 0; g < 12; ++g) {
+            const double2 x = q[g];
+            c[2 * g] = TC(x.x);
+            c[2 * g + 1] = TC(x.y);
+        }
+    }
+}
+
+// J_l^T J_p v of one observation from its point record and folded camera data.
+template <typename TC>
+__device__ __forceinline__ void point_lm_term(const TC* P, TC sw, const TC* c, TC* v) {
+    const PointShape<TC> sh(P, c[9], c[10], c[11]);
+    TC wv[3];
+    wv[0] = c[1] * P[2] - c[2] * P[1] + c[3];
+    wv[1] = c[2] * P[0] - c[0] * P[2] + c[4];
+    wv[2] = c[0] * P[1] - c[1] * P[0] + c[5];
+    TC q0, q1;
+    sh.JP(wv, q0, q1);
+    const TC ci = sh.d * c[6] + c[9] * sh.n * (c[7] + sh.n * c[8]);
+    q0 += ci * sh.p0;
+    q1 += ci * sh.p1;
+    TC g[3];
+    sh.JPt(q0, q1, g);
+    const TC w = sw * sw;
+    // R^T g with R row-major in c[12..20]
+    v[0] = w * (c[12] * g[0] + c[15] * g[1] + c[18] * g[2]);
+    v[1] = w * (c[13] * g[0] + c[16] * g[1] + c[19] * g[2]);
+    v[2] = w * (c[14] * g[0] + c[17] * g[1] + c[20] * g[2]);
+}
+
+// Landmark pass over point records: wavefronts walk `tpw` tiles as one range
+// in chunks of 64 (two-stage pipeline as in lm_pass_range); `fold` is the
+// folded camera data, in LDS or in global memory.
+template <typename TP, typename TC, typename TS>
+__device__ __forceinline__ void lm_pass_range_pt(const Buffers& b, const Sizes& z, int64_t t0, int64_t t1,
+                                                 const TS* __restrict__ fold, TS* __restrict__ sout) {
+    const TS* __restrict__ Vinv = reinterpret_cast<const TS*>(b.Vinv);
+    const uint32_t* __restrict__ lo_cam = b.lo_cam;
+    const int lane = lane_id();
+    const int32_t start = b.tile_start[t0];
+    const int32_t end = b.tile_start[t1];
+    if (start >= end) return;
+    int32_t seg = b.seg_base[t0] - 1;
+    uint32_t w = 0u;
+    TC P[3] = {TC(0), TC(0), TC(1)}, sw = TC(0);
+    TS A[6];
+    uint64_t hm;
+    int32_t my_seg;
+    {
+        const int32_t i = start + lane;
+        if (i < end) {
+            w = lo_cam[i];
+            load_point<TP, TC>(b.J_lo, z.npad, i, P, sw);
+        }
+        hm = ballot64(w & kHeadBit);
+        my_seg = seg + __popcll(hm & mask_upto(lane));
+        if (w & kTailBit) load_vinv(Vinv, my_seg, A);
+    }
+    TC carry[3] = {TC(0), TC(0), TC(0)};
+    for (int32_t base = start; base < end; base += kWave) {
+        const int32_t i = base + lane;
+        const bool valid = i < end;
+        const int32_t ni = i + kWave;
+        uint32_t wn = 0u;
+        TC Pn[3] = {TC(0), TC(0), TC(1)}, swn = TC(0);
+        if (ni < end) {
+            wn = lo_cam[ni];
+            load_point<TP, TC>(b.J_lo, z.npad, ni, Pn, swn);
+        }
+        TC v[3] = {TC(0), TC(0), TC(0)};
+        if (valid) {
+            TC c[24];
+            load_fold(fold, int64_t(w & kIndexMask), c);
+            point_lm_term(P, sw, c, v);
+        }
+        const bool head = w & kHeadBit;
+        if (lane == 0 && !head) {
+            v[0] += carry[0];
+            v[1] += carry[1];
+            v[2] += carry[2];
+        }
+        const uint64_t hu = hm & mask_upto(lane);
+        const int seg_start = hu ? 63 - __builtin_clzll(hu) : 0;
+        segmented_scan<TC, 3>(v, lane, seg_start);
+        if (w & kTailBit) {
+            TC Ac[6], y[3];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Ac[k] = TC(A[k]);
+            sym3_apply(Ac, v, y);
+            TS ys[3] = {TS(y[0]), TS(y[1]), TS(y[2])};
+            store_s(sout, my_seg, ys);
+        }
+        const int last = min(end - base, kWave) - 1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) carry[k] = __shfl(v[k], last, kWave);
+        seg += __popcll(hm);
+        w = wn;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) P[k] = Pn[k];
+        sw = swn;
+        hm = ballot64(w & kHeadBit);
+        my_seg = seg + __popcll(hm & mask_upto(lane));
+        if (w & kTailBit) load_vinv(Vinv, my_seg, A);
+    }
+}
+
+constexpr int kPtBlock = 1024;  // persistent LDS variant: one block of 16 waves per compute unit
+
+// Folded camera data staged in LDS once per block; wavefronts take tile groups in turn.
+template <typename TP, typename TC, typename TS>
+__global__ __launch_bounds__(kPtBlock) void k_lm_pass_pt_lds(Buffers b, Sizes z, int tpw, TS* __restrict__ sout,
+                                                              const Ctrl* ctrl) {
+    extern __shared__ unsigned char lds_raw[];
+    if (ctrl->running == 0) return;
+    TS* cf = reinterpret_cast<TS*>(lds_raw);
+    const TS* __restrict__ src = reinterpret_cast<const TS*>(b.vq);
+    for (int64_t k = threadIdx.x; k < int64_t(z.nc) * 24; k += kPtBlock) cf[k] = src[k];
+    __syncthreads();
+    const int64_t ngroups = ceil_div_d(z.ntiles, tpw);
+    const int waves = kPtBlock / kWave;
+    const int64_t nwaves = int64_t(gridDim.x) * waves;
+    for (int64_t g = int64_t(blockIdx.x) * waves + threadIdx.x / kWave; g < ngroups; g += nwaves) {
+        const int64_t t0 = g * tpw;
+        const int64_t t1 = min(t0 + int64_t(tpw), z.ntiles);
+        lm_pass_range_pt<TP, TC, TS>(b, z, t0, t1, cf, sout);
+    }
+}
+
+// Folded camera data gathered from global memory (L2-resident).
+template <typename TP, typename TC, typename TS>
+__global__ __launch_bounds__(kBlock) void k_lm_pass_pt(Buffers b, Sizes z, int tpw, TS* __restrict__ sout,
+                                                       const Ctrl* ctrl) {
+    if (ctrl->running == 0) return;
+    const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t t0 = wave * tpw;
+    if (t0 >= z.ntiles) return;
+    const int64_t t1 = min(t0 + int64_t(tpw), z.ntiles);
+    lm_pass_range_pt<TP, TC, TS>(b, z, t0, t1, reinterpret_cast<const TS*>(b.vq), sout);
+}
+
+template <typename TP, typename TC, typename TS>
+void launch_lm_pass_pt(Problem* p, hipStream_t s) {
+    const Buffers& b = p->b;
+    const Sizes& z = p->z;
+    const int tpw = p->tiles_per_wave;
+    const int64_t ngroups = ceil_div(z.ntiles, tpw);
+    const size_t lds = size_t(z.nc) * 24 * sizeof(TS);
+    TS* sout = reinterpret_cast<TS*>(b.s);
+    if (p->lds_cam && lds <= size_t(p->lds_max)) {
+        const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(p->n_cus, ceil_div(ngroups, kPtBlock / kWave)));
+        hipLaunchKernelGGL((k_lm_pass_pt_lds<TP, TC, TS>), dim3(unsigned(nblk)), dim3(kPtBlock), lds, s, b, z, tpw,
+                           sout, b.ctrl);
+    } else {
+        hipLaunchKernelGGL((k_lm_pass_pt<TP, TC, TS>), dim3(unsigned(ceil_div(ngroups, kWavesPerBlock))), dim3(kBlock),
+                           0, s, b, z, tpw, sout, b.ctrl);
+    }
+}
+
+// Camera pass over point records, one block per camera piece: per
+// observation z = J_P (R s), h = J_P^T z; the piece accumulates
+// (P - t) x h, h and (d, f n, f n^2) p.z, weighted by sw^2, in float64, and
+// multiplies the first by J_l(w)^T at the end.  TC: per-observation arithmetic.
+template <typename TP, typename TSin, typename TC>
+__global__ __launch_bounds__(kBlock) void k_cam_pass_pt(Buffers b, Sizes z, const TSin* __restrict__ sin,
+                                                        const Ctrl* ctrl) {
+    __shared__ double lds[kWavesPerBlock * 9];
+    if (ctrl->running == 0) return;
+    const int32_t p = b.sched[blockIdx.x];
+    if (p < 0) return;
+    const int64_t cam = b.piece_cam[p];
+    {
+        const PCtrl& q = b.pctl[b.cam_prob[cam]];
+        if (!q.active || q.stopped) return;
+    }
+    const double* rec = b.lin_rec + kCamRec * cam;
+    TC R[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) R[k] = TC(rec[13 + k]);
+    const TC t0 = TC(rec[3]), t1 = TC(rec[4]), t2 = TC(rec[5]);
+    const TC f = TC(rec[6]), k1 = TC(rec[7]), k2 = TC(rec[8]);
+    const int32_t a = b.piece_begin[p], e = b.piece_end[p];
+    const int32_t* __restrict__ co_seg = b.co_seg;
+    double acc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+    int32_t i = a + threadIdx.x;
+    TC P[3] = {TC(0), TC(0), TC(1)}, sw = TC(0);
+    double sv[3] = {0.0, 0.0, 0.0};
+    if (i < e) {
+        const int64_t g = co_seg[i];
+        load_point<TP, TC>(b.J_co, z.npad, i, P, sw);
+        load_s3(sin, g, sv);
+    }
+    for (; i < e; i += kBlock) {
+        const int32_t ni = i + kBlock;
+        int64_t gn = 0;
+        TC Pn[3] = {TC(0), TC(0), TC(1)}, swn = TC(0);
+        if (ni < e) {
+            gn = co_seg[ni];
+            load_point<TP, TC>(b.J_co, z.npad, ni, Pn, swn);
+        }
+        const PointShape<TC> sh(P, f, k1, k2);
+        const TC s0 = TC(sv[0]), s1 = TC(sv[1]), s2 = TC(sv[2]);
+        const TC Rs[3] = {R[0] * s0 + R[1] * s1 + R[2] * s2, R[3] * s0 + R[4] * s1 + R[5] * s2,
+                          R[6] * s0 + R[7] * s1 + R[8] * s2};
+        TC z0, z1, h[3];
+        sh.JP(Rs, z0, z1);
+        sh.JPt(z0, z1, h);
+        const TC w = sw * sw;
+        const TC X0 = P[0] - t0, X1 = P[1] - t1, X2 = P[2] - t2;
+        const TC pz = sh.p0 * z0 + sh.p1 * z1;
+        acc[0] += double(w * (X1 * h[2] - X2 * h[1]));
+        acc[1] += double(w * (X2 * h[0] - X0 * h[2]));
+        acc[2] += double(w * (X0 * h[1] - X1 * h[0]));
+        acc[3] += double(w * h[0]);
+        acc[4] += double(w * h[1]);
+        acc[5] += double(w * h[2]);
+        acc[6] += double(w * sh.d * pz);
+        acc[7] += double(w * f * sh.n * pz);
+        acc[8] += double(w * f * sh.n * sh.n * pz);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) P[k] = Pn[k];
+        sw = swn;
+        if (ni < e) load_s3(sin, gn, sv);
+    }
+    block_sum<9>(acc, lds);
+    if (threadIdx.x == 0) {
+        // rotation part: J_l(w)^T times the accumulated (P - t) x h
+        const double w0 = rec[0], w1 = rec[1], w2 = rec[2], B = rec[10], E = rec[22];
+        const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
+        const double ww[3] = {w0, w1, w2};
+        const double W[3][3] = {{0.0, -w2, w1}, {w2, 0.0, -w0}, {-w1, w0, 0.0}};
+        double u[3];
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int i2 = 0; i2 < 3; ++i2) {
+                const double jl = (i2 == j ? 1.0 - E * th2 : 0.0) + B * W[i2][j] + E * ww[i2] * ww[j];
+                s += jl * acc[i2];
+            }
+            u[j] = s;
+        }
+        double* out = b.part + 9 * int64_t(p);
+        out[0] = u[0];
+        out[1] = u[1];
+        out[2] = u[2];
+#pragma unroll
+        for (int k = 3; k < 9; ++k) out[k] = acc[k];
+    }
+}
+
 // --------------------------------------------------------------- host side --
 
-template <typename TJ, typename TS, typename TCL>
+// Camera pass of one order over the handle's records.
+template <typename TJ, typename TSin, typename TCL, bool PT>
+void launch_cam_pass(Problem* p, const Buffers& b, const TSin* sin, hipStream_t s) {
+    const dim3 g(unsigned(std::max<int64_t>(p->sched_len, 1)));
+    if constexpr (PT)
+        hipLaunchKernelGGL((k_cam_pass_pt<TJ, TSin, TCL>), g, dim3(kBlock), 0, s, b, p->z, sin, b.ctrl);
+    else
+        hipLaunchKernelGGL((k_cam_pass<TJ, TSin>), g, dim3(kBlock), 0, s, b, p->z, sin, b.ctrl);
+}
+
+template <typename TJ, typename TCL, typename TS, bool PT>
+void launch_lm_pass_any(Problem* p, hipStream_t s) {
+    if constexpr (PT) launch_lm_pass_pt<TJ, TCL, TS>(p, s);
+    else launch_lm_pass<TJ, TCL, TS>(p, s);
+}
+
+// TJ: record storage (Jacobian blocks, or the point-record type when PT),
+// TS: landmark-side storage, TCL: landmark-pass arithmetic.
+template <typename TJ, typename TS, typename TCL, bool PT>
 poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx_lms, poba_solve_info* info,
                       const double* rhs_p, const double* rhs_l, hipStream_t s) {
     // a replacement right-hand side stands in for (b_p, b_l) in every kernel
@@ -670,8 +980,7 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
     if (pieces) {
         {
             ProfScope pr(p, POBA_K_CAM_PASS, s);
-            hipLaunchKernelGGL((k_cam_pass<TJ, double>), g_pieces, blk, 0, s, b, z,
-                               reinterpret_cast<const double*>(b.s), b.ctrl);
+            launch_cam_pass<TJ, double, double, PT>(p, b, reinterpret_cast<const double*>(b.s), s);
         }
         {
             ProfScope pr(p, POBA_K_CAM_FIN, s);
@@ -680,12 +989,11 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
         for (int i = 1; i <= m; ++i) {
             {
                 ProfScope pr(p, POBA_K_LM_PASS, s);
-                launch_lm_pass<TJ, TCL, TS>(p, s);
+                launch_lm_pass_any<TJ, TCL, TS, PT>(p, s);
             }
             {
                 ProfScope pr(p, POBA_K_CAM_PASS, s);
-                hipLaunchKernelGGL((k_cam_pass<TJ, TS>), g_pieces, blk, 0, s, b, z,
-                                   reinterpret_cast<const TS*>(b.s), b.ctrl);
+                launch_cam_pass<TJ, TS, TCL, PT>(p, b, reinterpret_cast<const TS*>(b.s), s);
             }
             {
                 ProfScope pr(p, POBA_K_CAM_FIN, s);
@@ -695,7 +1003,7 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
     }
     {
         ProfScope pr(p, POBA_K_BACKSUB, s);
-        hipLaunchKernelGGL(k_backsub<TJ>, g_tiles, blk, 0, s, b, z, b.x, dx_lms, b.ctrl);
+        hipLaunchKernelGGL((k_backsub<TJ, PT>), g_tiles, blk, 0, s, b, z, b.x, dx_lms, b.ctrl);
         hipLaunchKernelGGL(k_zero_empty, g_lm, blk, 0, s, b, z, dx_lms, b.ctrl);
         const int64_t nfin = std::max<int64_t>(int64_t(z.nc) * 9, z.np);
         hipLaunchKernelGGL(k_finish, dim3(unsigned(ceil_div(nfin, kBlock))), blk, 0, s, b, z, dx_cams, info, b.ctrl);
@@ -705,10 +1013,15 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
 
 poba_status launch_solve(Problem* p, int m, double eps, double* dx_cams, double* dx_lms, poba_solve_info* info,
                          hipStream_t s, const double* rhs_p, const double* rhs_l) {
+    if (p->z.point) {
+        if (p->d.precision == POBA_F64)
+            return run_solve<double, double, double, true>(p, m, eps, dx_cams, dx_lms, info, rhs_p, rhs_l, s);
+        return run_solve<float, float, float, true>(p, m, eps, dx_cams, dx_lms, info, rhs_p, rhs_l, s);
+    }
     switch (p->d.precision) {
-        case POBA_F64: return run_solve<double, double, double>(p, m, eps, dx_cams, dx_lms, info, rhs_p, rhs_l, s);
-        case POBA_F32: return run_solve<float, float, float>(p, m, eps, dx_cams, dx_lms, info, rhs_p, rhs_l, s);
-        default: return run_solve<bf16_t, float, float>(p, m, eps, dx_cams, dx_lms, info, rhs_p, rhs_l, s);
+        case POBA_F64: return run_solve<double, double, double, false>(p, m, eps, dx_cams, dx_lms, info, rhs_p, rhs_l, s);
+        case POBA_F32: return run_solve<float, float, float, false>(p, m, eps, dx_cams, dx_lms, info, rhs_p, rhs_l, s);
+        default: return run_solve<bf16_t, float, float, false>(p, m, eps, dx_cams, dx_lms, info, rhs_p, rhs_l, s);
     }
 }
 
@@ -717,20 +1030,19 @@ poba_status launch_begin_solve(Problem* p, double lam, hipStream_t s) {
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }
 
-template <typename TJ, typename TS, typename TCL>
+template <typename TJ, typename TS, typename TCL, bool PT>
 poba_status run_apply_P(Problem* p, const double* vin, double* vout, hipStream_t s) {
     const Buffers& b = p->b;
     const Sizes& z = p->z;
     const dim3 blk(kBlock);
     const dim3 g_cam(unsigned(ceil_div(z.nc, kBlock)));
     const int tpw = p->tiles_per_wave;
-    hipLaunchKernelGGL(k_load_v<TS>, g_cam, blk, 0, s, b, z, vin, b.ctrl);
+    hipLaunchKernelGGL((k_load_v<TS, PT>), g_cam, blk, 0, s, b, z, vin, b.ctrl);
     hipLaunchKernelGGL(k_zero_f64v, dim3(unsigned(ceil_div(int64_t(z.nc) * 9, kBlock))), blk, 0, s, vout,
                        int64_t(z.nc) * 9);
-    launch_lm_pass<TJ, TCL, TS>(p, s);
+    launch_lm_pass_any<TJ, TCL, TS, PT>(p, s);
     if (p->npieces > 0) {
-        hipLaunchKernelGGL((k_cam_pass<TJ, TS>), dim3(unsigned(p->sched_len)), blk, 0, s, b, z,
-                           reinterpret_cast<const TS*>(b.s), b.ctrl);
+        launch_cam_pass<TJ, TS, TCL, PT>(p, b, reinterpret_cast<const TS*>(b.s), s);
         launch_cam_fin<TS>(p, b, kFinApply, 0, 0.0, vout, s);
     }
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
@@ -758,7 +1070,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_begin_residual(Ctrl* ctrl, PCt
 }
 
 // s_l = V_lambda^-1 sum_{i in l} J_l^T J_p x_c in float64 (float64 view of s).
-template <typename TJ>
+template <typename TJ, bool PT>
 __global__ __launch_bounds__(kBlock) void k_lm_apply64(Buffers b, Sizes z, const double* __restrict__ x,
                                                        const Ctrl* ctrl) {
     if (!ctrl->active) return;
@@ -770,7 +1082,7 @@ __global__ __launch_bounds__(kBlock) void k_lm_apply64(Buffers b, Sizes z, const
             v[0] = v[1] = v[2] = 0.0;
             if (!valid) return;
             double J[24];
-            load_J<TJ, double>(b.J_lo, z.npad, i, J);
+            Rec<TJ, PT>::template jac<double>(b, z, b.J_lo, i, cam, J);
             const double* vc = x + 9 * int64_t(cam);
             double q0 = 0.0, q1 = 0.0;
 #pragma unroll
@@ -848,28 +1160,40 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(Buffers b, double* out
     if (threadIdx.x == 0) out[blockIdx.x] = tot[1] > 0.0 ? sqrt(tot[0]) / sqrt(tot[1]) : 0.0;
 }
 
-template <typename TJ>
+template <typename TJ, bool PT>
 poba_status run_residual(Problem* p, const double* x, double* out, hipStream_t s) {
     const Buffers& b = p->b;
     const Sizes& z = p->z;
     hipLaunchKernelGGL(k_begin_residual, dim3(1), dim3(kReduceBlock), 0, s, b.ctrl, b.pctl, z.np);
-    hipLaunchKernelGGL(k_lm_apply64<TJ>, dim3(unsigned(ceil_div(z.ntiles, kWavesPerBlock))), dim3(kBlock), 0, s, b,
-                       z, x, b.ctrl);
-    if (p->npieces > 0)
-        hipLaunchKernelGGL((k_cam_pass<TJ, double>), dim3(unsigned(p->sched_len)), dim3(kBlock), 0, s, b, z,
-                           reinterpret_cast<const double*>(b.s), b.ctrl);
+    hipLaunchKernelGGL((k_lm_apply64<TJ, PT>), dim3(unsigned(ceil_div(z.ntiles, kWavesPerBlock))), dim3(kBlock), 0,
+                       s, b, z, x, b.ctrl);
+    if (p->npieces > 0) launch_cam_pass<TJ, double, double, PT>(p, b, reinterpret_cast<const double*>(b.s), s);
     hipLaunchKernelGGL(k_residual_cam, dim3(unsigned(ceil_div(z.nc, kBlock))), dim3(kBlock), 0, s, b, z, x, b.ctrl);
     hipLaunchKernelGGL(k_residual_norm, dim3(unsigned(z.np)), dim3(kBlock), 0, s, b, out, b.ctrl);
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }
 
-// Widens the stored records of one order to float64 in original order.
-template <typename TJ>
+// Widens the blocks of one order (stored, or rebuilt from point records) to
+// float64 in original observation order.
+template <typename TJ, bool PT>
 __global__ __launch_bounds__(kBlock) void k_get_jac(Buffers b, Sizes z, int order, double* Jp, double* Jl, double* r) {
     const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
     if (i >= z.N) return;
+    int64_t cam = 0;
+    if (PT) {
+        if (order == 0) {
+            cam = b.lo_cam[i] & kIndexMask;
+        } else {  // camera of a camera-major position: last cam_off[c] <= i
+            int32_t lo = 0, hi = z.nc - 1;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (b.cam_off[mid] <= i) lo = mid; else hi = mid - 1;
+            }
+            cam = lo;
+        }
+    }
     double J[24];
-    load_J<TJ, double>(order == 0 ? b.J_lo : b.J_co, z.npad, i, J);
+    Rec<TJ, PT>::template jac<double>(b, z, order == 0 ? b.J_lo : b.J_co, i, cam, J);
     const int64_t o = order == 0 ? b.perm_l[i] : b.perm_c[i];
 #pragma unroll
     for (int k = 0; k < 18; ++k) Jp[18 * o + k] = J[k];
@@ -918,10 +1242,14 @@ poba_status poba_solve_residual(poba_problem p, const double* dx_cams, double* r
     (void)hipGetLastError();  // report only this call's launch errors
     if (!p || !dx_cams || !rel_residual) return POBA_ERR_INVALID_ARG;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (p->z.point) {
+        if (p->d.precision == POBA_F64) return run_residual<double, true>(p, dx_cams, rel_residual, s);
+        return run_residual<float, true>(p, dx_cams, rel_residual, s);
+    }
     switch (p->d.precision) {
-        case POBA_F64: return run_residual<double>(p, dx_cams, rel_residual, s);
-        case POBA_F32: return run_residual<float>(p, dx_cams, rel_residual, s);
-        default: return run_residual<bf16_t>(p, dx_cams, rel_residual, s);
+        case POBA_F64: return run_residual<double, false>(p, dx_cams, rel_residual, s);
+        case POBA_F32: return run_residual<float, false>(p, dx_cams, rel_residual, s);
+        default: return run_residual<bf16_t, false>(p, dx_cams, rel_residual, s);
     }
 }
 
@@ -932,10 +1260,14 @@ poba_status poba_apply_P(poba_problem p, const double* v_in, double* v_out, poba
     hipLaunchKernelGGL(k_begin_solve, dim3(1), dim3(kReduceBlock), 0, s, p->b.ctrl, p->b.pctl, p->z.np, 0.0);
     // k_begin_solve overwrote lambda; the inverses of the last solve are kept,
     // and apply-P does not read lambda.
+    if (p->z.point) {
+        if (p->d.precision == POBA_F64) return run_apply_P<double, double, double, true>(p, v_in, v_out, s);
+        return run_apply_P<float, float, float, true>(p, v_in, v_out, s);
+    }
     switch (p->d.precision) {
-        case POBA_F64: return run_apply_P<double, double, double>(p, v_in, v_out, s);
-        case POBA_F32: return run_apply_P<float, float, float>(p, v_in, v_out, s);
-        default: return run_apply_P<bf16_t, float, float>(p, v_in, v_out, s);
+        case POBA_F64: return run_apply_P<double, double, double, false>(p, v_in, v_out, s);
+        case POBA_F32: return run_apply_P<float, float, float, false>(p, v_in, v_out, s);
+        default: return run_apply_P<bf16_t, float, float, false>(p, v_in, v_out, s);
     }
 }
 
@@ -945,10 +1277,17 @@ poba_status poba_get_jacobians(poba_problem p, int32_t order, double* Jp, double
     if (p->z.N == 0) return POBA_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const dim3 g(unsigned(ceil_div(p->z.N, kBlock)));
+    if (p->z.point) {
+        if (p->d.precision == POBA_F64)
+            hipLaunchKernelGGL((k_get_jac<double, true>), g, dim3(kBlock), 0, s, p->b, p->z, order, Jp, Jl, r);
+        else
+            hipLaunchKernelGGL((k_get_jac<float, true>), g, dim3(kBlock), 0, s, p->b, p->z, order, Jp, Jl, r);
+        return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
+    }
     switch (p->d.precision) {
-        case POBA_F64: hipLaunchKernelGGL(k_get_jac<double>, g, dim3(kBlock), 0, s, p->b, p->z, order, Jp, Jl, r); break;
-        case POBA_F32: hipLaunchKernelGGL(k_get_jac<float>, g, dim3(kBlock), 0, s, p->b, p->z, order, Jp, Jl, r); break;
-        default: hipLaunchKernelGGL(k_get_jac<bf16_t>, g, dim3(kBlock), 0, s, p->b, p->z, order, Jp, Jl, r); break;
+        case POBA_F64: hipLaunchKernelGGL((k_get_jac<double, false>), g, dim3(kBlock), 0, s, p->b, p->z, order, Jp, Jl, r); break;
+        case POBA_F32: hipLaunchKernelGGL((k_get_jac<float, false>), g, dim3(kBlock), 0, s, p->b, p->z, order, Jp, Jl, r); break;
+        default: hipLaunchKernelGGL((k_get_jac<bf16_t, false>), g, dim3(kBlock), 0, s, p->b, p->z, order, Jp, Jl, r); break;
     }
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }

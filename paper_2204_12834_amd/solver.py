@@ -81,10 +81,10 @@ def read_lm_states(t: torch.Tensor) -> list:
 
 
 def workspace_bytes(n_cams, n_lms, n_obs, precision="f64", damping="marquardt", loss="l2", huber_delta=0.0,
-                    piece_size=0) -> int:
+                    piece_size=0, records="jacobian") -> int:
     lib = _lib.load()
     d = _lib.PobaDesc(int(n_cams), int(n_lms), int(n_obs), _lib.PRECISION[precision], _lib.DAMPING[damping],
-                      _lib.LOSS[loss], int(piece_size), 0, 0, float(huber_delta))
+                      _lib.LOSS[loss], int(piece_size), 0, _lib.RECORDS[records], float(huber_delta))
     return int(lib.poba_workspace_bytes(ctypes.byref(d)))
 
 
@@ -96,7 +96,8 @@ class Problem:
 
     def __init__(self, obs_cam, obs_lm, obs_xy, n_cams: int, n_lms: int, precision: str = "f64",
                  damping: str = "marquardt", loss: str = "l2", huber_delta: float = 0.0, piece_size: int = 0,
-                 lm_ranges: int = 0, device="cuda", stream=None, prob_cam_off=None, prob_lm_off=None):
+                 lm_ranges: int = 0, device="cuda", stream=None, prob_cam_off=None, prob_lm_off=None,
+                 records: str = "jacobian"):
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.precision = precision
@@ -106,8 +107,9 @@ class Problem:
         self.n_obs = int(obs_cam.numel())
         obs_xy = _dev(obs_xy, torch.float64, self.device, (self.n_obs, 2))
         self.desc = _lib.PobaDesc(self.n_cams, self.n_lms, self.n_obs, _lib.PRECISION[precision],
-                                  _lib.DAMPING[damping], _lib.LOSS[loss], int(piece_size), int(lm_ranges), 0,
-                                  float(huber_delta))
+                                  _lib.DAMPING[damping], _lib.LOSS[loss], int(piece_size), int(lm_ranges),
+                                  _lib.RECORDS[records], float(huber_delta))
+        self.records = records
         if prob_cam_off is None:
             prob_cam_off, prob_lm_off = [0, self.n_cams], [0, self.n_lms]
         self.prob_cam_off = [int(v) for v in prob_cam_off]

@@ -33,14 +33,14 @@ class Case:
         s = self.scene
         return schur.solve(self.Jp, self.Jl, self.r, s.obs_cam, s.obs_lm, s.n_cams, s.n_lms, lam, m, eps, damping)
 
-    def problem(self, precision="f64", damping="marquardt", piece_size=0, lm_ranges=0):
+    def problem(self, precision="f64", damping="marquardt", piece_size=0, lm_ranges=0, records="jacobian"):
         import torch
         from paper_2204_12834_amd.solver import Problem
         s = self.scene
         loss = "huber" if self.delta else "l2"
         return Problem(s.obs_cam, s.obs_lm, self.obs, s.n_cams, s.n_lms, precision=precision, damping=damping,
                        loss=loss, huber_delta=self.delta or 0.0, piece_size=piece_size, lm_ranges=lm_ranges,
-                       device="cuda")
+                       device="cuda", records=records)
 
     def state(self):
         import torch

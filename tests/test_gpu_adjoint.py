@@ -34,9 +34,10 @@ def c1_adjoint():
     return s, obs, gp, gl, dense, series
 
 
-def _gpu_adjoint(s, obs, gp, gl, precision, lam=LAM, m=M):
+def _gpu_adjoint(s, obs, gp, gl, precision, lam=LAM, m=M, records="jacobian"):
     from paper_2204_12834_amd.solver import Problem
-    prob = Problem(s.obs_cam, s.obs_lm, obs, s.n_cams, s.n_lms, precision=precision, device="cuda")
+    prob = Problem(s.obs_cam, s.obs_lm, obs, s.n_cams, s.n_lms, precision=precision, device="cuda",
+                   records=records)
     cams = torch.tensor(s.cams0, dtype=torch.float64, device="cuda")
     lms = torch.tensor(s.lms0, dtype=torch.float64, device="cuda")
     prob.linearize(cams, lms)
@@ -46,10 +47,11 @@ def _gpu_adjoint(s, obs, gp, gl, precision, lam=LAM, m=M):
     return prob, dxc, dxl, go, gi, zc, zl
 
 
-def test_adjoint_f64_matches_oracle():
+@pytest.mark.parametrize("records", ["jacobian", "point"])
+def test_adjoint_f64_matches_oracle(records):
     s, obs, gp, gl, dense, series = c1_adjoint()
-    log("adjoint f64 c1")
-    _, dxc, dxl, go, gi, zc, zl = _gpu_adjoint(s, obs, gp, gl, "f64")
+    log(f"adjoint f64 c1 {records}")
+    _, dxc, dxl, go, gi, zc, zl = _gpu_adjoint(s, obs, gp, gl, "f64", records=records)
     assert rel(np_(dxc), series.dxp) <= 1e-10 and rel(np_(dxl), series.dxl) <= 1e-10
     assert rel(np_(zc), series.zp) <= 1e-10 and rel(np_(zl), series.zl) <= 1e-10
     assert rel(np_(go), series.grad_obs) <= 1e-9
@@ -59,10 +61,10 @@ def test_adjoint_f64_matches_oracle():
     assert rel(np_(gi), dense.grad_intr) <= 1e-8
 
 
-@pytest.mark.parametrize("precision", ["f32", "bf16"])
-def test_adjoint_reduced_precision(precision):
+@pytest.mark.parametrize("precision,records", [("f32", "jacobian"), ("bf16", "jacobian"), ("f32", "point")])
+def test_adjoint_reduced_precision(precision, records):
     s, obs, gp, gl, dense, series = c1_adjoint()
-    _, _, _, go, gi, _, _ = _gpu_adjoint(s, obs, gp, gl, precision)
+    _, _, _, go, gi, _, _ = _gpu_adjoint(s, obs, gp, gl, precision, records=records)
     eo = rel(np_(go), dense.grad_obs)
     ei = rel(np_(gi), dense.grad_intr)
     log(f"adjoint {precision}: obs {eo:.2e} intrinsics {ei:.2e}")

@@ -24,11 +24,11 @@ def batch():
     return scenes, cat, co, lo, np.concatenate(obs)
 
 
-def _problem(precision="f64", lm_ranges=0, piece_size=0):
+def _problem(precision="f64", lm_ranges=0, piece_size=0, records="jacobian"):
     from paper_2204_12834_amd.solver import Problem
     scenes, cat, co, lo, obs = batch()
     return Problem(cat.obs_cam, cat.obs_lm, obs, cat.n_cams, cat.n_lms, precision=precision, device="cuda",
-                   prob_cam_off=co, prob_lm_off=lo, lm_ranges=lm_ranges, piece_size=piece_size)
+                   prob_cam_off=co, prob_lm_off=lo, lm_ranges=lm_ranges, piece_size=piece_size, records=records)
 
 
 def _state():
@@ -36,11 +36,14 @@ def _state():
     return (torch.tensor(cat.cams0, device="cuda"), torch.tensor(cat.lms0, device="cuda"))
 
 
-@pytest.mark.parametrize("precision,tol,ranges,piece", [("f64", 1e-10, 0, 0), ("f64", 1e-10, 8, 64),
-                                                       ("f32", 1e-4, 0, 0)])
-def test_batched_solve_matches_each_problem(precision, tol, ranges, piece):
+@pytest.mark.parametrize("precision,tol,ranges,piece,records", [("f64", 1e-10, 0, 0, "jacobian"),
+                                                               ("f64", 1e-10, 8, 64, "jacobian"),
+                                                               ("f32", 1e-4, 0, 0, "jacobian"),
+                                                               ("f64", 1e-10, 8, 64, "point"),
+                                                               ("f32", 1e-4, 0, 0, "point")])
+def test_batched_solve_matches_each_problem(precision, tol, ranges, piece, records):
     scenes, cat, co, lo, obs = batch()
-    prob = _problem(precision, ranges, piece)
+    prob = _problem(precision, ranges, piece, records)
     cams, lms = _state()
     cost = np_(prob.linearize(cams, lms))
     lam, m = 1e-2, 20

@@ -34,12 +34,13 @@ def _ragged_scene():
 
 
 @pytest.mark.parametrize("piece,ranges", [(0, 0), (64, 0), (100, 0), (64, 8)])
-@pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_ragged_segments_and_empty_entities(piece, ranges, precision):
-    log(f"ragged piece={piece} ranges={ranges} {precision}")
+@pytest.mark.parametrize("precision,records", [("f64", "jacobian"), ("f32", "jacobian"), ("f64", "point"),
+                                               ("f32", "point")])
+def test_ragged_segments_and_empty_entities(piece, ranges, precision, records):
+    log(f"ragged piece={piece} ranges={ranges} {precision} {records}")
     case = Case(_ragged_scene())
     s = case.scene
-    prob = case.problem(precision, piece_size=piece, lm_ranges=ranges)
+    prob = case.problem(precision, piece_size=piece, lm_ranges=ranges, records=records)
     cams, lms = case.state()
     cost = prob.linearize(cams, lms)
     assert abs(cost.item() - case.F) <= 1e-12 * case.F

@@ -12,9 +12,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def _run_gpu(case, precision, opts, iters):
+def _run_gpu(case, precision, opts, iters, records="jacobian"):
     from paper_2204_12834_amd.solver import LMOptions, read_lm_state
-    prob = case.problem(precision)
+    prob = case.problem(precision, records=records)
     cams, lms = case.state()
     o = LMOptions(lambda0=opts.lambda0, func_tol=opts.func_tol, eps=opts.eps, eta=opts.eta, m=opts.m,
                   max_iters=opts.max_iters)
@@ -29,8 +29,9 @@ def _run_gpu(case, precision, opts, iters):
 
 
 @pytest.mark.parametrize("name", ["c1", "city_small"])
-def test_lm_trajectory_f64(name):
-    log(f"lm trajectory {name}")
+@pytest.mark.parametrize("records", ["jacobian", "point"])
+def test_lm_trajectory_f64(name, records):
+    log(f"lm trajectory {name} {records}")
     if name == "c1":
         case = Case(synth.config("c1"))
     else:
@@ -38,7 +39,7 @@ def test_lm_trajectory_f64(name):
     s = case.scene
     opts = olm.LMOptions(max_iters=10, m=20, eps=0.0, huber_delta=case.delta)
     ref = olm.lm(s.cams0, s.lms0, s.obs_cam, s.obs_lm, case.obs, opts)
-    trace, cams, lms = _run_gpu(case, "f64", opts, 10)
+    trace, cams, lms = _run_gpu(case, "f64", opts, 10, records)
     assert len(trace) == len(ref.iterations)
     for g, o in zip(trace, ref.iterations):
         assert abs(g["cost"] - (o.cost_new if o.accepted else o.cost)) <= 1e-9 * o.cost
@@ -50,13 +51,14 @@ def test_lm_trajectory_f64(name):
     assert trace[-1]["converged"] == int(ref.converged)
 
 
-def test_lm_f32_reaches_f64_optimum():
+@pytest.mark.parametrize("records", ["jacobian", "point"])
+def test_lm_f32_reaches_f64_optimum(records):
     case = Case(synth.config("c1"))
     s = case.scene
     opts = olm.LMOptions(max_iters=50)
     ref = olm.lm(s.cams0, s.lms0, s.obs_cam, s.obs_lm, case.obs, opts)
     f_ref = min(it.cost_new for it in ref.iterations if it.accepted)
-    trace, _, _ = _run_gpu(case, "f32", opts, 50)
+    trace, _, _ = _run_gpu(case, "f32", opts, 50, records)
     f32 = min(t["cost"] for t in trace)
     log(f"f32 final {f32} vs f64 oracle {f_ref}")
     assert abs(f32 - f_ref) <= 1e-6 * f_ref

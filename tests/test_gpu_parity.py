@@ -2,7 +2,9 @@
 
 Tolerances: float64 solves <= 1e-10 relative (2-norm, camera and landmark
 steps separately, fixed order, eps = 0); float32 <= 1e-4; Jacobian blocks and
-cost <= 1e-12 in float64; integer orders and offsets bit-exact."""
+cost <= 1e-12 in float64; integer orders and offsets bit-exact.  Both record
+kinds are covered: stored Jacobian blocks and point records (P, sqrt(w)) from
+which every pass rebuilds the blocks."""
 import functools
 
 import numpy as np
@@ -95,12 +97,13 @@ def test_power_solve_with_landmark_ranges(name, ranges, precision, tol):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("precision", ["f64", "f32", "bf16"])
-def test_linearize_matches_oracle(name, precision):
-    log(f"linearize {name} {precision}")
+@pytest.mark.parametrize("precision,records", [("f64", "jacobian"), ("f32", "jacobian"), ("bf16", "jacobian"),
+                                               ("f64", "point"), ("f32", "point")])
+def test_linearize_matches_oracle(name, precision, records):
+    log(f"linearize {name} {precision} {records}")
     case = CASES[name]()
     s = case.scene
-    prob = case.problem(precision)
+    prob = case.problem(precision, records=records)
     cams, lms = case.state()
     cost = prob.linearize(cams, lms)
     Jp0, Jl0, r0 = (np_(t) for t in prob.get_jacobians(0))
@@ -109,8 +112,11 @@ def test_linearize_matches_oracle(name, precision):
     np.testing.assert_array_equal(Jp0, Jp1)
     np.testing.assert_array_equal(Jl0, Jl1)
     assert abs(cost.item() - case.F) <= 1e-12 * case.F
-    assert rel(r0, case.r) < 1e-13
+    # point records keep sqrt(w) in the record precision, which scales r
+    assert rel(r0, case.r) < (1e-7 if (records, precision) == ("point", "f32") else 1e-13)
     tol = {"f64": 1e-12, "f32": 1e-6, "bf16": 1e-2}[precision]
+    if (records, precision) == ("point", "f32"):
+        tol = 1e-5  # blocks rebuilt from a float32 point: the projection amplifies its rounding
     ep = np.linalg.norm(Jp0 - case.Jp, axis=(1, 2)) / np.linalg.norm(case.Jp, axis=(1, 2))
     el = np.linalg.norm(Jl0 - case.Jl, axis=(1, 2)) / np.linalg.norm(case.Jl, axis=(1, 2))
     assert ep.max() < tol and el.max() < tol, (ep.max(), el.max())
@@ -151,27 +157,43 @@ def test_power_solve_damping_modes(damping):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("precision,tol", [("f32", 1e-4), ("bf16", 0.2)])
-def test_power_solve_reduced_precision(name, precision, tol):
+@pytest.mark.parametrize("lam", [1e-4, 1.0])
+@pytest.mark.parametrize("m", [0, 20])
+def test_power_solve_f64_point_records(name, lam, m):
+    case = CASES[name]()
+    prob = case.problem("f64", records="point")
+    cams, lms = case.state()
+    prob.linearize(cams, lms)
+    dxp, dxl, info = prob.power_solve(lam, m, 0.0)
+    ref = case.solve(lam, m)
+    assert rel(np_(dxp), ref.dxp) <= 1e-10
+    assert rel(np_(dxl), ref.dxl) <= 1e-10
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("precision,records,tol", [("f32", "jacobian", 1e-4), ("bf16", "jacobian", 0.2),
+                                                   ("f32", "point", 1e-4)])
+def test_power_solve_reduced_precision(name, precision, records, tol):
     """float32 storage must stay within 1e-4 of the float64 oracle; bfloat16
     Jacobian storage is an experiment and only checked loosely (the error is
     reported by the benchmark)."""
     case = CASES[name]()
-    prob = case.problem(precision)
+    prob = case.problem(precision, records=records)
     cams, lms = case.state()
     prob.linearize(cams, lms)
     for lam in [1e-4, 1e-2]:
         dxp, dxl, _ = prob.power_solve(lam, 20, 0.0)
         ref = case.solve(lam, 20)
         ep, el = rel(np_(dxp), ref.dxp), rel(np_(dxl), ref.dxl)
-        log(f"{precision} {name} lam={lam}: dx_p {ep:.2e} dx_l {el:.2e}")
+        log(f"{precision} {records} {name} lam={lam}: dx_p {ep:.2e} dx_l {el:.2e}")
         assert ep <= tol and el <= tol
 
 
-def test_apply_P_matches_oracle():
+@pytest.mark.parametrize("records", ["jacobian", "point"])
+def test_apply_P_matches_oracle(records):
     case = c1()
     s = case.scene
-    prob = case.problem("f64")
+    prob = case.problem("f64", records=records)
     cams, lms = case.state()
     prob.linearize(cams, lms)
     prob.power_solve(1e-2, 0, 0.0)  # forms the damped inverses
@@ -204,9 +226,10 @@ def test_stop_rule_matches_oracle():
         assert rel(np_(dxp), ref.dxp) <= 1e-10
 
 
-def test_bitwise_determinism():
+@pytest.mark.parametrize("records", ["jacobian", "point"])
+def test_bitwise_determinism(records):
     case = city_small()
-    prob = case.problem("f32")
+    prob = case.problem("f32", records=records)
     cams, lms = case.state()
     outs = []
     for _ in range(2):
@@ -217,13 +240,14 @@ def test_bitwise_determinism():
 
 
 @pytest.mark.parametrize("name", ["c1", "city_small"])
-@pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_solve_residual_matches_oracle(name, precision):
+@pytest.mark.parametrize("precision,records", [("f64", "jacobian"), ("f32", "jacobian"), ("f64", "point"),
+                                               ("f32", "point")])
+def test_solve_residual_matches_oracle(name, precision, records):
     """|S x + b~| / |b~| on the GPU against the oracle's matrix-free residual
     of the same step, built from the stored (rounded) Jacobian blocks."""
     case = CASES[name]()
     s = case.scene
-    prob = case.problem(precision)
+    prob = case.problem(precision, records=records)
     cams, lms = case.state()
     prob.linearize(cams, lms)
     Jp, Jl, r = (np_(t) for t in prob.get_jacobians(0))
