@@ -43,14 +43,16 @@ KERNEL_SOURCES = ["paper_2204_12834_amd/csrc/solve.hip", "paper_2204_12834_amd/c
                   "paper_2204_12834_amd/csrc/common.hpp"]
 
 
-def series_bytes(n_obs, n_lms, prec):
+def series_bytes(n_obs, n_lms, prec, records="jacobian"):
     """Algorithmic bytes of one series order, per pass (dual-order design):
-    landmark pass reads each Jacobian record and camera index once and each
+    landmark pass reads each observation record and camera index once and each
     V^-1 once, writes s; camera pass reads each record, landmark index and the
-    gathered s once per observation."""
+    gathered s once per observation.  A record is the 24 Jacobian scalars, or
+    the 4 scalars (P, sqrt(w)) of a point record."""
     sj, sx = SJ[prec], SX[prec]
-    lm = n_obs * (24 * sj + 4) + n_lms * (6 * sx + 3 * sx)
-    cam = n_obs * (24 * sj + 4 + 3 * sx)
+    rec = 24 * sj if records == "jacobian" else 4 * sx
+    lm = n_obs * (rec + 4) + n_lms * (6 * sx + 3 * sx)
+    cam = n_obs * (rec + 4 + 3 * sx)
     return lm, cam
 
 
@@ -123,13 +125,13 @@ def run_cpu_baseline(workload, m, sample_lms):
 
 # --------------------------------------------------------------- GPU leg ----
 
-def gpu_setup(scene, delta, precision, dev):
+def gpu_setup(scene, delta, precision, dev, records="jacobian"):
     import torch
     from paper_2204_12834_amd.solver import Problem, project
     obs = project(scene.obs_cam, scene.obs_lm, scene.cams_gt, scene.lms_gt, device=dev)
     obs += torch.as_tensor(scene.noise, device=dev)
     prob = Problem(scene.obs_cam, scene.obs_lm, obs, scene.n_cams, scene.n_lms, precision=precision,
-                   loss="huber" if delta else "l2", huber_delta=delta or 0.0, device=dev)
+                   loss="huber" if delta else "l2", huber_delta=delta or 0.0, device=dev, records=records)
     cams0 = torch.as_tensor(scene.cams0, dtype=torch.float64, device=dev)
     lms0 = torch.as_tensor(scene.lms0, dtype=torch.float64, device=dev)
     return prob, cams0, lms0, obs
@@ -395,6 +397,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--precision", default="f32", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--records", default="jacobian", choices=["jacobian", "point"],
+                    help="per-observation records: Jacobian blocks, or camera-frame points the passes rebuild them from")
     ap.add_argument("--m", type=int, default=32)
     ap.add_argument("--sample-lms", type=int, default=600000,
                     help="landmarks of the scene the CPU oracle's series runs on (about 10-20 s of CPU work)")
@@ -429,7 +433,7 @@ def main():
     print(f"[bench] scene {scene.name}: {scene.n_cams} cams, {scene.n_lms} lms, {scene.n_obs} obs "
           f"({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
 
-    prob, cams0, lms0, obs = gpu_setup(scene, delta, args.precision, dev)
+    prob, cams0, lms0, obs = gpu_setup(scene, delta, args.precision, dev, args.records)
     if args.tpw:
         prob.set_tuning("tiles_per_wave", args.tpw)
     cams, lms = cams0.clone(), lms0.clone()
@@ -477,7 +481,7 @@ def main():
           file=sys.stderr, flush=True)
 
     N, nl, nc = scene.n_obs, scene.n_lms, scene.n_cams
-    lmb, camb = series_bytes(N, nl, args.precision)
+    lmb, camb = series_bytes(N, nl, args.precision, args.records)
     k = args.steps
     t_lm = prof["landmark_pass"][0] / 1e3
     t_cam = prof["camera_pass"][0] / 1e3
@@ -499,7 +503,7 @@ def main():
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
-        key = f"{args.workload}_{args.precision}_{dom}"
+        key = f"{args.workload}_{args.precision}_{dom}" + ("" if args.records == "jacobian" else "_point")
         if tr.get("source_hash") == kernel_source_hash() and key in tr.get("bytes_per_launch", {}):
             traffic = tr["bytes_per_launch"][key]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -517,7 +521,7 @@ def main():
         runs = {}
         steps_at_x0 = {}
         for prec in ["f64", "f32", "bf16"]:
-            p2, c0, l0, _ = gpu_setup(scene, delta, prec, dev)
+            p2, c0, l0, _ = gpu_setup(scene, delta, prec, dev, "jacobian" if prec == "bf16" else args.records)
             # the damped step at x0 (lambda0, fixed order) for the precision comparison
             p2.linearize(c0, l0)
             dxc, dxl, _ = p2.power_solve(1e-4, args.m, 0.0)
@@ -568,8 +572,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{scene.name}: {nc} cameras, {nl} landmarks, {N} observations, "
                                f"{'Huber delta 3 px, 2% outliers, ' if delta else ''}m={args.m}, "
-                               f"{args.precision} Jacobian storage, one LM iteration per step",
-                   "n_cams": nc, "n_lms": nl, "n_obs": N, "m": args.m, "precision": args.precision},
+                               f"{args.precision} {'Jacobian blocks' if args.records == 'jacobian' else 'point records'}"
+                               f", one LM iteration per step",
+                   "n_cams": nc, "n_lms": nl, "n_obs": N, "m": args.m, "precision": args.precision,
+                   "records": args.records},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phase_ms_per_step": phases,

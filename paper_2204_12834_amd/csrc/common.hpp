@@ -218,17 +218,63 @@ __device__ __forceinline__ uint64_t mask_upto(int lane) {
     return lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
 }
 
+// Lane exchange through the DPP crossbar (no LDS): a 32-bit word of another
+// lane chosen by the DPP control; rows outside row_mask keep `old`.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf,
+                                                                  false));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(u)), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(u >> 32)), CTRL, ROW_MASK, 0xf, false);
+    return __builtin_bit_cast(double, (uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
+}
+template <int CTRL, int ROW_MASK, typename T>
+__device__ __forceinline__ T dpp(T v) {
+    if constexpr (sizeof(T) == 8) return dpp_f64<CTRL, ROW_MASK>(v);
+    else return dpp_f32<CTRL, ROW_MASK>(v);
+}
+
 // Inclusive segmented scan over the wave.  seg_start is the first lane of the
 // calling lane's segment; after the call v[k] holds the sum of v[k] over
-// lanes seg_start..lane.
+// lanes seg_start..lane.  Within each row of 16 lanes the scan shifts by 1,
+// 2, 4, 8 (DPP row_shr); the rows are then joined by broadcasting the last
+// lane of row 0 into row 1 and of row 2 into row 3 (row_bcast:15), and of
+// row 1 into rows 2 and 3 (row_bcast:31), each taken only by lanes whose
+// segment reaches back past that lane.
 template <typename T, int K>
 __device__ __forceinline__ void segmented_scan(T* v, int lane, int seg_start) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const bool take = lane - d >= seg_start;
+    const int rl = lane & 15;
+#define POBA_ROW_STEP(D)                                                   \
+    {                                                                      \
+        const bool take = rl >= D && lane - D >= seg_start;                \
+        _Pragma("unroll") for (int k = 0; k < K; ++k) {                    \
+            const T y = dpp<0x110 | D, 0xf>(v[k]);                         \
+            if (take) v[k] += y;                                           \
+        }                                                                  \
+    }
+    POBA_ROW_STEP(1)
+    POBA_ROW_STEP(2)
+    POBA_ROW_STEP(4)
+    POBA_ROW_STEP(8)
+#undef POBA_ROW_STEP
+    const int row = lane >> 4;
+    {
+        const bool take = (row == 1 && seg_start <= 15) || (row == 3 && seg_start <= 47);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            T y = __shfl_up(v[k], d, kWave);
+            const T y = dpp<0x142, 0xa>(v[k]);
+            if (take) v[k] += y;
+        }
+    }
+    {
+        const bool take = row >= 2 && seg_start <= 31;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const T y = dpp<0x143, 0xc>(v[k]);
             if (take) v[k] += y;
         }
     }
@@ -278,6 +324,12 @@ struct PCtrl {
     int32_t pad;
 };
 
+// One camera-pass work item as a block reads it in a single request: the
+// piece (-1: idle slot), its camera-major range, camera and problem.
+struct alignas(32) PieceRec {
+    int32_t p, begin, end, cam, prob, pad0, pad1, pad2;
+};
+
 // ---------------------------------------------------------------- handle --
 
 struct Buffers {
@@ -300,6 +352,7 @@ struct Buffers {
     int32_t* grp_off;     // [nc*R+1] camera-major offsets of the (camera, range) groups
     int32_t* grp_piece;   // [nc*R+1] first piece of each group
     int32_t* sched;       // [kXcds*npieces_max] camera-pass block -> piece (-1: idle)
+    PieceRec* sched_rec;  // [kXcds*npieces_max] the same slots with their piece data
     double* obs_lo;       // [N][2] observations, landmark-major
     double* obs_co;       // [N][2] observations, camera-major
     // linearisation

@@ -88,6 +88,7 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.grp_off = (int32_t*)take((nc * size_t(z.ranges_max) + 1) * 4);
     t.grp_piece = (int32_t*)take((nc * size_t(z.ranges_max) + 1) * 4);
     t.sched = (int32_t*)take(size_t(kXcds) * size_t(z.npieces_max) * 4);
+    t.sched_rec = (PieceRec*)take(size_t(kXcds) * size_t(z.npieces_max) * sizeof(PieceRec));
     t.obs_lo = (double*)take(N * 16);
     t.obs_co = (double*)take(N * 16);
     t.J_lo = take(jrec);
@@ -163,6 +164,23 @@ __global__ void k_fill_prob(const int32_t* off, int32_t np, int32_t n, int32_t* 
         if (off[mid] <= i) lo = mid; else hi = mid - 1;
     }
     prob[i] = lo;
+}
+
+// Piece data of every schedule slot.
+__global__ void k_sched_rec(const int32_t* sched, const int32_t* piece_begin, const int32_t* piece_end,
+                            const int32_t* piece_cam, const int32_t* cam_prob, int64_t n, PieceRec* out) {
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int32_t p = sched[j];
+    PieceRec r{-1, 0, 0, 0, 0, 0, 0, 0};
+    if (p >= 0) {
+        r.p = p;
+        r.begin = piece_begin[p];
+        r.end = piece_end[p];
+        r.cam = piece_cam[p];
+        r.prob = cam_prob[r.cam];
+    }
+    out[j] = r;
 }
 
 // First camera piece of every problem (pieces are ordered by camera).
@@ -587,6 +605,8 @@ poba_status poba_batch_create(const poba_desc* d, int32_t n_problems, const int3
         if (!sched.empty() &&
             hipMemcpyAsync(b.sched, sched.data(), sched.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
             return fail(POBA_ERR_HIP);
+        hipLaunchKernelGGL(k_sched_rec, dim3(grid_for(int64_t(sched.size()))), dim3(kBlock), 0, s, b.sched,
+                           b.piece_begin, b.piece_end, b.piece_cam, b.cam_prob, int64_t(sched.size()), b.sched_rec);
         if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
     }
     // blocks of landmarks without observations are never written by a pass

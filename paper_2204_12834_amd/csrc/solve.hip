@@ -460,13 +460,13 @@ __global__ __launch_bounds__(kBlock) void k_cam_pass(Buffers b, Sizes z, const T
                                                      const Ctrl* ctrl) {
     __shared__ double lds[kWavesPerBlock * 9];
     if (ctrl->running == 0) return;
-    const int32_t p = b.sched[blockIdx.x];
-    if (p < 0) return;
+    const PieceRec pr = b.sched_rec[blockIdx.x];
+    if (pr.p < 0) return;
     {
-        const PCtrl& q = b.pctl[b.cam_prob[b.piece_cam[p]]];
+        const PCtrl& q = b.pctl[pr.prob];
         if (!q.active || q.stopped) return;
     }
-    const int32_t a = b.piece_begin[p], e = b.piece_end[p];
+    const int32_t p = pr.p, a = pr.begin, e = pr.end;
     const int32_t* __restrict__ co_seg = b.co_seg;
     double acc[9];
 #pragma unroll
@@ -707,131 +707,144 @@ __device__ __forceinline__ void point_lm_term(const TC* P, TC sw, const TC* c, T
     v[2] = w * (c[14] * g[0] + c[17] * g[1] + c[20] * g[2]);
 }
 
-// Landmark pass over point records: wavefronts walk `tpw` tiles as one range
-// in chunks of 64 (two-stage pipeline as in lm_pass_range); `fold` is the
-// folded camera data, in LDS or in global memory.
+// Landmark pass over point records, one wavefront over the positions of a
+// contiguous range of tiles in chunks of 64, as a software pipeline: the
+// records (camera word, point, weight) of chunk c + kPtDepth are requested
+// when chunk c is done, and the V^-1 of the landmarks ending in chunk
+// c + kPtAhead when chunk c starts; each request is consumed at least
+// kPtAhead chunks later, so with in-order completion no wait covers a load
+// issued in the last kPtAhead chunks.  `fold` holds the folded camera data,
+// in LDS or in global memory.
+constexpr int kPtDepth = 4;
+constexpr int kPtAhead = 2;
+
 template <typename TP, typename TC, typename TS>
-__device__ __forceinline__ void lm_pass_range_pt(const Buffers& b, const Sizes& z, int64_t t0, int64_t t1,
-                                                 const TS* __restrict__ fold, TS* __restrict__ sout) {
+__device__ __forceinline__ void lm_pass_stream_pt(const Buffers& b, const Sizes& z, int64_t t0, int64_t t1,
+                                                  const TS* __restrict__ fold, TS* __restrict__ sout) {
     const TS* __restrict__ Vinv = reinterpret_cast<const TS*>(b.Vinv);
     const uint32_t* __restrict__ lo_cam = b.lo_cam;
     const int lane = lane_id();
     const int32_t start = b.tile_start[t0];
     const int32_t end = b.tile_start[t1];
     if (start >= end) return;
-    int32_t seg = b.seg_base[t0] - 1;
-    uint32_t w = 0u;
-    TC P[3] = {TC(0), TC(0), TC(1)}, sw = TC(0);
-    TS A[6];
-    uint64_t hm;
-    int32_t my_seg;
-    {
-        const int32_t i = start + lane;
+    const int32_t seg0 = b.seg_base[t0] - 1;  // segment open at the range start
+    uint32_t w[kPtDepth];
+    TC P[kPtDepth][3], sw[kPtDepth];
+    TS A[kPtDepth][6];
+    auto fetch = [&](int u, int32_t pos) {  // records of the chunk at pos into slot u
+        const int32_t i = pos + lane;
+        w[u] = 0u;
+        P[u][0] = P[u][1] = TC(0);
+        P[u][2] = TC(1);
+        sw[u] = TC(0);
         if (i < end) {
-            w = lo_cam[i];
-            load_point<TP, TC>(b.J_lo, z.npad, i, P, sw);
+            w[u] = lo_cam[i];
+            load_point<TP, TC>(b.J_lo, z.npad, i, P[u], sw[u]);
         }
-        hm = ballot64(w & kHeadBit);
-        my_seg = seg + __popcll(hm & mask_upto(lane));
-        if (w & kTailBit) load_vinv(Vinv, my_seg, A);
-    }
+    };
+    int32_t seg_v = seg0;  // segment open at the start of the chunk whose V^-1 is requested next
+    auto request_vinv = [&](int u) {
+        const uint64_t hm = ballot64(w[u] & kHeadBit);
+        const int32_t my = seg_v + __popcll(hm & mask_upto(lane));
+        if (w[u] & kTailBit) load_vinv(Vinv, my, A[u]);
+        seg_v += __popcll(hm);
+    };
+#pragma unroll
+    for (int u = 0; u < kPtDepth; ++u) fetch(u, start + u * kWave);
+#pragma unroll
+    for (int u = 0; u < kPtAhead; ++u)
+        if (start + u * kWave < end) request_vinv(u);
+    int32_t seg = seg0;
     TC carry[3] = {TC(0), TC(0), TC(0)};
-    for (int32_t base = start; base < end; base += kWave) {
-        const int32_t i = base + lane;
-        const bool valid = i < end;
-        const int32_t ni = i + kWave;
-        uint32_t wn = 0u;
-        TC Pn[3] = {TC(0), TC(0), TC(1)}, swn = TC(0);
-        if (ni < end) {
-            wn = lo_cam[ni];
-            load_point<TP, TC>(b.J_lo, z.npad, ni, Pn, swn);
-        }
-        TC v[3] = {TC(0), TC(0), TC(0)};
-        if (valid) {
-            TC c[24];
-            load_fold(fold, int64_t(w & kIndexMask), c);
-            point_lm_term(P, sw, c, v);
-        }
-        const bool head = w & kHeadBit;
-        if (lane == 0 && !head) {
-            v[0] += carry[0];
-            v[1] += carry[1];
-            v[2] += carry[2];
-        }
-        const uint64_t hu = hm & mask_upto(lane);
-        const int seg_start = hu ? 63 - __builtin_clzll(hu) : 0;
-        segmented_scan<TC, 3>(v, lane, seg_start);
-        if (w & kTailBit) {
-            TC Ac[6], y[3];
+    for (int32_t base = start; base < end; base += kPtDepth * kWave) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) Ac[k] = TC(A[k]);
-            sym3_apply(Ac, v, y);
-            TS ys[3] = {TS(y[0]), TS(y[1]), TS(y[2])};
-            store_s(sout, my_seg, ys);
+        for (int u = 0; u < kPtDepth; ++u) {
+            const int32_t pos = base + u * kWave;
+            if (pos >= end) break;
+            const int ua = (u + kPtAhead) % kPtDepth;
+            if (pos + kPtAhead * kWave < end) request_vinv(ua);
+            TC v[3] = {TC(0), TC(0), TC(0)};
+            const uint32_t wc = w[u];
+            if (pos + lane < end) {
+                TC c[24];
+                load_fold(fold, int64_t(wc & kIndexMask), c);
+                point_lm_term(P[u], sw[u], c, v);
+            }
+            const uint64_t hm = ballot64(wc & kHeadBit);
+            const bool head = wc & kHeadBit;
+            if (lane == 0 && !head) {
+                v[0] += carry[0];
+                v[1] += carry[1];
+                v[2] += carry[2];
+            }
+            const uint64_t hu = hm & mask_upto(lane);
+            const int seg_start = hu ? 63 - __builtin_clzll(hu) : 0;
+            segmented_scan<TC, 3>(v, lane, seg_start);
+            if (wc & kTailBit) {
+                TC Ac[6], y[3];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) Ac[k] = TC(A[u][k]);
+                sym3_apply(Ac, v, y);
+                TS ys[3] = {TS(y[0]), TS(y[1]), TS(y[2])};
+                store_s(sout, seg + __popcll(hu), ys);
+            }
+            const int last = min(end - pos, kWave) - 1;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) carry[k] = __shfl(v[k], last, kWave);
+            seg += __popcll(hm);
+            fetch(u, pos + kPtDepth * kWave);
         }
-        const int last = min(end - base, kWave) - 1;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) carry[k] = __shfl(v[k], last, kWave);
-        seg += __popcll(hm);
-        w = wn;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) P[k] = Pn[k];
-        sw = swn;
-        hm = ballot64(w & kHeadBit);
-        my_seg = seg + __popcll(hm & mask_upto(lane));
-        if (w & kTailBit) load_vinv(Vinv, my_seg, A);
     }
 }
 
 constexpr int kPtBlock = 1024;  // persistent LDS variant: one block of 16 waves per compute unit
 
-// Folded camera data staged in LDS once per block; wavefronts take tile groups in turn.
+// Folded camera data staged in LDS once per block; every wavefront of the
+// grid takes one contiguous range of tiles.
 template <typename TP, typename TC, typename TS>
-__global__ __launch_bounds__(kPtBlock) void k_lm_pass_pt_lds(Buffers b, Sizes z, int tpw, TS* __restrict__ sout,
-                                                              const Ctrl* ctrl) {
+__global__ __launch_bounds__(kPtBlock) void k_lm_pass_pt_lds(Buffers b, Sizes z, int64_t tiles_per_wave,
+                                                              TS* __restrict__ sout, const Ctrl* ctrl) {
     extern __shared__ unsigned char lds_raw[];
     if (ctrl->running == 0) return;
     TS* cf = reinterpret_cast<TS*>(lds_raw);
     const TS* __restrict__ src = reinterpret_cast<const TS*>(b.vq);
     for (int64_t k = threadIdx.x; k < int64_t(z.nc) * 24; k += kPtBlock) cf[k] = src[k];
     __syncthreads();
-    const int64_t ngroups = ceil_div_d(z.ntiles, tpw);
-    const int waves = kPtBlock / kWave;
-    const int64_t nwaves = int64_t(gridDim.x) * waves;
-    for (int64_t g = int64_t(blockIdx.x) * waves + threadIdx.x / kWave; g < ngroups; g += nwaves) {
-        const int64_t t0 = g * tpw;
-        const int64_t t1 = min(t0 + int64_t(tpw), z.ntiles);
-        lm_pass_range_pt<TP, TC, TS>(b, z, t0, t1, cf, sout);
-    }
+    const int64_t wave = int64_t(blockIdx.x) * (kPtBlock / kWave) + threadIdx.x / kWave;
+    const int64_t t0 = wave * tiles_per_wave;
+    if (t0 >= z.ntiles) return;
+    lm_pass_stream_pt<TP, TC, TS>(b, z, t0, min(t0 + tiles_per_wave, z.ntiles), cf, sout);
 }
 
 // Folded camera data gathered from global memory (L2-resident).
 template <typename TP, typename TC, typename TS>
-__global__ __launch_bounds__(kBlock) void k_lm_pass_pt(Buffers b, Sizes z, int tpw, TS* __restrict__ sout,
-                                                       const Ctrl* ctrl) {
+__global__ __launch_bounds__(kBlock) void k_lm_pass_pt(Buffers b, Sizes z, int64_t tiles_per_wave,
+                                                       TS* __restrict__ sout, const Ctrl* ctrl) {
     if (ctrl->running == 0) return;
     const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
-    const int64_t t0 = wave * tpw;
+    const int64_t t0 = wave * tiles_per_wave;
     if (t0 >= z.ntiles) return;
-    const int64_t t1 = min(t0 + int64_t(tpw), z.ntiles);
-    lm_pass_range_pt<TP, TC, TS>(b, z, t0, t1, reinterpret_cast<const TS*>(b.vq), sout);
+    lm_pass_stream_pt<TP, TC, TS>(b, z, t0, min(t0 + tiles_per_wave, z.ntiles), reinterpret_cast<const TS*>(b.vq),
+                                  sout);
 }
 
 template <typename TP, typename TC, typename TS>
 void launch_lm_pass_pt(Problem* p, hipStream_t s) {
     const Buffers& b = p->b;
     const Sizes& z = p->z;
-    const int tpw = p->tiles_per_wave;
-    const int64_t ngroups = ceil_div(z.ntiles, tpw);
     const size_t lds = size_t(z.nc) * 24 * sizeof(TS);
     TS* sout = reinterpret_cast<TS*>(b.s);
     if (p->lds_cam && lds <= size_t(p->lds_max)) {
-        const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(p->n_cus, ceil_div(ngroups, kPtBlock / kWave)));
-        hipLaunchKernelGGL((k_lm_pass_pt_lds<TP, TC, TS>), dim3(unsigned(nblk)), dim3(kPtBlock), lds, s, b, z, tpw,
+        // one block per compute unit; the tiles are split evenly over all wavefronts
+        const int64_t waves = p->n_cus * (kPtBlock / kWave);
+        const int64_t per = std::max<int64_t>(1, ceil_div(z.ntiles, waves));
+        const int64_t nblk = ceil_div(ceil_div(z.ntiles, per), kPtBlock / kWave);
+        hipLaunchKernelGGL((k_lm_pass_pt_lds<TP, TC, TS>), dim3(unsigned(nblk)), dim3(kPtBlock), lds, s, b, z, per,
                            sout, b.ctrl);
     } else {
-        hipLaunchKernelGGL((k_lm_pass_pt<TP, TC, TS>), dim3(unsigned(ceil_div(ngroups, kWavesPerBlock))), dim3(kBlock),
-                           0, s, b, z, tpw, sout, b.ctrl);
+        const int64_t per = p->tiles_per_wave;
+        hipLaunchKernelGGL((k_lm_pass_pt<TP, TC, TS>), dim3(unsigned(ceil_div(ceil_div(z.ntiles, per), kWavesPerBlock))),
+                           dim3(kBlock), 0, s, b, z, per, sout, b.ctrl);
     }
 }
 
@@ -844,12 +857,18 @@ __global__ __launch_bounds__(kBlock) void k_cam_pass_pt(Buffers b, Sizes z, cons
                                                         const Ctrl* ctrl) {
     __shared__ double lds[kWavesPerBlock * 9];
     if (ctrl->running == 0) return;
-    const int32_t p = b.sched[blockIdx.x];
-    if (p < 0) return;
-    const int64_t cam = b.piece_cam[p];
-    {
-        const PCtrl& q = b.pctl[b.cam_prob[cam]];
-        if (!q.active || q.stopped) return;
+    const PieceRec pr = b.sched_rec[blockIdx.x];
+    if (pr.p < 0) return;
+    const int32_t p = pr.p, a = pr.begin, e = pr.end;
+    const int64_t cam = pr.cam;
+    const int32_t* __restrict__ co_seg = b.co_seg;
+    // the first observation's loads go out before the problem's flags are read
+    int32_t i = a + threadIdx.x;
+    TC P[3] = {TC(0), TC(0), TC(1)}, sw = TC(0);
+    int64_t g = 0;
+    if (i < e) {
+        g = co_seg[i];
+        load_point<TP, TC>(b.J_co, z.npad, i, P, sw);
     }
     const double* rec = b.lin_rec + kCamRec * cam;
     TC R[9];
@@ -857,19 +876,15 @@ __global__ __launch_bounds__(kBlock) void k_cam_pass_pt(Buffers b, Sizes z, cons
     for (int k = 0; k < 9; ++k) R[k] = TC(rec[13 + k]);
     const TC t0 = TC(rec[3]), t1 = TC(rec[4]), t2 = TC(rec[5]);
     const TC f = TC(rec[6]), k1 = TC(rec[7]), k2 = TC(rec[8]);
-    const int32_t a = b.piece_begin[p], e = b.piece_end[p];
-    const int32_t* __restrict__ co_seg = b.co_seg;
+    {
+        const PCtrl& q = b.pctl[pr.prob];
+        if (!q.active || q.stopped) return;
+    }
+    double sv[3] = {0.0, 0.0, 0.0};
+    if (i < e) load_s3(sin, g, sv);
     double acc[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc[k] = 0.0;
-    int32_t i = a + threadIdx.x;
-    TC P[3] = {TC(0), TC(0), TC(1)}, sw = TC(0);
-    double sv[3] = {0.0, 0.0, 0.0};
-    if (i < e) {
-        const int64_t g = co_seg[i];
-        load_point<TP, TC>(b.J_co, z.npad, i, P, sw);
-        load_s3(sin, g, sv);
-    }
     for (; i < e; i += kBlock) {
         const int32_t ni = i + kBlock;
         int64_t gn = 0;
