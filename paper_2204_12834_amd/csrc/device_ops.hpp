@@ -71,7 +71,10 @@ template <typename T>
 struct PointShape {
     T iz, p0, p1, n, d, A00, A01, A11;
     __device__ __forceinline__ PointShape(const T* P, T f, T k1, T k2) {
-        iz = T(1) / P[2];
+        // float32: the hardware reciprocal (1 ulp) instead of a correctly
+        // rounded division
+        if constexpr (sizeof(T) == 4) iz = __builtin_amdgcn_rcpf(P[2]);
+        else iz = T(1) / P[2];
         p0 = -P[0] * iz;
         p1 = -P[1] * iz;
         n = p0 * p0 + p1 * p1;

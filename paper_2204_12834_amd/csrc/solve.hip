@@ -441,6 +441,17 @@ __global__ __launch_bounds__(kBlock) void k_zero_empty(Buffers b, Sizes z, doubl
 
 // -------------------------------------------------------------- camera pass --
 
+// The three stored scalars of s at segment l, kept in the storage type.
+__device__ __forceinline__ void load_s3_raw(const float* s, int64_t l, float* o) {
+    const float4 a = reinterpret_cast<const float4*>(s)[l];
+    o[0] = a.x; o[1] = a.y; o[2] = a.z;
+}
+__device__ __forceinline__ void load_s3_raw(const double* s, int64_t l, double* o) {
+    const double2* p = reinterpret_cast<const double2*>(s + 4 * l);
+    const double2 a = p[0];
+    o[0] = a.x; o[1] = a.y; o[2] = s[4 * l + 2];
+}
+
 __device__ __forceinline__ void load_s3(const float* s, int64_t l, double* o) {
     const float4 a = reinterpret_cast<const float4*>(s)[l];
     o[0] = a.x; o[1] = a.y; o[2] = a.z;
@@ -852,24 +863,40 @@ void launch_lm_pass_pt(Problem* p, hipStream_t s) {
 // observation z = J_P (R s), h = J_P^T z; the piece accumulates
 // (P - t) x h, h and (d, f n, f n^2) p.z, weighted by sw^2, in float64, and
 // multiplies the first by J_l(w)^T at the end.  TC: per-observation arithmetic.
-template <typename TP, typename TSin, typename TC>
-__global__ __launch_bounds__(kBlock) void k_cam_pass_pt(Buffers b, Sizes z, const TSin* __restrict__ sin,
-                                                        const Ctrl* ctrl) {
-    __shared__ double lds[kWavesPerBlock * 9];
+template <typename TP, typename TSin, typename TC, int NT>
+__global__ __launch_bounds__(NT) void k_cam_pass_pt(Buffers b, Sizes z, const TSin* __restrict__ sin,
+                                                    const Ctrl* ctrl) {
+    __shared__ double lds[(NT / kWave) * 9];
     if (ctrl->running == 0) return;
     const PieceRec pr = b.sched_rec[blockIdx.x];
     if (pr.p < 0) return;
     const int32_t p = pr.p, a = pr.begin, e = pr.end;
     const int64_t cam = pr.cam;
     const int32_t* __restrict__ co_seg = b.co_seg;
-    // the first observation's loads go out before the problem's flags are read
-    int32_t i = a + threadIdx.x;
-    TC P[3] = {TC(0), TC(0), TC(1)}, sw = TC(0);
-    int64_t g = 0;
-    if (i < e) {
-        g = co_seg[i];
-        load_point<TP, TC>(b.J_co, z.npad, i, P, sw);
-    }
+    // three-stage pipeline per thread over a ring of three slots (unrolled,
+    // so no register of a load in flight is ever copied): the records of
+    // observation k + 2 and the gather of s for observation k + 1 are in
+    // flight while k is added.  Lanes past the piece read its first
+    // observation and add it with weight 0, so every load is unconditional
+    // and the wave runs a uniform number of steps.
+    struct Obs {
+        int32_t g;
+        TC P[3], sw;
+        bool valid;
+    };
+    const int32_t lane = threadIdx.x;
+    const int32_t n_it = (e - a + NT - 1) / NT;
+    auto fetch = [&](int32_t it, Obs& o) {
+        const int32_t i = a + lane + it * NT;
+        o.valid = i < e;
+        const int32_t ic = o.valid ? i : a;
+        o.g = co_seg[ic];
+        load_point<TP, TC>(b.J_co, z.npad, ic, o.P, o.sw);
+    };
+    Obs o[3];
+    TSin sr[3][3];
+    fetch(0, o[0]);
+    fetch(1, o[1]);
     const double* rec = b.lin_rec + kCamRec * cam;
     TC R[9];
 #pragma unroll
@@ -880,44 +907,45 @@ __global__ __launch_bounds__(kBlock) void k_cam_pass_pt(Buffers b, Sizes z, cons
         const PCtrl& q = b.pctl[pr.prob];
         if (!q.active || q.stopped) return;
     }
-    double sv[3] = {0.0, 0.0, 0.0};
-    if (i < e) load_s3(sin, g, sv);
+    load_s3_raw(sin, o[0].g, sr[0]);
+    // per-lane sums in the arithmetic type (each lane adds a few dozen terms
+    // at most), combined across the wave in float64
+    TC accl[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) accl[k] = TC(0);
+    for (int32_t it = 0; it < n_it; it += 3) {
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            if (it + u >= n_it) break;
+            fetch(it + u + 2, o[(u + 2) % 3]);
+            load_s3_raw(sin, o[(u + 1) % 3].g, sr[(u + 1) % 3]);
+            const Obs& c = o[u];
+            const PointShape<TC> sh(c.P, f, k1, k2);
+            const TC s0 = TC(sr[u][0]), s1 = TC(sr[u][1]), s2 = TC(sr[u][2]);
+            const TC Rs[3] = {R[0] * s0 + R[1] * s1 + R[2] * s2, R[3] * s0 + R[4] * s1 + R[5] * s2,
+                              R[6] * s0 + R[7] * s1 + R[8] * s2};
+            TC z0, z1, h[3];
+            sh.JP(Rs, z0, z1);
+            sh.JPt(z0, z1, h);
+            const TC w = c.valid ? c.sw * c.sw : TC(0);
+            const TC X0 = c.P[0] - t0, X1 = c.P[1] - t1, X2 = c.P[2] - t2;
+            const TC wpz = w * (sh.p0 * z0 + sh.p1 * z1);
+            accl[0] += w * (X1 * h[2] - X2 * h[1]);
+            accl[1] += w * (X2 * h[0] - X0 * h[2]);
+            accl[2] += w * (X0 * h[1] - X1 * h[0]);
+            accl[3] += w * h[0];
+            accl[4] += w * h[1];
+            accl[5] += w * h[2];
+            accl[6] += sh.d * wpz;
+            accl[7] += f * sh.n * wpz;
+            accl[8] += f * sh.n * sh.n * wpz;
+        }
+    }
     double acc[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) acc[k] = 0.0;
-    for (; i < e; i += kBlock) {
-        const int32_t ni = i + kBlock;
-        int64_t gn = 0;
-        TC Pn[3] = {TC(0), TC(0), TC(1)}, swn = TC(0);
-        if (ni < e) {
-            gn = co_seg[ni];
-            load_point<TP, TC>(b.J_co, z.npad, ni, Pn, swn);
-        }
-        const PointShape<TC> sh(P, f, k1, k2);
-        const TC s0 = TC(sv[0]), s1 = TC(sv[1]), s2 = TC(sv[2]);
-        const TC Rs[3] = {R[0] * s0 + R[1] * s1 + R[2] * s2, R[3] * s0 + R[4] * s1 + R[5] * s2,
-                          R[6] * s0 + R[7] * s1 + R[8] * s2};
-        TC z0, z1, h[3];
-        sh.JP(Rs, z0, z1);
-        sh.JPt(z0, z1, h);
-        const TC w = sw * sw;
-        const TC X0 = P[0] - t0, X1 = P[1] - t1, X2 = P[2] - t2;
-        const TC pz = sh.p0 * z0 + sh.p1 * z1;
-        acc[0] += double(w * (X1 * h[2] - X2 * h[1]));
-        acc[1] += double(w * (X2 * h[0] - X0 * h[2]));
-        acc[2] += double(w * (X0 * h[1] - X1 * h[0]));
-        acc[3] += double(w * h[0]);
-        acc[4] += double(w * h[1]);
-        acc[5] += double(w * h[2]);
-        acc[6] += double(w * sh.d * pz);
-        acc[7] += double(w * f * sh.n * pz);
-        acc[8] += double(w * f * sh.n * sh.n * pz);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) P[k] = Pn[k];
-        sw = swn;
-        if (ni < e) load_s3(sin, gn, sv);
-    }
-    block_sum<9>(acc, lds);
+    for (int k = 0; k < 9; ++k) acc[k] = double(accl[k]);
+    if constexpr (NT == kWave) wave_sum<double, 9>(acc);
+    else block_sum<9>(acc, lds);
     if (threadIdx.x == 0) {
         // rotation part: J_l(w)^T times the accumulated (P - t) x h
         const double w0 = rec[0], w1 = rec[1], w2 = rec[2], B = rec[10], E = rec[22];
@@ -949,7 +977,7 @@ template <typename TJ, typename TSin, typename TCL, bool PT>
 void launch_cam_pass(Problem* p, const Buffers& b, const TSin* sin, hipStream_t s) {
     const dim3 g(unsigned(std::max<int64_t>(p->sched_len, 1)));
     if constexpr (PT)
-        hipLaunchKernelGGL((k_cam_pass_pt<TJ, TSin, TCL>), g, dim3(kBlock), 0, s, b, p->z, sin, b.ctrl);
+        hipLaunchKernelGGL((k_cam_pass_pt<TJ, TSin, TCL, kWave>), g, dim3(kWave), 0, s, b, p->z, sin, b.ctrl);
     else
         hipLaunchKernelGGL((k_cam_pass<TJ, TSin>), g, dim3(kBlock), 0, s, b, p->z, sin, b.ctrl);
 }
