@@ -202,6 +202,71 @@ def lm_run(prob, cams0, lms0, opts, max_iters):
     return out
 
 
+def measure_steps(prob, cams0, lms0, scene, args, precision, records):
+    """Times args.steps LM iterations from x0 (state reset before each) with
+    the library's per-kernel event timing; returns the step time, the
+    per-class kernel times, the series throughput and the roofline of the
+    dominant series kernel."""
+    import torch
+    from paper_2204_12834_amd.solver import LMOptions
+    cams, lms = cams0.clone(), lms0.clone()
+    opts = LMOptions(m=args.m, eps=0.0, func_tol=0.0, max_iters=1 << 30)
+    st = prob.lm_init(opts)
+
+    def step():
+        cams.copy_(cams0)
+        lms.copy_(lms0)
+        prob.lm_init(opts, state=st)
+        prob.lm_step(cams, lms, st, opts)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    prob.profile(True)
+    prob.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = prob.profile_read()
+    prob.profile(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    print(f"[bench] {precision} {records}: {args.steps} steps, {ms_per_step:.3f} ms/step; per step: "
+          + ", ".join(f"{k} {v[0] / args.steps:.3f} ms ({v[1] // args.steps})" for k, v in prof.items()),
+          file=sys.stderr, flush=True)
+    N, nl = scene.n_obs, scene.n_lms
+    lmb, camb = series_bytes(N, nl, precision, records)
+    k = args.steps
+    # one landmark pass per order; camera pass and finish run m + 1 times
+    # (the extra one forms the reduced right-hand side)
+    t_lm, n_lm = prof["landmark_pass"][0] / 1e3, prof["landmark_pass"][1]
+    t_cam, n_cam = prof["camera_pass"][0] / 1e3, prof["camera_pass"][1]
+    t_fin, n_fin = prof["camera_finish"][0] / 1e3, prof["camera_finish"][1]
+    avg_lm, avg_cam = t_lm / n_lm, t_cam / n_cam
+    avg_fin = t_fin / n_fin if n_fin else 0.0
+    series_time = k * args.m * (avg_lm + avg_cam + avg_fin)
+    value = k * args.m * (lmb + camb) / series_time / 1e9
+    dom = "landmark_pass" if t_lm >= t_cam else "camera_pass"
+    dom_bytes = lmb if dom == "landmark_pass" else camb
+    dom_avg = avg_lm if dom == "landmark_pass" else avg_cam
+    achieved = dom_bytes / dom_avg / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        key = f"{args.workload}_{precision}_{dom}" + ("" if records == "jacobian" else "_point")
+        if tr.get("source_hash") == kernel_source_hash() and key in tr.get("bytes_per_launch", {}):
+            traffic = tr["bytes_per_launch"][key]
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_avg * 1e3, 4)}
+    phases = {name: round(v[0] / k, 4) for name, v in prof.items()}
+    return {"ms_per_step": round(ms_per_step, 4), "prof": prof, "value": round(value, 1), "roofline": roofline,
+            "phases": phases, "series_us_per_order": round(1e6 * (avg_lm + avg_cam + avg_fin), 2),
+            "series_bytes_per_order": lmb + camb, "records": records}
+
+
 def _events():
     import torch
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -406,6 +471,7 @@ def main():
     ap.add_argument("--sweep-tpw", default="", help="comma list: time the series for each and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tau", action="store_true", help="skip the time-to-tolerance LM runs")
+    ap.add_argument("--no-point", action="store_true", help="skip the point-record measurements")
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
 
@@ -436,7 +502,6 @@ def main():
     prob, cams0, lms0, obs = gpu_setup(scene, delta, args.precision, dev, args.records)
     if args.tpw:
         prob.set_tuning("tiles_per_wave", args.tpw)
-    cams, lms = cams0.clone(), lms0.clone()
     if args.sweep_tpw:
         prob.linearize(cams0, lms0)
         for tpw in [int(x) for x in args.sweep_tpw.split(",")]:
@@ -453,82 +518,43 @@ def main():
             print(f"[sweep] tpw={tpw}: " + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f} us x{v[1] // 3}"
                                                     for k, v in pr.items() if v[1]), file=sys.stderr, flush=True)
         return 0
-    opts = LMOptions(m=args.m, eps=0.0, func_tol=0.0, max_iters=1 << 30)
-    st = prob.lm_init(opts)
-
-    def step():
-        cams.copy_(cams0)
-        lms.copy_(lms0)
-        prob.lm_init(opts, state=st)
-        prob.lm_step(cams, lms, st, opts)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    prob.profile(True)
-    prob.profile_read()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = prob.profile_read()
-    prob.profile(False)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    print(f"[bench] {args.steps} steps, {ms_per_step:.3f} ms/step; per step: "
-          + ", ".join(f"{k} {v[0] / args.steps:.3f} ms ({v[1] // args.steps})" for k, v in prof.items()),
-          file=sys.stderr, flush=True)
-
+    res = measure_steps(prob, cams0, lms0, scene, args, args.precision, args.records)
+    ms_per_step, prof, value, roofline, phases = (res[k] for k in ("ms_per_step", "prof", "value", "roofline",
+                                                                  "phases"))
     N, nl, nc = scene.n_obs, scene.n_lms, scene.n_cams
-    lmb, camb = series_bytes(N, nl, args.precision, args.records)
-    k = args.steps
-    t_lm = prof["landmark_pass"][0] / 1e3
-    t_cam = prof["camera_pass"][0] / 1e3
-    t_fin = prof["camera_finish"][0] / 1e3
-    n_lm = prof["landmark_pass"][1]
-    n_cam = prof["camera_pass"][1]
-    # one landmark pass per order; camera pass and finish run m + 1 times
-    # (the extra one forms the reduced right-hand side)
-    avg_lm = t_lm / n_lm
-    avg_cam = t_cam / n_cam
-    n_fin = prof["camera_finish"][1]
-    avg_fin = t_fin / n_fin if n_fin else 0.0
-    series_time = k * args.m * (avg_lm + avg_cam + avg_fin)
-    value = k * args.m * (lmb + camb) / series_time / 1e9
-    dom = "landmark_pass" if t_lm >= t_cam else "camera_pass"
-    dom_bytes = lmb if dom == "landmark_pass" else camb
-    dom_avg = avg_lm if dom == "landmark_pass" else avg_cam
-    achieved = dom_bytes / dom_avg / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE))
-        key = f"{args.workload}_{args.precision}_{dom}" + ("" if args.records == "jacobian" else "_point")
-        if tr.get("source_hash") == kernel_source_hash() and key in tr.get("bytes_per_launch", {}):
-            traffic = tr["bytes_per_launch"][key]
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_avg * 1e3, 4)}
-    phases = {name: round(v[0] / k, 4) for name, v in prof.items()}
+    achieved = roofline["achieved"]
+    del prob
+    torch.cuda.empty_cache()
+
+    alt = None
+    if args.records == "jacobian" and args.precision != "bf16" and not args.no_point:
+        # the same step with point records (blocks rebuilt in every pass)
+        p2, c2, l2, _ = gpu_setup(scene, delta, args.precision, dev, "point")
+        alt = measure_steps(p2, c2, l2, scene, args, args.precision, "point")
+        alt.pop("prof")
+        del p2
+        torch.cuda.empty_cache()
 
     probe = stream_probe(dev)
     print(f"[bench] probe: {probe}", file=sys.stderr, flush=True)
 
     extra = {}
     if not args.no_tau:
-        del prob
-        torch.cuda.empty_cache()
         runs = {}
         steps_at_x0 = {}
-        for prec in ["f64", "f32", "bf16"]:
-            p2, c0, l0, _ = gpu_setup(scene, delta, prec, dev, "jacobian" if prec == "bf16" else args.records)
+        configs = [("f64", "jacobian"), ("f32", "jacobian"), ("bf16", "jacobian")]
+        if not args.no_point:
+            configs += [("f64", "point"), ("f32", "point")]
+        for prec, rec in configs:
+            name = prec if rec == "jacobian" else f"{prec}_point"
+            p2, c0, l0, _ = gpu_setup(scene, delta, prec, dev, rec)
             # the damped step at x0 (lambda0, fixed order) for the precision comparison
             p2.linearize(c0, l0)
             dxc, dxl, _ = p2.power_solve(1e-4, args.m, 0.0)
-            steps_at_x0[prec] = (dxc.cpu().numpy(), dxl.cpu().numpy())
+            steps_at_x0[name] = (dxc.cpu().numpy(), dxl.cpu().numpy())
             o2 = LMOptions(m=args.m)  # Sec. 5.1 settings, series order m
-            runs[prec] = lm_run(p2, c0, l0, o2, 50)
-            print(f"[bench] LM {prec}: {len(runs[prec])} iterations, final cost {runs[prec][-1][0]:.6e}",
+            runs[name] = lm_run(p2, c0, l0, o2, 50)
+            print(f"[bench] LM {name}: {len(runs[name])} iterations, final cost {runs[name][-1][0]:.6e}",
                   file=sys.stderr, flush=True)
             del p2
             torch.cuda.empty_cache()
@@ -539,19 +565,22 @@ def main():
         fstar = min(min(c for c, _, _ in out) for out in runs.values())
         ftau = fstar + 0.01 * (f0 - fstar)
         tau = {}
-        for prec, out in runs.items():
+        for name, out in runs.items():
             hit = [t for c, t, _ in out if c <= ftau]
-            tau[prec] = {"t_1pct_s": round(hit[0], 4) if hit else None, "iterations": len(out),
+            tau[name] = {"t_1pct_s": round(hit[0], 4) if hit else None, "iterations": len(out),
                          "final_cost": out[-1][0], "lm_iter_ms": round(1e3 * out[-1][1] / len(out), 3),
                          "iters_to_1pct": next((i + 1 for i, (c, _, _) in enumerate(out) if c <= ftau), None)}
         ref_c, ref_l = steps_at_x0["f64"]
         prec_err = {}
-        for prec in ["f32", "bf16"]:
-            c_, l_ = steps_at_x0[prec]
-            prec_err[prec] = {"dx_cams": float(np.linalg.norm(c_ - ref_c) / np.linalg.norm(ref_c)),
+        for name, (c_, l_) in steps_at_x0.items():
+            if name == "f64":
+                continue
+            prec_err[name] = {"dx_cams": float(np.linalg.norm(c_ - ref_c) / np.linalg.norm(ref_c)),
                               "dx_lms": float(np.linalg.norm(l_ - ref_l) / np.linalg.norm(ref_l))}
         extra = {"f0": f0, "f_star": fstar, "f_tau": ftau, "time_to_1pct": tau,
                  "step_error_vs_f64_at_x0": prec_err}
+    if alt is not None:
+        extra["point_records"] = alt
 
     cpu = None
     if not args.no_cpu_baseline:
