@@ -88,8 +88,9 @@ typedef struct {
     int32_t damping;    /* POBA_DAMP_* */
     int32_t loss;       /* POBA_LOSS_* */
     int32_t piece_size; /* observations per camera-pass work item; 0 = default (1024) */
-    int32_t lm_ranges;  /* landmark ranges of the camera-major order (XCD-local gathers);
-                           0 = automatic, 1 = none, else a multiple of 8            */
+    int32_t lm_ranges;  /* landmark ranges of the camera-major order (XCD-local gathers,
+                           and with point records the slices staged in LDS by the
+                           camera pass); 0 = automatic, 1 = none, else a multiple of 8 */
     int32_t records;    /* POBA_RECORDS_*: what is stored per observation      */
     double huber_delta; /* pixels; used when loss == POBA_LOSS_HUBER, must be > 0 */
 } poba_desc;
@@ -333,8 +334,13 @@ enum {
     POBA_TUNE_TILES_PER_WAVE = 0, /* 64-observation landmark tiles per wavefront in the
                                      landmark pass (1..64, default 4)            */
     POBA_TUNE_LM_RANGES = 1,      /* landmark ranges chosen at creation (read only) */
-    POBA_TUNE_LDS_CAMERA = 2      /* 1: landmark pass reads the camera vector from LDS when
+    POBA_TUNE_LDS_CAMERA = 2,     /* 1: landmark pass reads the camera vector from LDS when
                                      it fits in 64 KB (default); 0: from global memory */
+    POBA_TUNE_RANGE_LDS = 3       /* point records: 1 (default where possible): the series
+                                     camera pass stages each landmark range's slice of the
+                                     landmark vector in LDS; possible when the handle was
+                                     created with ranges of at most 80 KB of that vector
+                                     (automatic ranges are); 0: gathers from L2 per piece */
 };
 
 /* Sets a launch parameter of the handle's kernels (results do not depend on

@@ -24,7 +24,7 @@ PRECISION = {"f64": 0, "f32": 1, "bf16": 2}
 DAMPING = {"marquardt": 0, "identity": 1}
 RECORDS = {"jacobian": 0, "point": 1}
 LOSS = {"l2": 0, "huber": 1}
-TUNING = {"tiles_per_wave": 0, "lm_ranges": 1, "lds_camera": 2}
+TUNING = {"tiles_per_wave": 0, "lm_ranges": 1, "lds_camera": 2, "range_lds": 3}
 KERNEL_CLASSES = ["linearize", "inverse", "landmark_pass", "camera_pass", "camera_finish", "backsub", "eval", "other"]
 
 

@@ -19,6 +19,14 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kDefaultPiece = 1024;
 constexpr int kXcds = 8;                      // dies of an MI355X; workgroups are dealt to them in turn
 constexpr int64_t kRangeBytes = 2ll << 20;   // landmark-vector slice gathered by one die
+constexpr int64_t kRangeLds = 144 << 10;     // landmark-vector slice per range when staged in LDS (target)
+constexpr int64_t kRangeLdsMax = 156 << 10;  // the same, upper bound (one workgroup per compute unit)
+constexpr int kMaxCwWaves = 16;              // wavefronts per workgroup of the range-staged camera pass (max)
+constexpr int kMaxRangeBlocks = 16;          // workgroups per landmark range in that pass
+
+// Wavefronts per workgroup of the range-staged camera pass: 16 with float32
+// arithmetic, 8 with float64 (whose registers allow two waves per SIMD).
+inline constexpr int range_pass_waves(int sbytes) { return sbytes == 8 ? 8 : 16; }
 constexpr uint32_t kHeadBit = 0x80000000u;  // first observation of its landmark
 constexpr uint32_t kTailBit = 0x40000000u;  // last observation of its landmark
 constexpr uint32_t kIndexMask = 0x3fffffffu;
@@ -353,6 +361,10 @@ struct Buffers {
     int32_t* grp_piece;   // [nc*R+1] first piece of each group
     int32_t* sched;       // [kXcds*npieces_max] camera-pass block -> piece (-1: idle)
     PieceRec* sched_rec;  // [kXcds*npieces_max] the same slots with their piece data
+    int4* cw_rec;         // [R*kMaxRangeBlocks*kMaxCwWaves] range-staged camera pass: per wavefront
+                          // {landmark range, list begin, list end, 0} into cw_list
+    int4* cw_list;        // [R*nc] the non-empty (camera, range) groups of each wavefront:
+                          // {camera, first camera-major position, length, problem}
     double* obs_lo;       // [N][2] observations, landmark-major
     double* obs_co;       // [N][2] observations, camera-major
     // linearisation
@@ -374,6 +386,7 @@ struct Buffers {
     double* x;            // [nc][9] series sum
     double* bt;           // [nc][9] reduced right-hand side b~ of the last solve
     double* part;         // [npieces_max][54] per-piece partial sums
+    void* part_grp;       // [R][nc][9] storage type: per (camera, range) group sums of the camera pass
     double* dxl;          // [nl][3] landmark step (lm step)
     double* dxp;          // [nc][9] camera step (lm step)
     double* cam_rec;      // [nc][24] camera records of the state being evaluated (trial state)
@@ -427,6 +440,10 @@ struct poba_problem_s {
     int tiles_per_wave = 4;     // landmark-tile groups handled by one wavefront
     int32_t lm_ranges = 1;      // landmark ranges of the camera-major order
     int64_t sched_len = 0;      // camera-pass grid size
+    int32_t seg_per_range = 1;  // non-empty landmarks per landmark range
+    int range_lds_ok = 0;       // pieces and wave records of the range-staged camera pass exist
+    int range_lds = 0;          // series camera passes over point records stage the ranges in LDS
+    int64_t cw_blocks = 0;      // grid of the range-staged camera pass
     int64_t n_cus = 256;        // compute units of the device
     int lds_cam = 1;            // stage the camera vector in LDS when it fits
     int64_t lds_max = 65536;    // bytes of LDS one workgroup may allocate

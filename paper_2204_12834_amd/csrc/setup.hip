@@ -11,12 +11,23 @@
 // that never straddle two cameras.
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+
 #include "camera_model.hpp"
 #include "common.hpp"
 
 namespace poba {
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Landmark ranges whose slices of the landmark vector (three scalars of
+// `sbytes` per observed landmark) meet the LDS target of the range-staged
+// camera pass; a multiple of the die count above one.
+int32_t point_ranges(int64_t nseg, int sbytes) {
+    const int64_t bytes = nseg * 3 * sbytes;
+    if (bytes <= kRangeLds) return 1;
+    return int32_t(std::min<int64_t>(4096, kXcds * ceil_div(bytes, kXcds * kRangeLds)));
+}
 
 bool compute_sizes(const poba_desc* d, int32_t n_problems, Sizes* z) {
     if (!d) return false;
@@ -42,7 +53,9 @@ bool compute_sizes(const poba_desc* d, int32_t n_problems, Sizes* z) {
     // automatic choice: one range per die when the landmark vector exceeds the
     // slice size, more when a slice per die would still be larger
     const int64_t s_bytes_max = int64_t(z->nl) * 32;
-    const int64_t auto_max = s_bytes_max > kRangeBytes ? kXcds * ceil_div(s_bytes_max, kXcds * kRangeBytes) : 1;
+    int64_t auto_max = s_bytes_max > kRangeBytes ? kXcds * ceil_div(s_bytes_max, kXcds * kRangeBytes) : 1;
+    if (d->records == POBA_RECORDS_POINT)
+        auto_max = std::max<int64_t>(auto_max, point_ranges(z->nl, d->precision == POBA_F64 ? 8 : 4));
     z->ranges_max = d->lm_ranges ? d->lm_ranges : auto_max;
     z->npieces_max = z->N / z->piece + int64_t(z->nc) * z->ranges_max + 1;
     z->jbytes = d->precision == POBA_F64 ? 8 : (d->precision == POBA_F32 ? 4 : 2);
@@ -89,6 +102,8 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.grp_piece = (int32_t*)take((nc * size_t(z.ranges_max) + 1) * 4);
     t.sched = (int32_t*)take(size_t(kXcds) * size_t(z.npieces_max) * 4);
     t.sched_rec = (PieceRec*)take(size_t(kXcds) * size_t(z.npieces_max) * sizeof(PieceRec));
+    t.cw_rec = (int4*)take(size_t(z.ranges_max) * kMaxRangeBlocks * kMaxCwWaves * sizeof(int4));
+    t.cw_list = (int4*)take(z.point ? size_t(z.ranges_max) * nc * sizeof(int4) : 0);
     t.obs_lo = (double*)take(N * 16);
     t.obs_co = (double*)take(N * 16);
     t.J_lo = take(jrec);
@@ -108,6 +123,7 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.x = (double*)take(nc * 9 * 8);
     t.bt = (double*)take(nc * 9 * 8);
     t.part = (double*)take(size_t(z.npieces_max) * 54 * 8);
+    t.part_grp = take(z.point ? size_t(z.ranges_max) * nc * 9 * size_t(z.sbytes) : 0);
     t.dxl = (double*)take(nl * 3 * 8);
     t.dxp = (double*)take(nc * 9 * 8);
     t.cam_rec = (double*)take(nc * 24 * 8);
@@ -516,15 +532,24 @@ poba_status poba_batch_create(const poba_desc* d, int32_t n_problems, const int3
 
     // landmark ranges of the camera-major order: each die of the GPU gathers
     // the landmark vector from one slice small enough for its L2
+    // (point records: slices that the camera pass stages in LDS)
     int32_t R = d->lm_ranges;
     if (R == 0) {
-        const int64_t s_bytes = p->nnel * (d->precision == POBA_F64 ? 32 : 16);
-        R = s_bytes > kRangeBytes ? int32_t(kXcds * ceil_div(s_bytes, kXcds * kRangeBytes)) : 1;
+        if (z.point) {
+            R = point_ranges(p->nnel, z.sbytes);
+        } else {
+            const int64_t s_bytes = p->nnel * (d->precision == POBA_F64 ? 32 : 16);
+            R = s_bytes > kRangeBytes ? int32_t(kXcds * ceil_div(s_bytes, kXcds * kRangeBytes)) : 1;
+        }
     }
     if (R > z.ranges_max) return fail(POBA_ERR_STATE);
     p->lm_ranges = R;
     const int32_t spr = int32_t(std::max<int64_t>(1, ceil_div(std::max<int64_t>(p->nnel, 1), R)));
     const int64_t ngrp = int64_t(z.nc) * R;
+    p->seg_per_range = spr;
+    p->range_lds_ok = z.point && N > 0 &&
+                      int64_t(spr) * 3 * z.sbytes <= std::min<int64_t>(kRangeLdsMax, p->lds_max) ? 1 : 0;
+    p->range_lds = p->range_lds_ok;
 
     if (N > 0) {
         // camera-major: stable radix sort by (camera, landmark range)
@@ -555,25 +580,32 @@ poba_status poba_batch_create(const poba_desc* d, int32_t n_problems, const int3
     }
     hipLaunchKernelGGL(k_cam_off, dim3(grid_for(z.nc + 1)), dim3(kBlock), 0, s, b.grp_off, z.nc, R, b.cam_off);
 
-    // camera pieces: at most `piece` observations of one (camera, range) group
+    // camera pieces: at most `piece` observations of one (camera, range)
+    // group; with range-staged camera passes of one camera (the series passes
+    // then walk the groups themselves, and the per-piece kernels keep pieces
+    // of the full size)
+    const int32_t Rp = p->range_lds_ok ? 1 : R;
     {
+        const int32_t* goff = p->range_lds_ok ? b.cam_off : b.grp_off;
+        const int64_t ngp = p->range_lds_ok ? int64_t(z.nc) : ngrp;
         int32_t* counts = b.sched;  // scratch until the schedule is written
-        hipLaunchKernelGGL(k_piece_counts, dim3(grid_for(ngrp + 1)), dim3(kBlock), 0, s, b.grp_off, int32_t(ngrp),
-                           z.piece, counts);
+        hipLaunchKernelGGL(k_piece_counts, dim3(grid_for(ngp + 1)), dim3(kBlock), 0, s, goff, int32_t(ngp), z.piece,
+                           counts);
         size_t tmp = 0;
-        if (hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, counts, b.grp_piece, int(ngrp + 1), s) != hipSuccess)
+        if (hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, counts, b.grp_piece, int(ngp + 1), s) != hipSuccess)
             return fail(POBA_ERR_HIP);
         if (tmp > b.sort_tmp_bytes) return fail(POBA_ERR_WORKSPACE);
         tmp = b.sort_tmp_bytes;
-        if (hipcub::DeviceScan::ExclusiveSum(b.sort_tmp, tmp, counts, b.grp_piece, int(ngrp + 1), s) != hipSuccess)
+        if (hipcub::DeviceScan::ExclusiveSum(b.sort_tmp, tmp, counts, b.grp_piece, int(ngp + 1), s) != hipSuccess)
             return fail(POBA_ERR_HIP);
-        hipLaunchKernelGGL(k_piece_fill, dim3(grid_for(ngrp)), dim3(kBlock), 0, s, b.grp_off, b.grp_piece,
-                           int32_t(ngrp), R, z.piece, b.piece_cam, b.piece_begin, b.piece_end, b.piece_grp);
-        hipLaunchKernelGGL(k_cam_piece, dim3(grid_for(z.nc + 1)), dim3(kBlock), 0, s, b.grp_piece, z.nc, R, b.cam_piece);
+        hipLaunchKernelGGL(k_piece_fill, dim3(grid_for(ngp)), dim3(kBlock), 0, s, goff, b.grp_piece, int32_t(ngp), Rp,
+                           z.piece, b.piece_cam, b.piece_begin, b.piece_end, b.piece_grp);
+        hipLaunchKernelGGL(k_cam_piece, dim3(grid_for(z.nc + 1)), dim3(kBlock), 0, s, b.grp_piece, z.nc, Rp,
+                           b.cam_piece);
         hipLaunchKernelGGL(k_prob_pieces, dim3(grid_for(z.np + 1)), dim3(kBlock), 0, s, b.prob_cam_off, b.cam_piece,
                            z.np, b.prob_piece_off);
         int32_t np = 0;
-        if (hipMemcpyAsync(&np, b.grp_piece + ngrp, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return fail(POBA_ERR_HIP);
+        if (hipMemcpyAsync(&np, b.grp_piece + ngp, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return fail(POBA_ERR_HIP);
         if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
         if (np > z.npieces_max) return fail(POBA_ERR_STATE);
         p->npieces = np;
@@ -583,13 +615,13 @@ poba_status poba_batch_create(const poba_desc* d, int32_t n_problems, const int3
     // r % 8 == b % 8, otherwise piece b
     {
         std::vector<int32_t> sched;
-        if (R > 1 && p->npieces > 0) {
+        if (Rp > 1 && p->npieces > 0) {
             std::vector<int32_t> pgrp(size_t(p->npieces));
             if (hipMemcpyAsync(pgrp.data(), b.piece_grp, pgrp.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
                 return fail(POBA_ERR_HIP);
             if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
             std::vector<std::vector<int32_t>> lists(kXcds);
-            for (int32_t q = 0; q < int32_t(pgrp.size()); ++q) lists[(pgrp[q] % R) % kXcds].push_back(q);
+            for (int32_t q = 0; q < int32_t(pgrp.size()); ++q) lists[(pgrp[q] % Rp) % kXcds].push_back(q);
             size_t maxlen = 0;
             for (auto& l : lists) maxlen = std::max(maxlen, l.size());
             sched.assign(maxlen * kXcds, -1);
@@ -608,6 +640,74 @@ poba_status poba_batch_create(const poba_desc* d, int32_t n_problems, const int3
         hipLaunchKernelGGL(k_sched_rec, dim3(grid_for(int64_t(sched.size()))), dim3(kBlock), 0, s, b.sched,
                            b.piece_begin, b.piece_end, b.piece_cam, b.cam_prob, int64_t(sched.size()), b.sched_rec);
         if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
+    }
+    // range-staged camera pass: G workgroups per landmark range (one per
+    // compute unit in all), each with range_pass_waves wavefronts; a range's
+    // non-empty (camera, range) groups are cut, in camera order, into runs of
+    // about equal observation counts, one per wavefront, and each run is
+    // listed longest group first (so that the groups a wavefront serves side
+    // by side have similar lengths).  Neighbouring ranges run on the same die
+    // (workgroups are dealt to the dies in turn), so the cache lines that two
+    // adjacent groups of one camera share, and the staged slices, are fetched
+    // into one L2.  Group sums of empty groups stay zero.
+    if (p->range_lds_ok) {
+        std::vector<int32_t> go(size_t(ngrp) + 1);
+        std::vector<int32_t> cprob(size_t(z.nc));
+        if (hipMemcpyAsync(go.data(), b.grp_off, go.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(cprob.data(), b.cam_prob, cprob.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+            return fail(POBA_ERR_HIP);
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
+        const int waves = range_pass_waves(z.sbytes);
+        int64_t G = std::max<int64_t>(1, (p->n_cus + R / 2) / R);
+        G = std::min<int64_t>(G, kMaxRangeBlocks);
+        G = std::min<int64_t>(G, std::max<int64_t>(1, N / (int64_t(R) * waves * 256)));
+        const int64_t W = G * waves;
+        const int64_t nblk = int64_t(R) * G;
+        const int64_t per_die = R % kXcds == 0 ? R / kXcds : 0;  // consecutive ranges per die
+        std::vector<int4> rec(size_t(nblk) * waves);
+        std::vector<int4> list;
+        list.reserve(size_t(ngrp));
+        std::vector<std::pair<int32_t, int32_t>> grp;  // (length, camera) of the range's non-empty groups
+        for (int32_t r = 0; r < R; ++r) {
+            grp.clear();
+            int64_t tot = 0;
+            for (int32_t c = 0; c < z.nc; ++c) {
+                const int32_t len = go[size_t(c) * R + r + 1] - go[size_t(c) * R + r];
+                if (len > 0) {
+                    grp.emplace_back(len, c);
+                    tot += len;
+                }
+            }
+            // run w ends at the first group where the running count reaches (w+1)/W of the range
+            size_t gi = 0;
+            int64_t cum = 0;
+            for (int64_t w = 0; w < W; ++w) {
+                const size_t g0 = gi;
+                while (gi < grp.size() && (w == W - 1 || cum * W < (w + 1) * tot)) cum += grp[gi++].first;
+                std::stable_sort(grp.begin() + g0, grp.begin() + gi,
+                                 [](const std::pair<int32_t, int32_t>& x, const std::pair<int32_t, int32_t>& y) {
+                                     return x.first > y.first;
+                                 });
+                const int32_t begin = int32_t(list.size());
+                for (size_t q = g0; q < gi; ++q) {
+                    const int32_t c = grp[q].second;
+                    list.push_back(make_int4(c, go[size_t(c) * R + r], grp[q].first, cprob[size_t(c)]));
+                }
+                const int64_t j = w / waves;
+                const int64_t blk = per_die ? ((r % per_die) * G + j) * kXcds + r / per_die : int64_t(r) * G + j;
+                rec[size_t(blk) * waves + size_t(w % waves)] = make_int4(r, begin, int32_t(list.size()), 0);
+            }
+        }
+        if (int64_t(list.size()) > ngrp) return fail(POBA_ERR_STATE);
+        if (hipMemcpyAsync(b.cw_rec, rec.data(), rec.size() * sizeof(int4), hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(POBA_ERR_HIP);
+        if (!list.empty() &&
+            hipMemcpyAsync(b.cw_list, list.data(), list.size() * sizeof(int4), hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(POBA_ERR_HIP);
+        if (hipMemsetAsync(b.part_grp, 0, size_t(ngrp) * 9 * size_t(z.sbytes), s) != hipSuccess)
+            return fail(POBA_ERR_HIP);
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
+        p->cw_blocks = nblk;
     }
     // blocks of landmarks without observations are never written by a pass
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(z.nl) * 6)), dim3(kBlock), 0, s, b.V, int64_t(z.nl) * 6);
@@ -673,6 +773,11 @@ poba_status poba_set_tuning(poba_problem p, int32_t key, int32_t value) {
             if (value != 0 && value != 1) return POBA_ERR_INVALID_ARG;
             p->lds_cam = value;
             return POBA_OK;
+        case POBA_TUNE_RANGE_LDS:
+            if (value != 0 && value != 1) return POBA_ERR_INVALID_ARG;
+            if (value == 1 && !p->range_lds_ok) return POBA_ERR_INVALID_ARG;
+            p->range_lds = value;
+            return POBA_OK;
         default: return POBA_ERR_INVALID_ARG;
     }
 }
@@ -683,6 +788,7 @@ poba_status poba_get_tuning(poba_problem p, int32_t key, int32_t* value) {
         case POBA_TUNE_TILES_PER_WAVE: *value = p->tiles_per_wave; return POBA_OK;
         case POBA_TUNE_LM_RANGES: *value = p->lm_ranges; return POBA_OK;
         case POBA_TUNE_LDS_CAMERA: *value = p->lds_cam; return POBA_OK;
+        case POBA_TUNE_RANGE_LDS: *value = p->range_lds; return POBA_OK;
         default: return POBA_ERR_INVALID_ARG;
     }
 }

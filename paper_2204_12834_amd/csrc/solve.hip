@@ -739,73 +739,83 @@ __device__ __forceinline__ void lm_pass_stream_pt(const Buffers& b, const Sizes&
     const int32_t end = b.tile_start[t1];
     if (start >= end) return;
     const int32_t seg0 = b.seg_base[t0] - 1;  // segment open at the range start
+    const int32_t nch = (end - start + kWave - 1) / kWave;  // chunks of 64 positions
     uint32_t w[kPtDepth];
     TC P[kPtDepth][3], sw[kPtDepth];
     TS A[kPtDepth][6];
-    auto fetch = [&](int u, int32_t pos) {  // records of the chunk at pos into slot u
-        const int32_t i = pos + lane;
-        w[u] = 0u;
-        P[u][0] = P[u][1] = TC(0);
-        P[u][2] = TC(1);
-        sw[u] = TC(0);
-        if (i < end) {
-            w[u] = lo_cam[i];
-            load_point<TP, TC>(b.J_lo, z.npad, i, P[u], sw[u]);
-        }
+    // records of chunk c into slot u; every load is unconditional (lanes past
+    // the end read the last position and are masked where the slot is used),
+    // so a slot's registers are only ever written by its own loads
+    auto fetch = [&](int u, int32_t c) {
+        const int32_t i = min(start + c * kWave + lane, end - 1);
+        w[u] = lo_cam[i];
+        load_point<TP, TC>(b.J_lo, z.npad, i, P[u], sw[u]);
     };
+    auto flags = [&](int u, int32_t c) -> uint32_t { return start + c * kWave + lane < end ? w[u] : 0u; };
     int32_t seg_v = seg0;  // segment open at the start of the chunk whose V^-1 is requested next
-    auto request_vinv = [&](int u) {
-        const uint64_t hm = ballot64(w[u] & kHeadBit);
+    auto request_vinv = [&](int u, int32_t c) {
+        const uint32_t wu = flags(u, c);
+        const uint64_t hm = ballot64(wu & kHeadBit);
         const int32_t my = seg_v + __popcll(hm & mask_upto(lane));
-        if (w[u] & kTailBit) load_vinv(Vinv, my, A[u]);
+        if (wu & kTailBit) load_vinv(Vinv, my, A[u]);
         seg_v += __popcll(hm);
     };
 #pragma unroll
-    for (int u = 0; u < kPtDepth; ++u) fetch(u, start + u * kWave);
+    for (int u = 0; u < kPtDepth; ++u) fetch(u, u);
 #pragma unroll
     for (int u = 0; u < kPtAhead; ++u)
-        if (start + u * kWave < end) request_vinv(u);
+        if (u < nch) request_vinv(u, u);
     int32_t seg = seg0;
     TC carry[3] = {TC(0), TC(0), TC(0)};
-    for (int32_t base = start; base < end; base += kPtDepth * kWave) {
-#pragma unroll
-        for (int u = 0; u < kPtDepth; ++u) {
-            const int32_t pos = base + u * kWave;
-            if (pos >= end) break;
-            const int ua = (u + kPtAhead) % kPtDepth;
-            if (pos + kPtAhead * kWave < end) request_vinv(ua);
-            TC v[3] = {TC(0), TC(0), TC(0)};
-            const uint32_t wc = w[u];
-            if (pos + lane < end) {
-                TC c[24];
-                load_fold(fold, int64_t(wc & kIndexMask), c);
-                point_lm_term(P[u], sw[u], c, v);
-            }
-            const uint64_t hm = ballot64(wc & kHeadBit);
-            const bool head = wc & kHeadBit;
-            if (lane == 0 && !head) {
-                v[0] += carry[0];
-                v[1] += carry[1];
-                v[2] += carry[2];
-            }
-            const uint64_t hu = hm & mask_upto(lane);
-            const int seg_start = hu ? 63 - __builtin_clzll(hu) : 0;
-            segmented_scan<TC, 3>(v, lane, seg_start);
-            if (wc & kTailBit) {
-                TC Ac[6], y[3];
-#pragma unroll
-                for (int k = 0; k < 6; ++k) Ac[k] = TC(A[u][k]);
-                sym3_apply(Ac, v, y);
-                TS ys[3] = {TS(y[0]), TS(y[1]), TS(y[2])};
-                store_s(sout, seg + __popcll(hu), ys);
-            }
-            const int last = min(end - pos, kWave) - 1;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) carry[k] = __shfl(v[k], last, kWave);
-            seg += __popcll(hm);
-            fetch(u, pos + kPtDepth * kWave);
+    auto chunk = [&](auto U, int32_t c) {  // chunk c from slot u = c % kPtDepth
+        constexpr int u = decltype(U)::value;
+        constexpr int ua = (u + kPtAhead) % kPtDepth;
+        if (c + kPtAhead < nch) request_vinv(ua, c + kPtAhead);
+        const int32_t pos = start + c * kWave;
+        const uint32_t wc = flags(u, c);
+        TC v[3] = {TC(0), TC(0), TC(0)};
+        if (pos + lane < end) {
+            TC cd[24];
+            load_fold(fold, int64_t(wc & kIndexMask), cd);
+            point_lm_term(P[u], sw[u], cd, v);
         }
+        const uint64_t hm = ballot64(wc & kHeadBit);
+        const bool head = wc & kHeadBit;
+        if (lane == 0 && !head) {
+            v[0] += carry[0];
+            v[1] += carry[1];
+            v[2] += carry[2];
+        }
+        const uint64_t hu = hm & mask_upto(lane);
+        const int seg_start = hu ? 63 - __builtin_clzll(hu) : 0;
+        segmented_scan<TC, 3>(v, lane, seg_start);
+        if (wc & kTailBit) {
+            TC Ac[6], y[3];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Ac[k] = TC(A[u][k]);
+            sym3_apply(Ac, v, y);
+            TS ys[3] = {TS(y[0]), TS(y[1]), TS(y[2])};
+            store_s(sout, seg + __popcll(hu), ys);
+        }
+        const int last = min(end - pos, kWave) - 1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) carry[k] = __shfl(v[k], last, kWave);
+        seg += __popcll(hm);
+        fetch(u, c + kPtDepth);
+    };
+    // whole rounds of kPtDepth chunks, then the rest: no path re-enters the
+    // loop with a slot's load unconsumed, so no wait drains the pipeline
+    static_assert(kPtDepth == 4, "the round below is written out for four slots");
+    int32_t c = 0;
+    for (; c + kPtDepth <= nch; c += kPtDepth) {
+        chunk(std::integral_constant<int, 0>{}, c);
+        chunk(std::integral_constant<int, 1>{}, c + 1);
+        chunk(std::integral_constant<int, 2>{}, c + 2);
+        chunk(std::integral_constant<int, 3>{}, c + 3);
     }
+    if (c < nch) chunk(std::integral_constant<int, 0>{}, c);
+    if (c + 1 < nch) chunk(std::integral_constant<int, 1>{}, c + 1);
+    if (c + 2 < nch) chunk(std::integral_constant<int, 2>{}, c + 2);
 }
 
 constexpr int kPtBlock = 1024;  // persistent LDS variant: one block of 16 waves per compute unit
@@ -970,16 +980,302 @@ __global__ __launch_bounds__(NT) void k_cam_pass_pt(Buffers b, Sizes z, const TS
     }
 }
 
+// Camera pass over point records with the landmark vector staged in LDS,
+// one landmark range r per workgroup of NW wavefronts.  The workgroup copies
+// its range's slice of s into LDS (structure of arrays); each wavefront then
+// walks its list of (camera, r) groups (non-empty, sorted by length, longest
+// first) in windows of 64: lane k of a window holds group k's run in the
+// camera-major order and its camera data.  A window is taken in batches of eight groups; in a batch
+// each set of eight lanes serves one group, eight consecutive observations
+// per step (records from global memory, s from LDS), each lane summing its
+// terms; at the batch's last step every set adds its eight lanes (DPP shifts
+// within the set) and its last lane writes the group's nine sums (the
+// rotation part still without J_l(w)^T, which the finish applies per camera)
+// to the slot [range][camera][9].  Steps run as one stream across the batches
+// of a window: the records of step t + 2 and s of step t + 1 are in flight
+// while step t is added (a ring of three unrolled slots; lanes past their
+// group read position 0 with weight 0, so every load is unconditional).
+// Cameras of inactive or stopped problems contribute no group.
+constexpr int kSetLanes = 8;  // lanes per group in a batch
+
+template <typename TS, typename TC>
+struct RangeSlot {
+    int32_t seg;
+    bool valid;
+    TC P[3], sw;
+    TS s[3];
+};
+
+template <typename TP, typename TS, typename TC, int NW>
+__global__ __launch_bounds__(NW * kWave) void k_cam_pass_range(Buffers b, Sizes z, int32_t R, int32_t spr,
+                                                               int64_t nseg, const TS* __restrict__ sin,
+                                                               const Ctrl* ctrl) {
+    extern __shared__ unsigned char lds_raw[];
+    if (ctrl->running == 0) return;
+    TS* ls = reinterpret_cast<TS*>(lds_raw);  // [3][spr]
+    const int4 wr = b.cw_rec[int64_t(blockIdx.x) * NW + threadIdx.x / kWave];
+    const int32_t r = b.cw_rec[int64_t(blockIdx.x) * NW].x;
+    const int64_t seg0 = int64_t(r) * spr;
+    const int32_t nloc = int32_t(max<int64_t>(0, min<int64_t>(seg0 + spr, nseg) - seg0));
+    {
+        // the slice is at most kRangeLdsMax bytes: at most kStage landmarks per
+        // thread, all requested before the first is written
+        constexpr int kStage = int(kRangeLdsMax / (3 * sizeof(TS) * NW * kWave));
+        static_assert(int64_t(kStage) * NW * kWave * 3 * sizeof(TS) >= kRangeLdsMax, "staging covers the slice");
+        TS v[kStage][3];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int32_t k = threadIdx.x + u * NW * kWave;
+            if (k < nloc) load_s3_raw(sin, seg0 + k, v[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int32_t k = threadIdx.x + u * NW * kWave;
+            if (k < nloc) {
+                ls[k] = v[u][0];
+                ls[spr + k] = v[u][1];
+                ls[2 * spr + k] = v[u][2];
+            }
+        }
+    }
+    __syncthreads();
+    const int lane = lane_id();
+    const int set = lane / kSetLanes, sl = lane % kSetLanes;
+    TS* __restrict__ out = reinterpret_cast<TS*>(b.part_grp);
+    const int32_t* __restrict__ co_seg = b.co_seg;
+    using Slot = RangeSlot<TS, TC>;
+    for (int32_t wb = wr.y; wb < wr.z; wb += kWave) {
+        // lane k: group k of the window
+        const int32_t k = wb + lane;
+        int32_t cam = 0, start = 0, len = 0;
+        TC prm[15];  // R (9, row-major), t (3), f, k1, k2
+#pragma unroll
+        for (int q = 0; q < 15; ++q) prm[q] = TC(0);
+        {
+            // every lane reads an entry (lanes past the list the last one) and
+            // its camera data, so all these loads are in flight together
+            const int4 e = b.cw_list[min(k, wr.z - 1)];
+            cam = e.x;
+            const int2 f = *reinterpret_cast<const int2*>(&b.pctl[e.w].active);  // (active, stopped)
+            const double* rec = b.lin_rec + kCamRec * int64_t(cam);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) prm[q] = TC(rec[13 + q]);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) prm[9 + q] = TC(rec[3 + q]);
+            if (k < wr.z && f.x && !f.y) {
+                start = e.y;
+                len = e.z;
+            }
+        }
+        // steps of each batch: the longest group of its eight, in units of 8
+        int32_t nit = (len + kSetLanes - 1) / kSetLanes;
+        nit = max(nit, __shfl_xor(nit, 1, kWave));
+        nit = max(nit, __shfl_xor(nit, 2, kWave));
+        nit = max(nit, __shfl_xor(nit, 4, kWave));
+        const int nbat = int((min(wr.z - wb, kWave) + kSetLanes - 1) / kSetLanes);
+        auto steps_of = [&](int bt) -> int { return __builtin_amdgcn_readlane(nit, bt * kSetLanes); };
+        int32_t T = 0;
+        for (int bt = 0; bt < nbat; ++bt) T += steps_of(bt);
+        if (T == 0) continue;
+        auto advance = [&](int& bt, int& it) {
+            ++it;
+            while (bt < nbat && it >= steps_of(bt)) {
+                ++bt;
+                it = 0;
+            }
+        };
+        int bi = 0, ii = -1;  // issue cursor (batch, step)
+        advance(bi, ii);
+        auto issue = [&](Slot& o) {
+            const bool live = bi < nbat;
+            const int g = (live ? bi : 0) * kSetLanes + set;
+            const int32_t gs = __shfl(start, g, kWave);
+            const int32_t gl = __shfl(len, g, kWave);
+            const int32_t j = ii * kSetLanes + sl;
+            o.valid = live && j < gl;
+            const int32_t mem = o.valid ? gs + j : 0;
+            o.seg = co_seg[mem];
+            load_point<TP, TC>(b.J_co, z.npad, mem, o.P, o.sw);
+            if (live) advance(bi, ii);
+        };
+        auto gather = [&](Slot& o) {
+            const int32_t l = o.seg - int32_t(seg0);
+            const int32_t lc = (o.valid && l >= 0 && l < nloc) ? l : 0;
+            o.s[0] = ls[lc];
+            o.s[1] = ls[spr + lc];
+            o.s[2] = ls[2 * spr + lc];
+        };
+        int bc = 0, ic = -1;  // compute cursor
+        advance(bc, ic);
+        TC acc[9], cp[15];
+        auto add = [&](const Slot& o) {
+            if (ic == 0) {
+                const int g = bc * kSetLanes + set;
+#pragma unroll
+                for (int q = 0; q < 15; ++q) cp[q] = __shfl(prm[q], g, kWave);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) acc[q] = TC(0);
+            }
+            const PointShape<TC> sh(o.P, cp[12], cp[13], cp[14]);
+            const TC s0 = TC(o.s[0]), s1 = TC(o.s[1]), s2 = TC(o.s[2]);
+            const TC Rs[3] = {cp[0] * s0 + cp[1] * s1 + cp[2] * s2, cp[3] * s0 + cp[4] * s1 + cp[5] * s2,
+                              cp[6] * s0 + cp[7] * s1 + cp[8] * s2};
+            TC z0, z1, h[3];
+            sh.JP(Rs, z0, z1);
+            sh.JPt(z0, z1, h);
+            const TC w = o.valid ? o.sw * o.sw : TC(0);
+            const TC X0 = o.P[0] - cp[9], X1 = o.P[1] - cp[10], X2 = o.P[2] - cp[11];
+            const TC wpz = w * (sh.p0 * z0 + sh.p1 * z1);
+            acc[0] += w * (X1 * h[2] - X2 * h[1]);
+            acc[1] += w * (X2 * h[0] - X0 * h[2]);
+            acc[2] += w * (X0 * h[1] - X1 * h[0]);
+            acc[3] += w * h[0];
+            acc[4] += w * h[1];
+            acc[5] += w * h[2];
+            acc[6] += sh.d * wpz;
+            acc[7] += cp[12] * sh.n * wpz;
+            acc[8] += cp[12] * sh.n * sh.n * wpz;
+            if (ic == steps_of(bc) - 1) {
+                // sum of the set's eight lanes into its last lane (shifts stay inside the set)
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    acc[q] += dpp<0x111, 0xf>(acc[q]);
+                    acc[q] += dpp<0x112, 0xf>(acc[q]);
+                    acc[q] += dpp<0x114, 0xf>(acc[q]);
+                }
+                const int g = bc * kSetLanes + set;
+                const int32_t gl = __shfl(len, g, kWave);
+                const int32_t gc = __shfl(cam, g, kWave);
+                if (sl == kSetLanes - 1 && gl > 0) {
+                    TS* dst = out + (int64_t(r) * z.nc + gc) * 9;
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) dst[q] = TS(acc[q]);
+                }
+            }
+            advance(bc, ic);
+        };
+        Slot o[3];
+        auto step = [&](auto U) {
+            constexpr int u = decltype(U)::value;
+            issue(o[(u + 2) % 3]);
+            gather(o[(u + 1) % 3]);
+            add(o[u]);
+        };
+        issue(o[0]);
+        issue(o[1]);
+        gather(o[0]);
+        // whole rounds of three steps, then the rest: no path re-enters the
+        // loop with a slot's load unconsumed, so no wait drains the ring
+        int32_t t = 0;
+        for (; t + 3 <= T; t += 3) {
+            step(std::integral_constant<int, 0>{});
+            step(std::integral_constant<int, 1>{});
+            step(std::integral_constant<int, 2>{});
+        }
+        if (t < T) step(std::integral_constant<int, 0>{});
+        if (t + 1 < T) step(std::integral_constant<int, 1>{});
+    }
+}
+
+// Camera finish after a range-staged pass (series mode), one wavefront per
+// camera: the camera's group sums over the landmark ranges (lane-strided in
+// range order, then a butterfly over the wave, bit-identical on every lane),
+// the rotation part multiplied by J_l(w)^T, then v_c = U^-1 u_c, x_c += v_c,
+// the squared norms of v_c and x_c, and the folded camera data of v_c.
+// Cameras of inactive or stopped problems are left alone.
+constexpr int kFinRangeCams = kBlock / kWave;
+
+template <typename TS>
+__global__ __launch_bounds__(kBlock) void k_cam_fin_range(Buffers b, Sizes z, int32_t R, const Ctrl* ctrl) {
+    if (ctrl->running == 0) return;
+    const int lane = lane_id();
+    const int32_t c = blockIdx.x * kFinRangeCams + threadIdx.x / kWave;
+    if (c >= z.nc) return;
+    {
+        const PCtrl& q = b.pctl[b.cam_prob[c]];
+        if (!q.active || q.stopped) return;
+    }
+    const TS* __restrict__ src = reinterpret_cast<const TS*>(b.part_grp);
+    double a[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) a[k] = 0.0;
+    for (int32_t r = lane; r < R; r += kWave) {
+        const TS* g = src + (int64_t(r) * z.nc + c) * 9;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) a[k] += double(g[k]);
+    }
+    wave_sum<double, 9>(a);
+    const double* rec = b.lin_rec + kCamRec * int64_t(c);
+    double u[9];
+    {
+        // J_l(w)^T times the accumulated (P - t) x h
+        const double w0 = rec[0], w1 = rec[1], w2 = rec[2], B = rec[10], E = rec[22];
+        const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
+        const double ww[3] = {w0, w1, w2};
+        const double W[3][3] = {{0.0, -w2, w1}, {w2, 0.0, -w0}, {-w1, w0, 0.0}};
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int i2 = 0; i2 < 3; ++i2) {
+                const double jl = (i2 == j ? 1.0 - E * th2 : 0.0) + B * W[i2][j] + E * ww[i2] * ww[j];
+                t += jl * a[i2];
+            }
+            u[j] = t;
+        }
+#pragma unroll
+        for (int k = 3; k < 9; ++k) u[k] = a[k];
+    }
+    double v = 0.0, xn = 0.0;
+    if (lane < 9) {
+        const double* Ui = b.Uinv + 81 * int64_t(c) + 9 * lane;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v += Ui[k] * u[k];
+        double* xc = b.x + 9 * int64_t(c) + lane;
+        xn = *xc + v;
+        *xc = xn;
+        b.v[9 * int64_t(c) + lane] = v;
+    }
+    double vs[9], sv = 0.0, sx = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        vs[k] = __shfl(v, k, kWave);
+        const double xk = __shfl(xn, k, kWave);
+        sv += vs[k] * vs[k];
+        sx += xk * xk;
+    }
+    if (lane == 0) {
+        b.cam_red[2 * int64_t(c)] = sv;
+        b.cam_red[2 * int64_t(c) + 1] = sx;
+        fold_camera<TS>(rec, vs, reinterpret_cast<TS*>(b.vq) + 24 * int64_t(c));
+    }
+}
+
 // --------------------------------------------------------------- host side --
 
 // Camera pass of one order over the handle's records.
+// A series pass over point records (sin in the storage type) stages the
+// landmark ranges in LDS when the handle allows it; its finish is then
+// k_cam_fin_range (uses_range_pass tells which).
+inline bool uses_range_pass(const Problem* p, bool series) {
+    return series && p->range_lds && p->range_lds_ok;
+}
+
 template <typename TJ, typename TSin, typename TCL, bool PT>
-void launch_cam_pass(Problem* p, const Buffers& b, const TSin* sin, hipStream_t s) {
+void launch_cam_pass(Problem* p, const Buffers& b, const TSin* sin, hipStream_t s, bool series = false) {
     const dim3 g(unsigned(std::max<int64_t>(p->sched_len, 1)));
-    if constexpr (PT)
-        hipLaunchKernelGGL((k_cam_pass_pt<TJ, TSin, TCL, kWave>), g, dim3(kWave), 0, s, b, p->z, sin, b.ctrl);
-    else
+    if constexpr (PT) {
+        if (uses_range_pass(p, series)) {
+            constexpr int NW = range_pass_waves(sizeof(TSin));
+            const size_t lds = size_t(p->seg_per_range) * 3 * sizeof(TSin);
+            hipLaunchKernelGGL((k_cam_pass_range<TJ, TSin, TCL, NW>), dim3(unsigned(p->cw_blocks)), dim3(NW * kWave),
+                               lds, s, b, p->z, p->lm_ranges, p->seg_per_range, p->nnel, sin, b.ctrl);
+        } else {
+            hipLaunchKernelGGL((k_cam_pass_pt<TJ, TSin, TCL, kWave>), g, dim3(kWave), 0, s, b, p->z, sin, b.ctrl);
+        }
+    } else {
         hipLaunchKernelGGL((k_cam_pass<TJ, TSin>), g, dim3(kBlock), 0, s, b, p->z, sin, b.ctrl);
+    }
 }
 
 template <typename TJ, typename TCL, typename TS, bool PT>
@@ -1034,13 +1330,20 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
                 ProfScope pr(p, POBA_K_LM_PASS, s);
                 launch_lm_pass_any<TJ, TCL, TS, PT>(p, s);
             }
+            const bool range = PT && uses_range_pass(p, true);
             {
                 ProfScope pr(p, POBA_K_CAM_PASS, s);
-                launch_cam_pass<TJ, TS, TCL, PT>(p, b, reinterpret_cast<const TS*>(b.s), s);
+                launch_cam_pass<TJ, TS, TCL, PT>(p, b, reinterpret_cast<const TS*>(b.s), s, true);
             }
             {
                 ProfScope pr(p, POBA_K_CAM_FIN, s);
-                launch_cam_fin<TS>(p, b, kFinSeries, i, eps, nullptr, s);
+                if (range) {
+                    hipLaunchKernelGGL(k_cam_fin_range<TS>, dim3(unsigned(ceil_div(z.nc, kFinRangeCams))), blk, 0, s,
+                                       b, z, p->lm_ranges, b.ctrl);
+                    hipLaunchKernelGGL(k_norm_stop, dim3(unsigned(z.np)), blk, 0, s, b, kFinSeries, i, eps, b.ctrl);
+                } else {
+                    launch_cam_fin<TS>(p, b, kFinSeries, i, eps, nullptr, s);
+                }
             }
         }
     }
