@@ -332,7 +332,9 @@ poba_status poba_apply_P(poba_problem p, const double *v_in, double *v_out, poba
 
 enum {
     POBA_TUNE_TILES_PER_WAVE = 0, /* 64-observation landmark tiles per wavefront in the
-                                     landmark pass (1..64, default 4)            */
+                                     landmark pass that gathers the camera vector
+                                     from global memory (1..64, default 4); the LDS
+                                     variants split the tiles evenly instead     */
     POBA_TUNE_LM_RANGES = 1,      /* landmark ranges chosen at creation (read only) */
     POBA_TUNE_LDS_CAMERA = 2,     /* 1: landmark pass reads the camera vector from LDS when
                                      it fits in 64 KB (default); 0: from global memory */

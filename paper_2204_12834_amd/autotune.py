@@ -4,7 +4,8 @@ A measurement loop over the launch parameters that change only the
 floating-point summation order, never the result beyond it:
 
   piece_size      observations per camera-pass work item (set at creation)
-  tiles_per_wave  64-observation landmark tiles walked by one wavefront
+  tiles_per_wave  64-observation landmark tiles walked by one wavefront (the
+                  landmark pass that reads the camera vector from L2)
   lds_camera      landmark pass reads the camera vector from LDS or L2
 
 Each candidate is timed on the problem itself (a few series orders with the

@@ -251,10 +251,12 @@ __global__ __launch_bounds__(kBlock) void k_lm_pass(Buffers b, Sizes z, int tpw,
     lm_pass_range<TJ, TC, TS, false>(b, z, t0, t1, reinterpret_cast<const TS*>(b.vq), sout);
 }
 
-// Landmark pass with the camera vector staged in LDS: persistent blocks copy
-// the n_c x 9 vector once, then their wavefronts take tile groups in turn.
+// Landmark pass with the camera vector staged in LDS: as many blocks as fit
+// on the device at once copy the n_c x 9 vector, then every wavefront takes
+// one contiguous range of `per` tiles (one pipeline start per wavefront, and
+// equal work for all).
 template <typename TJ, typename TC, typename TS>
-__global__ __launch_bounds__(kBlock) void k_lm_pass_lds(Buffers b, Sizes z, int tpw, TS* __restrict__ sout,
+__global__ __launch_bounds__(kBlock) void k_lm_pass_lds(Buffers b, Sizes z, int64_t per, TS* __restrict__ sout,
                                                         const Ctrl* ctrl) {
     extern __shared__ unsigned char lds_raw[];
     if (ctrl->running == 0) return;
@@ -262,61 +264,126 @@ __global__ __launch_bounds__(kBlock) void k_lm_pass_lds(Buffers b, Sizes z, int 
     const TS* __restrict__ vq = reinterpret_cast<const TS*>(b.vq);
     for (int64_t k = threadIdx.x; k < int64_t(z.nc) * 9; k += kBlock) cv[k] = vq[12 * (k / 9) + k % 9];
     __syncthreads();
-    const int64_t ngroups = ceil_div_d(z.ntiles, tpw);
-    const int64_t nwaves = int64_t(gridDim.x) * kWavesPerBlock;
-    for (int64_t g = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave; g < ngroups; g += nwaves) {
-        const int64_t t0 = g * tpw;
-        const int64_t t1 = min(t0 + int64_t(tpw), z.ntiles);
-        lm_pass_range<TJ, TC, TS, true>(b, z, t0, t1, cv, sout);
+    const int64_t t0 = (int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave) * per;
+    if (t0 >= z.ntiles) return;
+    lm_pass_range<TJ, TC, TS, true>(b, z, t0, min(t0 + per, z.ntiles), cv, sout);
+}
+
+// One observation's record words as loaded (unpacked to the arithmetic type
+// only where they are used, so that no instruction touches a load in flight).
+template <typename TJ>
+struct RawRec;
+template <>
+struct RawRec<double> {
+    d2v g[12];
+};
+template <>
+struct RawRec<float> {
+    f4v g[6];
+};
+template <>
+struct RawRec<bf16_t> {
+    u4v g[3];
+};
+
+template <typename TJ>
+__device__ __forceinline__ void load_raw(const void* base, int64_t npad, int64_t i, RawRec<TJ>& r) {
+    using G = typename std::remove_reference<decltype(r.g[0])>::type;
+    const G* p = reinterpret_cast<const G*>(base);
+    constexpr int n = sizeof(r.g) / sizeof(r.g[0]);
+#pragma unroll
+    for (int g = 0; g < n; ++g) r.g[g] = __builtin_nontemporal_load(&p[g * npad + i]);
+}
+
+template <typename TC>
+__device__ __forceinline__ void unpack(const RawRec<double>& r, TC* v) {
+#pragma unroll
+    for (int g = 0; g < 12; ++g) {
+        v[2 * g] = TC(r.g[g].x);
+        v[2 * g + 1] = TC(r.g[g].y);
+    }
+}
+template <typename TC>
+__device__ __forceinline__ void unpack(const RawRec<float>& r, TC* v) {
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+        v[4 * g] = TC(r.g[g].x);
+        v[4 * g + 1] = TC(r.g[g].y);
+        v[4 * g + 2] = TC(r.g[g].z);
+        v[4 * g + 3] = TC(r.g[g].w);
+    }
+}
+template <typename TC>
+__device__ __forceinline__ void unpack(const RawRec<bf16_t>& r, TC* v) {
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        const uint32_t w4[4] = {r.g[g].x, r.g[g].y, r.g[g].z, r.g[g].w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[8 * g + 2 * k] = TC(bf16_to_float(uint16_t(w4[k] & 0xffffu)));
+            v[8 * g + 2 * k + 1] = TC(bf16_to_float(uint16_t(w4[k] >> 16)));
+        }
     }
 }
 
+// The stream over a range of tiles in chunks of 64 positions, as a software
+// pipeline over a ring of D record slots (three; two for float64 records):
+// while chunk c is summed, the records (camera word first, then the blocks)
+// of chunk c + D - 1 are in flight, and the V^-1 of the landmarks ending in
+// chunk c + 1 has been requested (its camera words were the first loads of
+// their group, so that request waits for nothing younger).  Every record load
+// is unconditional (lanes past the end read the last position and are masked
+// where the slot is used), and the ring is walked in whole rounds followed by
+// the remaining chunks, so no path reaches a slot's reuse with its load
+// unconsumed.
 template <typename TJ, typename TC, typename TS, bool LDS_CAM>
 __device__ __forceinline__ void lm_pass_range(const Buffers& b, const Sizes& z, int64_t t0, int64_t t1,
                                               const TS* __restrict__ vq, TS* __restrict__ sout) {
+    constexpr int D = sizeof(TJ) == 8 ? 2 : 3;
     const TS* __restrict__ Vinv = reinterpret_cast<const TS*>(b.Vinv);
     const uint32_t* __restrict__ lo_cam = b.lo_cam;
     const int lane = lane_id();
     const int32_t start = b.tile_start[t0];
     const int32_t end = b.tile_start[t1];
     if (start >= end) return;
-    int32_t seg = b.seg_base[t0] - 1;
-    auto cam_vec = [&](int64_t cam, TS* x) {
-        if (LDS_CAM) load_cam_vec_lds(vq, cam, x);
-        else load_cam_vec(vq, cam, x);
+    const int32_t nch = (end - start + kWave - 1) / kWave;
+    RawRec<TJ> rec[D];
+    uint32_t w[D];
+    TS A[2][6];
+    int32_t my_seg[2];
+    uint64_t hms[2];
+    auto fetch = [&](int u, int32_t c) {
+        const int32_t i = min(start + c * kWave + lane, end - 1);
+        w[u] = lo_cam[i];
+        load_raw<TJ>(b.J_lo, z.npad, i, rec[u]);
     };
-
-    // stage: chunk k (current)
-    uint32_t w = 0u;
-    TC J[24];
-    TS xs[9], A[6];
-    uint64_t hm;
-    int32_t my_seg;
-    {
-        const int32_t i = start + lane;
-        if (i < end) {
-            w = lo_cam[i];
-            load_J<TJ, TC>(b.J_lo, z.npad, i, J);
-        }
-        hm = ballot64(w & kHeadBit);
-        my_seg = seg + __popcll(hm & mask_upto(lane));
-        if (i < end) cam_vec(int64_t(w & kIndexMask), xs);
-        if (w & kTailBit) load_vinv(Vinv, my_seg, A);
-    }
+    auto flags = [&](int u, int32_t c) -> uint32_t { return start + c * kWave + lane < end ? w[u] : 0u; };
+    int32_t seg_v = b.seg_base[t0] - 1;  // segment open at the start of the next chunk to prepare
+    auto prep = [&](int u, int a, int32_t c) {  // chunk c (slot u): heads, segments, V^-1 request into A[a]
+        const uint32_t wu = flags(u, c);
+        const uint64_t hm = ballot64(wu & kHeadBit);
+        hms[a] = hm;
+        my_seg[a] = seg_v + __popcll(hm & mask_upto(lane));
+        if (wu & kTailBit) load_vinv(Vinv, my_seg[a], A[a]);
+        seg_v += __popcll(hm);
+    };
+#pragma unroll
+    for (int u = 0; u < D; ++u) fetch(u, u);
+    prep(0, 0, 0);
     TC carry[3] = {TC(0), TC(0), TC(0)};
-    for (int32_t base = start; base < end; base += kWave) {
-        const int32_t i = base + lane;
-        const bool valid = i < end;
-        // chunk k+1: records in flight while chunk k is reduced
-        const int32_t ni = i + kWave;
-        uint32_t wn = 0u;
-        TC Jn[24];
-        if (ni < end) {
-            wn = lo_cam[ni];
-            load_J<TJ, TC>(b.J_lo, z.npad, ni, Jn);
-        }
+    auto chunk = [&](auto U, int32_t c) {  // chunk c from record slot u = c % D, gather slot a = c % 2
+        constexpr int u = decltype(U)::value % D;
+        constexpr int a = decltype(U)::value % 2;
+        if (c + 1 < nch) prep((u + 1) % D, 1 - a, c + 1);
+        const int32_t pos = start + c * kWave;
+        const uint32_t wc = flags(u, c);
         TC v[3] = {TC(0), TC(0), TC(0)};
-        if (valid) {
+        if (pos + lane < end) {
+            TS xs[9];
+            if (LDS_CAM) load_cam_vec_lds(vq, int64_t(wc & kIndexMask), xs);
+            else load_cam_vec(vq, int64_t(wc & kIndexMask), xs);
+            TC J[24];
+            unpack<TC>(rec[u], J);
             TC q0 = TC(0), q1 = TC(0);
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
@@ -328,35 +395,47 @@ __device__ __forceinline__ void lm_pass_range(const Buffers& b, const Sizes& z, 
             v[1] = J[19] * q0 + J[22] * q1;
             v[2] = J[20] * q0 + J[23] * q1;
         }
-        const bool head = w & kHeadBit;
+        const bool head = wc & kHeadBit;
         if (lane == 0 && !head) {
             v[0] += carry[0];
             v[1] += carry[1];
             v[2] += carry[2];
         }
-        const uint64_t hu = hm & mask_upto(lane);
+        const uint64_t hu = hms[a] & mask_upto(lane);
         const int seg_start = hu ? 63 - __builtin_clzll(hu) : 0;
         segmented_scan<TC, 3>(v, lane, seg_start);
-        if (w & kTailBit) {
+        if (wc & kTailBit) {
             TC Ac[6], y[3];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) Ac[k] = TC(A[k]);
+            for (int k = 0; k < 6; ++k) Ac[k] = TC(A[a][k]);
             sym3_apply(Ac, v, y);
             TS ys[3] = {TS(y[0]), TS(y[1]), TS(y[2])};
-            store_s(sout, my_seg, ys);
+            store_s(sout, my_seg[a], ys);
         }
-        const int last = min(end - base, kWave) - 1;
+        const int last = min(end - pos, kWave) - 1;
 #pragma unroll
         for (int k = 0; k < 3; ++k) carry[k] = __shfl(v[k], last, kWave);
-        seg += __popcll(hm);
-        // advance: chunk k+1 becomes current, its gathers are issued now
-        w = wn;
-#pragma unroll
-        for (int k = 0; k < 24; ++k) J[k] = Jn[k];
-        hm = ballot64(w & kHeadBit);
-        my_seg = seg + __popcll(hm & mask_upto(lane));
-        if (ni < end) cam_vec(int64_t(w & kIndexMask), xs);
-        if (w & kTailBit) load_vinv(Vinv, my_seg, A);
+        fetch(u, c + D);
+    };
+    // rounds of lcm(D, 2) chunks keep both rings aligned
+    constexpr int RND = D == 3 ? 6 : 2;
+    int32_t c = 0;
+    for (; c + RND <= nch; c += RND) {
+        chunk(std::integral_constant<int, 0>{}, c);
+        chunk(std::integral_constant<int, 1>{}, c + 1);
+        if constexpr (RND == 6) {
+            chunk(std::integral_constant<int, 2>{}, c + 2);
+            chunk(std::integral_constant<int, 3>{}, c + 3);
+            chunk(std::integral_constant<int, 4>{}, c + 4);
+            chunk(std::integral_constant<int, 5>{}, c + 5);
+        }
+    }
+    if (c < nch) chunk(std::integral_constant<int, 0>{}, c);
+    if constexpr (RND == 6) {
+        if (c + 1 < nch) chunk(std::integral_constant<int, 1>{}, c + 1);
+        if (c + 2 < nch) chunk(std::integral_constant<int, 2>{}, c + 2);
+        if (c + 3 < nch) chunk(std::integral_constant<int, 3>{}, c + 3);
+        if (c + 4 < nch) chunk(std::integral_constant<int, 4>{}, c + 4);
     }
 }
 
@@ -373,9 +452,16 @@ void launch_lm_pass(Problem* p, hipStream_t s) {
     const size_t lds = size_t(z.nc) * 9 * sizeof(TS);
     TS* sout = reinterpret_cast<TS*>(b.s);
     if (p->lds_cam && lds <= kLdsCamMax) {
-        const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(4, (160 << 10) / int64_t(lds)));
-        const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(p->n_cus * per_cu, ceil_div(ngroups, kWavesPerBlock)));
-        hipLaunchKernelGGL((k_lm_pass_lds<TJ, TC, TS>), dim3(unsigned(nblk)), dim3(kBlock), lds, s, b, z, tpw, sout,
+        // as many persistent blocks as fit at once (registers and LDS), at most four per compute unit
+        int fit = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, k_lm_pass_lds<TJ, TC, TS>, kBlock, lds) != hipSuccess ||
+            fit < 1)
+            fit = 1;
+        const int64_t per_cu = std::min<int64_t>(4, fit);
+        const int64_t waves = p->n_cus * per_cu * kWavesPerBlock;
+        const int64_t per = std::max<int64_t>(1, ceil_div(z.ntiles, waves));
+        const int64_t nblk = std::max<int64_t>(1, ceil_div(ceil_div(z.ntiles, per), kWavesPerBlock));
+        hipLaunchKernelGGL((k_lm_pass_lds<TJ, TC, TS>), dim3(unsigned(nblk)), dim3(kBlock), lds, s, b, z, per, sout,
                            b.ctrl);
     } else {
         hipLaunchKernelGGL((k_lm_pass<TJ, TC, TS>), dim3(unsigned(ceil_div(ngroups, kWavesPerBlock))), dim3(kBlock), 0,
