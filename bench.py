@@ -43,17 +43,36 @@ KERNEL_SOURCES = ["paper_2204_12834_amd/csrc/solve.hip", "paper_2204_12834_amd/c
                   "paper_2204_12834_amd/csrc/common.hpp"]
 
 
-def series_bytes(n_obs, n_lms, prec, records="jacobian"):
+def series_bytes(n_obs, n_lms, prec, records="jacobian", range_pass=None):
     """Algorithmic bytes of one series order, per pass (dual-order design):
     landmark pass reads each observation record and camera index once and each
     V^-1 once, writes s; camera pass reads each record, landmark index and the
     gathered s once per observation.  A record is the 24 Jacobian scalars, or
-    the 4 scalars (P, sqrt(w)) of a point record."""
+    the 4 scalars (P, sqrt(w)) of a point record.  With the range-staged
+    camera pass (range_pass = (non-empty groups, observed landmarks)) the
+    camera pass reads s once per landmark as stored (4 scalars) instead of
+    once per observation, and writes 9 sums per (camera, range) group."""
     sj, sx = SJ[prec], SX[prec]
     rec = 24 * sj if records == "jacobian" else 4 * sx
     lm = n_obs * (rec + 4) + n_lms * (6 * sx + 3 * sx)
-    cam = n_obs * (rec + 4 + 3 * sx)
+    if range_pass is None:
+        cam = n_obs * (rec + 4 + 3 * sx)
+    else:
+        groups, nseg = range_pass
+        cam = n_obs * (rec + 4) + nseg * 4 * sx + groups * 9 * sx
     return lm, cam
+
+
+def range_groups(scene, R):
+    """(non-empty (camera, landmark range) groups, observed landmarks) of the
+    camera-major order with R ranges over the observed landmarks."""
+    import numpy as np
+    observed = np.bincount(scene.obs_lm, minlength=scene.n_lms) > 0
+    rank = np.cumsum(observed) - observed
+    nseg = int(observed.sum())
+    spr = max(1, -(-max(nseg, 1) // R))
+    key = scene.obs_cam.astype(np.int64) * R + rank[scene.obs_lm] // spr
+    return int(np.unique(key).size), nseg
 
 
 def kernel_source_hash():
@@ -237,10 +256,13 @@ def measure_steps(prob, cams0, lms0, scene, args, precision, records):
           + ", ".join(f"{k} {v[0] / args.steps:.3f} ms ({v[1] // args.steps})" for k, v in prof.items()),
           file=sys.stderr, flush=True)
     N, nl = scene.n_obs, scene.n_lms
-    lmb, camb = series_bytes(N, nl, precision, records)
+    rp = None
+    if records == "point" and prob.get_tuning("range_lds"):
+        rp = range_groups(scene, prob.get_tuning("lm_ranges"))
+    lmb, camb = series_bytes(N, nl, precision, records, rp)
     k = args.steps
-    # one landmark pass per order; camera pass and finish run m + 1 times
-    # (the extra one forms the reduced right-hand side)
+    # one landmark pass, camera pass and finish per order (the reduced
+    # right-hand side is timed apart)
     t_lm, n_lm = prof["landmark_pass"][0] / 1e3, prof["landmark_pass"][1]
     t_cam, n_cam = prof["camera_pass"][0] / 1e3, prof["camera_pass"][1]
     t_fin, n_fin = prof["camera_finish"][0] / 1e3, prof["camera_finish"][1]
@@ -264,7 +286,8 @@ def measure_steps(prob, cams0, lms0, scene, args, precision, records):
     phases = {name: round(v[0] / k, 4) for name, v in prof.items()}
     return {"ms_per_step": round(ms_per_step, 4), "prof": prof, "value": round(value, 1), "roofline": roofline,
             "phases": phases, "series_us_per_order": round(1e6 * (avg_lm + avg_cam + avg_fin), 2),
-            "series_bytes_per_order": lmb + camb, "records": records}
+            "series_bytes_per_order": lmb + camb, "records": records,
+            "camera_pass": "range-staged" if rp else "per-piece gather"}
 
 
 def _events():

@@ -359,12 +359,15 @@ poba_status poba_get_tuning(poba_problem p, int32_t key, int32_t *value);
 enum {
     POBA_K_LINEARIZE = 0, /* both linearisation passes                   */
     POBA_K_INVERSE = 1,   /* damped block inversions                      */
-    POBA_K_LM_PASS = 2,   /* landmark pass: t_l = W^T v, s_l = V^-1 t_l   */
-    POBA_K_CAM_PASS = 3,  /* camera pass: per-piece partial W s           */
-    POBA_K_CAM_FIN = 4,   /* camera finalize: U^-1, series sum, norms     */
+    POBA_K_LM_PASS = 2,   /* landmark pass of a series order: t_l = W^T v,
+                             s_l = V^-1 t_l                               */
+    POBA_K_CAM_PASS = 3,  /* camera pass of a series order: partial W s   */
+    POBA_K_CAM_FIN = 4,   /* camera finish of a series order: U^-1,
+                             series sum, norms, stop rule                 */
     POBA_K_BACKSUB = 5,   /* back-substitution                            */
     POBA_K_EVAL = 6,      /* trial cost and model decrease                */
-    POBA_K_OTHER = 7,
+    POBA_K_OTHER = 7,     /* the rest, among it the reduced right-hand
+                             side b~ (its camera pass and finish)         */
     POBA_K_COUNT = 8
 };
 

@@ -1404,11 +1404,9 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
     }
     if (pieces) {
         {
-            ProfScope pr(p, POBA_K_CAM_PASS, s);
+            // the reduced right-hand side (not a series order)
+            ProfScope pr(p, POBA_K_OTHER, s);
             launch_cam_pass<TJ, double, double, PT>(p, b, reinterpret_cast<const double*>(b.s), s);
-        }
-        {
-            ProfScope pr(p, POBA_K_CAM_FIN, s);
             launch_cam_fin<TS>(p, b, kFinRhs, 0, eps, nullptr, s);
         }
         for (int i = 1; i <= m; ++i) {
