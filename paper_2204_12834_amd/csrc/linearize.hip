@@ -37,17 +37,53 @@ __global__ __launch_bounds__(kBlock) void k_cam_prep(Sizes z, const double* __re
 // the block's rounded J_p rows go through LDS, where 216 threads (54 entries
 // x 4 groups) accumulate the upper triangle of J_p^T J_p (45) and J_p^T r (9)
 // in float64.  The piece's partial cost goes to its slot of piece_red.
+// Gram accumulation on the matrix cores.  The block's observations are staged
+// in LDS as rows M[2 * kBlock][kGramCols]: per observation its two J_p rows
+// (9 scalars each, as stored) with the reweighted residual in column 9.
+// Wavefront w adds M_w^T M_w over its quarter of the rows into its 16 x 16
+// float64 accumulator, four rows per v_mfma_f64_16x16x4f64: lane l supplies
+// M[r + l / 16][l % 16] as both operands (zero past column 9 and past the
+// valid rows), so the product is M^T M.  Its entry (i, j) sits in lane
+// 16 (i % 4) + j, element i / 4 (or the transposed entry, the same value of
+// the symmetric product).  U is the leading 9 x 9 block and b_p column 9.
+constexpr int kGramCols = 10;
+typedef double gram_acc __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ gram_acc gram_rows(const double* M, int r0, int r1, int rows_valid, gram_acc c) {
+    const int lane = lane_id(), kk = lane / 16, col = lane % 16;
+    // two chains of products, added at the end, halve the dependent MFMA
+    // latency; eight rows per round
+    gram_acc d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int r = r0; r < r1; r += 8) {
+        const int ra = r + kk, rb = r + 4 + kk;
+        const double xa = (col < kGramCols && ra < rows_valid) ? M[ra * kGramCols + col] : 0.0;
+        const double xb = (col < kGramCols && rb < rows_valid) ? M[rb * kGramCols + col] : 0.0;
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, xa, c, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(xb, xb, d, 0, 0, 0);
+    }
+    return c + d;
+}
+
+// The 45 upper-triangle entries of U and the 9 of b_p (in the order of the
+// per-piece partial slots) from the four wavefronts' accumulators staged in
+// red[4][64][4], added in wavefront order.
+__device__ __forceinline__ double gram_entry(const double (*red)[kWave][4], int ea, int eb) {
+    const int lane = 16 * (ea % 4) + eb, v = ea / 4;
+    return (red[0][lane][v] + red[1][lane][v]) + (red[2][lane][v] + red[3][lane][v]);
+}
+
 template <typename TJ>
 __global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
                                                     double delta, const int32_t* gate) {
-    using TL = typename std::conditional<std::is_same<TJ, double>::value, double, float>::type;
-    __shared__ TL js[kBlock][18];
-    __shared__ double rs[kBlock][2];
-    __shared__ double red[4][54];
+    __shared__ double M[2 * kBlock * kGramCols];
+    __shared__ double red[kWavesPerBlock][kWave][4];
     __shared__ double lds[kWavesPerBlock * 2];
+    static_assert(kWavesPerBlock == 4, "four wavefronts share the rows");
     if (gate && !*gate) return;
     const int t = threadIdx.x;
-    const int ent = t % 54, grp = t / 54;  // grp 4 (t >= 216) only evaluates
+    const int wv = t / kWave;
+    const int ent = t;  // threads 0..53 write the partial entries
     int ea = 0, eb = 0;
     if (ent < 45) {
         int e = ent, row = 0;
@@ -58,9 +94,11 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const do
         ea = row;
         eb = row + e;
     } else {
-        ea = ent - 45;
+        ea = ent - 45;  // b_p: column 9 of the Gram matrix
+        eb = kGramCols - 1;
     }
-    double acc = 0.0, cost = 0.0, bad = 0.0;
+    gram_acc gacc = {0.0, 0.0, 0.0, 0.0};
+    double cost = 0.0, bad = 0.0;
     const int32_t p = b.sched[blockIdx.x];
     if (p >= 0) {
         const int32_t cam = b.piece_cam[p];
@@ -88,30 +126,27 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const do
                 const double r0 = sw * ev.r[0], r1 = sw * ev.r[1];
                 b.r_co[2 * int64_t(i)] = r0;
                 b.r_co[2 * int64_t(i) + 1] = r1;
+                double* m0 = M + (2 * t) * kGramCols;
 #pragma unroll
-                for (int k = 0; k < 18; ++k) js[t][k] = TL(round_to_storage<TJ>(J[k]));
-                rs[t][0] = r0;
-                rs[t][1] = r1;
+                for (int k = 0; k < 9; ++k) {
+                    m0[k] = double(round_to_storage<TJ>(J[k]));
+                    m0[kGramCols + k] = double(round_to_storage<TJ>(J[9 + k]));
+                }
+                m0[9] = r0;
+                m0[kGramCols + 9] = r1;
             }
             __syncthreads();
-            const int cnt = min(kBlock, e - base);
-            if (grp < 4) {
-                if (ent < 45) {
-                    for (int j = grp; j < cnt; j += 4)
-                        acc += double(js[j][ea]) * double(js[j][eb]) + double(js[j][9 + ea]) * double(js[j][9 + eb]);
-                } else {
-                    for (int j = grp; j < cnt; j += 4)
-                        acc += double(js[j][ea]) * rs[j][0] + double(js[j][9 + ea]) * rs[j][1];
-                }
-            }
+            const int rows = 2 * min(kBlock, e - base);
+            gacc = gram_rows(M, wv * (2 * kBlock / kWavesPerBlock), (wv + 1) * (2 * kBlock / kWavesPerBlock), rows,
+                             gacc);
             __syncthreads();
         }
     }
-    if (grp < 4) red[grp][ent] = acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wv][lane_id()][v] = gacc[v];
     double tot[2] = {cost, bad};
     block_sum<2>(tot, lds);  // contains barriers (also publishes red)
-    if (p >= 0 && t < 54)
-        b.part[54 * int64_t(p) + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+    if (p >= 0 && t < 54) b.part[54 * int64_t(p) + t] = gram_entry(red, ea, eb);
     if (p >= 0 && t == 0) {
         b.piece_red[3 * int64_t(p)] = tot[0];
         b.piece_red[3 * int64_t(p) + 1] = tot[1];
@@ -183,13 +218,13 @@ __global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const dou
 template <typename TP>
 __global__ __launch_bounds__(kBlock) void k_lin_cam_pt(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
                                                        double delta, const int32_t* gate) {
-    __shared__ double js[kBlock][18];
-    __shared__ double rs[kBlock][2];
-    __shared__ double red[4][54];
+    __shared__ double M[2 * kBlock * kGramCols];
+    __shared__ double red[kWavesPerBlock][kWave][4];
     __shared__ double lds[kWavesPerBlock * 2];
     if (gate && !*gate) return;
     const int t = threadIdx.x;
-    const int ent = t % 54, grp = t / 54;
+    const int wv = t / kWave;
+    const int ent = t;
     int ea = 0, eb = 0;
     if (ent < 45) {
         int e = ent, row = 0;
@@ -200,9 +235,11 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam_pt(Buffers b, Sizes z, const
         ea = row;
         eb = row + e;
     } else {
-        ea = ent - 45;
+        ea = ent - 45;  // b_p: column 9 of the Gram matrix
+        eb = kGramCols - 1;
     }
-    double acc = 0.0, cost = 0.0, bad = 0.0;
+    gram_acc gacc = {0.0, 0.0, 0.0, 0.0};
+    double cost = 0.0, bad = 0.0;
     const int32_t p = b.sched[blockIdx.x];
     if (p >= 0) {
         const int32_t cam = b.piece_cam[p];
@@ -229,29 +266,27 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam_pt(Buffers b, Sizes z, const
                 const double r0 = swr * r[0], r1 = swr * r[1];
                 b.r_co[2 * int64_t(i)] = r0;
                 b.r_co[2 * int64_t(i) + 1] = r1;
+                double* m0 = M + (2 * t) * kGramCols;
 #pragma unroll
-                for (int k = 0; k < 18; ++k) js[t][k] = J[k];
-                rs[t][0] = r0;
-                rs[t][1] = r1;
+                for (int k = 0; k < 9; ++k) {
+                    m0[k] = J[k];
+                    m0[kGramCols + k] = J[9 + k];
+                }
+                m0[9] = r0;
+                m0[kGramCols + 9] = r1;
             }
             __syncthreads();
-            const int cnt = min(kBlock, e - base);
-            if (grp < 4) {
-                if (ent < 45) {
-                    for (int j = grp; j < cnt; j += 4)
-                        acc += js[j][ea] * js[j][eb] + js[j][9 + ea] * js[j][9 + eb];
-                } else {
-                    for (int j = grp; j < cnt; j += 4) acc += js[j][ea] * rs[j][0] + js[j][9 + ea] * rs[j][1];
-                }
-            }
+            const int rows = 2 * min(kBlock, e - base);
+            gacc = gram_rows(M, wv * (2 * kBlock / kWavesPerBlock), (wv + 1) * (2 * kBlock / kWavesPerBlock), rows,
+                             gacc);
             __syncthreads();
         }
     }
-    if (grp < 4) red[grp][ent] = acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wv][lane_id()][v] = gacc[v];
     double tot[2] = {cost, bad};
-    block_sum<2>(tot, lds);
-    if (p >= 0 && t < 54)
-        b.part[54 * int64_t(p) + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+    block_sum<2>(tot, lds);  // contains barriers (also publishes red)
+    if (p >= 0 && t < 54) b.part[54 * int64_t(p) + t] = gram_entry(red, ea, eb);
     if (p >= 0 && t == 0) {
         b.piece_red[3 * int64_t(p)] = tot[0];
         b.piece_red[3 * int64_t(p) + 1] = tot[1];
