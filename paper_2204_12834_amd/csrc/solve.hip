@@ -692,13 +692,17 @@ __global__ __launch_bounds__(kBlock) void k_norm_stop(Buffers b, int mode, int o
 }
 
 template <typename TS>
-void launch_cam_fin(Problem* p, const Buffers& b, int mode, int order, double eps, double* vout, hipStream_t s) {
+// `norms`: the per-problem norms (and with eps > 0 the stop rule) are needed
+// after this order; with eps = 0 only the last order's are (they go into the
+// solve info), so the others are skipped.
+void launch_cam_fin(Problem* p, const Buffers& b, int mode, int order, double eps, double* vout, hipStream_t s,
+                    bool norms = true) {
     const unsigned nblk = unsigned(ceil_div(p->z.nc, kFinCams));
     if (p->z.point)
         hipLaunchKernelGGL((k_cam_fin<TS, true>), dim3(nblk), dim3(kBlock), 0, s, b, p->z, mode, vout, b.ctrl);
     else
         hipLaunchKernelGGL((k_cam_fin<TS, false>), dim3(nblk), dim3(kBlock), 0, s, b, p->z, mode, vout, b.ctrl);
-    if (mode != kFinApply)
+    if (mode != kFinApply && norms)
         hipLaunchKernelGGL(k_norm_stop, dim3(unsigned(p->z.np)), dim3(kBlock), 0, s, b, mode, order, eps, b.ctrl);
 }
 
@@ -1407,7 +1411,7 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
             // the reduced right-hand side (not a series order)
             ProfScope pr(p, POBA_K_OTHER, s);
             launch_cam_pass<TJ, double, double, PT>(p, b, reinterpret_cast<const double*>(b.s), s);
-            launch_cam_fin<TS>(p, b, kFinRhs, 0, eps, nullptr, s);
+            launch_cam_fin<TS>(p, b, kFinRhs, 0, eps, nullptr, s, m == 0);
         }
         for (int i = 1; i <= m; ++i) {
             {
@@ -1424,9 +1428,11 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
                 if (range) {
                     hipLaunchKernelGGL(k_cam_fin_range<TS>, dim3(unsigned(ceil_div(z.nc, kFinRangeCams))), blk, 0, s,
                                        b, z, p->lm_ranges, b.ctrl);
-                    hipLaunchKernelGGL(k_norm_stop, dim3(unsigned(z.np)), blk, 0, s, b, kFinSeries, i, eps, b.ctrl);
+                    if (eps > 0.0 || i == m)
+                        hipLaunchKernelGGL(k_norm_stop, dim3(unsigned(z.np)), blk, 0, s, b, kFinSeries, i, eps,
+                                           b.ctrl);
                 } else {
-                    launch_cam_fin<TS>(p, b, kFinSeries, i, eps, nullptr, s);
+                    launch_cam_fin<TS>(p, b, kFinSeries, i, eps, nullptr, s, eps > 0.0 || i == m);
                 }
             }
         }
