@@ -386,7 +386,7 @@ struct Buffers {
     double* x;            // [nc][9] series sum
     double* bt;           // [nc][9] reduced right-hand side b~ of the last solve
     double* part;         // [npieces_max][54] per-piece partial sums
-    void* part_grp;       // [R][nc][9] storage type: per (camera, range) group sums of the camera pass
+    void* part_grp;       // [nc][R][9] storage type: per (camera, range) group sums of the camera pass
     double* dxl;          // [nl][3] landmark step (lm step)
     double* dxp;          // [nc][9] camera step (lm step)
     double* cam_rec;      // [nc][24] camera records of the state being evaluated (trial state)

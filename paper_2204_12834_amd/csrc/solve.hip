@@ -620,23 +620,34 @@ __global__ __launch_bounds__(kBlock) void k_cam_fin(Buffers b, Sizes z, int mode
     if (ctrl->running == 0) return;
     const int lc = threadIdx.x / 9, r = threadIdx.x % 9;
     const int32_t c = blockIdx.x * kFinCams + lc;
-    bool own = lc < kFinCams && c < z.nc;
+    const bool valid = lc < kFinCams && c < z.nc;
+    // every load that does not depend on the problem's state is issued before
+    // its check (camera 0 stands in for threads without a camera)
+    const int64_t cc = valid ? c : 0;
+    const int32_t prob = b.cam_prob[cc];
+    const int32_t q0 = b.cam_piece[cc], q1 = b.cam_piece[cc + 1];
+    double Ui[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Ui[k] = b.Uinv[81 * cc + 9 * r + k];
+    const double xo = b.x[9 * cc + r];
+    const double bpr = b.bp[9 * cc + r];
+    bool own = valid;
     if (own) {
-        const PCtrl& q = b.pctl[b.cam_prob[c]];
+        const PCtrl& q = b.pctl[prob];
         own = q.active && !q.stopped;
     }
     if (own) {
         double u = 0.0;
-        for (int32_t q = b.cam_piece[c]; q < b.cam_piece[c + 1]; ++q) u += b.part[9 * int64_t(q) + r];
+#pragma unroll 4
+        for (int32_t q = q0; q < q1; ++q) u += b.part[9 * int64_t(q) + r];
         if (mode == kFinRhs) {
-            u = b.bp[9 * int64_t(c) + r] - u;
+            u = bpr - u;
             b.bt[9 * int64_t(c) + r] = u;
         }
         us[lc][r] = u;
     }
     __syncthreads();
     if (own) {
-        const double* Ui = b.Uinv + 81 * int64_t(c) + 9 * r;
         double sacc = 0.0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) sacc += Ui[k] * us[lc][k];
@@ -645,7 +656,7 @@ __global__ __launch_bounds__(kBlock) void k_cam_fin(Buffers b, Sizes z, int mode
             vout[9 * int64_t(c) + r] = v;
         } else {
             double* xc = b.x + 9 * int64_t(c) + r;
-            const double xn = mode == kFinRhs ? v : *xc + v;
+            const double xn = mode == kFinRhs ? v : xo + v;
             *xc = xn;
             b.v[9 * int64_t(c) + r] = v;
             if (FOLD) vs[lc][r] = v;
@@ -1081,7 +1092,7 @@ __global__ __launch_bounds__(NT) void k_cam_pass_pt(Buffers b, Sizes z, const TS
 // terms; at the batch's last step every set adds its eight lanes (DPP shifts
 // within the set) and its last lane writes the group's nine sums (the
 // rotation part still without J_l(w)^T, which the finish applies per camera)
-// to the slot [range][camera][9].  Steps run as one stream across the batches
+// to the slot [camera][range][9].  Steps run as one stream across the batches
 // of a window: the records of step t + 2 and s of step t + 1 are in flight
 // while step t is added (a ring of three unrolled slots; lanes past their
 // group read position 0 with weight 0, so every load is unconditional).
@@ -1237,7 +1248,7 @@ __global__ __launch_bounds__(NW * kWave) void k_cam_pass_range(Buffers b, Sizes 
                 const int32_t gl = __shfl(len, g, kWave);
                 const int32_t gc = __shfl(cam, g, kWave);
                 if (sl == kSetLanes - 1 && gl > 0) {
-                    TS* dst = out + (int64_t(r) * z.nc + gc) * 9;
+                    TS* dst = out + (int64_t(gc) * R + r) * 9;
 #pragma unroll
                     for (int q = 0; q < 9; ++q) dst[q] = TS(acc[q]);
                 }
@@ -1281,25 +1292,36 @@ __global__ __launch_bounds__(kBlock) void k_cam_fin_range(Buffers b, Sizes z, in
     const int lane = lane_id();
     const int32_t c = blockIdx.x * kFinRangeCams + threadIdx.x / kWave;
     if (c >= z.nc) return;
-    {
-        const PCtrl& q = b.pctl[b.cam_prob[c]];
-        if (!q.active || q.stopped) return;
-    }
+    // every load that does not depend on the problem's state is issued before
+    // its check, so the camera's data arrive in one round trip
+    const int32_t prob = b.cam_prob[c];
     const TS* __restrict__ src = reinterpret_cast<const TS*>(b.part_grp);
     double a[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) a[k] = 0.0;
     for (int32_t r = lane; r < R; r += kWave) {
-        const TS* g = src + (int64_t(r) * z.nc + c) * 9;
+        const TS* g = src + (int64_t(c) * R + r) * 9;
 #pragma unroll
         for (int k = 0; k < 9; ++k) a[k] += double(g[k]);
     }
-    wave_sum<double, 9>(a);
     const double* rec = b.lin_rec + kCamRec * int64_t(c);
+    const double w0 = rec[0], w1 = rec[1], w2 = rec[2], B = rec[10], E = rec[22];
+    double Ui[9], xo = 0.0;
+    {
+        const int row = lane < 9 ? lane : 0;
+        const double* Up = b.Uinv + 81 * int64_t(c) + 9 * row;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Ui[k] = Up[k];
+        xo = b.x[9 * int64_t(c) + row];
+    }
+    {
+        const PCtrl& q = b.pctl[prob];
+        if (!q.active || q.stopped) return;
+    }
+    wave_sum<double, 9>(a);
     double u[9];
     {
         // J_l(w)^T times the accumulated (P - t) x h
-        const double w0 = rec[0], w1 = rec[1], w2 = rec[2], B = rec[10], E = rec[22];
         const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
         const double ww[3] = {w0, w1, w2};
         const double W[3][3] = {{0.0, -w2, w1}, {w2, 0.0, -w0}, {-w1, w0, 0.0}};
@@ -1318,12 +1340,10 @@ __global__ __launch_bounds__(kBlock) void k_cam_fin_range(Buffers b, Sizes z, in
     }
     double v = 0.0, xn = 0.0;
     if (lane < 9) {
-        const double* Ui = b.Uinv + 81 * int64_t(c) + 9 * lane;
 #pragma unroll
         for (int k = 0; k < 9; ++k) v += Ui[k] * u[k];
-        double* xc = b.x + 9 * int64_t(c) + lane;
-        xn = *xc + v;
-        *xc = xn;
+        xn = xo + v;
+        b.x[9 * int64_t(c) + lane] = xn;
         b.v[9 * int64_t(c) + lane] = v;
     }
     double vs[9], sv = 0.0, sx = 0.0;
