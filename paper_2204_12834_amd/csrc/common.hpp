@@ -395,6 +395,7 @@ struct Buffers {
     double* lms_new;      // [nl][3]
     double* piece_red;    // [npieces_max][3] per-piece partial sums (cost, model, flags)
     double* cam_red;      // [nc][2] per-camera squared norms of v and x
+    double* xq;           // [nc][24] folded camera data of the camera step (point-record back-substitution)
     // independent problems: contiguous camera and landmark ranges
     int32_t* prob_cam_off;   // [np+1]
     int32_t* prob_lm_off;    // [np+1]

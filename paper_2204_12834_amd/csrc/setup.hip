@@ -132,6 +132,7 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.lms_new = (double*)take(nl * 3 * 8);
     t.piece_red = (double*)take(size_t(z.npieces_max) * 3 * 8);
     t.cam_red = (double*)take(nc * 2 * 8);
+    t.xq = (double*)take(nc * 24 * 8);
     const size_t np1 = size_t(z.np) + 1;
     t.prob_cam_off = (int32_t*)take(np1 * 4);
     t.prob_lm_off = (int32_t*)take(np1 * 4);

@@ -469,6 +469,62 @@ void launch_lm_pass(Problem* p, hipStream_t s) {
     }
 }
 
+// Folded camera data (24 slots) of camera `cam` from LDS or global memory.
+template <typename TS, typename TC>
+__device__ __forceinline__ void load_fold(const TS* src, int64_t cam, TC* c) {
+    if constexpr (std::is_same<TS, float>::value) {
+        const float4* q = reinterpret_cast<const float4*>(src + 24 * cam);
+#pragma unroll
+        for (int g = 0; g < 6; ++g) {
+            const float4 x = q[g];
+            c[4 * g] = TC(x.x);
+            c[4 * g + 1] = TC(x.y);
+            c[4 * g + 2] = TC(x.z);
+            c[4 * g + 3] = TC(x.w);
+        }
+    } else {
+        const double2* q = reinterpret_cast<const double2*>(src + 24 * cam);
+#pragma unroll
+        for (int g = 0; g < 12; ++g) {
+            const double2 x = q[g];
+            c[2 * g] = TC(x.x);
+            c[2 * g + 1] = TC(x.y);
+        }
+    }
+}
+
+// J_l^T J_p v of one observation from its point record and folded camera data.
+template <typename TC>
+__device__ __forceinline__ void point_lm_term(const TC* P, TC sw, const TC* c, TC* v) {
+    const PointShape<TC> sh(P, c[9], c[10], c[11]);
+    TC wv[3];
+    wv[0] = c[1] * P[2] - c[2] * P[1] + c[3];
+    wv[1] = c[2] * P[0] - c[0] * P[2] + c[4];
+    wv[2] = c[0] * P[1] - c[1] * P[0] + c[5];
+    TC q0, q1;
+    sh.JP(wv, q0, q1);
+    const TC ci = sh.d * c[6] + c[9] * sh.n * (c[7] + sh.n * c[8]);
+    q0 += ci * sh.p0;
+    q1 += ci * sh.p1;
+    TC g[3];
+    sh.JPt(q0, q1, g);
+    const TC w = sw * sw;
+    // R^T g with R row-major in c[12..20]
+    v[0] = w * (c[12] * g[0] + c[15] * g[1] + c[18] * g[2]);
+    v[1] = w * (c[13] * g[0] + c[16] * g[1] + c[19] * g[2]);
+    v[2] = w * (c[14] * g[0] + c[17] * g[1] + c[20] * g[2]);
+}
+
+// Folded camera data of the camera step x (float64), for the back-substitution
+// over point records.
+__global__ __launch_bounds__(kBlock) void k_fold_x(Buffers b, Sizes z, const double* __restrict__ x,
+                                                   const Ctrl* ctrl) {
+    if (!ctrl->active) return;
+    const int32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= z.nc) return;
+    fold_camera<double>(b.lin_rec + kCamRec * int64_t(c), x + 9 * int64_t(c), b.xq + 24 * int64_t(c));
+}
+
 // Back-substitution dx_l = -V_lambda^-1 (b_l + sum_{i in l} J_l^T J_p x_c) in
 // float64 with V_lambda^-1 recomputed from the float64 V.
 template <typename TJ, bool PT>
@@ -482,18 +538,26 @@ __global__ __launch_bounds__(kBlock) void k_backsub(Buffers b, Sizes z, const do
         [&](int32_t i, bool valid, int32_t cam, int32_t, double* v) {
             v[0] = v[1] = v[2] = 0.0;
             if (!valid) return;
-            double J[24];
-            Rec<TJ, PT>::template jac<double>(b, z, b.J_lo, i, cam, J);
-            const double* vc = x + 9 * int64_t(cam);
-            double q0 = 0.0, q1 = 0.0;
+            if constexpr (PT) {
+                // J_l^T J_p x from the point record and the camera's folded x (float64)
+                double P[3], sw, c[24];
+                load_point<TJ, double>(b.J_lo, z.npad, i, P, sw);
+                load_fold(b.xq, int64_t(cam), c);
+                point_lm_term(P, sw, c, v);
+            } else {
+                double J[24];
+                Rec<TJ, PT>::template jac<double>(b, z, b.J_lo, i, cam, J);
+                const double* vc = x + 9 * int64_t(cam);
+                double q0 = 0.0, q1 = 0.0;
 #pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                q0 += J[k] * vc[k];
-                q1 += J[9 + k] * vc[k];
+                for (int k = 0; k < 9; ++k) {
+                    q0 += J[k] * vc[k];
+                    q1 += J[9 + k] * vc[k];
+                }
+                v[0] = J[18] * q0 + J[21] * q1;
+                v[1] = J[19] * q0 + J[22] * q1;
+                v[2] = J[20] * q0 + J[23] * q1;
             }
-            v[0] = J[18] * q0 + J[21] * q1;
-            v[1] = J[19] * q0 + J[22] * q1;
-            v[2] = J[20] * q0 + J[23] * q1;
         },
         [&](int32_t seg, const double* t) {
             const int64_t l = b.nel[seg];
@@ -772,52 +836,6 @@ __global__ __launch_bounds__(kBlock) void k_load_v(Buffers b, Sizes z, const dou
 //   camera pass:   J_l s = J_P (R s); J_p^T z = (J_l(w)^T ((P - t) x h), h,
 //                  (d, f n, f n^2) p.z) with h = J_P^T z, the rotation part
 //                  multiplied by J_l(w)^T once per piece.
-
-// Folded camera data (24 slots) of camera `cam` from LDS or global memory.
-template <typename TS, typename TC>
-__device__ __forceinline__ void load_fold(const TS* src, int64_t cam, TC* c) {
-    if constexpr (std::is_same<TS, float>::value) {
-        const float4* q = reinterpret_cast<const float4*>(src + 24 * cam);
-#pragma unroll
-        for (int g = 0; g < 6; ++g) {
-            const float4 x = q[g];
-            c[4 * g] = TC(x.x);
-            c[4 * g + 1] = TC(x.y);
-            c[4 * g + 2] = TC(x.z);
-            c[4 * g + 3] = TC(x.w);
-        }
-    } else {
-        const double2* q = reinterpret_cast<const double2*>(src + 24 * cam);
-#pragma unroll
-        for (int g = 0; g < 12; ++g) {
-            const double2 x = q[g];
-            c[2 * g] = TC(x.x);
-            c[2 * g + 1] = TC(x.y);
-        }
-    }
-}
-
-// J_l^T J_p v of one observation from its point record and folded camera data.
-template <typename TC>
-__device__ __forceinline__ void point_lm_term(const TC* P, TC sw, const TC* c, TC* v) {
-    const PointShape<TC> sh(P, c[9], c[10], c[11]);
-    TC wv[3];
-    wv[0] = c[1] * P[2] - c[2] * P[1] + c[3];
-    wv[1] = c[2] * P[0] - c[0] * P[2] + c[4];
-    wv[2] = c[0] * P[1] - c[1] * P[0] + c[5];
-    TC q0, q1;
-    sh.JP(wv, q0, q1);
-    const TC ci = sh.d * c[6] + c[9] * sh.n * (c[7] + sh.n * c[8]);
-    q0 += ci * sh.p0;
-    q1 += ci * sh.p1;
-    TC g[3];
-    sh.JPt(q0, q1, g);
-    const TC w = sw * sw;
-    // R^T g with R row-major in c[12..20]
-    v[0] = w * (c[12] * g[0] + c[15] * g[1] + c[18] * g[2]);
-    v[1] = w * (c[13] * g[0] + c[16] * g[1] + c[19] * g[2]);
-    v[2] = w * (c[14] * g[0] + c[17] * g[1] + c[20] * g[2]);
-}
 
 // Landmark pass over point records, one wavefront over the positions of a
 // contiguous range of tiles in chunks of 64, as a software pipeline: the
@@ -1459,6 +1477,7 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
     }
     {
         ProfScope pr(p, POBA_K_BACKSUB, s);
+        if constexpr (PT) hipLaunchKernelGGL(k_fold_x, g_cam, blk, 0, s, b, z, b.x, b.ctrl);
         hipLaunchKernelGGL((k_backsub<TJ, PT>), g_tiles, blk, 0, s, b, z, b.x, dx_lms, b.ctrl);
         hipLaunchKernelGGL(k_zero_empty, g_lm, blk, 0, s, b, z, dx_lms, b.ctrl);
         const int64_t nfin = std::max<int64_t>(int64_t(z.nc) * 9, z.np);

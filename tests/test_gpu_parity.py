@@ -143,6 +143,12 @@ def test_power_solve_f64(name, lam, m):
     from paper_2204_12834_amd.solver import read_solve_info
     inf = read_solve_info(info)
     assert inf["stop_order"] == m and inf["stopped"] == 0 and inf["status"] == 0
+    # the norms of the last order (x(m) and its term v_m = x(m) - x(m-1))
+    it = ref.series.iterates
+    nx = np.linalg.norm(it[-1])
+    vm = it[-1] - it[-2] if m > 0 else it[-1]
+    assert abs(inf["norm_x"] - nx) <= 1e-10 * nx
+    assert abs(inf["norm_v"] - np.linalg.norm(vm)) <= 1e-10 * nx
 
 
 @pytest.mark.parametrize("damping", ["marquardt", "identity"])
