@@ -85,8 +85,22 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def make_scene(workload):
+class FileScene:
+    """A problem read from a BAL file: observations and initial state as given."""
+
+    def __init__(self, path):
+        from paper_2204_12834_amd import bal
+        p = bal.read(path)
+        self.name = f"bal file {p.name}"
+        self.n_cams, self.n_lms, self.n_obs = p.n_cams, p.n_lms, p.n_obs
+        self.obs_cam, self.obs_lm, self.obs_xy = p.obs_cam, p.obs_lm, p.obs_xy
+        self.cams0, self.lms0 = p.cams, p.lms
+
+
+def make_scene(workload, huber=0.0):
     from paper_2204_12834_amd import synth
+    if workload.startswith("bal:"):
+        return FileScene(workload[4:]), (huber or None)
     if workload == "c3":
         return synth.config("c3"), 3.0
     if workload == "c3s":  # reduced city for quick checks
@@ -98,16 +112,20 @@ def make_scene(workload):
 
 # --------------------------------------------------------------- CPU leg ----
 
-def cpu_baseline_child(workload, m, sample_lms):
+def cpu_baseline_child(workload, m, sample_lms, huber=0.0):
     """Oracle (float64 NumPy) series on a landmark subset, single thread."""
     import numpy as np
     import oracle
     from oracle import camera, lm as olm, schur
-    scene, delta = make_scene(workload)
+    scene, delta = make_scene(workload, huber)
+    sample_lms = min(sample_lms, scene.n_lms)
     keep = scene.obs_lm < sample_lms
     oc, ol = scene.obs_cam[keep], scene.obs_lm[keep]
     cams0, lms0 = scene.cams0, scene.lms0[:sample_lms]
-    obs = camera.project(scene.cams_gt, scene.lms_gt[:sample_lms], oc, ol) + scene.noise[keep]
+    if isinstance(scene, FileScene):
+        obs = scene.obs_xy[keep]
+    else:
+        obs = camera.project(scene.cams_gt, scene.lms_gt[:sample_lms], oc, ol) + scene.noise[keep]
     F, r, Jp, Jl = olm.linearize(cams0, lms0, oc, ol, obs, delta)
     from oracle import normal
     U, V, bp, bl = normal.assemble(Jp, Jl, r, oc, ol, scene.n_cams, sample_lms)
@@ -132,11 +150,11 @@ def cpu_baseline_child(workload, m, sample_lms):
     print(json.dumps(out))
 
 
-def run_cpu_baseline(workload, m, sample_lms):
+def run_cpu_baseline(workload, m, sample_lms, huber=0.0):
     env = dict(os.environ, OMP_NUM_THREADS="1", MKL_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
                HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", "--workload", workload, "--m", str(m),
-           "--sample-lms", str(sample_lms)]
+           "--sample-lms", str(sample_lms), "--huber", str(huber)]
     res = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=900)
     if res.returncode != 0:
         print(res.stderr[-2000:], file=sys.stderr)
@@ -149,8 +167,11 @@ def run_cpu_baseline(workload, m, sample_lms):
 def gpu_setup(scene, delta, precision, dev, records="jacobian"):
     import torch
     from paper_2204_12834_amd.solver import Problem, project
-    obs = project(scene.obs_cam, scene.obs_lm, scene.cams_gt, scene.lms_gt, device=dev)
-    obs += torch.as_tensor(scene.noise, device=dev)
+    if isinstance(scene, FileScene):
+        obs = torch.as_tensor(scene.obs_xy, dtype=torch.float64, device=dev)
+    else:
+        obs = project(scene.obs_cam, scene.obs_lm, scene.cams_gt, scene.lms_gt, device=dev)
+        obs += torch.as_tensor(scene.noise, device=dev)
     prob = Problem(scene.obs_cam, scene.obs_lm, obs, scene.n_cams, scene.n_lms, precision=precision,
                    loss="huber" if delta else "l2", huber_delta=delta or 0.0, device=dev, records=records)
     cams0 = torch.as_tensor(scene.cams0, dtype=torch.float64, device=dev)
@@ -490,7 +511,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--workload", default="c3",
+                    help="c3 (default), c2, c3s, c4, c5, or bal:PATH for a problem in the BAL text format")
+    ap.add_argument("--huber", type=float, default=0.0, help="Huber delta in pixels for a bal: workload (0: squared loss)")
     ap.add_argument("--precision", default="f32", choices=["f64", "f32", "bf16"])
     ap.add_argument("--records", default="jacobian", choices=["jacobian", "point"],
                     help="per-observation records: Jacobian blocks, or camera-frame points the passes rebuild them from")
@@ -506,7 +529,7 @@ def main():
     args = ap.parse_args()
 
     if args.cpu_baseline_child:
-        cpu_baseline_child(args.workload, args.m, args.sample_lms)
+        cpu_baseline_child(args.workload, args.m, args.sample_lms, args.huber)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -525,7 +548,7 @@ def main():
     if args.workload == "c5":
         return bench_adjoint(args, dev)
     t_gen = time.perf_counter()
-    scene, delta = make_scene(args.workload)
+    scene, delta = make_scene(args.workload, args.huber)
     print(f"[bench] scene {scene.name}: {scene.n_cams} cams, {scene.n_lms} lms, {scene.n_obs} obs "
           f"({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
 
@@ -614,8 +637,12 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = run_cpu_baseline(args.workload, args.m, args.sample_lms)
+        cpu = run_cpu_baseline(args.workload, args.m, args.sample_lms, args.huber)
 
+    if isinstance(scene, FileScene):
+        loss_text = f"Huber delta {delta:g} px, " if delta else ""
+    else:
+        loss_text = "Huber delta 3 px, 2% outliers, " if delta else ""
     line = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -628,9 +655,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.precision,
-        "data": "synthetic",
+        "data": "file" if isinstance(scene, FileScene) else "synthetic",
         "config": {"workload": f"{scene.name}: {nc} cameras, {nl} landmarks, {N} observations, "
-                               f"{'Huber delta 3 px, 2% outliers, ' if delta else ''}m={args.m}, "
+                               f"{loss_text}m={args.m}, "
                                f"{args.precision} {'Jacobian blocks' if args.records == 'jacobian' else 'point records'}"
                                f", one LM iteration per step",
                    "n_cams": nc, "n_lms": nl, "n_obs": N, "m": args.m, "precision": args.precision,
