@@ -214,6 +214,47 @@ poba_status poba_linearize(poba_problem p, const double *cams, const double *lms
 poba_status poba_power_solve(poba_problem p, double lambda, int32_t m, double eps, double *dx_cams,
                              double *dx_lms, poba_solve_info *info, poba_stream stream);
 
+/* ---- preconditioned conjugate gradients (the comparison of Sec. 2) ----- */
+
+/* Preconditioners M^-1 of poba_pcg_solve (Sec. 2, Fig. 2). */
+enum {
+    POBA_PRECOND_NONE = 0,          /* the identity                                    */
+    POBA_PRECOND_SCHUR_JACOBI = 1,  /* inverted 9x9 diagonal blocks of S               */
+    POBA_PRECOND_POWER = 2          /* S~(m) = sum_{i<=m} P^i U^-1 (eq. S_approx)      */
+};
+
+/* [dev] Written by poba_pcg_solve, one per problem of the handle. */
+typedef struct {
+    int32_t iterations;   /* CG iterations taken                                    */
+    int32_t converged;    /* 1 if |r| <= tol |b~| was reached                       */
+    int32_t status;       /* OR of POBA_ERR_* bits seen on the device               */
+    int32_t reserved;
+    double rel_residual;  /* |r| / |b~| of the recursion at the last iterate        */
+    double rz;            /* r . M^-1 r at the last iterate                         */
+} poba_pcg_info;
+
+/* The damped step of poba_power_solve with the camera step from conjugate
+ * gradients (Hestenes-Stiefel, x_0 = 0) on the reduced camera system
+ * S dx_p = -b~ (eqs. Schur, Sx), S = U_lambda - W V_lambda^-1 W^T applied
+ * matrix-free in float64 (stored blocks widened, V^-1 recomputed in float64),
+ * preconditioned by `precond` (POBA_PRECOND_*; the power series runs order
+ * m in the storage precision, as poba_power_solve does, costing m
+ * applications of P per iteration).  Each problem iterates until
+ * |r_k| <= tol |b~| or max_iters; then dx_l = -V^-1 (b_l + W^T dx_p).
+ * dx_cams [dev] float64 [n_cams][9], dx_lms [dev] float64 [n_lms][3],
+ * info [dev] [n_problems] (may be NULL), coeffs [dev] float64
+ * [max_iters][n_problems][2] (may be NULL): alpha_k and beta_k of iteration
+ * k + 1 per problem (the Lanczos coefficients behind a condition-number
+ * estimate of M^-1 S; entries of iterations not taken, and the beta of the
+ * last one, are left as they were).  lambda > 0, tol >= 0,
+ * 0 <= max_iters <= 1000000, 0 <= m <= 100000 for the power series.
+ * Synchronises the stream every four iterations to end the loop once every
+ * problem has converged; not for graph capture.  A non-positive p.q or r.z
+ * ends that problem's iteration with POBA_ERR_NOT_SPD in its status. */
+poba_status poba_pcg_solve(poba_problem p, double lambda, int32_t precond, int32_t m, double tol,
+                           int32_t max_iters, double *dx_cams, double *dx_lms, poba_pcg_info *info,
+                           double *coeffs, poba_stream stream);
+
 /* Resets the LM states st [dev] [n_problems]: lambda = lambda0, nu = 2,
  * iteration 0, needs a linearisation, not done. */
 poba_status poba_lm_init(poba_problem p, poba_lm_state *st, const poba_lm_options *o,

@@ -25,6 +25,7 @@ DAMPING = {"marquardt": 0, "identity": 1}
 RECORDS = {"jacobian": 0, "point": 1}
 LOSS = {"l2": 0, "huber": 1}
 TUNING = {"tiles_per_wave": 0, "lm_ranges": 1, "lds_camera": 2, "range_lds": 3}
+PRECOND = {"none": 0, "schur_jacobi": 1, "power": 2}
 KERNEL_CLASSES = ["linearize", "inverse", "landmark_pass", "camera_pass", "camera_finish", "backsub", "eval", "other"]
 
 
@@ -51,6 +52,17 @@ class PobaSolveInfo(ctypes.Structure):
         ("reserved", ctypes.c_int32),
         ("norm_x", ctypes.c_double),
         ("norm_v", ctypes.c_double),
+    ]
+
+
+class PobaPCGInfo(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("rel_residual", ctypes.c_double),
+        ("rz", ctypes.c_double),
     ]
 
 
@@ -107,6 +119,7 @@ SIGNATURES = {
     "poba_destroy": (I32, [P]),
     "poba_linearize": (I32, [P, P, P, P, P]),
     "poba_power_solve": (I32, [P, F64, I32, F64, P, P, P, P]),
+    "poba_pcg_solve": (I32, [P, F64, I32, I32, F64, I32, P, P, P, P, P]),
     "poba_lm_init": (I32, [P, P, ctypes.POINTER(PobaLMOptions), P]),
     "poba_lm_step": (I32, [P, P, P, P, ctypes.POINTER(PobaLMOptions), P]),
     "poba_project": (I32, [I64, P, P, P, P, P, P]),

@@ -332,6 +332,18 @@ struct PCtrl {
     int32_t pad;
 };
 
+// Per-problem state of preconditioned conjugate gradients on the reduced
+// camera system.
+struct PcgCtl {
+    double rz;          // r . z of the current residual
+    double b2;          // |b|^2 of the right-hand side
+    double r2;          // |r|^2 of the current residual
+    double alpha, beta; // coefficients of the last iteration
+    int32_t iterations; // iterations taken
+    int32_t converged;  // |r| <= tol |b| reached
+    int32_t pad[2];
+};
+
 // One camera-pass work item as a block reads it in a single request: the
 // piece (-1: idle slot), its camera-major range, camera and problem.
 struct alignas(32) PieceRec {
@@ -396,6 +408,9 @@ struct Buffers {
     double* piece_red;    // [npieces_max][3] per-piece partial sums (cost, model, flags)
     double* cam_red;      // [nc][2] per-camera squared norms of v and x
     double* xq;           // [nc][24] folded camera data of the camera step (point-record back-substitution)
+    double* cg;           // [5][nc][9] conjugate-gradient vectors x, r, z, p, q
+    double* sj;           // [nc][81] inverted diagonal blocks of S (Schur-Jacobi preconditioner)
+    PcgCtl* pcg_ctl;      // [np]
     // independent problems: contiguous camera and landmark ranges
     int32_t* prob_cam_off;   // [np+1]
     int32_t* prob_lm_off;    // [np+1]

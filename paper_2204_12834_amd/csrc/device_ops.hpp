@@ -260,6 +260,57 @@ __device__ __forceinline__ bool inv3_damped(const double* V, double lam, const d
     return ok;
 }
 
+// Inverse of a symmetric positive definite 9x9 matrix in float64 by Cholesky
+// factorisation A = L L^T and A^-1 = L^-T L^-1.  L holds A (row-major) on
+// entry and its factor on return; out receives the 81 entries of A^-1.
+// Returns false if a pivot is not positive or an entry is not finite.
+__device__ __forceinline__ bool spd_inverse9(double* L, double* out) {
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        double d = L[9 * j + j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= L[9 * j + k] * L[9 * j + k];
+        ok = ok && d > 0.0;
+        const double ljj = sqrt(d);
+        L[9 * j + j] = ljj;
+#pragma unroll
+        for (int i = j + 1; i < 9; ++i) {
+            double sacc = L[9 * i + j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) sacc -= L[9 * i + k] * L[9 * j + k];
+            L[9 * i + j] = sacc / ljj;
+        }
+    }
+    double M[81];  // L^-1, lower
+#pragma unroll
+    for (int k = 0; k < 81; ++k) M[k] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        M[9 * j + j] = 1.0 / L[9 * j + j];
+#pragma unroll
+        for (int i = j + 1; i < 9; ++i) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int k = j; k < i; ++k) sacc -= L[9 * i + k] * M[9 * k + j];
+            M[9 * i + j] = sacc / L[9 * i + i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+#pragma unroll
+        for (int j = i; j < 9; ++j) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int k = j; k < 9; ++k) sacc += M[9 * k + i] * M[9 * k + j];
+            ok = ok && isfinite(sacc);
+            out[9 * i + j] = sacc;
+            out[9 * j + i] = sacc;
+        }
+    }
+    return ok;
+}
+
 template <typename T>
 __device__ __forceinline__ void sym3_apply(const T* A, const T* x, T* y) {
     y[0] = A[0] * x[0] + A[1] * x[1] + A[2] * x[2];

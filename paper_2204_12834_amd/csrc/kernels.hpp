@@ -26,4 +26,19 @@ poba_status launch_solve(Problem* p, int m, double eps, double* dx_cams, double*
 // Makes every problem active with damping lam and clears the series flags.
 poba_status launch_begin_solve(Problem* p, double lam, hipStream_t s);
 
+// Building blocks of the conjugate-gradient solver (each covers the active
+// problems of the handle):
+//  - damped inverses and b~ (into b.bt), as a power solve computes them;
+//  - orders 1..m of the power series from the current term (b.v with its
+//    gather copy or folded data) into the sum b.x;
+//  - v into the gather copy or folded data of the series' current term;
+//  - the float64 product W V_lambda^-1 W^T x as per-piece partial sums
+//    (b.part, 9 per piece, summed per camera over cam_piece);
+//  - dx_l = -V^-1 (b_l + W^T b.x) and dx_cams = b.x.
+poba_status launch_solve_prepare(Problem* p, hipStream_t s);
+poba_status launch_series_orders(Problem* p, int m, hipStream_t s);
+poba_status launch_load_v(Problem* p, const double* v, hipStream_t s);
+poba_status launch_schur_part64(Problem* p, const double* x, hipStream_t s);
+poba_status launch_backsub_from_x(Problem* p, double* dx_cams, double* dx_lms, hipStream_t s);
+
 }  // namespace poba

@@ -133,6 +133,8 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.piece_red = (double*)take(size_t(z.npieces_max) * 3 * 8);
     t.cam_red = (double*)take(nc * 2 * 8);
     t.xq = (double*)take(nc * 24 * 8);
+    t.cg = (double*)take(5 * nc * 9 * 8);
+    t.sj = (double*)take(nc * 81 * 8);
     const size_t np1 = size_t(z.np) + 1;
     t.prob_cam_off = (int32_t*)take(np1 * 4);
     t.prob_lm_off = (int32_t*)take(np1 * 4);
@@ -140,6 +142,7 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.cam_prob = (int32_t*)take(nc * 4);
     t.lm_prob = (int32_t*)take(nl * 4);
     t.pctl = (PCtrl*)take(size_t(z.np) * sizeof(PCtrl));
+    t.pcg_ctl = (PcgCtl*)take(size_t(z.np) * sizeof(PcgCtl));
 
     t.ctrl = (Ctrl*)take(sizeof(Ctrl));
     t.keys_tmp = (int32_t*)take(N * 4);

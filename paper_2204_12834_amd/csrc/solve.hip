@@ -70,51 +70,8 @@ __global__ __launch_bounds__(kBlock) void k_inv_cam(Buffers b, Sizes z, int damp
         dg[j] = lam * dj;
         L[10 * j] += dg[j];
     }
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < 9; ++j) {
-        double d = L[9 * j + j];
-#pragma unroll
-        for (int k = 0; k < j; ++k) d -= L[9 * j + k] * L[9 * j + k];
-        ok = ok && d > 0.0;
-        const double ljj = sqrt(d);
-        L[9 * j + j] = ljj;
-#pragma unroll
-        for (int i = j + 1; i < 9; ++i) {
-            double sacc = L[9 * i + j];
-#pragma unroll
-            for (int k = 0; k < j; ++k) sacc -= L[9 * i + k] * L[9 * j + k];
-            L[9 * i + j] = sacc / ljj;
-        }
-    }
-    double M[81];  // L^-1, lower
-#pragma unroll
-    for (int k = 0; k < 81; ++k) M[k] = 0.0;
-#pragma unroll
-    for (int j = 0; j < 9; ++j) {
-        M[9 * j + j] = 1.0 / L[9 * j + j];
-#pragma unroll
-        for (int i = j + 1; i < 9; ++i) {
-            double sacc = 0.0;
-#pragma unroll
-            for (int k = j; k < i; ++k) sacc -= L[9 * i + k] * M[9 * k + j];
-            M[9 * i + j] = sacc / L[9 * i + i];
-        }
-    }
     double* out = b.Uinv + 81 * int64_t(c);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-#pragma unroll
-        for (int j = i; j < 9; ++j) {
-            double sacc = 0.0;
-#pragma unroll
-            for (int k = j; k < 9; ++k) sacc += M[9 * k + i] * M[9 * k + j];
-            ok = ok && isfinite(sacc);
-            M[9 * i + j] = M[9 * i + j];  // keep M intact (upper part unused)
-            out[9 * i + j] = sacc;
-            out[9 * j + i] = sacc;
-        }
-    }
+    const bool ok = spd_inverse9(L, out);
     if (!ok) {
 #pragma unroll
         for (int i = 0; i < 9; ++i)
@@ -1414,27 +1371,19 @@ void launch_lm_pass_any(Problem* p, hipStream_t s) {
 
 // TJ: record storage (Jacobian blocks, or the point-record type when PT),
 // TS: landmark-side storage, TCL: landmark-pass arithmetic.
+// Damped inverses of every block (float64) and the reduced right-hand side
+// b~ = b_p - W V^-1 b_l, with x = v = -U^-1 b~ as order 0 of the series;
+// `norms0`: the per-problem norms of order 0 are computed (the solve info
+// needs them when the series ends there).
 template <typename TJ, typename TS, typename TCL, bool PT>
-poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx_lms, poba_solve_info* info,
-                      const double* rhs_p, const double* rhs_l, hipStream_t s) {
-    // a replacement right-hand side stands in for (b_p, b_l) in every kernel
-    // of this solve (the buffers are passed by value)
-    Buffers b = p->b;
-    if (rhs_p) b.bp = const_cast<double*>(rhs_p);
-    if (rhs_l) b.bl = const_cast<double*>(rhs_l);
+void solve_prepare(Problem* p, const Buffers& b, double eps, bool norms0, hipStream_t s) {
     const int frozen = p->damping_frozen;
     const Sizes& z = p->z;
     const int damping = p->d.damping;
     const dim3 blk(kBlock);
     const dim3 g_cam(unsigned(ceil_div(z.nc, kBlock)));
-    const dim3 g_lm(unsigned(ceil_div(z.nl, kBlock)));
     const int32_t nseg = int32_t(p->nnel);
     const dim3 g_seg(unsigned(std::max<int64_t>(ceil_div(nseg, kBlock), 1)));
-    const int tpw = p->tiles_per_wave;
-    const dim3 g_waves(unsigned(ceil_div(ceil_div(z.ntiles, tpw), kWavesPerBlock)));
-    const dim3 g_tiles(unsigned(ceil_div(z.ntiles, kWavesPerBlock)));
-    const dim3 g_pieces(unsigned(std::max<int64_t>(p->sched_len, 1)));
-    const bool pieces = p->npieces > 0;
     {
         ProfScope pr(p, POBA_K_INVERSE, s);
         hipLaunchKernelGGL(k_inv_cam, g_cam, blk, 0, s, b, z, damping, frozen, b.ctrl);
@@ -1444,45 +1393,77 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
         ProfScope pr(p, POBA_K_OTHER, s);
         hipLaunchKernelGGL(k_rhs_lm, g_seg, blk, 0, s, b, nseg, b.ctrl);
     }
-    if (pieces) {
+    if (p->npieces > 0) {
+        // the reduced right-hand side (not a series order)
+        ProfScope pr(p, POBA_K_OTHER, s);
+        launch_cam_pass<TJ, double, double, PT>(p, b, reinterpret_cast<const double*>(b.s), s);
+        launch_cam_fin<TS>(p, b, kFinRhs, 0, eps, nullptr, s, norms0);
+    }
+}
+
+// Orders 1..m of the series from the current term (v and its gather copy or
+// folded data) and sum x.  `last_norms`: the per-problem norms of order m are
+// computed (with eps > 0 every order's are, for the stop rule).
+template <typename TJ, typename TS, typename TCL, bool PT>
+void series_orders(Problem* p, const Buffers& b, int m, double eps, bool last_norms, hipStream_t s) {
+    if (p->npieces == 0) return;
+    const Sizes& z = p->z;
+    const dim3 blk(kBlock);
+    for (int i = 1; i <= m; ++i) {
         {
-            // the reduced right-hand side (not a series order)
-            ProfScope pr(p, POBA_K_OTHER, s);
-            launch_cam_pass<TJ, double, double, PT>(p, b, reinterpret_cast<const double*>(b.s), s);
-            launch_cam_fin<TS>(p, b, kFinRhs, 0, eps, nullptr, s, m == 0);
+            ProfScope pr(p, POBA_K_LM_PASS, s);
+            launch_lm_pass_any<TJ, TCL, TS, PT>(p, s);
         }
-        for (int i = 1; i <= m; ++i) {
-            {
-                ProfScope pr(p, POBA_K_LM_PASS, s);
-                launch_lm_pass_any<TJ, TCL, TS, PT>(p, s);
-            }
-            const bool range = PT && uses_range_pass(p, true);
-            {
-                ProfScope pr(p, POBA_K_CAM_PASS, s);
-                launch_cam_pass<TJ, TS, TCL, PT>(p, b, reinterpret_cast<const TS*>(b.s), s, true);
-            }
-            {
-                ProfScope pr(p, POBA_K_CAM_FIN, s);
-                if (range) {
-                    hipLaunchKernelGGL(k_cam_fin_range<TS>, dim3(unsigned(ceil_div(z.nc, kFinRangeCams))), blk, 0, s,
-                                       b, z, p->lm_ranges, b.ctrl);
-                    if (eps > 0.0 || i == m)
-                        hipLaunchKernelGGL(k_norm_stop, dim3(unsigned(z.np)), blk, 0, s, b, kFinSeries, i, eps,
-                                           b.ctrl);
-                } else {
-                    launch_cam_fin<TS>(p, b, kFinSeries, i, eps, nullptr, s, eps > 0.0 || i == m);
-                }
+        const bool range = PT && uses_range_pass(p, true);
+        {
+            ProfScope pr(p, POBA_K_CAM_PASS, s);
+            launch_cam_pass<TJ, TS, TCL, PT>(p, b, reinterpret_cast<const TS*>(b.s), s, true);
+        }
+        {
+            ProfScope pr(p, POBA_K_CAM_FIN, s);
+            const bool norms = eps > 0.0 || (i == m && last_norms);
+            if (range) {
+                hipLaunchKernelGGL(k_cam_fin_range<TS>, dim3(unsigned(ceil_div(z.nc, kFinRangeCams))), blk, 0, s,
+                                   b, z, p->lm_ranges, b.ctrl);
+                if (norms)
+                    hipLaunchKernelGGL(k_norm_stop, dim3(unsigned(z.np)), blk, 0, s, b, kFinSeries, i, eps,
+                                       b.ctrl);
+            } else {
+                launch_cam_fin<TS>(p, b, kFinSeries, i, eps, nullptr, s, norms);
             }
         }
     }
-    {
-        ProfScope pr(p, POBA_K_BACKSUB, s);
-        if constexpr (PT) hipLaunchKernelGGL(k_fold_x, g_cam, blk, 0, s, b, z, b.x, b.ctrl);
-        hipLaunchKernelGGL((k_backsub<TJ, PT>), g_tiles, blk, 0, s, b, z, b.x, dx_lms, b.ctrl);
-        hipLaunchKernelGGL(k_zero_empty, g_lm, blk, 0, s, b, z, dx_lms, b.ctrl);
-        const int64_t nfin = std::max<int64_t>(int64_t(z.nc) * 9, z.np);
-        hipLaunchKernelGGL(k_finish, dim3(unsigned(ceil_div(nfin, kBlock))), blk, 0, s, b, z, dx_cams, info, b.ctrl);
-    }
+}
+
+// dx_l = -V^-1 (b_l + W^T x) for the camera step x = b.x, which is copied to
+// dx_cams; the solve info of every active problem to info (may be null).
+template <typename TJ, bool PT>
+void solve_backsub(Problem* p, const Buffers& b, double* dx_cams, double* dx_lms, poba_solve_info* info,
+                   hipStream_t s) {
+    const Sizes& z = p->z;
+    const dim3 blk(kBlock);
+    const dim3 g_cam(unsigned(ceil_div(z.nc, kBlock)));
+    const dim3 g_lm(unsigned(ceil_div(z.nl, kBlock)));
+    const dim3 g_tiles(unsigned(ceil_div(z.ntiles, kWavesPerBlock)));
+    ProfScope pr(p, POBA_K_BACKSUB, s);
+    if constexpr (PT) hipLaunchKernelGGL(k_fold_x, g_cam, blk, 0, s, b, z, b.x, b.ctrl);
+    hipLaunchKernelGGL((k_backsub<TJ, PT>), g_tiles, blk, 0, s, b, z, b.x, dx_lms, b.ctrl);
+    hipLaunchKernelGGL(k_zero_empty, g_lm, blk, 0, s, b, z, dx_lms, b.ctrl);
+    const int64_t nfin = std::max<int64_t>(int64_t(z.nc) * 9, z.np);
+    hipLaunchKernelGGL(k_finish, dim3(unsigned(ceil_div(nfin, kBlock))), blk, 0, s, b, z, dx_cams, info, b.ctrl);
+}
+
+template <typename TJ, typename TS, typename TCL, bool PT>
+poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx_lms, poba_solve_info* info,
+                      const double* rhs_p, const double* rhs_l, hipStream_t s) {
+    // a replacement right-hand side stands in for (b_p, b_l) in every kernel
+    // of this solve (the buffers are passed by value)
+    Buffers b = p->b;
+    if (rhs_p) b.bp = const_cast<double*>(rhs_p);
+    if (rhs_l) b.bl = const_cast<double*>(rhs_l);
+    solve_prepare<TJ, TS, TCL, PT>(p, b, eps, m == 0, s);
+    series_orders<TJ, TS, TCL, PT>(p, b, m, eps, true, s);
+    solve_backsub<TJ, PT>(p, b, dx_cams, dx_lms, info, s);
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }
 
@@ -1694,6 +1675,83 @@ __global__ __launch_bounds__(kBlock) void k_get_blocks(Buffers b, Sizes z, doubl
         o[6] = s[2]; o[7] = s[4]; o[8] = s[5];
     }
     if (bl && i < int64_t(z.nl) * 3) bl[i] = b.bl[i];
+}
+
+// ------------------------------------ building blocks for other solvers --
+
+template <typename TJ_, typename TS_, typename TCL_, bool PT_>
+struct Types {
+    using TJ = TJ_;
+    using TS = TS_;
+    using TCL = TCL_;
+    static constexpr bool PT = PT_;
+};
+
+// Calls f with the Types of the handle's records and precision.
+template <typename F>
+poba_status with_types(const Problem* p, F&& f) {
+    if (p->z.point) {
+        if (p->d.precision == POBA_F64) return f(Types<double, double, double, true>{});
+        return f(Types<float, float, float, true>{});
+    }
+    switch (p->d.precision) {
+        case POBA_F64: return f(Types<double, double, double, false>{});
+        case POBA_F32: return f(Types<float, float, float, false>{});
+        default: return f(Types<bf16_t, float, float, false>{});
+    }
+}
+
+inline poba_status last_error() { return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP; }
+
+poba_status launch_solve_prepare(Problem* p, hipStream_t s) {
+    return with_types(p, [&](auto t) {
+        using T = decltype(t);
+        solve_prepare<typename T::TJ, typename T::TS, typename T::TCL, T::PT>(p, p->b, 0.0, false, s);
+        return last_error();
+    });
+}
+
+poba_status launch_series_orders(Problem* p, int m, hipStream_t s) {
+    return with_types(p, [&](auto t) {
+        using T = decltype(t);
+        series_orders<typename T::TJ, typename T::TS, typename T::TCL, T::PT>(p, p->b, m, 0.0, false, s);
+        return last_error();
+    });
+}
+
+poba_status launch_load_v(Problem* p, const double* v, hipStream_t s) {
+    return with_types(p, [&](auto t) {
+        using T = decltype(t);
+        hipLaunchKernelGGL((k_load_v<typename T::TS, T::PT>), dim3(unsigned(ceil_div(p->z.nc, kBlock))),
+                           dim3(kBlock), 0, s, p->b, p->z, v, p->b.ctrl);
+        return last_error();
+    });
+}
+
+poba_status launch_schur_part64(Problem* p, const double* x, hipStream_t s) {
+    return with_types(p, [&](auto t) {
+        using T = decltype(t);
+        const Buffers& b = p->b;
+        {
+            ProfScope pr(p, POBA_K_LM_PASS, s);
+            hipLaunchKernelGGL((k_lm_apply64<typename T::TJ, T::PT>),
+                               dim3(unsigned(ceil_div(p->z.ntiles, kWavesPerBlock))), dim3(kBlock), 0, s, b, p->z, x,
+                               b.ctrl);
+        }
+        if (p->npieces > 0) {
+            ProfScope pr(p, POBA_K_CAM_PASS, s);
+            launch_cam_pass<typename T::TJ, double, double, T::PT>(p, b, reinterpret_cast<const double*>(b.s), s);
+        }
+        return last_error();
+    });
+}
+
+poba_status launch_backsub_from_x(Problem* p, double* dx_cams, double* dx_lms, hipStream_t s) {
+    return with_types(p, [&](auto t) {
+        using T = decltype(t);
+        solve_backsub<typename T::TJ, T::PT>(p, p->b, dx_cams, dx_lms, nullptr, s);
+        return last_error();
+    });
 }
 
 }  // namespace poba

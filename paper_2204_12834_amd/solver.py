@@ -65,6 +65,17 @@ def read_solve_info(t: torch.Tensor, index: int = 0) -> dict:
     return {f: getattr(info, f) for f, _ in _lib.PobaSolveInfo._fields_}
 
 
+def read_pcg_info(t: torch.Tensor) -> list:
+    """PCG info of every problem from the info buffer."""
+    n = ctypes.sizeof(_lib.PobaPCGInfo)
+    raw = bytes(t.cpu().numpy().tobytes())
+    out = []
+    for j in range(len(raw) // n):
+        info = _lib.PobaPCGInfo.from_buffer_copy(raw[j * n:(j + 1) * n])
+        out.append({f: getattr(info, f) for f, _ in _lib.PobaPCGInfo._fields_})
+    return out
+
+
 def read_lm_state(t: torch.Tensor, index: int = 0) -> dict:
     """LM state of problem `index` from the state buffer."""
     n = ctypes.sizeof(_lib.PobaLMState)
@@ -169,6 +180,26 @@ class Problem:
                                                                  _ptr(dx_cams), _ptr(dx_lms), _ptr(info),
                                                                  _stream(stream)))
         return dx_cams, dx_lms, info
+
+    def pcg_solve(self, lam: float, precond: str = "schur_jacobi", m: int = 0, tol: float = 1e-8,
+                  max_iters: int = 500, dx_cams=None, dx_lms=None, coeffs: bool = False, stream=None):
+        """Damped step with the camera step from preconditioned CG on the
+        reduced camera system.  Returns dx_cams, dx_lms, the per-problem info
+        (list of dicts) and, if `coeffs`, a [max_iters, n_problems, 2] tensor of
+        (alpha, beta) per iteration (NaN where not taken)."""
+        if dx_cams is None:
+            dx_cams = torch.empty(self.n_cams, 9, dtype=torch.float64, device=self.device)
+        if dx_lms is None:
+            dx_lms = torch.empty(self.n_lms, 3, dtype=torch.float64, device=self.device)
+        info = torch.zeros(self.n_problems * ctypes.sizeof(_lib.PobaPCGInfo), dtype=torch.uint8, device=self.device)
+        co = None
+        if coeffs:
+            co = torch.full((max(int(max_iters), 1), self.n_problems, 2), float("nan"), dtype=torch.float64,
+                            device=self.device)
+        _lib.check("poba_pcg_solve", self.lib.poba_pcg_solve(self.handle, float(lam), _lib.PRECOND[precond], int(m),
+                                                             float(tol), int(max_iters), _ptr(dx_cams), _ptr(dx_lms),
+                                                             _ptr(info), _ptr(co), _stream(stream)))
+        return dx_cams, dx_lms, read_pcg_info(info), co
 
     def solve_residual(self, dx_cams: torch.Tensor, stream=None) -> torch.Tensor:
         """|S x + b~| / |b~| per problem for a camera step of the last power_solve."""
