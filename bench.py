@@ -506,6 +506,100 @@ def bench_adjoint(args, dev):
     return 0
 
 
+def bench_pcg(args, dev):
+    """Fig. 2 comparison: preconditioned CG on the reduced camera system at
+    the first LM linearisation points of the workload (the trajectory of the
+    power-series LM with the Sec. 5.1 settings).  At each point: the power
+    series (order args.m, stop rule eps = 0.01) and its reduced residual
+    |S x + b~| / |b~|; then CG with the Schur-Jacobi preconditioner and with
+    the power-series preconditioner S~(m) for m in 0, 1, 2, 4, run to that
+    same residual (equal accuracy), with their iteration counts and times;
+    and a run of each to 1e-10 whose CG coefficients give the Lanczos
+    estimate of kappa(M^-1 S)."""
+    import numpy as np
+    import torch
+    from paper_2204_12834_amd.solver import LMOptions, read_lm_state, read_solve_info
+
+    def kappa(co, k):
+        # Ritz values of the k-step Lanczos matrix (diagonal 1/a_j + b_{j-1}/a_{j-1},
+        # off-diagonal sqrt(b_j)/a_j)
+        a, b = co[:k, 0, 0], co[:k - 1, 0, 1]
+        T = np.diag(1.0 / a)
+        T[1:, 1:] += np.diag(b / a[:-1])
+        off = np.sqrt(b) / a[:-1]
+        T += np.diag(off, 1) + np.diag(off, -1)
+        ev = np.linalg.eigvalsh(T)
+        return float(ev[-1] / ev[0])
+
+    scene, delta = make_scene(args.workload, args.huber)
+    prob, cams0, lms0, _ = gpu_setup(scene, delta, args.precision, dev, args.records)
+    opts = LMOptions(m=args.m)
+    cams, lms = cams0.clone(), lms0.clone()
+    st = prob.lm_init(opts)
+    precs = [("schur_jacobi", 0)] + [("power", m) for m in (0, 1, 2, 4)]
+    rows = []
+    for it in range(args.pcg_points):
+        lam = read_lm_state(st)["lambda"]
+        prob.linearize(cams, lms)
+        row = {"lm_iteration": it, "lambda": lam}
+        e0, e1 = _events()
+        for _ in range(2):  # warm, then timed
+            e0.record()
+            dxc, _, info = prob.power_solve(lam, args.m, 0.01)
+            e1.record()
+            torch.cuda.synchronize()
+        si = read_solve_info(info)
+        res = prob.solve_residual(dxc).item()
+        row["series"] = {"ms": round(e0.elapsed_time(e1), 3), "order": si["stop_order"], "rel_residual": res}
+        for name, m in precs:
+            key = name if name != "power" else f"power_m{m}"
+            out = {}
+            for tol, tag in [(res, "equal_accuracy"), (1e-10, "tight")]:
+                e0.record()
+                dxc, _, pinfo, co = prob.pcg_solve(lam, name, m, tol, 2000, coeffs=True)
+                e1.record()
+                torch.cuda.synchronize()
+                k = pinfo[0]["iterations"]
+                d = {"iterations": k, "ms": round(e0.elapsed_time(e1), 3), "converged": pinfo[0]["converged"],
+                     "rel_residual": prob.solve_residual(dxc).item()}
+                if tag == "tight" and k > 1:
+                    d["kappa_estimate"] = round(kappa(co.cpu().numpy(), k), 3)
+                out[tag] = d
+            row[key] = out
+        rows.append(row)
+        print(f"[pcg] point {it}: lambda {lam:.2e}, series {row['series']}, "
+              + ", ".join(f"{k} {row[k]['equal_accuracy']['iterations']} it {row[k]['equal_accuracy']['ms']} ms"
+                          for k in row if k.startswith(("schur", "power"))), file=sys.stderr, flush=True)
+        prob.lm_step(cams, lms, st, opts)
+    # per-iteration phases of one Schur-Jacobi solve at the last point
+    prob.profile(True)
+    prob.profile_read()
+    _, _, pinfo, _ = prob.pcg_solve(read_lm_state(st)["lambda"], "schur_jacobi", 0, 1e-10, 200)
+    prof = prob.profile_read()
+    prob.profile(False)
+    n_it = max(pinfo[0]["iterations"], 1)
+    cg_iter_ms = sum(v[0] for v in prof.values()) / n_it
+    mean = lambda key: float(np.mean([r[key]["equal_accuracy"]["ms"] for r in rows]))
+    line = {"metric": "PCG on the reduced camera system vs the power series: solve time at equal accuracy "
+                      "(Schur-Jacobi PCG), 1 GPU",
+            "value": round(mean("schur_jacobi"), 3), "unit": "ms", "n_gpus": 1, "steps": args.pcg_points,
+            "warmup": 1, "ms_per_step": round(mean("schur_jacobi"), 3), "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
+            "data": "file" if isinstance(scene, FileScene) else "synthetic",
+            "config": {"workload": f"{scene.name}: {scene.n_cams} cameras, {scene.n_lms} landmarks, "
+                                   f"{scene.n_obs} observations, {args.precision} "
+                                   f"{'Jacobian blocks' if args.records == 'jacobian' else 'point records'}, "
+                                   f"first {args.pcg_points} LM linearisation points, series m={args.m} eps=0.01",
+                       "records": args.records},
+            "series_ms_mean": round(float(np.mean([r["series"]["ms"] for r in rows])), 3),
+            "mean_ms_equal_accuracy": {k: round(mean(k), 3) for k in rows[0] if k.startswith(("schur", "power"))},
+            "sj_iteration_ms": round(cg_iter_ms, 4),
+            "sj_phases_ms_per_iteration": {k: round(v[0] / n_it, 4) for k, v in prof.items() if v[1]},
+            "points": rows}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -525,6 +619,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tau", action="store_true", help="skip the time-to-tolerance LM runs")
     ap.add_argument("--no-point", action="store_true", help="skip the point-record measurements")
+    ap.add_argument("--pcg", action="store_true",
+                    help="compare CG on the reduced camera system (Schur-Jacobi and power-series "
+                         "preconditioners) with the power series at the first LM points, and exit")
+    ap.add_argument("--pcg-points", type=int, default=5, help="LM linearisation points of the --pcg comparison")
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
 
@@ -547,6 +645,8 @@ def main():
         return bench_batched(args, dev)
     if args.workload == "c5":
         return bench_adjoint(args, dev)
+    if args.pcg:
+        return bench_pcg(args, dev)
     t_gen = time.perf_counter()
     scene, delta = make_scene(args.workload, args.huber)
     print(f"[bench] scene {scene.name}: {scene.n_cams} cams, {scene.n_lms} lms, {scene.n_obs} obs "

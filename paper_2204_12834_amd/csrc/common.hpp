@@ -426,7 +426,7 @@ struct Buffers {
     int32_t* vals_tmp;    // [N]
     int32_t* keys_out;    // [N]
     int32_t* iota;        // [N]
-    int32_t* scratch_i;   // [max(nc, nl) + 2]
+    int32_t* scratch_i;   // [max(nc, nl) + 2] set-up scratch; afterwards word 0 is the repeated-pair flag
 };
 
 struct Sizes {
@@ -464,6 +464,7 @@ struct poba_problem_s {
     int lds_cam = 1;            // stage the camera vector in LDS when it fits
     int64_t lds_max = 65536;    // bytes of LDS one workgroup may allocate
     int damping_frozen = 0;     // solves reuse the damping diagonal of the last unfrozen solve
+    int repeats = -1;           // some (camera, landmark) pair is observed twice (-1: not yet known)
     hipStream_t last_stream = nullptr;
     // profiling
     bool profiling = false;

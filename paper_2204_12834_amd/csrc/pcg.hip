@@ -44,16 +44,17 @@ __device__ __forceinline__ void pcg_leave(PCtrl& q, Ctrl* ctrl) {
 
 // ------------------------------------------------- Schur-Jacobi blocks --
 //
-// One block per camera c over its camera-major observations.  For the
-// observation of landmark l, W_cl sums J_p^T J_l over every observation of l
-// by camera c (found in the landmark-major segment of l; nearly always the
-// observation itself); only the first of them in that segment contributes
-// W_cl V_l^-1 W_cl^T, so a repeated (camera, landmark) pair enters once with
-// its summed block.  The 45 upper entries are summed over the block in a
-// fixed order; thread 0 forms S_cc = U_c + lambda D_c - sum and inverts it.
-template <typename TJ, bool PT>
-__global__ __launch_bounds__(kBlock) void k_sj_blocks(Buffers b, Sizes z, const Ctrl* ctrl) {
-    __shared__ double lds[kWavesPerBlock * 45];
+// One wavefront per camera c over its camera-major observations; the observation
+// of landmark l contributes W_cl V_l^-1 W_cl^T with W_cl = J_p^T J_l.  When
+// the handle has repeated (camera, landmark) pairs (DUPS), W_cl sums J_p^T J_l
+// over every observation of l by camera c (found in the landmark-major
+// segment of l) and only the first of them in that segment contributes, so a
+// repeated pair enters once with its summed block.  The 45 upper entries are
+// summed over the lanes in a fixed order (through LDS); lanes 0..44 write
+// S_cc = U_c + lambda D_c - sum (inverted by k_sj_invert).
+template <typename TJ, bool PT, bool DUPS>
+__global__ __launch_bounds__(kWave) void k_sj_blocks(Buffers b, Sizes z, const Ctrl* ctrl) {
+    __shared__ double lds[45][kWave];
     if (!ctrl->active) return;
     const int32_t c = blockIdx.x;
     PCtrl& q = b.pctl[b.cam_prob[c]];
@@ -63,17 +64,9 @@ __global__ __launch_bounds__(kBlock) void k_sj_blocks(Buffers b, Sizes z, const 
 #pragma unroll
     for (int k = 0; k < 45; ++k) acc[k] = 0.0;
     const int32_t i0 = b.cam_off[c], i1 = b.cam_off[c + 1];
-    for (int32_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+    for (int32_t i = i0 + threadIdx.x; i < i1; i += kWave) {
         const int32_t l = b.co_lm[i];
         const int32_t seg = b.co_seg[i];
-        const int32_t j0 = b.lm_off[l], j1 = b.lm_off[l + 1];
-        int32_t first = -1, count = 0;
-        for (int32_t j = j0; j < j1; ++j) {
-            if (int32_t(b.lo_cam[j] & kIndexMask) == c) {
-                if (first < 0) first = j;
-                ++count;
-            }
-        }
         double W[27];  // W_cl, 9x3 row-major
 #pragma unroll
         for (int k = 0; k < 27; ++k) W[k] = 0.0;
@@ -85,6 +78,17 @@ __global__ __launch_bounds__(kBlock) void k_sj_blocks(Buffers b, Sizes z, const 
 #pragma unroll
                 for (int k = 0; k < 3; ++k) W[3 * r + k] += J[r] * J[18 + k] + J[9 + r] * J[21 + k];
         };
+        int32_t first = -1, count = 1;
+        const int32_t j1 = DUPS ? b.lm_off[l + 1] : 0;
+        if (DUPS) {
+            count = 0;
+            for (int32_t j = b.lm_off[l]; j < j1; ++j) {
+                if (int32_t(b.lo_cam[j] & kIndexMask) == c) {
+                    if (first < 0) first = j;
+                    ++count;
+                }
+            }
+        }
         if (count <= 1) {
             add_w(b.J_co, i);
         } else {
@@ -98,36 +102,75 @@ __global__ __launch_bounds__(kBlock) void k_sj_blocks(Buffers b, Sizes z, const 
 #pragma unroll
         for (int k = 0; k < 3; ++k) dd[k] = b.Dl[3 * int64_t(seg) + k];
         inv3_damped(Vd, lam, dd, inv);
-        double Y[27];  // W V^-1
-#pragma unroll
-        for (int r = 0; r < 9; ++r) sym3_apply(inv, W + 3 * r, Y + 3 * r);
         int e = 0;
 #pragma unroll
-        for (int r = 0; r < 9; ++r)
+        for (int r = 0; r < 9; ++r) {
+            double y[3];  // row r of W V^-1
+            sym3_apply(inv, W + 3 * r, y);
 #pragma unroll
-            for (int k = r; k < 9; ++k, ++e)
-                acc[e] += Y[3 * r] * W[3 * k] + Y[3 * r + 1] * W[3 * k + 1] + Y[3 * r + 2] * W[3 * k + 2];
-    }
-    block_sum<45>(acc, lds);
-    if (threadIdx.x != 0) return;
-    double L[81];
-    const double* U = b.U + 81 * int64_t(c);
-    int e = 0;
-#pragma unroll
-    for (int r = 0; r < 9; ++r)
-#pragma unroll
-        for (int k = r; k < 9; ++k, ++e) {
-            double v = U[9 * r + k] - acc[e];
-            if (k == r) v += lam * b.Dp[9 * int64_t(c) + r];
-            L[9 * r + k] = v;
-            L[9 * k + r] = v;
+            for (int k = r; k < 9; ++k, ++e) acc[e] += y[0] * W[3 * k] + y[1] * W[3 * k + 1] + y[2] * W[3 * k + 2];
         }
+    }
+    // lane e < 45 sums entry e over the lanes in lane order
+#pragma unroll
+    for (int k = 0; k < 45; ++k) lds[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    const int e = threadIdx.x;
+    if (e >= 45) return;
+    double sum = 0.0;
+    for (int k = 0; k < kWave; ++k) sum += lds[e][k];
+    int r = 0, base = 0;  // entry e is (r, k) of the upper triangle, row-major
+    while (e >= base + 9 - r) {
+        base += 9 - r;
+        ++r;
+    }
+    const int k = r + (e - base);
+    double v = b.U[81 * int64_t(c) + 9 * r + k] - sum;
+    if (k == r) v += lam * b.Dp[9 * int64_t(c) + r];
     double* out = b.sj + 81 * int64_t(c);
+    out[9 * r + k] = v;
+    out[9 * k + r] = v;
+}
+
+// S_cc^-1 in place, one thread per camera.
+__global__ __launch_bounds__(kBlock) void k_sj_invert(Buffers b, Sizes z, const Ctrl* ctrl) {
+    if (!ctrl->active) return;
+    const int32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= z.nc) return;
+    PCtrl& q = b.pctl[b.cam_prob[c]];
+    if (!q.active) return;
+    double* out = b.sj + 81 * int64_t(c);
+    double L[81];
+#pragma unroll
+    for (int k = 0; k < 81; ++k) L[k] = out[k];
     if (!spd_inverse9(L, out)) {
         // not invertible: the preconditioner falls back to the identity here
 #pragma unroll
         for (int k = 0; k < 81; ++k) out[k] = (k % 10 == 0) ? 1.0 : 0.0;
         atomicOr(&q.status, POBA_ERR_NOT_SPD);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_clear_flag(int32_t* flag) {
+    if (threadIdx.x == 0) *flag = 0;
+}
+
+// flag = 1 if some camera observes some landmark more than once: every
+// landmark-major position compares its camera with the earlier positions of
+// its segment (back to the segment's head).
+__global__ __launch_bounds__(kBlock) void k_find_repeats(Buffers b, Sizes z, int32_t* flag) {
+    const int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (j >= z.N) return;
+    const uint32_t w = b.lo_cam[j];
+    if (w & kHeadBit) return;
+    const uint32_t c = w & kIndexMask;
+    for (int64_t k = j - 1; k >= 0; --k) {
+        const uint32_t v = b.lo_cam[k];
+        if ((v & kIndexMask) == c) {
+            *flag = 1;  // every writer stores the same value
+            return;
+        }
+        if (v & kHeadBit) return;
     }
 }
 
@@ -385,10 +428,29 @@ __global__ __launch_bounds__(kReduceBlock) void k_pcg_end(Buffers b, int32_t np,
 
 template <typename TJ, bool PT>
 void launch_sj_blocks(Problem* p, hipStream_t s) {
-    hipLaunchKernelGGL((k_sj_blocks<TJ, PT>), dim3(unsigned(p->z.nc)), dim3(kBlock), 0, s, p->b, p->z, p->b.ctrl);
+    const dim3 g(unsigned(p->z.nc)), wave(kWave);
+    if (p->repeats)
+        hipLaunchKernelGGL((k_sj_blocks<TJ, PT, true>), g, wave, 0, s, p->b, p->z, p->b.ctrl);
+    else
+        hipLaunchKernelGGL((k_sj_blocks<TJ, PT, false>), g, wave, 0, s, p->b, p->z, p->b.ctrl);
+    hipLaunchKernelGGL(k_sj_invert, dim3(unsigned(ceil_div(p->z.nc, kBlock))), dim3(kBlock), 0, s, p->b, p->z,
+                       p->b.ctrl);
 }
 
 poba_status sj_blocks(Problem* p, hipStream_t s) {
+    if (p->repeats < 0) {
+        // once per handle: does any (camera, landmark) pair repeat?
+        int32_t* flag = p->b.scratch_i;
+        hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(kBlock), 0, s, flag);
+        if (p->z.N > 0)
+            hipLaunchKernelGGL(k_find_repeats, dim3(unsigned(ceil_div(p->z.N, kBlock))), dim3(kBlock), 0, s, p->b,
+                               p->z, flag);
+        int32_t h = 0;
+        if (hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return POBA_ERR_HIP;
+        p->repeats = h ? 1 : 0;
+    }
     ProfScope pr(p, POBA_K_INVERSE, s);
     if (p->z.point) {
         if (p->d.precision == POBA_F64) launch_sj_blocks<double, true>(p, s);
