@@ -274,6 +274,75 @@ poba_status poba_lm_init(poba_problem p, poba_lm_state *st, const poba_lm_option
 poba_status poba_lm_step(poba_problem p, double *cams, double *lms, poba_lm_state *st,
                          const poba_lm_options *o, poba_stream stream);
 
+/* ---- LM with a step computed elsewhere --------------------------------- */
+
+/* The two halves of poba_lm_step around its solve, for a caller that computes
+ * the step itself (e.g. by the clustered solve of Sec. 5.3):
+ * poba_lm_begin sets up the problems that are not done and linearises where
+ * st[j].need_linearize is set (writing st[j].cost); poba_lm_finish takes the
+ * step dx_cams [dev] float64 [n_cams][9], dx_lms [dev] float64 [n_lms][3] and
+ * evaluates, accepts or rejects it and updates lambda exactly as
+ * poba_lm_step does (o->m and o->eps are not used).  Between the two calls
+ * the handle may be used for other calls at st[j].lambda. */
+poba_status poba_lm_begin(poba_problem p, double *cams, double *lms, poba_lm_state *st, poba_stream stream);
+poba_status poba_lm_finish(poba_problem p, double *cams, double *lms, poba_lm_state *st,
+                           const poba_lm_options *o, const double *dx_cams, const double *dx_lms,
+                           poba_stream stream);
+
+/* Sec. 4.2, eq. (back_substitution) for a given camera step: with the blocks
+ * of the last poba_linearize and damping lambda > 0, dx_lms [dev] float64
+ * [n_lms][3] = -V_lambda^-1 (b_l + W^T dx_cams), dx_cams [dev] float64
+ * [n_cams][9].  (Every problem of a batch uses the same lambda.) */
+poba_status poba_back_substitute(poba_problem p, double lambda, const double *dx_cams, double *dx_lms,
+                                 poba_stream stream);
+
+/* ---- camera clusters (Sec. 5.3, PoST) --------------------------------- */
+
+/* [host] The camera graph of a problem: an edge between two cameras that
+ * observe a common landmark, weighted by the number of such landmarks (each
+ * landmark counted once per camera pair).  obs_cam, obs_lm [host] int32
+ * [n_obs].  Returns POBA_ERR_INDEX_RANGE for an index out of range. */
+typedef struct poba_camera_graph_s *poba_camera_graph;
+poba_status poba_camera_graph_create(int64_t n_obs, const int32_t *obs_cam, const int32_t *obs_lm,
+                                     int32_t n_cams, int32_t n_lms, poba_camera_graph *out);
+poba_status poba_camera_graph_destroy(poba_camera_graph g);
+
+/* [host] The edges (a < b, ordered by (a, b)) and weights; with a, b, w NULL
+ * only their number. */
+poba_status poba_camera_graph_edges(poba_camera_graph g, int64_t *n_edges, int32_t *a, int32_t *b, int32_t *w);
+
+/* [host] Greedy clustering of the cameras: edges are visited by decreasing
+ * key (ties: the edge order), where the key is the weight, or for seed >= 0
+ * the weight times a uniform number in [0, 1) drawn per edge by the SplitMix64
+ * finaliser of seed ^ (a << 32 | b) (top 53 bits); the two clusters of an edge
+ * merge when the result has at most max_size cameras.  cluster [host] int32
+ * [n_cams] receives cluster indices numbered in the order of each cluster's
+ * smallest camera, *n_clusters their number (may be NULL). */
+poba_status poba_camera_graph_cluster(poba_camera_graph g, int32_t max_size, int64_t seed, int32_t *cluster,
+                                      int32_t *n_clusters);
+
+/* [host] The batched layout of a clustered problem (Sec. 5.3): problem k is
+ * cluster k.  cam_pos [n_cams]: the camera's index in cluster order (clusters
+ * in turn, cameras ascending); the landmarks are the (cluster, landmark) pairs
+ * that have observations, numbered by cluster then landmark, plus one
+ * unobserved pair (landmark 0) for a cluster without observations:
+ * obs_vlm [n_obs] the pair of each observation, vlm_src [n_obs + n_clusters]
+ * the landmark of each pair, *n_vlm their number; prob_cam_off,
+ * prob_lm_off [n_clusters + 1] the ranges for poba_batch_create.  All host
+ * memory; cluster values must lie in [0, n_clusters) and use every index. */
+poba_status poba_cluster_layout(int64_t n_obs, const int32_t *obs_cam, const int32_t *obs_lm, int32_t n_cams,
+                                int32_t n_lms, const int32_t *cluster, int32_t n_clusters, int32_t *cam_pos,
+                                int32_t *obs_vlm, int32_t *vlm_src, int32_t *n_vlm, int32_t *prob_cam_off,
+                                int32_t *prob_lm_off);
+
+/* Replaces the undamped landmark blocks of the last poba_linearize: V [dev]
+ * float64 [n_lms][3][3] (the upper triangle is read) and b_l [dev] float64
+ * [n_lms][3].  With the V and b_l of a whole problem gathered onto the
+ * (cluster, landmark) pairs of its clustered layout, the clustered handle's
+ * reduced system is the block diagonal of the whole one over the clusters
+ * (Sec. 5.3).  Valid until the next poba_linearize. */
+poba_status poba_set_landmark_blocks(poba_problem p, const double *V, const double *bl, poba_stream stream);
+
 /* ---- differentiation of the damped step (an extension) ------------------ */
 
 /* Replaces the observed pixel positions of the handle: obs_xy [dev] float64

@@ -26,7 +26,7 @@ import math
 
 import numpy as np
 
-from . import camera, robust, schur, dense
+from . import camera, dense, post, robust, schur
 
 
 @dataclasses.dataclass
@@ -82,7 +82,11 @@ def model_decrease(rw, Jp, Jl, obs_cam, obs_lm, dxp, dxl):
     return math.fsum(terms.tolist())
 
 
-def step_direction(rw, Jp, Jl, obs_cam, obs_lm, n_cams, n_lms, lam, opts, solver="series"):
+def step_direction(rw, Jp, Jl, obs_cam, obs_lm, n_cams, n_lms, lam, opts, solver="series", cluster=None):
+    if solver == "clustered":  # PoST's per-cluster series (Sec. 5.3)
+        sol = post.solve_clustered(Jp, Jl, rw, obs_cam, obs_lm, n_cams, n_lms, lam, opts.m, opts.eps, cluster,
+                                   opts.damping)
+        return sol.dxp, sol.dxl, max(sol.stop_orders, default=0)
     if solver == "series":
         sol = schur.solve(Jp, Jl, rw, obs_cam, obs_lm, n_cams, n_lms, lam, opts.m, opts.eps,
                           opts.damping)
@@ -95,7 +99,7 @@ def step_direction(rw, Jp, Jl, obs_cam, obs_lm, n_cams, n_lms, lam, opts, solver
 
 
 def lm(cams0, lms0, obs_cam, obs_lm, obs_xy, opts: LMOptions | None = None, solver="series",
-       callback=None) -> LMResult:
+       callback=None, cluster=None) -> LMResult:
     opts = opts or LMOptions()
     cams = np.array(cams0, dtype=np.float64)
     lms = np.array(lms0, dtype=np.float64)
@@ -104,8 +108,9 @@ def lm(cams0, lms0, obs_cam, obs_lm, obs_xy, opts: LMOptions | None = None, solv
     F, rw, Jp, Jl = linearize(cams, lms, obs_cam, obs_lm, obs_xy, opts.huber_delta)
     its = []
     converged = False
-    for _ in range(opts.max_iters):
-        dxp, dxl, order = step_direction(rw, Jp, Jl, obs_cam, obs_lm, n_cams, n_lms, lam, opts, solver)
+    for it in range(opts.max_iters):
+        cl = cluster(it) if callable(cluster) else cluster  # clusters drawn per iteration (Sec. 5.3)
+        dxp, dxl, order = step_direction(rw, Jp, Jl, obs_cam, obs_lm, n_cams, n_lms, lam, opts, solver, cl)
         cams_new = cams + dxp
         lms_new = lms + dxl
         r_new = camera.residuals(cams_new, lms_new, obs_cam, obs_lm, obs_xy)

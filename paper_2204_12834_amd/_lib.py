@@ -120,6 +120,15 @@ SIGNATURES = {
     "poba_linearize": (I32, [P, P, P, P, P]),
     "poba_power_solve": (I32, [P, F64, I32, F64, P, P, P, P]),
     "poba_pcg_solve": (I32, [P, F64, I32, I32, F64, I32, P, P, P, P, P]),
+    "poba_lm_begin": (I32, [P, P, P, P, P]),
+    "poba_lm_finish": (I32, [P, P, P, P, ctypes.POINTER(PobaLMOptions), P, P, P]),
+    "poba_back_substitute": (I32, [P, F64, P, P, P]),
+    "poba_set_landmark_blocks": (I32, [P, P, P, P]),
+    "poba_camera_graph_create": (I32, [I64, P, P, I32, I32, ctypes.POINTER(P)]),
+    "poba_camera_graph_destroy": (I32, [P]),
+    "poba_camera_graph_edges": (I32, [P, ctypes.POINTER(I64), P, P, P]),
+    "poba_camera_graph_cluster": (I32, [P, I32, I64, P, ctypes.POINTER(I32)]),
+    "poba_cluster_layout": (I32, [I64, P, P, I32, I32, P, I32, P, P, P, ctypes.POINTER(I32), P, P]),
     "poba_lm_init": (I32, [P, P, ctypes.POINTER(PobaLMOptions), P]),
     "poba_lm_step": (I32, [P, P, P, P, ctypes.POINTER(PobaLMOptions), P]),
     "poba_project": (I32, [I64, P, P, P, P, P, P]),

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpoba.so")
-SOURCES = ["setup.hip", "linearize.hip", "solve.hip", "lm.hip", "adjoint.hip", "graph.hip", "probe.hip", "pcg.hip"]
+SOURCES = ["setup.hip", "linearize.hip", "solve.hip", "lm.hip", "adjoint.hip", "graph.hip", "probe.hip", "pcg.hip", "post.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("POBA_ARCH", "gfx950")
 

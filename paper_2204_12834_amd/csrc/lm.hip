@@ -215,21 +215,36 @@ poba_status poba_lm_init(poba_problem p, poba_lm_state* st, const poba_lm_option
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }
 
-poba_status poba_lm_step(poba_problem p, double* cams, double* lms, poba_lm_state* st, const poba_lm_options* o,
-                         poba_stream stream) {
-    (void)hipGetLastError();  // report only this call's launch errors
-    if (!p || !cams || !lms || !st || !o) return POBA_ERR_INVALID_ARG;
-    if (o->m < 0 || o->m > 100000 || !(o->eps >= 0.0) || o->max_iters < 1 || !(o->lambda_min > 0.0) ||
-        !(o->lambda_max >= o->lambda_min))
-        return POBA_ERR_INVALID_ARG;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+}  // extern "C"
+
+namespace {
+
+bool bad_options(const poba_lm_options* o) {
+    return o->m < 0 || o->m > 100000 || !(o->eps >= 0.0) || o->max_iters < 1 || !(o->lambda_min > 0.0) ||
+           !(o->lambda_max >= o->lambda_min);
+}
+
+// Problem flags from the LM states, and the linearisation where a step asks for it.
+poba_status lm_begin(Problem* p, double* cams, double* lms, poba_lm_state* st, hipStream_t s) {
+    const Buffers& b = p->b;
+    hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(kReduceBlock), 0, s, b.ctrl, b.pctl, st, p->z.np);
+    return launch_linearize(p, cams, lms, &b.ctrl->lin, nullptr, st, s);
+}
+
+__global__ __launch_bounds__(kBlock) void k_take_step(Buffers b, Sizes z, const double* __restrict__ dxp,
+                                                      const double* __restrict__ dxl) {
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < int64_t(z.nc) * 9) b.dxp[i] = dxp[i];
+    if (i < int64_t(z.nl) * 3) b.dxl[i] = dxl[i];
+}
+
+// Trial state, F there and the model decrease, the decision and the damping
+// update for the step in b.dxp, b.dxl.
+poba_status lm_finish(Problem* p, double* cams, double* lms, poba_lm_state* st, const poba_lm_options* o,
+                      hipStream_t s) {
     const Buffers& b = p->b;
     const Sizes& z = p->z;
-    hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(kReduceBlock), 0, s, b.ctrl, b.pctl, st, z.np);
-    poba_status rc = launch_linearize(p, cams, lms, &b.ctrl->lin, nullptr, st, s);
-    if (rc) return rc;
-    rc = launch_solve(p, o->m, o->eps, b.dxp, b.dxl, nullptr, s);
-    if (rc) return rc;
+    poba_status rc = POBA_OK;
     const int64_t nstate = std::max<int64_t>(int64_t(z.nc) * 9, int64_t(z.nl) * 3);
     const dim3 g_state(unsigned(ceil_div(nstate, kBlock)));
     {
@@ -258,6 +273,44 @@ poba_status poba_lm_step(poba_problem p, double* cams, double* lms, poba_lm_stat
     hipLaunchKernelGGL(k_control, dim3(unsigned(ceil_div(z.np, kBlock))), dim3(kBlock), 0, s, b, z.np, st, prm);
     hipLaunchKernelGGL(k_apply, g_state, dim3(kBlock), 0, s, b, z, cams, lms, b.ctrl);
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+poba_status poba_lm_step(poba_problem p, double* cams, double* lms, poba_lm_state* st, const poba_lm_options* o,
+                         poba_stream stream) {
+    (void)hipGetLastError();  // report only this call's launch errors
+    if (!p || !cams || !lms || !st || !o || bad_options(o)) return POBA_ERR_INVALID_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    poba_status rc = lm_begin(p, cams, lms, st, s);
+    if (rc) return rc;
+    rc = launch_solve(p, o->m, o->eps, p->b.dxp, p->b.dxl, nullptr, s);
+    if (rc) return rc;
+    return lm_finish(p, cams, lms, st, o, s);
+}
+
+poba_status poba_lm_begin(poba_problem p, double* cams, double* lms, poba_lm_state* st, poba_stream stream) {
+    (void)hipGetLastError();  // report only this call's launch errors
+    if (!p || !cams || !lms || !st) return POBA_ERR_INVALID_ARG;
+    return lm_begin(p, cams, lms, st, reinterpret_cast<hipStream_t>(stream));
+}
+
+poba_status poba_lm_finish(poba_problem p, double* cams, double* lms, poba_lm_state* st, const poba_lm_options* o,
+                           const double* dx_cams, const double* dx_lms, poba_stream stream) {
+    (void)hipGetLastError();  // report only this call's launch errors
+    if (!p || !cams || !lms || !st || !o || !dx_cams || !dx_lms || bad_options(o)) return POBA_ERR_INVALID_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const Buffers& b = p->b;
+    const Sizes& z = p->z;
+    // the flags again (calls between begin and finish may have changed them)
+    hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(kReduceBlock), 0, s, b.ctrl, b.pctl, st, z.np);
+    const int64_t nstate = std::max<int64_t>(int64_t(z.nc) * 9, int64_t(z.nl) * 3);
+    hipLaunchKernelGGL(k_take_step, dim3(unsigned(ceil_div(nstate, kBlock))), dim3(kBlock), 0, s, b, z, dx_cams,
+                       dx_lms);
+    if (hipGetLastError() != hipSuccess) return POBA_ERR_HIP;
+    return lm_finish(p, cams, lms, st, o, s);
 }
 
 }  // extern "C"

@@ -231,6 +231,47 @@ class Problem:
         _lib.check("poba_lm_step", self.lib.poba_lm_step(self.handle, _ptr(cams), _ptr(lms), _ptr(state),
                                                          ctypes.byref(o), _stream(stream)))
 
+    def _check_state(self, cams, lms):
+        if cams.dtype != torch.float64 or not cams.is_contiguous() or tuple(cams.shape) != (self.n_cams, 9):
+            raise ValueError("cams must be a contiguous float64 [n_cams, 9] device tensor")
+        if lms.dtype != torch.float64 or not lms.is_contiguous() or tuple(lms.shape) != (self.n_lms, 3):
+            raise ValueError("lms must be a contiguous float64 [n_lms, 3] device tensor")
+
+    def lm_begin(self, cams: torch.Tensor, lms: torch.Tensor, state: torch.Tensor, stream=None):
+        """First half of an LM iteration whose step the caller computes:
+        linearises where the state asks for it."""
+        self._check_state(cams, lms)
+        _lib.check("poba_lm_begin", self.lib.poba_lm_begin(self.handle, _ptr(cams), _ptr(lms), _ptr(state),
+                                                           _stream(stream)))
+
+    def lm_finish(self, cams: torch.Tensor, lms: torch.Tensor, state: torch.Tensor, dx_cams: torch.Tensor,
+                  dx_lms: torch.Tensor, opts: LMOptions | None = None, stream=None):
+        """Second half: evaluates, accepts or rejects the step (dx_cams, dx_lms)."""
+        self._check_state(cams, lms)
+        opts = opts or LMOptions()
+        o = opts.c()
+        dx_cams = _dev(dx_cams, torch.float64, self.device, (self.n_cams, 9))
+        dx_lms = _dev(dx_lms, torch.float64, self.device, (self.n_lms, 3))
+        _lib.check("poba_lm_finish", self.lib.poba_lm_finish(self.handle, _ptr(cams), _ptr(lms), _ptr(state),
+                                                             ctypes.byref(o), _ptr(dx_cams), _ptr(dx_lms),
+                                                             _stream(stream)))
+
+    def back_substitute(self, lam: float, dx_cams: torch.Tensor, dx_lms=None, stream=None) -> torch.Tensor:
+        """dx_l = -V_lambda^-1 (b_l + W^T dx_cams) with the last linearisation."""
+        dx_cams = _dev(dx_cams, torch.float64, self.device, (self.n_cams, 9))
+        if dx_lms is None:
+            dx_lms = torch.empty(self.n_lms, 3, dtype=torch.float64, device=self.device)
+        _lib.check("poba_back_substitute", self.lib.poba_back_substitute(self.handle, float(lam), _ptr(dx_cams),
+                                                                         _ptr(dx_lms), _stream(stream)))
+        return dx_lms
+
+    def set_landmark_blocks(self, V: torch.Tensor, bl: torch.Tensor, stream=None):
+        """Replaces the undamped V [n_lms, 3, 3] and b_l [n_lms, 3] of the last linearisation."""
+        V = _dev(V, torch.float64, self.device, (self.n_lms, 3, 3))
+        bl = _dev(bl, torch.float64, self.device, (self.n_lms, 3))
+        _lib.check("poba_set_landmark_blocks", self.lib.poba_set_landmark_blocks(self.handle, _ptr(V), _ptr(bl),
+                                                                                 _stream(stream)))
+
     def lm_graph(self, cams: torch.Tensor, lms: torch.Tensor, state: torch.Tensor, n_steps: int,
                  opts: LMOptions | None = None) -> "LMGraph":
         """n_steps LM iterations captured in one HIP graph (poba_lm_graph_create)."""
