@@ -1,0 +1,139 @@
+"""The clustered reduced camera system of PoST (Sec. 5.3) on the GPU: the
+batched handle over (cluster, landmark) pairs with the whole problem's V and
+b_l, against the oracle's per-cluster power series; the LM halves with the
+clustered step against the oracle's LM with the same draws of clusters.
+
+Tolerances as the other parity tests: float64 1e-10 for the step, float32
+1e-4; LM costs 1e-9 relative (float64)."""
+import functools
+
+import numpy as np
+import pytest
+
+from paper_2204_12834_amd import synth
+from gpu_common import Case, log, np_, rel
+from oracle import lm, post as opost
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@functools.lru_cache(maxsize=None)
+def ring():
+    return Case(synth.config("c1"))
+
+
+@functools.lru_cache(maxsize=None)
+def city():
+    return Case(synth.city_scene(n_cams=60, n_lms=3000, seed=5, name="city_post"), delta=3.0)
+
+
+CASES = {"ring": ring, "city": city}
+
+
+def _post(case, precision="f64", records="jacobian", cap=5, seed=0, draws=0):
+    from paper_2204_12834_amd.post import PoST
+    s = case.scene
+    loss = "huber" if case.delta else "l2"
+    return PoST(s.obs_cam, s.obs_lm, case.obs, s.n_cams, s.n_lms, max_cluster=cap, seed=seed, draws=draws,
+                precision=precision, loss=loss, huber_delta=case.delta or 0.0, records=records)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("records", ["jacobian", "point"])
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-4)])
+@pytest.mark.parametrize("cap", [1, 7, 100])
+def test_clustered_step_matches_oracle(name, records, precision, tol, cap):
+    case = CASES[name]()
+    s = case.scene
+    log(f"post step {name} {records} {precision} cap={cap}")
+    p = _post(case, precision, records, cap, seed=3)
+    cams, lms = case.state()
+    p.whole.linearize(cams, lms)
+    for it, (lam, m, eps) in enumerate([(1e-2, 12, 0.0), (1.0, 20, 0.05)]):
+        dxp, dxl, info, c = p.step(cams, lms, lam, m, eps, iteration=it)
+        want_cl = opost.cluster_cameras(s.obs_cam, s.obs_lm, s.n_cams, cap, seed=3 + it)
+        assert c.cluster.tolist() == want_cl.tolist()
+        ref = opost.solve_clustered(case.Jp, case.Jl, case.r, s.obs_cam, s.obs_lm, s.n_cams, s.n_lms, lam, m, eps,
+                                    want_cl)
+        ep, el = rel(np_(dxp), ref.dxp), rel(np_(dxl), ref.dxl)
+        log(f"  {c.n_clusters} clusters, lambda {lam}: dx_p {ep:.2e} dx_l {el:.2e}")
+        assert ep <= tol and el <= tol
+        if eps == 0.0 and precision == "f64":
+            from paper_2204_12834_amd.solver import read_solve_info
+            orders = [read_solve_info(info, k)["stop_order"] for k in range(c.n_clusters)]
+            assert orders == ref.stop_orders
+
+
+def test_one_cluster_equals_the_power_solve():
+    case = ring()
+    p = _post(case, cap=1000)
+    cams, lms = case.state()
+    p.whole.linearize(cams, lms)
+    dxp, dxl, _, c = p.step(cams, lms, 1e-2, 16, 0.0)
+    assert c.n_clusters == 1
+    ref_p, ref_l, _ = p.whole.power_solve(1e-2, 16, 0.0)
+    assert rel(np_(dxp), np_(ref_p)) <= 1e-12 and rel(np_(dxl), np_(ref_l)) <= 1e-12
+
+
+@pytest.mark.parametrize("records", ["jacobian", "point"])
+@pytest.mark.parametrize("draws", [0, 3])
+def test_post_lm_follows_the_oracle(records, draws):
+    """Eight LM iterations with the clustered step: the costs, decisions and
+    the final state follow the oracle's LM with the same draws of clusters."""
+    case = ring()
+    s = case.scene
+    cap = 5
+    p = _post(case, "f64", records, cap, seed=11, draws=draws)
+    from paper_2204_12834_amd.solver import LMOptions
+    opts_gpu = LMOptions(m=12, eps=0.0, max_iters=8)
+    cams, lms = case.state()
+    states = p.lm(cams, lms, opts_gpu)
+    k = (lambda it: it % draws) if draws else (lambda it: it)
+    res = lm.lm(s.cams0, s.lms0, s.obs_cam, s.obs_lm, case.obs, lm.LMOptions(m=12, eps=0.0, max_iters=8),
+                solver="clustered",
+                cluster=lambda it: opost.cluster_cameras(s.obs_cam, s.obs_lm, s.n_cams, cap, seed=11 + k(it)))
+    assert len(states) == len(res.iterations)
+    for g, o in zip(states, res.iterations):
+        log(f"  cost {g['cost_new']:.9e} oracle {o.cost_new:.9e} accepted {g['accepted']} {o.accepted}")
+        assert g["accepted"] == int(o.accepted)
+        assert abs(g["cost_new"] - o.cost_new) <= 1e-9 * o.cost_new
+    assert rel(np_(cams), res.cams) <= 1e-8 and rel(np_(lms), res.lms) <= 1e-8
+
+
+def test_lm_halves_with_the_power_step_equal_lm_step():
+    """poba_lm_begin + poba_power_solve + poba_lm_finish is poba_lm_step."""
+    from paper_2204_12834_amd.solver import LMOptions, read_lm_states
+    case = ring()
+    a = case.problem("f64")
+    b = case.problem("f64")
+    ca, la = case.state()
+    cb, lb = case.state()
+    opts = LMOptions(m=10, eps=0.0, max_iters=6)
+    sa, sb = a.lm_init(opts), b.lm_init(opts)
+    for _ in range(6):
+        a.lm_step(ca, la, sa, opts)
+        b.lm_begin(cb, lb, sb)
+        lam = read_lm_states(sb)[0]["lambda"]
+        dxp, dxl, _ = b.power_solve(lam, 10, 0.0)
+        b.lm_finish(cb, lb, sb, dxp, dxl, opts)
+    ra, rb = read_lm_states(sa)[0], read_lm_states(sb)[0]
+    for key in ["cost", "lambda", "iteration", "n_accepted"]:
+        assert ra[key] == rb[key], key
+    assert torch.equal(ca, cb) and torch.equal(la, lb)
+
+
+def test_back_substitute_matches_the_oracle():
+    from oracle import normal, schur
+    case = ring()
+    s = case.scene
+    prob = case.problem("f64")
+    cams, lms = case.state()
+    prob.linearize(cams, lms)
+    x = np.random.default_rng(4).standard_normal((s.n_cams, 9)) * 1e-3
+    got = np_(prob.back_substitute(0.1, torch.tensor(x, device="cuda")))
+    U, V, bp, bl = normal.assemble(case.Jp, case.Jl, case.r, s.obs_cam, s.obs_lm, s.n_cams, s.n_lms)
+    dp, dl = normal.damping_diagonals(U, V)
+    _, Vl = normal.damp(U, V, 0.1, dp, dl)
+    want = schur.back_substitute(case.Jp, case.Jl, s.obs_cam, s.obs_lm, bl, normal.block_inverse(Vl), x)
+    assert rel(got, want) <= 1e-12
