@@ -600,6 +600,93 @@ def bench_pcg(args, dev):
     return 0
 
 
+def bench_post(args, dev):
+    """Sec. 5.3 on the GPU: LM with the clustered step of PoST (clusters of at
+    most 100 cameras, a new seeded draw of clusters per iteration, or a pool
+    of draws used in turn) against the LM with the power series of the whole
+    problem, from the same x0 with the Sec. 5.1 settings and series order
+    args.m.  Wall time per iteration (the clustering and relabelling run on
+    the host inside it), time and iterations to the 1% cost tolerance."""
+    import numpy as np
+    import torch
+    from paper_2204_12834_amd.post import PoST
+    from paper_2204_12834_amd.solver import LMOptions
+
+    scene, delta = make_scene(args.workload, args.huber)
+    opts = LMOptions(m=args.m)
+    prob, cams0, lms0, obs = gpu_setup(scene, delta, args.precision, dev, args.records)
+    lm_run(prob, cams0, lms0, LMOptions(m=args.m, max_iters=2), 2)  # warm
+    poba = lm_run(prob, cams0, lms0, opts, 50)
+    f0 = prob.linearize(cams0, lms0).item()
+    del prob
+    torch.cuda.empty_cache()
+    runs = {"poba": [(c, t) for c, t, _ in poba]}
+    detail = {}
+    for draws in ([0] + [args.post_draws] if args.post_draws else [0]):
+        t_setup = time.perf_counter()
+        p = PoST(scene.obs_cam, scene.obs_lm, obs, scene.n_cams, scene.n_lms, max_cluster=args.post_cluster,
+                 seed=1, draws=draws, precision=args.precision, loss="huber" if delta else "l2",
+                 huber_delta=delta or 0.0, records=args.records, device=dev)
+        if draws:
+            for it in range(draws):
+                p.clustered(it)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t_setup
+        cams, lms = cams0.clone(), lms0.clone()
+        times = []
+        t0 = time.perf_counter()
+        states = p.lm(cams, lms, opts, callback=lambda it, s: times.append(time.perf_counter() - t0))
+        name = f"post_draws{draws}" if draws else "post"
+        runs[name] = [(s["cost"], t) for s, t in zip(states, times)]
+        c = p.clustered(0)
+        sizes = np.bincount(c.cluster)
+        # one iteration's parts, timed apart at the final state
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cl, k = p.graph.cluster(args.post_cluster, 12345)
+        t2 = time.perf_counter()
+        p.graph.layout(cl, k)
+        t3 = time.perf_counter()
+        p.whole.linearize(cams, lms)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        p.step(cams, lms, 1e-4, args.m, 0.01, iteration=0)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        detail[name] = {"setup_s": round(t_setup, 3), "clusters": int(c.n_clusters),
+                        "cluster_size_min_mean_max": [int(sizes.min()), round(float(sizes.mean()), 1),
+                                                      int(sizes.max())],
+                        "cluster_ms": round(1e3 * (t2 - t1), 2), "layout_ms": round(1e3 * (t3 - t2), 2),
+                        "linearize_ms": round(1e3 * (t4 - t3), 2),
+                        "step_ms" + ("" if draws else "_incl_new_handle"): round(1e3 * (t5 - t4), 2)}
+        print(f"[post] {name}: {len(states)} iterations, {times[-1]:.3f} s, final cost {states[-1]['cost']:.6e}, "
+              f"{detail[name]}", file=sys.stderr, flush=True)
+        p.close()
+        del p
+        torch.cuda.empty_cache()
+    fstar = min(min(c for c, _ in r) for r in runs.values())
+    ftau = fstar + 0.01 * (f0 - fstar)
+    out = {}
+    for name, r in runs.items():
+        hit = next(((i + 1, t) for i, (c, t) in enumerate(r) if c <= ftau), None)
+        out[name] = {"iterations": len(r), "seconds": round(r[-1][1], 4), "final_cost": r[-1][0],
+                     "ms_per_iteration": round(1e3 * r[-1][1] / len(r), 3),
+                     "iters_to_1pct": hit[0] if hit else None, "t_1pct_s": round(hit[1], 4) if hit else None}
+    line = {"metric": "PoST on the GPU: LM time to 1% cost tol with per-cluster power series vs the whole-problem "
+                      "series, 1 GPU", "value": out["post"]["t_1pct_s"], "unit": "s", "n_gpus": 1,
+            "steps": out["post"]["iterations"], "warmup": 0, "ms_per_step": out["post"]["ms_per_iteration"],
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
+            "data": "file" if isinstance(scene, FileScene) else "synthetic",
+            "config": {"workload": f"{scene.name}: {scene.n_cams} cameras, {scene.n_lms} landmarks, "
+                                   f"{scene.n_obs} observations, {args.precision} "
+                                   f"{'Jacobian blocks' if args.records == 'jacobian' else 'point records'}, "
+                                   f"clusters of at most {args.post_cluster} cameras, m={args.m}, eps=0.01",
+                       "records": args.records},
+            "f0": f0, "f_star": fstar, "f_tau": ftau, "runs": out, "post_detail": detail}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -623,6 +710,11 @@ def main():
                     help="compare CG on the reduced camera system (Schur-Jacobi and power-series "
                          "preconditioners) with the power series at the first LM points, and exit")
     ap.add_argument("--pcg-points", type=int, default=5, help="LM linearisation points of the --pcg comparison")
+    ap.add_argument("--post", action="store_true",
+                    help="compare the LM of PoST (clustered reduced camera system) with the whole-problem LM, and exit")
+    ap.add_argument("--post-cluster", type=int, default=100, help="largest camera cluster of --post")
+    ap.add_argument("--post-draws", type=int, default=4,
+                    help="--post also runs with this many cluster draws used in turn (0: only new draws)")
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
 
@@ -647,6 +739,8 @@ def main():
         return bench_adjoint(args, dev)
     if args.pcg:
         return bench_pcg(args, dev)
+    if args.post:
+        return bench_post(args, dev)
     t_gen = time.perf_counter()
     scene, delta = make_scene(args.workload, args.huber)
     print(f"[bench] scene {scene.name}: {scene.n_cams} cams, {scene.n_lms} lms, {scene.n_obs} obs "

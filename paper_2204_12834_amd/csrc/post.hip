@@ -214,46 +214,52 @@ poba_status poba_cluster_layout(int64_t n_obs, const int32_t* obs_cam, const int
         for (int32_t c = 0; c < n_cams; ++c) cam_pos[c] = fill[cluster[c]]++;
     }
     // (cluster, landmark) pairs with observations, numbered cluster-major then
-    // by landmark; a cluster without any gets one unobserved pair (landmark 0)
-    std::vector<int64_t> keys(static_cast<size_t>(n_obs));
-    for (int64_t i = 0; i < n_obs; ++i) keys[size_t(i)] = int64_t(cluster[obs_cam[i]]) * n_lms + obs_lm[i];
-    std::vector<int64_t> uniq(keys);
-    std::sort(uniq.begin(), uniq.end());
-    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
-    std::vector<int32_t> per(size_t(n_clusters), 0);
-    for (int64_t u : uniq) ++per[size_t(u / n_lms)];
-    int32_t v = 0;
-    std::vector<int32_t> first(static_cast<size_t>(n_clusters));
-    prob_lm_off[0] = 0;
-    for (int32_t k = 0; k < n_clusters; ++k) {
-        first[k] = v;
-        v += std::max(per[k], 1);
-        prob_lm_off[k + 1] = v;
-    }
-    *n_vlm = v;
-    size_t u = 0;
-    for (int32_t k = 0; k < n_clusters; ++k) {
-        if (per[k] == 0) {
-            vlm_src[first[k]] = 0;
-            continue;
-        }
-        for (int32_t j = 0; j < per[k]; ++j, ++u) vlm_src[first[k] + j] = int32_t(uniq[u] % n_lms);
-    }
-    // an observation's pair: its position among the pairs, shifted by the
-    // unobserved pairs of the clusters before its own
+    // by landmark; a cluster without any gets one unobserved pair (landmark 0).
+    // Observations in (cluster, landmark) order by two stable counting sorts
+    // (landmark, then cluster), then one scan numbers the pairs.
+    std::vector<int32_t> by_lm(static_cast<size_t>(n_obs)), by_cl(static_cast<size_t>(n_obs));
     {
-        std::vector<int32_t> shift(static_cast<size_t>(n_clusters), 0);
-        int32_t s = 0;
-        for (int32_t k = 0; k < n_clusters; ++k) {
-            shift[k] = s;
-            if (per[k] == 0) ++s;
-        }
-        for (int64_t i = 0; i < n_obs; ++i) {
-            const int64_t kk = keys[size_t(i)];
-            const int32_t pos = int32_t(std::lower_bound(uniq.begin(), uniq.end(), kk) - uniq.begin());
-            obs_vlm[i] = pos + shift[size_t(kk / n_lms)];
+        std::vector<int64_t> off(static_cast<size_t>(n_lms) + 1, 0);
+        for (int64_t i = 0; i < n_obs; ++i) ++off[size_t(obs_lm[i]) + 1];
+        for (int32_t l = 0; l < n_lms; ++l) off[l + 1] += off[l];
+        for (int64_t i = 0; i < n_obs; ++i) by_lm[size_t(off[obs_lm[i]]++)] = int32_t(i);
+    }
+    {
+        std::vector<int64_t> off(static_cast<size_t>(n_clusters) + 1, 0);
+        for (int64_t i = 0; i < n_obs; ++i) ++off[size_t(cluster[obs_cam[i]]) + 1];
+        for (int32_t k = 0; k < n_clusters; ++k) off[k + 1] += off[k];
+        for (int64_t j = 0; j < n_obs; ++j) {
+            const int32_t i = by_lm[size_t(j)];
+            by_cl[size_t(off[cluster[obs_cam[i]]]++)] = i;
         }
     }
+    int32_t v = 0, k_prev = -1, l_prev = -1;
+    prob_lm_off[0] = 0;
+    auto close_clusters = [&](int32_t upto) {  // clusters k_prev + 1 .. upto - 1 have no pair
+        for (int32_t k = k_prev + 1; k < upto; ++k) {
+            vlm_src[v] = 0;
+            ++v;
+            prob_lm_off[k + 1] = v;
+        }
+    };
+    for (int64_t j = 0; j < n_obs; ++j) {
+        const int32_t i = by_cl[size_t(j)];
+        const int32_t k = cluster[obs_cam[i]], l = obs_lm[i];
+        if (k != k_prev) {
+            if (k_prev >= 0) prob_lm_off[k_prev + 1] = v;
+            close_clusters(k);
+            k_prev = k;
+            l_prev = -1;
+        }
+        if (l != l_prev) {
+            vlm_src[v++] = l;
+            l_prev = l;
+        }
+        obs_vlm[i] = v - 1;
+    }
+    if (k_prev >= 0) prob_lm_off[k_prev + 1] = v;
+    close_clusters(n_clusters);
+    *n_vlm = v;
     return POBA_OK;
 }
 

@@ -49,13 +49,16 @@ def test_hand_worked_graph_through_the_library():
         assert g.cluster(cap)[0].tolist() == want
 
 
-def test_layout():
+@pytest.mark.parametrize("lonely_cam", ["first", "last"])
+def test_layout(lonely_cam):
     """Cameras grouped by cluster (ascending inside), one pair per (cluster,
     landmark) with observations, numbered cluster-major then by landmark, and
-    an unobserved pair for a cluster without observations."""
+    an unobserved pair for a cluster without observations (camera 0 or the
+    last camera observes nothing)."""
     P = c1()
-    # camera 16 observes nothing
-    g = _graph((P.obs_cam, P.obs_lm, P.n_cams + 1, P.n_lms))
+    shift = 1 if lonely_cam == "first" else 0
+    obs_cam = np.asarray(P.obs_cam) + shift
+    g = _graph((obs_cam, P.obs_lm, P.n_cams + 1, P.n_lms))
     cl, k = g.cluster(5, 3)
     cam_pos, obs_vlm, vlm_src, pco, plo = g.layout(cl, k)
     assert sorted(cam_pos.tolist()) == list(range(P.n_cams + 1))
@@ -63,16 +66,16 @@ def test_layout():
         cams = np.flatnonzero(cl == j)
         assert sorted(cam_pos[cams].tolist()) == list(range(pco[j], pco[j + 1]))
         assert np.all(np.diff(cam_pos[cams]) > 0)
-    pairs = sorted({(int(cl[c]), int(l)) for c, l in zip(P.obs_cam, P.obs_lm)})
+    pairs = sorted({(int(cl[c]), int(l)) for c, l in zip(obs_cam, P.obs_lm)})
     lonely = [j for j in range(k) if not any(p[0] == j for p in pairs)]
-    assert lonely == [int(cl[P.n_cams])]
+    assert lonely == [int(cl[0 if shift else P.n_cams])]
     want_src, want_off = [], [0]
     for j in range(k):
         mine = [l for (kk, l) in pairs if kk == j] or [0]
         want_src += mine
         want_off.append(len(want_src))
     assert vlm_src.tolist() == want_src and plo.tolist() == want_off
-    for i, (c, l) in enumerate(zip(P.obs_cam, P.obs_lm)):
+    for i, (c, l) in enumerate(zip(obs_cam, P.obs_lm)):
         v = obs_vlm[i]
         assert vlm_src[v] == l and plo[cl[c]] <= v < plo[cl[c] + 1]
 
