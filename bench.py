@@ -192,7 +192,7 @@ def stream_probe(dev, nbytes=1 << 32):
     out = {}
     for kind, name, moved in [(0, "read", nbytes), (1, "copy", 2 * nbytes)]:
         best = 0.0
-        for blocks in [1024, 2048, 4096, 8192, 16384]:
+        for blocks in [512, 768, 1024, 2048, 4096, 8192, 16384]:
             for _ in range(2):
                 _lib.check("poba_probe", lib.poba_probe(kind, ctypes.c_void_p(src.data_ptr()),
                                                         ctypes.c_void_p(dst.data_ptr()), nbytes, blocks, s))
