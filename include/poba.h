@@ -321,19 +321,25 @@ poba_status poba_camera_graph_edges(poba_camera_graph g, int64_t *n_edges, int32
 poba_status poba_camera_graph_cluster(poba_camera_graph g, int32_t max_size, int64_t seed, int32_t *cluster,
                                       int32_t *n_clusters);
 
-/* [host] The batched layout of a clustered problem (Sec. 5.3): problem k is
- * cluster k.  cam_pos [n_cams]: the camera's index in cluster order (clusters
- * in turn, cameras ascending); the landmarks are the (cluster, landmark) pairs
- * that have observations, numbered by cluster then landmark, plus one
- * unobserved pair (landmark 0) for a cluster without observations:
- * obs_vlm [n_obs] the pair of each observation, vlm_src [n_obs + n_clusters]
- * the landmark of each pair, *n_vlm their number; prob_cam_off,
- * prob_lm_off [n_clusters + 1] the ranges for poba_batch_create.  All host
- * memory; cluster values must lie in [0, n_clusters) and use every index. */
-poba_status poba_cluster_layout(int64_t n_obs, const int32_t *obs_cam, const int32_t *obs_lm, int32_t n_cams,
-                                int32_t n_lms, const int32_t *cluster, int32_t n_clusters, int32_t *cam_pos,
-                                int32_t *obs_vlm, int32_t *vlm_src, int32_t *n_vlm, int32_t *prob_cam_off,
-                                int32_t *prob_lm_off);
+/* [host] The graph's observation order: order [n_obs] lists the original
+ * observation indices by landmark (stable within a landmark). */
+poba_status poba_camera_graph_order(poba_camera_graph g, int32_t *order);
+
+/* [host] The batched layout of the graph's problem clustered by `cluster`
+ * (Sec. 5.3): problem k is cluster k.  cam_pos [n_cams]: the camera's index
+ * in cluster order (clusters in turn, cameras ascending); the landmarks are
+ * the (cluster, landmark) pairs that have observations, numbered by cluster
+ * then landmark, plus one unobserved pair (landmark 0) for a cluster without
+ * observations: obs_vlm [n_obs] the pair of each observation taken in the
+ * graph's observation order (poba_camera_graph_order), vlm_src
+ * [n_obs + n_clusters] the landmark of each pair, *n_vlm their number;
+ * prob_cam_off, prob_lm_off [n_clusters + 1] the ranges for
+ * poba_batch_create.  All host memory; cluster values must lie in
+ * [0, n_clusters) (else POBA_ERR_INDEX_RANGE) and use every index (else
+ * POBA_ERR_INVALID_ARG). */
+poba_status poba_camera_graph_layout(poba_camera_graph g, const int32_t *cluster, int32_t n_clusters,
+                                     int32_t *cam_pos, int32_t *obs_vlm, int32_t *vlm_src, int32_t *n_vlm,
+                                     int32_t *prob_cam_off, int32_t *prob_lm_off);
 
 /* Replaces the undamped landmark blocks of the last poba_linearize: V [dev]
  * float64 [n_lms][3][3] (the upper triangle is read) and b_l [dev] float64

@@ -128,7 +128,8 @@ SIGNATURES = {
     "poba_camera_graph_destroy": (I32, [P]),
     "poba_camera_graph_edges": (I32, [P, ctypes.POINTER(I64), P, P, P]),
     "poba_camera_graph_cluster": (I32, [P, I32, I64, P, ctypes.POINTER(I32)]),
-    "poba_cluster_layout": (I32, [I64, P, P, I32, I32, P, I32, P, P, P, ctypes.POINTER(I32), P, P]),
+    "poba_camera_graph_layout": (I32, [P, P, I32, P, P, P, ctypes.POINTER(I32), P, P]),
+    "poba_camera_graph_order": (I32, [P, P]),
     "poba_lm_init": (I32, [P, P, ctypes.POINTER(PobaLMOptions), P]),
     "poba_lm_step": (I32, [P, P, P, P, ctypes.POINTER(PobaLMOptions), P]),
     "poba_project": (I32, [I64, P, P, P, P, P, P]),

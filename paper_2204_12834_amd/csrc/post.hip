@@ -23,8 +23,10 @@
 #include "kernels.hpp"
 
 struct poba_camera_graph_s {
-    int32_t n_cams = 0;
+    int32_t n_cams = 0, n_lms = 0;
     std::vector<int32_t> a, b, w;  // edges a < b with their weights, ordered by (a, b)
+    // the observations in landmark order (stable): original index, camera, landmark
+    std::vector<int32_t> lm_order, lm_order_cam, lm_order_lm;
 };
 
 namespace poba {
@@ -110,6 +112,20 @@ poba_status poba_camera_graph_create(int64_t n_obs, const int32_t* obs_cam, cons
     group_distinct(n_obs, obs_cam, obs_lm, n_cams, cam_off, cam_lms);
     auto* g = new poba_camera_graph_s;
     g->n_cams = n_cams;
+    g->n_lms = n_lms;
+    {
+        std::vector<int64_t> off(static_cast<size_t>(n_lms) + 1, 0);
+        for (int64_t i = 0; i < n_obs; ++i) ++off[size_t(obs_lm[i]) + 1];
+        for (int32_t l = 0; l < n_lms; ++l) off[l + 1] += off[l];
+        g->lm_order.resize(size_t(n_obs));
+        for (int64_t i = 0; i < n_obs; ++i) g->lm_order[size_t(off[obs_lm[i]]++)] = int32_t(i);
+        g->lm_order_cam.resize(size_t(n_obs));
+        g->lm_order_lm.resize(size_t(n_obs));
+        for (int64_t j = 0; j < n_obs; ++j) {
+            g->lm_order_cam[size_t(j)] = obs_cam[g->lm_order[size_t(j)]];
+            g->lm_order_lm[size_t(j)] = obs_lm[g->lm_order[size_t(j)]];
+        }
+    }
     std::vector<int32_t> cnt(size_t(n_cams), 0), touched;
     for (int32_t a = 0; a < n_cams; ++a) {
         touched.clear();
@@ -149,14 +165,18 @@ poba_status poba_camera_graph_cluster(poba_camera_graph g, int32_t max_size, int
                                       int32_t* n_clusters) {
     if (!g || !cluster || max_size < 1) return POBA_ERR_INVALID_ARG;
     const size_t ne = g->a.size();
-    std::vector<double> key(ne);
-    for (size_t e = 0; e < ne; ++e)
-        key[e] = seed < 0 ? double(g->w[e]) : double(g->w[e]) * edge_uniform(uint64_t(seed), g->a[e], g->b[e]);
-    std::vector<int32_t> order(ne);
-    std::iota(order.begin(), order.end(), 0);
-    // heavier first; ties by (a, b), which is the edge order
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return key[x] > key[y]; });
+    // Edges are visited heaviest first, ties in edge order ((a, b) ascending),
+    // from a binary heap, until no two clusters fit together any more.
     const int32_t n = g->n_cams;
+    std::vector<std::pair<double, int32_t>> heap(ne);
+    for (size_t e = 0; e < ne; ++e)
+        heap[e] = {seed < 0 ? double(g->w[e]) : double(g->w[e]) * edge_uniform(uint64_t(seed), g->a[e], g->b[e]),
+                   int32_t(e)};
+    // "less" for the max-heap: lighter, or as heavy and later in edge order
+    auto later = [](const std::pair<double, int32_t>& x, const std::pair<double, int32_t>& y) {
+        return x.first < y.first || (x.first == y.first && x.second > y.second);
+    };
+    std::make_heap(heap.begin(), heap.end(), later);
     std::vector<int32_t> root(static_cast<size_t>(n)), size(static_cast<size_t>(n), 1);
     std::iota(root.begin(), root.end(), 0);
     auto find = [&](int32_t x) {
@@ -166,12 +186,38 @@ poba_status poba_camera_graph_cluster(poba_camera_graph g, int32_t max_size, int
         }
         return x;
     };
-    for (int32_t e : order) {
+    // clusters by size (sizes up to the cap), to see when no merge can happen
+    const bool track = max_size <= 4096;
+    std::vector<int32_t> n_of_size(track ? size_t(max_size) + 1 : 0, 0);
+    if (track) n_of_size[1] = n;
+    auto can_merge = [&]() {
+        int32_t first = 0;  // smallest size, then the next one (possibly equal)
+        for (int32_t s2 = 1; s2 <= max_size; ++s2) {
+            if (n_of_size[s2] == 0) continue;
+            if (first == 0) {
+                if (n_of_size[s2] >= 2) return 2 * s2 <= max_size;
+                first = s2;
+            } else {
+                return first + s2 <= max_size;
+            }
+        }
+        return false;
+    };
+    size_t left = track && !can_merge() ? 0 : ne;
+    while (left > 0) {
+        std::pop_heap(heap.begin(), heap.begin() + left, later);
+        const int32_t e = heap[--left].second;
         const int32_t ra = find(g->a[e]), rb = find(g->b[e]);
         if (ra != rb && size[ra] + size[rb] <= max_size) {
             const int32_t lo = std::min(ra, rb), hi = std::max(ra, rb);
+            if (track) {
+                --n_of_size[size[lo]];
+                --n_of_size[size[hi]];
+                ++n_of_size[size[lo] + size[hi]];
+            }
             root[hi] = lo;
             size[lo] += size[hi];
+            if (track && !can_merge()) break;
         }
     }
     std::vector<int32_t> label(size_t(n), -1);
@@ -185,23 +231,27 @@ poba_status poba_camera_graph_cluster(poba_camera_graph g, int32_t max_size, int
     return POBA_OK;
 }
 
+poba_status poba_camera_graph_order(poba_camera_graph g, int32_t* order) {
+    if (!g || (!order && !g->lm_order.empty())) return POBA_ERR_INVALID_ARG;
+    std::memcpy(order, g->lm_order.data(), g->lm_order.size() * 4);
+    return POBA_OK;
+}
+
 poba_status poba_camera_graph_destroy(poba_camera_graph g) {
     delete g;
     return POBA_OK;
 }
 
-poba_status poba_cluster_layout(int64_t n_obs, const int32_t* obs_cam, const int32_t* obs_lm, int32_t n_cams,
-                                int32_t n_lms, const int32_t* cluster, int32_t n_clusters, int32_t* cam_pos,
-                                int32_t* obs_vlm, int32_t* vlm_src, int32_t* n_vlm, int32_t* prob_cam_off,
-                                int32_t* prob_lm_off) {
-    if (n_obs < 0 || n_cams < 1 || n_lms < 1 || n_clusters < 1 || !cluster || !cam_pos || !obs_vlm || !vlm_src ||
-        !n_vlm || !prob_cam_off || !prob_lm_off || (n_obs > 0 && (!obs_cam || !obs_lm)))
+poba_status poba_camera_graph_layout(poba_camera_graph g, const int32_t* cluster, int32_t n_clusters,
+                                     int32_t* cam_pos, int32_t* obs_vlm, int32_t* vlm_src, int32_t* n_vlm,
+                                     int32_t* prob_cam_off, int32_t* prob_lm_off) {
+    if (!g || n_clusters < 1 || !cluster || !cam_pos || !obs_vlm || !vlm_src || !n_vlm || !prob_cam_off ||
+        !prob_lm_off)
         return POBA_ERR_INVALID_ARG;
+    const int32_t n_cams = g->n_cams;
+    const int64_t n_obs = int64_t(g->lm_order.size());
     for (int32_t c = 0; c < n_cams; ++c)
         if (cluster[c] < 0 || cluster[c] >= n_clusters) return POBA_ERR_INDEX_RANGE;
-    for (int64_t i = 0; i < n_obs; ++i)
-        if (obs_cam[i] < 0 || obs_cam[i] >= n_cams || obs_lm[i] < 0 || obs_lm[i] >= n_lms)
-            return POBA_ERR_INDEX_RANGE;
     // cameras in cluster order, ascending within a cluster
     std::fill(prob_cam_off, prob_cam_off + n_clusters + 1, 0);
     for (int32_t c = 0; c < n_cams; ++c) ++prob_cam_off[cluster[c] + 1];
@@ -215,50 +265,34 @@ poba_status poba_cluster_layout(int64_t n_obs, const int32_t* obs_cam, const int
     }
     // (cluster, landmark) pairs with observations, numbered cluster-major then
     // by landmark; a cluster without any gets one unobserved pair (landmark 0).
-    // Observations in (cluster, landmark) order by two stable counting sorts
-    // (landmark, then cluster), then one scan numbers the pairs.
-    std::vector<int32_t> by_lm(static_cast<size_t>(n_obs)), by_cl(static_cast<size_t>(n_obs));
-    {
-        std::vector<int64_t> off(static_cast<size_t>(n_lms) + 1, 0);
-        for (int64_t i = 0; i < n_obs; ++i) ++off[size_t(obs_lm[i]) + 1];
-        for (int32_t l = 0; l < n_lms; ++l) off[l + 1] += off[l];
-        for (int64_t i = 0; i < n_obs; ++i) by_lm[size_t(off[obs_lm[i]]++)] = int32_t(i);
-    }
-    {
-        std::vector<int64_t> off(static_cast<size_t>(n_clusters) + 1, 0);
-        for (int64_t i = 0; i < n_obs; ++i) ++off[size_t(cluster[obs_cam[i]]) + 1];
-        for (int32_t k = 0; k < n_clusters; ++k) off[k + 1] += off[k];
-        for (int64_t j = 0; j < n_obs; ++j) {
-            const int32_t i = by_lm[size_t(j)];
-            by_cl[size_t(off[cluster[obs_cam[i]]]++)] = i;
-        }
-    }
-    int32_t v = 0, k_prev = -1, l_prev = -1;
-    prob_lm_off[0] = 0;
-    auto close_clusters = [&](int32_t upto) {  // clusters k_prev + 1 .. upto - 1 have no pair
-        for (int32_t k = k_prev + 1; k < upto; ++k) {
-            vlm_src[v] = 0;
-            ++v;
-            prob_lm_off[k + 1] = v;
-        }
-    };
+    // The observations come in landmark order, so a pair is new for its
+    // cluster exactly when the cluster's last landmark differs: one pass ranks
+    // the pairs within their clusters, a second adds the clusters' offsets.
+    const int32_t* oc = g->lm_order_cam.data();
+    const int32_t* ol = g->lm_order_lm.data();
+    std::vector<int32_t> cnt(static_cast<size_t>(n_clusters), 0), last(static_cast<size_t>(n_clusters), -1);
     for (int64_t j = 0; j < n_obs; ++j) {
-        const int32_t i = by_cl[size_t(j)];
-        const int32_t k = cluster[obs_cam[i]], l = obs_lm[i];
-        if (k != k_prev) {
-            if (k_prev >= 0) prob_lm_off[k_prev + 1] = v;
-            close_clusters(k);
-            k_prev = k;
-            l_prev = -1;
+        const int32_t k = cluster[oc[j]];
+        if (last[k] != ol[j]) {
+            last[k] = ol[j];
+            ++cnt[k];
         }
-        if (l != l_prev) {
-            vlm_src[v++] = l;
-            l_prev = l;
-        }
-        obs_vlm[i] = v - 1;
+        obs_vlm[j] = cnt[k] - 1;
     }
-    if (k_prev >= 0) prob_lm_off[k_prev + 1] = v;
-    close_clusters(n_clusters);
+    int32_t v = 0;
+    std::vector<int32_t> first(static_cast<size_t>(n_clusters));
+    prob_lm_off[0] = 0;
+    for (int32_t k = 0; k < n_clusters; ++k) {
+        first[k] = v;
+        if (cnt[k] == 0) vlm_src[v] = 0;
+        v += std::max(cnt[k], 1);
+        prob_lm_off[k + 1] = v;
+    }
+    for (int64_t j = 0; j < n_obs; ++j) {
+        const int32_t k = cluster[oc[j]];
+        obs_vlm[j] += first[k];
+        vlm_src[obs_vlm[j]] = ol[j];
+    }
     *n_vlm = v;
     return POBA_OK;
 }

@@ -39,6 +39,8 @@ class CameraGraph:
             self.obs_cam.size, self.obs_cam.ctypes.data, self.obs_lm.ctypes.data, self.n_cams, self.n_lms,
             ctypes.byref(h)))
         self.handle = h
+        self.order = np.empty(self.obs_cam.size, np.int32)
+        _lib.check("poba_camera_graph_order", self.lib.poba_camera_graph_order(self.handle, self.order.ctypes.data))
 
     def edges(self):
         n = ctypes.c_int64()
@@ -59,7 +61,8 @@ class CameraGraph:
         return out, int(k.value)
 
     def layout(self, cluster: np.ndarray, n_clusters: int):
-        """Batched layout of the clustered problem (see poba_cluster_layout)."""
+        """Batched layout of the clustered problem (see poba_camera_graph_layout);
+        obs_vlm follows the observations in the order `self.order`."""
         cluster = np.ascontiguousarray(cluster, dtype=np.int32)
         n = self.obs_cam.size
         cam_pos = np.empty(self.n_cams, np.int32)
@@ -68,10 +71,9 @@ class CameraGraph:
         pco = np.empty(n_clusters + 1, np.int32)
         plo = np.empty(n_clusters + 1, np.int32)
         nv = ctypes.c_int32()
-        _lib.check("poba_cluster_layout", self.lib.poba_cluster_layout(
-            n, self.obs_cam.ctypes.data, self.obs_lm.ctypes.data, self.n_cams, self.n_lms, cluster.ctypes.data,
-            int(n_clusters), cam_pos.ctypes.data, obs_vlm.ctypes.data, vlm_src.ctypes.data, ctypes.byref(nv),
-            pco.ctypes.data, plo.ctypes.data))
+        _lib.check("poba_camera_graph_layout", self.lib.poba_camera_graph_layout(
+            self.handle, cluster.ctypes.data, int(n_clusters), cam_pos.ctypes.data, obs_vlm.ctypes.data,
+            vlm_src.ctypes.data, ctypes.byref(nv), pco.ctypes.data, plo.ctypes.data))
         return cam_pos, obs_vlm, vlm_src[:nv.value].copy(), pco, plo
 
     def close(self):
@@ -110,8 +112,11 @@ class PoST:
                   device=self.device)
         self.kw = kw
         self.whole = Problem(obs_cam, obs_lm, obs_xy, n_cams, n_lms, **kw)
-        self.obs_xy = torch.as_tensor(obs_xy, dtype=torch.float64, device=self.device).contiguous()
         self.graph = CameraGraph(obs_cam, obs_lm, n_cams, n_lms)
+        # the clustered handles take the observations in the graph's (landmark) order
+        order = torch.as_tensor(self.graph.order, device=self.device).long()
+        self.obs_xy = torch.as_tensor(obs_xy, dtype=torch.float64, device=self.device)[order].contiguous()
+        self.obs_cam_ordered = torch.as_tensor(self.graph.obs_cam, device=self.device).long()[order]
         self.n_cams, self.n_lms = int(n_cams), int(n_lms)
         self.max_cluster, self.seed, self.draws = int(max_cluster), int(seed), int(draws)
         self._pool = {}
@@ -122,8 +127,7 @@ class PoST:
             return self._pool[key]
         cluster, k = self.graph.cluster(self.max_cluster, self.seed + key)
         cam_pos, obs_vlm, vlm_src, pco, plo = self.graph.layout(cluster, k)
-        obs_cam = torch.as_tensor(cam_pos, device=self.device)[torch.as_tensor(self.graph.obs_cam,
-                                                                                device=self.device).long()]
+        obs_cam = torch.as_tensor(cam_pos, device=self.device)[self.obs_cam_ordered]
         prob = Problem(obs_cam, obs_vlm, self.obs_xy, self.n_cams, int(vlm_src.size), prob_cam_off=pco,
                        prob_lm_off=plo, **self.kw)
         pos = torch.as_tensor(cam_pos, device=self.device).long()

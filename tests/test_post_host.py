@@ -75,8 +75,9 @@ def test_layout(lonely_cam):
         want_src += mine
         want_off.append(len(want_src))
     assert vlm_src.tolist() == want_src and plo.tolist() == want_off
-    for i, (c, l) in enumerate(zip(obs_cam, P.obs_lm)):
-        v = obs_vlm[i]
+    assert g.order.tolist() == np.argsort(np.asarray(P.obs_lm), kind="stable").tolist()
+    for j, i in enumerate(g.order):
+        c, l, v = obs_cam[i], P.obs_lm[i], obs_vlm[j]
         assert vlm_src[v] == l and plo[cl[c]] <= v < plo[cl[c] + 1]
 
 
