@@ -301,7 +301,8 @@ poba_status poba_back_substitute(poba_problem p, double lambda, const double *dx
 /* [host] The camera graph of a problem: an edge between two cameras that
  * observe a common landmark, weighted by the number of such landmarks (each
  * landmark counted once per camera pair).  obs_cam, obs_lm [host] int32
- * [n_obs].  Returns POBA_ERR_INDEX_RANGE for an index out of range. */
+ * [n_obs].  Returns POBA_ERR_INDEX_RANGE for an index out of range.  The
+ * host calls on a graph return POBA_ERR_WORKSPACE when host memory runs out. */
 typedef struct poba_camera_graph_s *poba_camera_graph;
 poba_status poba_camera_graph_create(int64_t n_obs, const int32_t *obs_cam, const int32_t *obs_lm,
                                      int32_t n_cams, int32_t n_lms, poba_camera_graph *out);

@@ -57,3 +57,13 @@ def rel(a, b):
 
 def np_(t):
     return t.detach().cpu().numpy()
+
+
+def round_bf16(a):
+    """float64 -> float32 -> bfloat16 (round to nearest even) -> float64: the
+    values a bfloat16 record holds."""
+    f = np.asarray(a, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return (u.astype(np.uint32)).view(np.float32).astype(np.float64)
+

@@ -21,7 +21,7 @@ import numpy as np
 import pytest
 
 from paper_2204_12834_amd import synth
-from gpu_common import Case, log, np_, observations, rel
+from gpu_common import Case, log, np_, observations, rel, round_bf16
 from oracle import lm, normal, pcg, schur
 
 torch = pytest.importorskip("torch")
@@ -244,3 +244,26 @@ def test_pcg_no_observations():
         dxp, dxl, info, _ = prob.pcg_solve(1e-2, precond, 3, 1e-8, 20)
         assert info[0]["converged"] == 1 and info[0]["iterations"] == 0
         assert torch.all(dxp == 0) and torch.all(dxl == 0)
+
+
+@pytest.mark.parametrize("precond,m", [("schur_jacobi", 0), ("power", 2)])
+def test_pcg_bf16_matches_oracle_on_rounded_blocks(precond, m):
+    """bfloat16 Jacobian storage: the oracle's PCG on its own blocks rounded to
+    bfloat16 (the values the records hold), so the comparison is tight
+    (Schur-Jacobi to 1e-8, steps 1e-5).  The power preconditioner runs in
+    float32 there: tol 1e-6 and steps 1e-4 as for float32 storage."""
+    case = city()
+    s = case.scene
+    log(f"pcg bf16 {precond} m={m}")
+    prob = case.problem("bf16")
+    cams, lms = case.state()
+    prob.linearize(cams, lms)
+    tol, step_tol = (1e-8, 1e-5) if precond == "schur_jacobi" else (1e-6, 1e-4)
+    dxp, dxl, info, _ = prob.pcg_solve(1e-2, precond, m, tol, 500)
+    Jp, Jl = round_bf16(case.Jp), round_bf16(case.Jl)
+    ref = pcg.solve_pcg(Jp, Jl, case.r, s.obs_cam, s.obs_lm, s.n_cams, s.n_lms, 1e-2, precond, m, tol, 500)
+    ep, el = rel(np_(dxp), ref.dxp), rel(np_(dxl), ref.dxl)
+    log(f"  iterations gpu {info[0]['iterations']} oracle {ref.result.iterations}: dx_p {ep:.2e} dx_l {el:.2e}")
+    assert info[0]["converged"] == 1 and abs(info[0]["iterations"] - ref.result.iterations) <= 3
+    assert ep <= step_tol and el <= step_tol
+

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from paper_2204_12834_amd import synth
-from gpu_common import Case, log, np_, rel
+from gpu_common import Case, log, np_, rel, round_bf16
 from oracle import lm, post as opost
 
 torch = pytest.importorskip("torch")
@@ -137,3 +137,20 @@ def test_back_substitute_matches_the_oracle():
     _, Vl = normal.damp(U, V, 0.1, dp, dl)
     want = schur.back_substitute(case.Jp, case.Jl, s.obs_cam, s.obs_lm, bl, normal.block_inverse(Vl), x)
     assert rel(got, want) <= 1e-12
+
+
+def test_clustered_step_bf16_on_rounded_blocks():
+    """bfloat16 Jacobian storage against the oracle's clustered step on its
+    blocks rounded to bfloat16 (the series runs in float32: 1e-4)."""
+    case = city()
+    s = case.scene
+    p = _post(case, "bf16", cap=7, seed=5)
+    cams, lms = case.state()
+    p.whole.linearize(cams, lms)
+    dxp, dxl, _, c = p.step(cams, lms, 1e-2, 12, 0.0)
+    ref = opost.solve_clustered(round_bf16(case.Jp), round_bf16(case.Jl), case.r, s.obs_cam, s.obs_lm, s.n_cams,
+                                s.n_lms, 1e-2, 12, 0.0, c.cluster)
+    ep, el = rel(np_(dxp), ref.dxp), rel(np_(dxl), ref.dxl)
+    log(f"post bf16: dx_p {ep:.2e} dx_l {el:.2e}")
+    assert ep <= 1e-4 and el <= 1e-4
+
