@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from paper_2204_12834_amd import synth
-from gpu_common import Case, log, np_, rel
+from gpu_common import Case, log, np_, rel, round_bf16
 from oracle import camera, lm, normal, robust, schur
 
 torch = pytest.importorskip("torch")
@@ -193,6 +193,26 @@ def test_power_solve_reduced_precision(name, precision, records, tol):
         ep, el = rel(np_(dxp), ref.dxp), rel(np_(dxl), ref.dxl)
         log(f"{precision} {records} {name} lam={lam}: dx_p {ep:.2e} dx_l {el:.2e}")
         assert ep <= tol and el <= tol
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_power_solve_bf16_on_rounded_blocks(name):
+    """bfloat16 Jacobian storage against the oracle run on its own blocks
+    rounded to bfloat16 (the values the records hold): the remaining
+    difference is the float32 arithmetic of the series passes (1e-4, as for
+    float32 storage)."""
+    case = CASES[name]()
+    s = case.scene
+    prob = case.problem("bf16")
+    cams, lms = case.state()
+    prob.linearize(cams, lms)
+    Jp, Jl = round_bf16(case.Jp), round_bf16(case.Jl)
+    for lam in [1e-4, 1e-2]:
+        dxp, dxl, _ = prob.power_solve(lam, 20, 0.0)
+        ref = schur.solve(Jp, Jl, case.r, s.obs_cam, s.obs_lm, s.n_cams, s.n_lms, lam, 20)
+        ep, el = rel(np_(dxp), ref.dxp), rel(np_(dxl), ref.dxl)
+        log(f"bf16 rounded-block oracle {name} lam={lam}: dx_p {ep:.2e} dx_l {el:.2e}")
+        assert ep <= 1e-4 and el <= 1e-4
 
 
 @pytest.mark.parametrize("records", ["jacobian", "point"])
