@@ -267,3 +267,28 @@ def test_pcg_bf16_matches_oracle_on_rounded_blocks(precond, m):
     assert info[0]["converged"] == 1 and abs(info[0]["iterations"] - ref.result.iterations) <= 3
     assert ep <= step_tol and el <= step_tol
 
+
+def test_pcg_batch_with_a_problem_without_observations():
+    """A batch whose second problem has no observations: it converges at
+    iteration 0 with a zero step while the first iterates as on its own."""
+    from paper_2204_12834_amd.solver import Problem
+    base = synth.ring_scene(12, 500, (2, 6), seed=21, name="pb_main")
+    obs = observations(base)
+    n_cams, n_lms = base.n_cams + 3, base.n_lms + 5
+    prob = Problem(base.obs_cam, base.obs_lm, obs, n_cams, n_lms, precision="f64", device="cuda",
+                   prob_cam_off=[0, base.n_cams, n_cams], prob_lm_off=[0, base.n_lms, n_lms])
+    cams = np.concatenate([base.cams0, np.tile([0, 0, 0, 0, 0, -5.0, 500.0, 0, 0], (3, 1))])
+    lms = np.concatenate([base.lms0, np.zeros((5, 3))])
+    prob.linearize(torch.tensor(cams, device="cuda"), torch.tensor(lms, device="cuda"))
+    dxp, dxl, info, co = prob.pcg_solve(1e-2, "schur_jacobi", 0, 1e-10, 500, coeffs=True)
+    F, r, Jp, Jl = lm.linearize(base.cams0, base.lms0, base.obs_cam, base.obs_lm, obs)
+    ref = pcg.solve_pcg(Jp, Jl, r, base.obs_cam, base.obs_lm, base.n_cams, base.n_lms, 1e-2, "schur_jacobi", 0,
+                        1e-10, 500)
+    assert info[1]["converged"] == 1 and info[1]["iterations"] == 0
+    assert info[0]["converged"] == 1 and abs(info[0]["iterations"] - ref.result.iterations) <= 1
+    dxp, dxl = np_(dxp), np_(dxl)
+    assert not np.any(dxp[base.n_cams:]) and not np.any(dxl[base.n_lms:])
+    assert rel(dxp[:base.n_cams], ref.dxp) <= 1e-7 and rel(dxl[:base.n_lms], ref.dxl) <= 1e-6
+    k = info[0]["iterations"]
+    assert np.all(np.isnan(np_(co)[:k, 1, 0]))  # nothing written for the problem that never iterated
+
