@@ -579,6 +579,19 @@ def bench_pcg(args, dev):
     prob.profile(False)
     n_it = max(pinfo[0]["iterations"], 1)
     cg_iter_ms = sum(v[0] for v in prof.values()) / n_it
+    # the float64 product S p per iteration: landmark part (records, camera words, V and the
+    # damping diagonal in float64, s written in float64) and camera part (records, landmark
+    # indices, the float64 s gathered per observation)
+    rec = 24 * SJ[args.precision] if args.records == "jacobian" else 4 * SX[args.precision]
+    nl_obs = int(np.count_nonzero(np.bincount(scene.obs_lm, minlength=scene.n_lms)))
+    s_apply = {}
+    for name, nbytes in [("landmark_pass", scene.n_obs * (rec + 4) + nl_obs * (6 + 3 + 4) * 8),
+                         ("camera_pass", scene.n_obs * (rec + 4 + 3 * 8))]:
+        t, n = prof[name]
+        if n:
+            gbs = nbytes / (t / n / 1e3) / 1e9
+            s_apply[name] = {"bytes_per_launch": nbytes, "avg_launch_ms": round(t / n, 4), "achieved": round(gbs, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
     mean = lambda key: float(np.mean([r[key]["equal_accuracy"]["ms"] for r in rows]))
     line = {"metric": "PCG on the reduced camera system vs the power series: solve time at equal accuracy "
                       "(Schur-Jacobi PCG), 1 GPU",
@@ -595,6 +608,7 @@ def bench_pcg(args, dev):
             "mean_ms_equal_accuracy": {k: round(mean(k), 3) for k in rows[0] if k.startswith(("schur", "power"))},
             "sj_iteration_ms": round(cg_iter_ms, 4),
             "sj_phases_ms_per_iteration": {k: round(v[0] / n_it, 4) for k, v in prof.items() if v[1]},
+            "s_apply_roofline": s_apply,
             "points": rows}
     print(json.dumps(line), flush=True)
     return 0
@@ -650,10 +664,25 @@ def bench_post(args, dev):
         p.whole.linearize(cams, lms)
         torch.cuda.synchronize()
         t4 = time.perf_counter()
-        p.step(cams, lms, 1e-4, args.m, 0.01, iteration=0)
+        _, _, _, c_step = p.step(cams, lms, 1e-4, args.m, 0.01, iteration=0)
         torch.cuda.synchronize()
         t5 = time.perf_counter()
-        detail[name] = {"setup_s": round(t_setup, 3), "clusters": int(c.n_clusters),
+        # one series at the final state, timed per kernel: the clustered (batched) handle against the whole one
+        series = {}
+        for key, hp in [("whole", p.whole), ("clustered", c_step.problem)]:
+            hp.profile(True)
+            hp.profile_read()
+            hp.power_solve(1e-4, args.m, 0.0)
+            pr = hp.profile_read()
+            hp.profile(False)
+            per = sum(pr[k][0] / pr[k][1] for k in ("landmark_pass", "camera_pass", "camera_finish") if pr[k][1])
+            series[key] = {"us_per_order": round(1e3 * per, 2)}
+            if args.records == "jacobian":
+                nbytes = sum(series_bytes(scene.n_obs, hp.n_lms, args.precision, "jacobian"))
+                gbs = nbytes / (per / 1e3) / 1e9
+                series[key].update({"bytes_per_order": nbytes, "GBps": round(gbs, 1),
+                                    "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)})
+        detail[name] = {"series": series, "setup_s": round(t_setup, 3), "clusters": int(c.n_clusters),
                         "cluster_size_min_mean_max": [int(sizes.min()), round(float(sizes.mean()), 1),
                                                       int(sizes.max())],
                         "cluster_ms": round(1e3 * (t2 - t1), 2), "layout_ms": round(1e3 * (t3 - t2), 2),
