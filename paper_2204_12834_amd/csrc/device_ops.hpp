@@ -102,19 +102,31 @@ struct PointShape {
 // ------------------------------------------------------ landmark-tile loop --
 //
 // One wavefront walks the landmark-major positions of its tile in chunks of
-// 64.  `obs(i, valid, cam, seg, v)` fills K values for position i (zero when
-// !valid); seg indexes the non-empty-landmark list of the landmark owning i.
-// A segmented inclusive scan over the chunk (carrying the open segment into
-// the next chunk) leaves every landmark's total in its last position, where
-// `tail(seg, v)` is called.  No other wavefront touches the tile's landmarks.
+// 64.  `obs(i, valid, cam, seg, l, v)` fills K values for position i (zero
+// when !valid); seg indexes the non-empty-landmark list nel of the landmark l
+// owning i.  A segmented inclusive scan over the chunk (carrying the open
+// segment into the next chunk) leaves every landmark's total in its last
+// position, where `tail(seg, l, v)` is called.  No other wavefront touches the
+// tile's landmarks.
+//
+// The segments that can start in a chunk are the 64 after the open one, so
+// every lane loads one entry of that window of nel together with its camera
+// word and takes its own landmark from the window by a lane shuffle: the
+// landmark gather then waits on one load instead of two in a row.  A tile
+// starts at a head, so its first chunk never needs the open segment's
+// landmark; later chunks take it from the previous chunk's last lane.  Lanes
+// past the end get the chunk's last segment, so every lane holds a valid
+// landmark index (window entries at or past the number of non-empty landmarks
+// are read, clamped to the array, but never selected).
 template <typename T, int K, typename Obs, typename Tail>
 __device__ __forceinline__ void tile_landmarks(const uint32_t* __restrict__ lo_cam, const int32_t* __restrict__ tile_start,
-                                               const int32_t* __restrict__ seg_base, int64_t tile, Obs&& obs,
-                                               Tail&& tail) {
+                                               const int32_t* __restrict__ seg_base, const int32_t* __restrict__ nel,
+                                               int32_t nl, int64_t tile, Obs&& obs, Tail&& tail) {
     const int lane = lane_id();
     const int32_t start = tile_start[tile];
     const int32_t end = tile_start[tile + 1];
     int32_t seg = seg_base[tile] - 1;  // segment open at the chunk start
+    int32_t l_open = 0;                // its landmark (unused in the first chunk)
     T carry[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) carry[k] = T(0);
@@ -122,22 +134,27 @@ __device__ __forceinline__ void tile_landmarks(const uint32_t* __restrict__ lo_c
         const int32_t i = base + lane;
         const bool valid = i < end;
         const uint32_t w = valid ? lo_cam[i] : 0u;
+        const int32_t lw = nel[min(seg + 1 + lane, nl - 1)];
         const bool head = valid && (w & kHeadBit);
         const uint64_t hm = ballot64(head);
         const uint64_t hu = hm & mask_upto(lane);
         const int seg_start = hu ? 63 - __builtin_clzll(hu) : 0;
-        const int32_t my_seg = seg + __popcll(hu);
+        const int nh = __popcll(hu);
+        const int32_t my_seg = seg + nh;
+        const int32_t lk = __shfl(lw, nh > 0 ? nh - 1 : 0, kWave);
+        const int32_t l = nh > 0 ? lk : l_open;
         T v[K];
-        obs(i, valid, int32_t(w & kIndexMask), my_seg, v);
+        obs(i, valid, int32_t(w & kIndexMask), my_seg, l, v);
         if (lane == 0 && !head) {
 #pragma unroll
             for (int k = 0; k < K; ++k) v[k] += carry[k];
         }
         segmented_scan<T, K>(v, lane, seg_start);
         const int last = min(end - base, kWave) - 1;
-        if (w & kTailBit) tail(my_seg, v);
+        if (w & kTailBit) tail(my_seg, l, v);
 #pragma unroll
         for (int k = 0; k < K; ++k) carry[k] = __shfl(v[k], last, kWave);
+        l_open = __shfl(l, last, kWave);
         seg += __popcll(hm);
     }
 }

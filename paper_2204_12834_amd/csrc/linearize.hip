@@ -166,12 +166,12 @@ __global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const dou
     const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
     if (tile >= z.ntiles) return;
     tile_landmarks<double, 9>(
-        b.lo_cam, b.tile_start, b.seg_base, tile,
-        [&](int32_t i, bool valid, int32_t cam, int32_t seg, double* v) {
+        b.lo_cam, b.tile_start, b.seg_base, b.nel, z.nl, tile,
+        [&](int32_t i, bool valid, int32_t cam, int32_t, int32_t lmk, double* v) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) v[k] = 0.0;
             if (!valid) return;
-            const int64_t l = b.nel[seg];
+            const int64_t l = lmk;
             double X[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
@@ -203,8 +203,8 @@ __global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const dou
             v[7] = a[1] * r0 + c[1] * r1;
             v[8] = a[2] * r0 + c[2] * r1;
         },
-        [&](int32_t seg, const double* v) {
-            const int64_t l = b.nel[seg];
+        [&](int32_t, int32_t lmk, const double* v) {
+            const int64_t l = lmk;
 #pragma unroll
             for (int k = 0; k < 6; ++k) b.V[6 * l + k] = v[k];
 #pragma unroll
@@ -303,12 +303,12 @@ __global__ __launch_bounds__(kBlock) void k_lin_lm_pt(Buffers b, Sizes z, const 
     const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
     if (tile >= z.ntiles) return;
     tile_landmarks<double, 9>(
-        b.lo_cam, b.tile_start, b.seg_base, tile,
-        [&](int32_t i, bool valid, int32_t cam, int32_t seg, double* v) {
+        b.lo_cam, b.tile_start, b.seg_base, b.nel, z.nl, tile,
+        [&](int32_t i, bool valid, int32_t cam, int32_t, int32_t lmk, double* v) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) v[k] = 0.0;
             if (!valid) return;
-            const int64_t l = b.nel[seg];
+            const int64_t l = lmk;
             const double* rec = b.lin_rec + kCamRec * int64_t(cam);
             double X[3], P[3], r[2];
 #pragma unroll
@@ -337,8 +337,8 @@ __global__ __launch_bounds__(kBlock) void k_lin_lm_pt(Buffers b, Sizes z, const 
             v[7] = a[1] * r0 + c[1] * r1;
             v[8] = a[2] * r0 + c[2] * r1;
         },
-        [&](int32_t seg, const double* v) {
-            const int64_t l = b.nel[seg];
+        [&](int32_t, int32_t lmk, const double* v) {
+            const int64_t l = lmk;
 #pragma unroll
             for (int k = 0; k < 6; ++k) b.V[6 * l + k] = v[k];
 #pragma unroll

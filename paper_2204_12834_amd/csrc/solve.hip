@@ -491,8 +491,8 @@ __global__ __launch_bounds__(kBlock) void k_backsub(Buffers b, Sizes z, const do
     const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
     if (tile >= z.ntiles) return;
     tile_landmarks<double, 3>(
-        b.lo_cam, b.tile_start, b.seg_base, tile,
-        [&](int32_t i, bool valid, int32_t cam, int32_t, double* v) {
+        b.lo_cam, b.tile_start, b.seg_base, b.nel, z.nl, tile,
+        [&](int32_t i, bool valid, int32_t cam, int32_t, int32_t, double* v) {
             v[0] = v[1] = v[2] = 0.0;
             if (!valid) return;
             if constexpr (PT) {
@@ -516,8 +516,8 @@ __global__ __launch_bounds__(kBlock) void k_backsub(Buffers b, Sizes z, const do
                 v[2] = J[20] * q0 + J[23] * q1;
             }
         },
-        [&](int32_t seg, const double* t) {
-            const int64_t l = b.nel[seg];
+        [&](int32_t seg, int32_t lmk, const double* t) {
+            const int64_t l = lmk;
             const PCtrl& q = b.pctl[b.lm_prob[l]];
             if (!q.active) return;
             double Vd[6], inv[6], rhs[3], y[3], dd[3];
@@ -1533,8 +1533,8 @@ __global__ __launch_bounds__(kBlock) void k_lm_apply64(Buffers b, Sizes z, const
     const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
     if (tile >= z.ntiles) return;
     tile_landmarks<double, 3>(
-        b.lo_cam, b.tile_start, b.seg_base, tile,
-        [&](int32_t i, bool valid, int32_t cam, int32_t, double* v) {
+        b.lo_cam, b.tile_start, b.seg_base, b.nel, z.nl, tile,
+        [&](int32_t i, bool valid, int32_t cam, int32_t, int32_t, double* v) {
             v[0] = v[1] = v[2] = 0.0;
             if (!valid) return;
             double J[24];
@@ -1550,8 +1550,8 @@ __global__ __launch_bounds__(kBlock) void k_lm_apply64(Buffers b, Sizes z, const
             v[1] = J[19] * q0 + J[22] * q1;
             v[2] = J[20] * q0 + J[23] * q1;
         },
-        [&](int32_t seg, const double* t) {
-            const int64_t l = b.nel[seg];
+        [&](int32_t seg, int32_t lmk, const double* t) {
+            const int64_t l = lmk;
             const PCtrl& q = b.pctl[b.lm_prob[l]];
             if (!q.active) return;
             double Vd[6], inv[6], y[3], dd[3];
