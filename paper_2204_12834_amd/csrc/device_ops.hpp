@@ -117,8 +117,11 @@ struct PointShape {
 // landmark; later chunks take it from the previous chunk's last lane.  Lanes
 // past the end get the chunk's last segment, so every lane holds a valid
 // landmark index (window entries at or past the number of non-empty landmarks
-// are read, clamped to the array, but never selected).
-template <typename T, int K, typename Obs, typename Tail>
+// are read, clamped to the array, but never selected).  With OBS_L false the
+// landmark is taken only after `obs` (which then gets l = 0): a kernel whose
+// per-observation step does not need it issues that step's loads before it
+// waits for the window.
+template <typename T, int K, bool OBS_L = true, typename Obs, typename Tail>
 __device__ __forceinline__ void tile_landmarks(const uint32_t* __restrict__ lo_cam, const int32_t* __restrict__ tile_start,
                                                const int32_t* __restrict__ seg_base, const int32_t* __restrict__ nel,
                                                int32_t nl, int64_t tile, Obs&& obs, Tail&& tail) {
@@ -141,10 +144,15 @@ __device__ __forceinline__ void tile_landmarks(const uint32_t* __restrict__ lo_c
         const int seg_start = hu ? 63 - __builtin_clzll(hu) : 0;
         const int nh = __popcll(hu);
         const int32_t my_seg = seg + nh;
-        const int32_t lk = __shfl(lw, nh > 0 ? nh - 1 : 0, kWave);
-        const int32_t l = nh > 0 ? lk : l_open;
+        auto pick = [&]() {
+            const int32_t lk = __shfl(lw, nh > 0 ? nh - 1 : 0, kWave);
+            return nh > 0 ? lk : l_open;
+        };
+        int32_t l = 0;
+        if constexpr (OBS_L) l = pick();
         T v[K];
         obs(i, valid, int32_t(w & kIndexMask), my_seg, l, v);
+        if constexpr (!OBS_L) l = pick();
         if (lane == 0 && !head) {
 #pragma unroll
             for (int k = 0; k < K; ++k) v[k] += carry[k];
