@@ -117,11 +117,16 @@ struct PointShape {
 // landmark; later chunks take it from the previous chunk's last lane.  Lanes
 // past the end get the chunk's last segment, so every lane holds a valid
 // landmark index (window entries at or past the number of non-empty landmarks
-// are read, clamped to the array, but never selected).  With OBS_L false the
-// landmark is taken only after `obs` (which then gets l = 0): a kernel whose
-// per-observation step does not need it issues that step's loads before it
-// waits for the window.
-template <typename T, int K, bool OBS_L = true, typename Obs, typename Tail>
+// are read, clamped to the array, but never selected).  The lookup mode says
+// when the landmark is taken (`obs` gets l = 0 unless it is kLookupEarly):
+//   kLookupEarly: before `obs`, which needs it;
+//   kLookupLate:  after `obs`, so that a kernel whose per-observation step
+//                 does not need it issues that step's loads before it waits
+//                 for the window;
+//   kLookupTail:  no window: the tail lanes read nel at their segment.
+// Which one is fastest depends on the kernel (measured per kernel).
+enum TileLookup { kLookupEarly = 0, kLookupLate = 1, kLookupTail = 2 };
+template <typename T, int K, int LOOKUP = kLookupEarly, typename Obs, typename Tail>
 __device__ __forceinline__ void tile_landmarks(const uint32_t* __restrict__ lo_cam, const int32_t* __restrict__ tile_start,
                                                const int32_t* __restrict__ seg_base, const int32_t* __restrict__ nel,
                                                int32_t nl, int64_t tile, Obs&& obs, Tail&& tail) {
@@ -137,7 +142,7 @@ __device__ __forceinline__ void tile_landmarks(const uint32_t* __restrict__ lo_c
         const int32_t i = base + lane;
         const bool valid = i < end;
         const uint32_t w = valid ? lo_cam[i] : 0u;
-        const int32_t lw = nel[min(seg + 1 + lane, nl - 1)];
+        const int32_t lw = LOOKUP == kLookupTail ? 0 : nel[min(seg + 1 + lane, nl - 1)];
         const bool head = valid && (w & kHeadBit);
         const uint64_t hm = ballot64(head);
         const uint64_t hu = hm & mask_upto(lane);
@@ -149,20 +154,20 @@ __device__ __forceinline__ void tile_landmarks(const uint32_t* __restrict__ lo_c
             return nh > 0 ? lk : l_open;
         };
         int32_t l = 0;
-        if constexpr (OBS_L) l = pick();
+        if constexpr (LOOKUP == kLookupEarly) l = pick();
         T v[K];
         obs(i, valid, int32_t(w & kIndexMask), my_seg, l, v);
-        if constexpr (!OBS_L) l = pick();
+        if constexpr (LOOKUP == kLookupLate) l = pick();
         if (lane == 0 && !head) {
 #pragma unroll
             for (int k = 0; k < K; ++k) v[k] += carry[k];
         }
         segmented_scan<T, K>(v, lane, seg_start);
         const int last = min(end - base, kWave) - 1;
-        if (w & kTailBit) tail(my_seg, l, v);
+        if (w & kTailBit) tail(my_seg, LOOKUP == kLookupTail ? nel[my_seg] : l, v);
 #pragma unroll
         for (int k = 0; k < K; ++k) carry[k] = __shfl(v[k], last, kWave);
-        l_open = __shfl(l, last, kWave);
+        if constexpr (LOOKUP != kLookupTail) l_open = __shfl(l, last, kWave);
         seg += __popcll(hm);
     }
 }

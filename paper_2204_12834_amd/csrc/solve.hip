@@ -490,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_backsub(Buffers b, Sizes z, const do
     if (!ctrl->active) return;
     const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
     if (tile >= z.ntiles) return;
-    tile_landmarks<double, 3, false>(
+    tile_landmarks<double, 3, kLookupLate>(
         b.lo_cam, b.tile_start, b.seg_base, b.nel, z.nl, tile,
         [&](int32_t i, bool valid, int32_t cam, int32_t, int32_t, double* v) {
             v[0] = v[1] = v[2] = 0.0;
@@ -1532,7 +1532,7 @@ __global__ __launch_bounds__(kBlock) void k_lm_apply64(Buffers b, Sizes z, const
     if (!ctrl->active) return;
     const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
     if (tile >= z.ntiles) return;
-    tile_landmarks<double, 3, false>(
+    tile_landmarks<double, 3, kLookupTail>(
         b.lo_cam, b.tile_start, b.seg_base, b.nel, z.nl, tile,
         [&](int32_t i, bool valid, int32_t cam, int32_t, int32_t, double* v) {
             v[0] = v[1] = v[2] = 0.0;
