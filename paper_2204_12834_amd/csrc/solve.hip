@@ -219,7 +219,22 @@ __global__ __launch_bounds__(kBlock) void k_lm_pass_lds(Buffers b, Sizes z, int6
     if (ctrl->running == 0) return;
     TS* cv = reinterpret_cast<TS*>(lds_raw);
     const TS* __restrict__ vq = reinterpret_cast<const TS*>(b.vq);
-    for (int64_t k = threadIdx.x; k < int64_t(z.nc) * 9; k += kBlock) cv[k] = vq[12 * (k / 9) + k % 9];
+    {
+        // R cameras per thread requested before the first is written, so the
+        // copy takes a few round trips instead of one per element
+        constexpr int R = sizeof(TS) == 4 ? 4 : 2;
+        for (int64_t c0 = threadIdx.x; c0 < z.nc; c0 += int64_t(R) * kBlock) {
+            TS x[R][9];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (c0 + r * kBlock < z.nc) load_cam_vec(vq, c0 + r * kBlock, x[r]);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (c0 + r * kBlock < z.nc)
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) cv[9 * (c0 + r * kBlock) + k] = x[r][k];
+        }
+    }
     __syncthreads();
     const int64_t t0 = (int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave) * per;
     if (t0 >= z.ntiles) return;
@@ -904,8 +919,14 @@ __global__ __launch_bounds__(kPtBlock) void k_lm_pass_pt_lds(Buffers b, Sizes z,
     extern __shared__ unsigned char lds_raw[];
     if (ctrl->running == 0) return;
     TS* cf = reinterpret_cast<TS*>(lds_raw);
-    const TS* __restrict__ src = reinterpret_cast<const TS*>(b.vq);
-    for (int64_t k = threadIdx.x; k < int64_t(z.nc) * 24; k += kPtBlock) cf[k] = src[k];
+    {
+        // 16-byte units (24 values per camera make whole units); one unit in
+        // flight per thread (this kernel has no registers to spare for more)
+        const uint4* __restrict__ src = reinterpret_cast<const uint4*>(b.vq);
+        uint4* dst = reinterpret_cast<uint4*>(lds_raw);
+        const int64_t n = int64_t(z.nc) * 24 * int64_t(sizeof(TS)) / 16;
+        for (int64_t k = threadIdx.x; k < n; k += kPtBlock) dst[k] = src[k];
+    }
     __syncthreads();
     const int64_t wave = int64_t(blockIdx.x) * (kPtBlock / kWave) + threadIdx.x / kWave;
     const int64_t t0 = wave * tiles_per_wave;
