@@ -584,14 +584,21 @@ __device__ __forceinline__ void load_s3(const double* s, int64_t l, double* o) {
     o[0] = a.x; o[1] = a.y; o[2] = s[4 * l + 2];
 }
 
-// Camera pass, one block per camera piece: u = sum_i J_p^T (J_l s_g(i)) over
-// the piece in float64, written to the piece's partial slot.  Two-stage
-// pipeline per thread: the next observation's record and segment index are in
-// flight while the current one is accumulated; its s gather is issued after.
-template <typename TJ, typename TSin>
-__global__ __launch_bounds__(kBlock) void k_cam_pass(Buffers b, Sizes z, const TSin* __restrict__ sin,
-                                                     const Ctrl* ctrl) {
-    __shared__ double lds[kWavesPerBlock * 9];
+// Camera pass, one workgroup of NT threads per camera piece: u = sum_i
+// J_p^T (J_l s_g(i)) over the piece in float64, written to the piece's partial
+// slot.  Two-stage pipeline per thread: the next observation's record and
+// segment index are in flight while the current one is accumulated; its s
+// gather is issued after.  A piece averages a few hundred observations, so a
+// small workgroup streams it in several pipelined steps.
+// Threads per piece (measured at the city size): one wavefront for float64
+// records (192 bytes per observation; 7% faster than four), four for the
+// narrower ones (one or two wavefronts were 6% and 3% slower).
+constexpr int cam_pass_threads(size_t jbytes) { return jbytes == 8 ? kWave : kBlock; }
+
+template <typename TJ, typename TSin, int NT>
+__global__ __launch_bounds__(NT) void k_cam_pass(Buffers b, Sizes z, const TSin* __restrict__ sin,
+                                                 const Ctrl* ctrl) {
+    __shared__ double lds[(NT / kWave) * 9];
     if (ctrl->running == 0) return;
     const PieceRec pr = b.sched_rec[blockIdx.x];
     if (pr.p < 0) return;
@@ -615,8 +622,8 @@ __global__ __launch_bounds__(kBlock) void k_cam_pass(Buffers b, Sizes z, const T
         load_J<TJ, TL>(b.J_co, z.npad, i, J);
         load_s3(sin, g, sv);
     }
-    for (; i < e; i += kBlock) {
-        const int32_t ni = i + kBlock;
+    for (; i < e; i += NT) {
+        const int32_t ni = i + NT;
         int64_t gn = 0;
         TL Jn[24];
         if (ni < e) {
@@ -1380,7 +1387,8 @@ void launch_cam_pass(Problem* p, const Buffers& b, const TSin* sin, hipStream_t 
             hipLaunchKernelGGL((k_cam_pass_pt<TJ, TSin, TCL, kWave>), g, dim3(kWave), 0, s, b, p->z, sin, b.ctrl);
         }
     } else {
-        hipLaunchKernelGGL((k_cam_pass<TJ, TSin>), g, dim3(kBlock), 0, s, b, p->z, sin, b.ctrl);
+        constexpr int NT = cam_pass_threads(sizeof(TJ));
+        hipLaunchKernelGGL((k_cam_pass<TJ, TSin, NT>), g, dim3(NT), 0, s, b, p->z, sin, b.ctrl);
     }
 }
 
