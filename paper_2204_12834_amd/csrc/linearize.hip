@@ -99,10 +99,11 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const do
     }
     gram_acc gacc = {0.0, 0.0, 0.0, 0.0};
     double cost = 0.0, bad = 0.0;
-    const int32_t p = b.sched[blockIdx.x];
+    const PieceRec pr = b.sched_rec[blockIdx.x];  // piece, its range and camera in one load
+    const int32_t p = pr.p;
     if (p >= 0) {
-        const int32_t cam = b.piece_cam[p];
-        const int32_t a = b.piece_begin[p], e = b.piece_end[p];
+        const int32_t cam = pr.cam;
+        const int32_t a = pr.begin, e = pr.end;
         const double* rec = b.lin_rec + kCamRec * int64_t(cam);
         for (int32_t base = a; base < e; base += kBlock) {
             const int32_t i = base + t;
@@ -240,10 +241,11 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam_pt(Buffers b, Sizes z, const
     }
     gram_acc gacc = {0.0, 0.0, 0.0, 0.0};
     double cost = 0.0, bad = 0.0;
-    const int32_t p = b.sched[blockIdx.x];
+    const PieceRec pr = b.sched_rec[blockIdx.x];  // piece, its range and camera in one load
+    const int32_t p = pr.p;
     if (p >= 0) {
-        const int32_t cam = b.piece_cam[p];
-        const int32_t a = b.piece_begin[p], e = b.piece_end[p];
+        const int32_t cam = pr.cam;
+        const int32_t a = pr.begin, e = pr.end;
         const double* rec = b.lin_rec + kCamRec * int64_t(cam);
         for (int32_t base = a; base < e; base += kBlock) {
             const int32_t i = base + t;

@@ -81,11 +81,12 @@ __global__ __launch_bounds__(kBlock) void k_eval(Buffers b, Sizes z, int loss, d
     __shared__ double lds[kWavesPerBlock * 3];
     if (!ctrl->active) return;
     double cost = 0.0, model = 0.0, bad = 0.0;
-    const int32_t p = b.sched[blockIdx.x];
-    if (p < 0 || !b.pctl[b.cam_prob[b.piece_cam[p]]].active) return;
+    const PieceRec pr = b.sched_rec[blockIdx.x];  // piece, its range, camera and problem in one load
+    const int32_t p = pr.p;
+    if (p < 0 || !b.pctl[pr.prob].active) return;
     {
-        const int64_t c = b.piece_cam[p];
-        const int32_t a = b.piece_begin[p], e = b.piece_end[p];
+        const int64_t c = pr.cam;
+        const int32_t a = pr.begin, e = pr.end;
         const double* rec = b.cam_rec + kCamRec * c;
         const double* dp = b.dxp + 9 * c;
         for (int32_t i = a + threadIdx.x; i < e; i += kBlock) {
