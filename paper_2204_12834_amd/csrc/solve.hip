@@ -599,29 +599,35 @@ template <typename TJ, typename TSin, int NT>
 __global__ __launch_bounds__(NT) void k_cam_pass(Buffers b, Sizes z, const TSin* __restrict__ sin,
                                                  const Ctrl* ctrl) {
     __shared__ double lds[(NT / kWave) * 9];
-    if (ctrl->running == 0) return;
+    // The control word and the piece are read together, and the piece's first
+    // records are requested before the checks (which only decide whether
+    // anything is written): a workgroup then waits two round trips, not four,
+    // before its first s gather.  An idle slot has an empty range.
+    const int32_t running = ctrl->running;
     const PieceRec pr = b.sched_rec[blockIdx.x];
-    if (pr.p < 0) return;
-    {
-        const PCtrl& q = b.pctl[pr.prob];
-        if (!q.active || q.stopped) return;
-    }
     const int32_t p = pr.p, a = pr.begin, e = pr.end;
+    // the problem's active and stopped flags (adjacent) in one request
+    static_assert(offsetof(PCtrl, stopped) == offsetof(PCtrl, active) + 4 && offsetof(PCtrl, active) % 8 == 0 &&
+                      sizeof(PCtrl) % 8 == 0,
+                  "active and stopped form one aligned 8-byte word");
+    const int2 flags = *reinterpret_cast<const int2*>(&b.pctl[pr.prob].active);
     const int32_t* __restrict__ co_seg = b.co_seg;
-    double acc[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) acc[k] = 0.0;
     // records stay in their storage width (float for float32 and bfloat16
     // storage) and are widened to float64 at use
     using TL = typename std::conditional<std::is_same<TJ, double>::value, double, float>::type;
     int32_t i = a + threadIdx.x;
     TL J[24];
     double sv[3];
+    int64_t g0 = 0;
     if (i < e) {
-        const int64_t g = co_seg[i];
+        g0 = co_seg[i];
         load_J<TJ, TL>(b.J_co, z.npad, i, J);
-        load_s3(sin, g, sv);
     }
+    if (running == 0 || p < 0 || !flags.x || flags.y) return;
+    if (i < e) load_s3(sin, g0, sv);
+    double acc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = 0.0;
     for (; i < e; i += NT) {
         const int32_t ni = i + NT;
         int64_t gn = 0;
