@@ -599,18 +599,24 @@ template <typename TJ, typename TSin, int NT>
 __global__ __launch_bounds__(NT) void k_cam_pass(Buffers b, Sizes z, const TSin* __restrict__ sin,
                                                  const Ctrl* ctrl) {
     __shared__ double lds[(NT / kWave) * 9];
-    // The control word and the piece are read together, and the piece's first
-    // records are requested before the checks (which only decide whether
-    // anything is written): a workgroup then waits two round trips, not four,
-    // before its first s gather.  An idle slot has an empty range.
-    const int32_t running = ctrl->running;
-    const PieceRec pr = b.sched_rec[blockIdx.x];
-    const int32_t p = pr.p, a = pr.begin, e = pr.end;
-    // the problem's active and stopped flags (adjacent) in one request
+    // The control word and the piece are read together, and the problem's
+    // active and stopped flags (adjacent) in one request after them, so a
+    // workgroup knows within two scalar round trips whether it has work.
+    // Nothing is read from the records before that: the launches that follow
+    // a stopped series must cost no bandwidth.
+    static_assert(sizeof(PieceRec) == 32 && offsetof(PieceRec, prob) == 16, "piece record: two 16-byte words");
     static_assert(offsetof(PCtrl, stopped) == offsetof(PCtrl, active) + 4 && offsetof(PCtrl, active) % 8 == 0 &&
                       sizeof(PCtrl) % 8 == 0,
                   "active and stopped form one aligned 8-byte word");
-    const int2 flags = *reinterpret_cast<const int2*>(&b.pctl[pr.prob].active);
+    const int32_t running = ctrl->running;
+    const int4* rec = reinterpret_cast<const int4*>(b.sched_rec) + 2 * int64_t(blockIdx.x);
+    const int4 r0 = rec[0], r1 = rec[1];  // (p, begin, end, cam), (prob, ...)
+    // (a problem index is never negative: testing it keeps the second word in
+    // the first request instead of after the branch)
+    if (running == 0 || r0.x < 0 || r1.x < 0) return;
+    const int2 flags = *reinterpret_cast<const int2*>(&b.pctl[r1.x].active);
+    if (!flags.x || flags.y) return;
+    const int32_t p = r0.x, a = r0.y, e = r0.z;
     const int32_t* __restrict__ co_seg = b.co_seg;
     // records stay in their storage width (float for float32 and bfloat16
     // storage) and are widened to float64 at use
@@ -618,13 +624,11 @@ __global__ __launch_bounds__(NT) void k_cam_pass(Buffers b, Sizes z, const TSin*
     int32_t i = a + threadIdx.x;
     TL J[24];
     double sv[3];
-    int64_t g0 = 0;
     if (i < e) {
-        g0 = co_seg[i];
+        const int64_t g = co_seg[i];
         load_J<TJ, TL>(b.J_co, z.npad, i, J);
+        load_s3(sin, g, sv);
     }
-    if (running == 0 || p < 0 || !flags.x || flags.y) return;
-    if (i < e) load_s3(sin, g0, sv);
     double acc[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc[k] = 0.0;
