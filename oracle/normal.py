@@ -60,3 +60,48 @@ def block_inverse(A):
     if A.shape[0] == 0:
         return A.copy()
     return np.linalg.inv(A)
+
+
+def _not_positive_definite(A):
+    """[n] bool: blocks whose Cholesky factorisation (LAPACK) meets a pivot
+    that is not positive, or that hold a non-finite entry."""
+    n = A.shape[0]
+    bad = ~np.all(np.isfinite(A.reshape(n, -1)), axis=1)
+    idx = np.nonzero(~bad)[0]
+    try:
+        np.linalg.cholesky(A[idx])
+    except np.linalg.LinAlgError:
+        for i in idx:
+            try:
+                np.linalg.cholesky(A[i])
+            except np.linalg.LinAlgError:
+                bad[i] = True
+    return bad
+
+
+def damped_inverse(A, lam_d):
+    """Inverses of the damped blocks A = B + lambda diag(d)  [n,k,k], with
+    lam_d = lambda d  [n,k].
+
+    Sec. 4.1 takes U_lambda and V_lambda to be positive definite, which holds
+    for Gram blocks once lambda d > 0; a block set from elsewhere, or one with
+    non-finite entries, need not be.  Reading for that case: a block whose
+    Cholesky factorisation meets a pivot that is not positive, or whose inverse
+    is not finite, is replaced by the inverse of its damping diagonal alone,
+    diag(1 / (lambda d_j)), with 0 where lambda d_j is not positive.
+
+    Returns (inverses [n,k,k], fell_back [n] bool)."""
+    n, k = A.shape[0], A.shape[1]
+    inv = np.zeros_like(A, dtype=np.float64)
+    bad = _not_positive_definite(A)
+    good = np.nonzero(~bad)[0]
+    if good.size:
+        inv[good] = np.linalg.inv(A[good])
+    bad |= ~np.all(np.isfinite(inv.reshape(n, -1)), axis=1)
+    if bad.any():
+        e = np.asarray(lam_d, dtype=np.float64)[bad]
+        pos = e > 0.0
+        diag = np.where(pos, 1.0 / np.where(pos, e, 1.0), 0.0)
+        inv[bad] = 0.0
+        inv[np.nonzero(bad)[0][:, None], np.arange(k)[None, :], np.arange(k)[None, :]] = diag
+    return inv, bad

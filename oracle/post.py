@@ -107,7 +107,8 @@ def solve_clustered(Jp, Jl, r, obs_cam, obs_lm, n_cams, n_lms, lam, m, eps, clus
     U, V, bp, bl = normal.assemble(Jp, Jl, r, obs_cam, obs_lm, n_cams, n_lms)
     dp, dl = normal.damping_diagonals(U, V, damping)
     Ul, Vl = normal.damp(U, V, lam, dp, dl)
-    Uinv, Vinv = normal.block_inverse(Ul), normal.block_inverse(Vl)
+    Uinv, _ = normal.damped_inverse(Ul, lam * dp)
+    Vinv, _ = normal.damped_inverse(Vl, lam * dl)
     bt = schur.reduced_rhs(Jp, Jl, obs_cam, obs_lm, bp, bl, Vinv)
     cluster = np.asarray(cluster)
     dxp = np.zeros((n_cams, 9))

@@ -119,27 +119,34 @@ class Solve:
     Vinv: np.ndarray
     series: SeriesResult
     Ul: np.ndarray = None    # damped camera blocks
+    not_spd: int = 0         # damped blocks that took the diagonal fallback
 
 
 def solve(Jp, Jl, r, obs_cam, obs_lm, n_cams, n_lms, lam, m, eps=0.0,
-          damping="marquardt", rhs=None, diagonals=None):
+          damping="marquardt", rhs=None, diagonals=None, landmark_blocks=None):
     """One damped step: blocks, damped inverses, b~, series, back-substitution.
 
     rhs: optional (g_p, g_l) replacing (b_p, b_l) (the right-hand side of
     eq. normal is then -(g_p, g_l)); the blocks always come from J.
     diagonals: optional fixed damping diagonals (d_p [n_c,9], d_l [n_l,3])
     replacing those taken from the blocks.
+    landmark_blocks: optional (V [n_l,3,3], b_l [n_l,3]) replacing the
+    undamped landmark blocks assembled from J (damping is taken from them).
+    A damped block that is not positive definite is inverted through its
+    damping diagonal alone (normal.damped_inverse); not_spd counts them.
     """
     from . import normal
 
     U, V, bp, bl = normal.assemble(Jp, Jl, r, obs_cam, obs_lm, n_cams, n_lms)
+    if landmark_blocks is not None:
+        V, bl = (np.asarray(a, dtype=np.float64) for a in landmark_blocks)
     if rhs is not None:
         bp, bl = rhs
     dp, dl = normal.damping_diagonals(U, V, damping) if diagonals is None else diagonals
     Ul, Vl = normal.damp(U, V, lam, dp, dl)
-    Uinv = normal.block_inverse(Ul)
-    Vinv = normal.block_inverse(Vl)
+    Uinv, bad_u = normal.damped_inverse(Ul, lam * dp)
+    Vinv, bad_v = normal.damped_inverse(Vl, lam * dl)
     bt = reduced_rhs(Jp, Jl, obs_cam, obs_lm, bp, bl, Vinv)
     ser = power_series(Jp, Jl, obs_cam, obs_lm, Uinv, Vinv, bt, m, eps)
     dxl = back_substitute(Jp, Jl, obs_cam, obs_lm, bl, Vinv, ser.x)
-    return Solve(ser.x, dxl, bt, Uinv, Vinv, ser, Ul)
+    return Solve(ser.x, dxl, bt, Uinv, Vinv, ser, Ul, int(bad_u.sum() + bad_v.sum()))
