@@ -11,7 +11,9 @@ ground truth into pixel observations with its own projection:
 Cameras follow the 9-parameter layout used by the public BAL files
 (angle-axis rotation, translation, focal length, two radial coefficients); the
 camera looks down its own -z axis.  Rotations are built as matrices from a
-look-at frame and converted to angle-axis with the SO(3) logarithm.
+look-at frame and converted to angle-axis with the SO(3) logarithm; the
+initial state turns each camera about its own centre and moves the centre
+(App. B perturbs camera positions), so it also uses the SO(3) exponential.
 
 The workloads stand in for the BAL problems the paper evaluates on (Sec. 5.1
 "Dataset", Appendix D); none of the dataset's own content is reproduced.
@@ -118,10 +120,30 @@ def _cameras(rng, centers, forwards, f_range=(450.0, 550.0), k_sigma=1e-3):
     return cams, R
 
 
+def _so3_exp(w: np.ndarray) -> np.ndarray:
+    """Rotation matrices [n,3,3] of angle-axis vectors [n,3] (Rodrigues)."""
+    th = np.linalg.norm(w, axis=1)
+    k = w / np.where(th > 0.0, th, 1.0)[:, None]
+    K = np.zeros((w.shape[0], 3, 3))
+    K[:, 0, 1], K[:, 0, 2], K[:, 1, 2] = -k[:, 2], k[:, 1], -k[:, 0]
+    K[:, 1, 0], K[:, 2, 0], K[:, 2, 1] = k[:, 2], -k[:, 1], k[:, 0]
+    s, c = np.sin(th)[:, None, None], np.cos(th)[:, None, None]
+    return np.eye(3)[None] + s * K + (1.0 - c) * (K @ K)
+
+
 def _perturb(rng, cams, lms, rot_sigma=1e-2, pos_sigma=0.1):
+    """Initial state: every camera turned about its own centre by a rotation
+    of angle-axis N(0, rot_sigma^2 I), its centre moved by N(0, pos_sigma^2 I)
+    in world units, and every landmark moved by N(0, pos_sigma^2 I).  The
+    translation follows from the moved centre, t0 = -R0 c0, so a camera far
+    from the world origin moves no further than one near it."""
+    R = _so3_exp(cams[:, 0:3])
+    centers = -np.einsum("nji,nj->ni", R, cams[:, 3:6])
+    R0 = _so3_exp(rng.normal(0.0, rot_sigma, (cams.shape[0], 3))) @ R
+    c0 = centers + rng.normal(0.0, pos_sigma, (cams.shape[0], 3))
     cams0 = cams.copy()
-    cams0[:, 0:3] += rng.normal(0.0, rot_sigma, (cams.shape[0], 3))
-    cams0[:, 3:6] += rng.normal(0.0, pos_sigma, (cams.shape[0], 3))
+    cams0[:, 0:3] = _so3_log(R0)
+    cams0[:, 3:6] = -np.einsum("nij,nj->ni", R0, c0)
     lms0 = lms + rng.normal(0.0, pos_sigma, lms.shape)
     return cams0, lms0
 

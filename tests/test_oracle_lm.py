@@ -39,13 +39,13 @@ def test_lm_accepted_costs_decrease_and_match_dense_solver():
 
 
 def test_rejected_step_raises_damping():
-    """Far from the optimum (0.3 rad rotation error), with lambda0 tiny and a
+    """Far from the optimum (0.8 rad rotation error), with lambda0 tiny and a
     single series term, steps fail; every failure multiplies lambda by nu and
     doubles nu, every success applies the Nielsen factor."""
     P = tiny()
     opts = lm.LMOptions(lambda0=1e-12, m=0, eps=0.0, max_iters=12)
     cams = P.cams.copy()
-    cams[:, 0] += 0.3
+    cams[:, 1] += 0.8
     res = lm.lm(cams, P.lms, P.obs_cam, P.obs_lm, P.obs, opts)
     lams = [it.lam for it in res.iterations]
     nu = 2.0
@@ -58,6 +58,7 @@ def test_rejected_step_raises_damping():
             nu *= 2.0
         assert b == pytest.approx(min(max(expect, 1e-16), 1e16), rel=1e-12)
     assert any(not it.accepted for it in res.iterations)
+    assert any(it.accepted for it in res.iterations)
 
 
 def test_cost_threshold():
