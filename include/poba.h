@@ -189,6 +189,26 @@ poba_status poba_batch_create(const poba_desc *d, int32_t n_problems, const int3
 /* Releases the host-side handle (the workspace stays the caller's). */
 poba_status poba_destroy(poba_problem p);
 
+/* Bytes of the library-held workspace of poba_create_static, per GPU. */
+#define POBA_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): poba_create
+ * with the workspace taken from a device array of POBA_STATIC_WORKSPACE_BYTES
+ * that the library holds on every GPU it runs on until the process ends.  It
+ * calls no hipMalloc, hipFree or allocating library routine; the scratch of
+ * its radix sorts and scans is sized exactly for the problem.  Arguments,
+ * results and errors as poba_create (one problem), except: a problem whose
+ * workspace would exceed the array returns POBA_ERR_WORKSPACE before any
+ * device work (in float32 storage about 150,000 observations fit, in float64
+ * about 100,000).  Every handle made by this call on one GPU uses that GPU's
+ * one array: a new call makes the handle of the previous call on the same
+ * GPU invalid (poba_destroy still releases it), and calls on two such handles
+ * that overlap in time race.  The array keeps the contents of the last
+ * handle; creation clears the part it lays out before use. */
+poba_status poba_create_static(const poba_desc *d, const int32_t *obs_cam, const int32_t *obs_lm,
+                               const double *obs_xy, poba_stream stream, poba_problem *out);
+
 /* Sec. 4 and 4.1: evaluates residuals r_i and Jacobian blocks J_p (2x9),
  * J_l (2x3) at cams [dev] float64 [n_cams][9], lms [dev] float64 [n_lms][3];
  * applies the Huber reweighting if configured; stores the blocks (rounded to

@@ -11,6 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpoba.so")
 
 POBA_OK = 0
+POBA_ERR_WORKSPACE = 32
+STATIC_WORKSPACE_BYTES = 64 << 20  # POBA_STATIC_WORKSPACE_BYTES
 STATUS_BITS = {
     1: "invalid argument",
     2: "observation index out of range",
@@ -110,6 +112,7 @@ SIGNATURES = {
     "poba_lm_default_options": (None, [ctypes.POINTER(PobaLMOptions)]),
     "poba_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(PobaDesc)]),
     "poba_create": (I32, [ctypes.POINTER(PobaDesc), P, P, P, P, ctypes.c_size_t, P, ctypes.POINTER(P)]),
+    "poba_create_static": (I32, [ctypes.POINTER(PobaDesc), P, P, P, P, ctypes.POINTER(P)]),
     "poba_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(PobaDesc), I32]),
     "poba_batch_create": (I32, [ctypes.POINTER(PobaDesc), I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P, P, P, P,
                                 ctypes.c_size_t, P, ctypes.POINTER(P)]),

@@ -12,6 +12,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <mutex>
 
 #include "camera_model.hpp"
 #include "common.hpp"
@@ -366,6 +367,51 @@ static int key_bits(int32_t n) {
     return b;
 }
 
+// ------------------------------------------------- library-held workspace --
+//
+// The workspace of poba_create_static: one array per GPU, held from the load
+// of the library until the process ends.  In host code the array's name is
+// a stand-in, not a device address: host code takes the address on each
+// device from hipGetSymbolAddress and passes only that to kernels and copies.
+constexpr size_t kStaticWorkspaceBytes = POBA_STATIC_WORKSPACE_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the array on the current device (looked up once per device).
+static poba_status static_workspace(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return POBA_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return POBA_ERR_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return POBA_OK;
+}
+
+// Scratch bytes that set-up's radix sorts and scans need for these sizes
+// (size queries only, nothing runs): both sorts at the widest key, the scans
+// at their longest input.
+static bool sort_tmp_exact(const Sizes& z, size_t* bytes) {
+    const int n = int(std::max<int64_t>(z.N, 1));
+    size_t sort = 0, scan = 0;
+    hipcub::DoubleBuffer<int32_t> kb(nullptr, nullptr), vb(nullptr, nullptr);
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, sort, kb, vb, n, 0, 31, hipStream_t(0)) != hipSuccess)
+        return false;
+    const int64_t scan_n = std::max<int64_t>(int64_t(z.nl) + 1, int64_t(z.nc) * z.ranges_max + 1);
+    if (scan_n >= (int64_t(1) << 31)) return false;
+    if (hipcub::DeviceScan::ExclusiveSum(nullptr, scan, static_cast<int32_t*>(nullptr),
+                                         static_cast<int32_t*>(nullptr), int(scan_n), hipStream_t(0)) != hipSuccess)
+        return false;
+    *bytes = std::max(sort, scan) + 256;
+    return true;
+}
+
 // ------------------------------------------------------------------ profiling --
 
 void prof_begin(Problem* p, int cls, hipStream_t s, ProfileSlot** slot) {
@@ -429,10 +475,12 @@ poba_status poba_create(const poba_desc* d, const int32_t* obs_cam, const int32_
     return poba_batch_create(d, 1, cam_off, lm_off, obs_cam, obs_lm, obs_xy, workspace, workspace_bytes, stream, out);
 }
 
-poba_status poba_batch_create(const poba_desc* d, int32_t n_problems, const int32_t* prob_cam_off,
-                              const int32_t* prob_lm_off, const int32_t* obs_cam, const int32_t* obs_lm,
-                              const double* obs_xy, void* workspace, size_t workspace_bytes, poba_stream stream,
-                              poba_problem* out) {
+// Set-up of poba_batch_create and poba_create_static over a workspace whose
+// layout reserves sort_tmp_bytes for the radix sorts and scans.
+static poba_status create_impl(const poba_desc* d, int32_t n_problems, const int32_t* prob_cam_off,
+                               const int32_t* prob_lm_off, const int32_t* obs_cam, const int32_t* obs_lm,
+                               const double* obs_xy, void* workspace, size_t workspace_bytes, size_t sort_tmp_bytes,
+                               hipStream_t s, poba_problem* out) {
     (void)hipGetLastError();  // report only this call's launch errors
     if (!out) return POBA_ERR_INVALID_ARG;
     *out = nullptr;
@@ -445,15 +493,14 @@ poba_status poba_batch_create(const poba_desc* d, int32_t n_problems, const int3
         return POBA_ERR_INVALID_ARG;
     for (int32_t j = 0; j < n_problems; ++j)
         if (prob_cam_off[j + 1] <= prob_cam_off[j] || prob_lm_off[j + 1] <= prob_lm_off[j]) return POBA_ERR_INVALID_ARG;
-    const size_t need = poba_batch_workspace_bytes(d, n_problems);
+    const size_t need = layout(d, z, nullptr, nullptr, sort_tmp_bytes);
     if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255u))
         return POBA_ERR_WORKSPACE;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
     Problem* p = new Problem();
     p->d = *d;
     p->z = z;
-    layout(d, z, reinterpret_cast<char*>(workspace), &p->b, sort_tmp_upper_bound(z.N));
+    layout(d, z, reinterpret_cast<char*>(workspace), &p->b, sort_tmp_bytes);
     Buffers& b = p->b;
     const int64_t N = z.N;
     poba_status st = POBA_OK;
@@ -728,6 +775,42 @@ poba_status poba_batch_create(const poba_desc* d, int32_t n_problems, const int3
     if (hipGetLastError() != hipSuccess) return fail(POBA_ERR_HIP);
     *out = p;
     return st;
+}
+
+poba_status poba_batch_create(const poba_desc* d, int32_t n_problems, const int32_t* prob_cam_off,
+                              const int32_t* prob_lm_off, const int32_t* obs_cam, const int32_t* obs_lm,
+                              const double* obs_xy, void* workspace, size_t workspace_bytes, poba_stream stream,
+                              poba_problem* out) {
+    Sizes z;
+    if (!compute_sizes(d, n_problems, &z)) {
+        if (out) *out = nullptr;
+        return POBA_ERR_INVALID_ARG;
+    }
+    return create_impl(d, n_problems, prob_cam_off, prob_lm_off, obs_cam, obs_lm, obs_xy, workspace, workspace_bytes,
+                       sort_tmp_upper_bound(z.N), reinterpret_cast<hipStream_t>(stream), out);
+}
+
+poba_status poba_create_static(const poba_desc* d, const int32_t* obs_cam, const int32_t* obs_lm,
+                               const double* obs_xy, poba_stream stream, poba_problem* out) {
+    (void)hipGetLastError();  // report only this call's launch errors
+    if (!d || !out) return POBA_ERR_INVALID_ARG;
+    *out = nullptr;
+    Sizes z;
+    if (!compute_sizes(d, 1, &z)) return POBA_ERR_INVALID_ARG;
+    size_t tmp = 0;
+    if (!sort_tmp_exact(z, &tmp)) return POBA_ERR_HIP;
+    const size_t need = layout(d, z, nullptr, nullptr, tmp);
+    if (need > kStaticWorkspaceBytes) return POBA_ERR_WORKSPACE;  // before any device work
+    void* ws = nullptr;
+    poba_status st = static_workspace(&ws);
+    if (st) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // the array keeps the previous handle's contents: start from zero
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(int64_t(need / 8))), dim3(kBlock), 0, s, static_cast<double*>(ws),
+                       int64_t(need / 8));
+    if (hipGetLastError() != hipSuccess) return POBA_ERR_HIP;
+    const int32_t cam_off[2] = {0, d->n_cams}, lm_off[2] = {0, d->n_lms};
+    return create_impl(d, 1, cam_off, lm_off, obs_cam, obs_lm, obs_xy, ws, kStaticWorkspaceBytes, tmp, s, out);
 }
 
 poba_status poba_destroy(poba_problem p) {

@@ -108,7 +108,7 @@ class Problem:
     def __init__(self, obs_cam, obs_lm, obs_xy, n_cams: int, n_lms: int, precision: str = "f64",
                  damping: str = "marquardt", loss: str = "l2", huber_delta: float = 0.0, piece_size: int = 0,
                  lm_ranges: int = 0, device="cuda", stream=None, prob_cam_off=None, prob_lm_off=None,
-                 records: str = "jacobian"):
+                 records: str = "jacobian", static_workspace: bool = False):
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.precision = precision
@@ -128,6 +128,22 @@ class Problem:
         if len(self.prob_cam_off) != len(self.prob_lm_off) or len(self.prob_cam_off) < 2:
             raise ValueError("prob_cam_off and prob_lm_off need n_problems + 1 entries each")
         self.n_problems = len(self.prob_cam_off) - 1
+        self._info = torch.zeros(ctypes.sizeof(_lib.PobaSolveInfo) * self.n_problems, dtype=torch.uint8,
+                                 device=self.device)
+        if static_workspace:
+            # the library's own per-device workspace (poba_create_static): no device allocation
+            if self.n_problems != 1:
+                raise ValueError("static_workspace holds one problem")
+            self.workspace = None
+            h = ctypes.c_void_p()
+            with torch.cuda.device(self.device):
+                rc = self.lib.poba_create_static(ctypes.byref(self.desc), _ptr(obs_cam), _ptr(obs_lm), _ptr(obs_xy),
+                                                 _stream(stream), ctypes.byref(h))
+            if rc == _lib.POBA_ERR_WORKSPACE:
+                raise _lib.PobaError("poba_create_static (problem larger than the library-held workspace)", rc)
+            _lib.check("poba_create_static", rc)
+            self.handle = h
+            return
         nbytes = int(self.lib.poba_batch_workspace_bytes(ctypes.byref(self.desc), self.n_problems))
         if nbytes == 0:
             raise _lib.PobaError("poba_batch_workspace_bytes", 1)
@@ -144,8 +160,6 @@ class Problem:
                                             ctypes.c_size_t(nbytes), _stream(stream), ctypes.byref(h))
         _lib.check("poba_batch_create", rc)
         self.handle = h
-        self._info = torch.zeros(ctypes.sizeof(_lib.PobaSolveInfo) * self.n_problems, dtype=torch.uint8,
-                                 device=self.device)
 
     def close(self):
         if getattr(self, "handle", None):
