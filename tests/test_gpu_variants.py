@@ -225,3 +225,20 @@ def test_city_full_size(precision, records):
     log(f"city full {precision} {records} (lm pass in LDS: {_lm_pass_in_lds(s.n_cams, precision, records)}, "
         f"ranges {prob.get_tuning('lm_ranges')}): dx_p {ep:.2e} dx_l {el:.2e}")
     assert ep <= TOL[precision] and el <= TOL[precision], (ep, el)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_autotuned_handle_matches_oracle(tmp_path, precision):
+    """The autotuner's handle (whatever shape it picks, and again from its
+    cache) gives the oracle's step."""
+    from paper_2204_12834_amd import autotune
+    case = city_small()
+    s = case.scene
+    cams, lms = case.state()
+    cache = str(tmp_path / "tune.json")
+    for _ in range(2):
+        cfg, prob = autotune.tune(lambda ps: case.problem(precision, piece_size=ps), precision, s.n_obs, s.n_lms,
+                                  cams, lms, piece_sizes=(256, 1024), tiles=(1, 8), cache=cache)
+        log(f"tuned {precision}: {cfg.get('piece_size')}/{cfg.get('tiles_per_wave')}/{cfg.get('lds_camera')} "
+            f"cached={cfg['cached']}")
+        _check_step(prob, case, 1e-2, 16, TOL[precision], f"autotuned {precision}")
