@@ -32,10 +32,15 @@ def weight(s, delta):
 
 def cost(r, delta=None):
     """F = 1/2 sum rho(||r_i||^2) with a correctly rounded sum (math.fsum).
-    delta None means the plain squared loss of Sec. 4."""
+    delta None means the plain squared loss of Sec. 4.  A sum beyond the
+    float64 range is +inf (a trial state whose cost is not finite is then
+    rejected by the LM loop), and a NaN term gives NaN."""
     s = np.sum(np.asarray(r, dtype=np.float64) ** 2, axis=1)
     terms = s if delta is None else rho(s, delta)
-    return 0.5 * math.fsum(terms.tolist())
+    try:
+        return 0.5 * math.fsum(terms.tolist())
+    except OverflowError:  # finite terms whose exact sum exceeds the float64 range
+        return math.inf
 
 
 def reweight(r, Jp, Jl, delta=None):

@@ -120,3 +120,16 @@ def test_cost_is_half_sum_of_squares_without_loss():
     P = tiny()
     assert robust.cost(P.r) == pytest.approx(0.5 * float(np.sum(P.r ** 2)), rel=1e-14)
     assert math.isfinite(P.F)
+
+
+def test_cost_beyond_float64_range_is_infinite():
+    """A trial state so far off that the sum of its squared residuals leaves
+    the float64 range has an infinite cost (every term is finite, only the
+    sum overflows), so the LM loop, which accepts a step only if F(x + dx) is
+    finite, rejects it instead of failing."""
+    huge = np.full((4, 2), 7e153)  # each term 9.8e307, their sum past 1.8e308
+    assert np.all(np.isfinite(np.sum(huge ** 2, axis=1)))
+    assert math.isinf(robust.cost(huge))
+    assert math.isfinite(robust.cost(huge, 3.0))  # Huber terms grow like |r| and stay summable
+    nan = np.array([[1.0, 2.0], [np.nan, 0.0]])
+    assert math.isnan(robust.cost(nan))
