@@ -363,6 +363,67 @@ __device__ __forceinline__ void point_jacobian(const double* rec, const T* P, T 
     }
 }
 
+// Residual in float64 and the blocks in float32 arithmetic, for float32
+// storage: the camera-frame point, the projection and the
+// residual in float64 exactly as evaluate_obs_rec forms them (the cost and
+// the gain ratio need them), then J_P = dpi/dP, J_p = [J_P dRX, J_P, d p,
+// f n p, f n^2 p] with dRX = -[R X]x J_l(w), and J_l = J_P R in float32 from
+// R X, 1/P_z, p, n and d rounded to float32 (no cancellation is left to the
+// float32 part).  J is unweighted.
+__device__ __forceinline__ void evaluate_obs_f32(const double* rec, const double* X, double ox, double oy, double* r,
+                                                 float* J) {
+#pragma clang fp contract(off)
+    const double* Rm = rec + 13;
+    double RX[3], P[3];
+    for (int k = 0; k < 3; ++k) {
+        RX[k] = Rm[3 * k] * X[0] + Rm[3 * k + 1] * X[1] + Rm[3 * k + 2] * X[2];
+        P[k] = RX[k] + rec[3 + k];
+    }
+    const double iz = 1.0 / P[2];
+    const double p0 = -P[0] * iz, p1 = -P[1] * iz;
+    const double n = p0 * p0 + p1 * p1;
+    const double d = 1.0 + rec[7] * n + rec[8] * n * n;
+    r[0] = rec[6] * d * p0 - ox;
+    r[1] = rec[6] * d * p1 - oy;
+    const float fz = float(iz), q0 = float(p0), q1 = float(p1), fn = float(n), fd = float(d);
+    const float f = float(rec[6]), k1 = float(rec[7]), k2 = float(rec[8]);
+    const float dd = 2.0f * (k1 + 2.0f * k2 * fn);
+    const float A00 = f * (fd + dd * q0 * q0), A01 = f * dd * q0 * q1, A11 = f * (fd + dd * q1 * q1);
+    float JP[2][3];
+    JP[0][0] = -fz * A00;
+    JP[0][1] = -fz * A01;
+    JP[0][2] = -fz * (A00 * q0 + A01 * q1);
+    JP[1][0] = -fz * A01;
+    JP[1][1] = -fz * A11;
+    JP[1][2] = -fz * (A01 * q0 + A11 * q1);
+    const float w0 = float(rec[0]), w1 = float(rec[1]), w2 = float(rec[2]);
+    const float B = float(rec[10]), E = float(rec[22]);
+    const float th2 = w0 * w0 + w1 * w1 + w2 * w2;
+    const float wv[3] = {w0, w1, w2};
+    const float W[3][3] = {{0.0f, -w2, w1}, {w2, 0.0f, -w0}, {-w1, w0, 0.0f}};
+    float Jw[3][3];  // J_l(w) = I + B [w]x + E (w w^T - th2 I)
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            Jw[i][j] = (i == j ? 1.0f : 0.0f) + B * W[i][j] + E * (wv[i] * wv[j] - (i == j ? th2 : 0.0f));
+    const float X0 = float(RX[0]), X1 = float(RX[1]), X2 = float(RX[2]);
+    const float S[3][3] = {{0.0f, X2, -X1}, {-X2, 0.0f, X0}, {X1, -X0, 0.0f}};  // -[R X]x
+    float dRX[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) dRX[i][j] = S[i][0] * Jw[0][j] + S[i][1] * Jw[1][j] + S[i][2] * Jw[2][j];
+    const float qq[2] = {q0, q1};
+    for (int a = 0; a < 2; ++a) {
+        float* Jp = J + 9 * a;
+        for (int j = 0; j < 3; ++j) Jp[j] = JP[a][0] * dRX[0][j] + JP[a][1] * dRX[1][j] + JP[a][2] * dRX[2][j];
+        for (int j = 0; j < 3; ++j) Jp[3 + j] = JP[a][j];
+        Jp[6] = fd * qq[a];
+        Jp[7] = f * fn * qq[a];
+        Jp[8] = f * fn * fn * qq[a];
+        float* Jl = J + 18 + 3 * a;
+        for (int j = 0; j < 3; ++j)
+            Jl[j] = JP[a][0] * float(Rm[j]) + JP[a][1] * float(Rm[3 + j]) + JP[a][2] * float(Rm[6 + j]);
+    }
+}
+
 // Huber on s = |r|^2: rho(s) = s (s <= delta^2), 2 delta sqrt(s) - delta^2 otherwise;
 // IRLS weight w = rho'(s) = min(1, delta / sqrt(s)).
 __device__ __forceinline__ void huber(double s, double delta, double& rho, double& w) {

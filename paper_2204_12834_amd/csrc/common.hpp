@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include <cstdint>
 #include <cstring>
@@ -105,6 +106,13 @@ __device__ __forceinline__ void store_J<bf16_t>(void* base, int64_t npad, int64_
         }
         b[g * npad + i] = make_uint4(w[0], w[1], w[2], w[3]);
     }
+}
+
+// Stores blocks computed in float32 arithmetic (float32 storage).
+__device__ __forceinline__ void store_J_f32(void* base, int64_t npad, int64_t i, const float* v) {
+    float4* b = reinterpret_cast<float4*>(base);
+#pragma unroll
+    for (int g = 0; g < 6; ++g) b[g * npad + i] = make_float4(v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]);
 }
 
 // Rounds a record to the storage type and back (the values every pass sees).
@@ -392,6 +400,8 @@ struct Buffers {
     double* Dp;           // [nc][9] damping diagonal of the last solve
     double* Dl;           // [nseg][3] damping diagonal of the last solve, by segment
     void* Vinv;           // [nseg][6] storage type, indexed by segment
+    double* vinv64;       // [nseg][6] the same damped inverses in float64 (back-substitution)
+    double* ybl;          // [nseg][4] V^-1 b_l in float64 and 1 (0 for a landmark of an inactive problem)
     void* s;              // [nseg][4] storage type (landmark vector of the series), by segment
     double* v;            // [nc][9] current series term
     void* vq;             // [nc][12] current term in storage type (gather copy)
@@ -407,7 +417,8 @@ struct Buffers {
     double* lms_new;      // [nl][3]
     double* piece_red;    // [npieces_max][3] per-piece partial sums (cost, model, flags)
     double* cam_red;      // [nc][2] per-camera squared norms of v and x
-    double* xq;           // [nc][24] folded camera data of the camera step (point-record back-substitution)
+    double* xq;           // [nc][24] folded camera data of the camera step (point-record back-substitution),
+                          // or the camera step at stride 12 (Jacobian-record back-substitution)
     double* cg;           // [5][nc][9] conjugate-gradient vectors x, r, z, p, q
     double* sj;           // [nc][81] inverted diagonal blocks of S (Schur-Jacobi preconditioner)
     PcgCtl* pcg_ctl;      // [np]
@@ -473,6 +484,14 @@ struct poba_problem_s {
     double prof_ms[POBA_K_COUNT] = {0};
     int64_t prof_n[POBA_K_COUNT] = {0};
 };
+
+namespace poba {
+// Pieces averaging fewer observations than a workgroup of four wavefronts
+// has lanes (cameras that see few landmarks per landmark range, as on the
+// ladybug-shaped problem: about 50 per piece) leave most of such a workgroup
+// idle; the per-piece kernels then run one wavefront per piece.
+inline bool small_pieces(const Problem* p) { return p->npieces > 0 && p->z.N < int64_t(kBlock) * p->npieces; }
+}  // namespace poba
 
 namespace poba {
 

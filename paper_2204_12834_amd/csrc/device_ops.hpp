@@ -99,6 +99,63 @@ struct PointShape {
     }
 };
 
+// One observation's record words as loaded (unpacked to the arithmetic type
+// only where they are used, so that no instruction touches a load in flight).
+template <typename TJ>
+struct RawRec;
+template <>
+struct RawRec<double> {
+    d2v g[12];
+};
+template <>
+struct RawRec<float> {
+    f4v g[6];
+};
+template <>
+struct RawRec<bf16_t> {
+    u4v g[3];
+};
+
+template <typename TJ>
+__device__ __forceinline__ void load_raw(const void* base, int64_t npad, int64_t i, RawRec<TJ>& r) {
+    using G = typename std::remove_reference<decltype(r.g[0])>::type;
+    const G* p = reinterpret_cast<const G*>(base);
+    constexpr int n = sizeof(r.g) / sizeof(r.g[0]);
+#pragma unroll
+    for (int g = 0; g < n; ++g) r.g[g] = __builtin_nontemporal_load(&p[g * npad + i]);
+}
+
+template <typename TC>
+__device__ __forceinline__ void unpack(const RawRec<double>& r, TC* v) {
+#pragma unroll
+    for (int g = 0; g < 12; ++g) {
+        v[2 * g] = TC(r.g[g].x);
+        v[2 * g + 1] = TC(r.g[g].y);
+    }
+}
+template <typename TC>
+__device__ __forceinline__ void unpack(const RawRec<float>& r, TC* v) {
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+        v[4 * g] = TC(r.g[g].x);
+        v[4 * g + 1] = TC(r.g[g].y);
+        v[4 * g + 2] = TC(r.g[g].z);
+        v[4 * g + 3] = TC(r.g[g].w);
+    }
+}
+template <typename TC>
+__device__ __forceinline__ void unpack(const RawRec<bf16_t>& r, TC* v) {
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        const uint32_t w4[4] = {r.g[g].x, r.g[g].y, r.g[g].z, r.g[g].w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[8 * g + 2 * k] = TC(bf16_to_float(uint16_t(w4[k] & 0xffffu)));
+            v[8 * g + 2 * k + 1] = TC(bf16_to_float(uint16_t(w4[k] >> 16)));
+        }
+    }
+}
+
 // ------------------------------------------------------ landmark-tile loop --
 //
 // One wavefront walks the landmark-major positions of its tile in chunks of

@@ -7,7 +7,11 @@
 // the cost and reduces U and b_p per camera piece; the landmark-major pass
 // evaluates the observations again, stores the landmark-major records and
 // reduces V and b_l per landmark segment.  Both accumulate in float64 from the Jacobian values rounded to the
-// storage precision, so U, V and W are built from one and the same J.
+// storage precision, so U, V and W are built from one and the same J.  The
+// residual and the cost are float64 in every mode; with float32 storage the
+// blocks themselves are float32 arithmetic (evaluate_obs_f32), which halves
+// their registers, and with float64 or bfloat16 storage float64 (bfloat16
+// records are the float64 blocks rounded to nearest).
 #include <type_traits>
 
 #include "camera_model.hpp"
@@ -100,11 +104,16 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const do
     gram_acc gacc = {0.0, 0.0, 0.0, 0.0};
     double cost = 0.0, bad = 0.0;
     const PieceRec pr = b.sched_rec[blockIdx.x];  // piece, its range and camera in one load
-    const int32_t p = pr.p;
+    // the same for the whole block: wave-uniform, so the camera record comes
+    // through the scalar cache once instead of per observation
+    const int32_t p = __builtin_amdgcn_readfirstlane(pr.p);
     if (p >= 0) {
-        const int32_t cam = pr.cam;
-        const int32_t a = pr.begin, e = pr.end;
-        const double* rec = b.lin_rec + kCamRec * int64_t(cam);
+        const int32_t cam = __builtin_amdgcn_readfirstlane(pr.cam);
+        const int32_t a = __builtin_amdgcn_readfirstlane(pr.begin), e = __builtin_amdgcn_readfirstlane(pr.end);
+        // read before the loop's stores: uniform loads the compiler can keep in scalar registers
+        double rec[kCamRec];
+#pragma unroll
+        for (int k = 0; k < kCamRec; ++k) rec[k] = b.lin_rec[kCamRec * int64_t(cam) + k];
         for (int32_t base = a; base < e; base += kBlock) {
             const int32_t i = base + t;
             if (i < e) {
@@ -112,29 +121,55 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const do
                 double X[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
-                ObsEval ev;
-                evaluate_obs_rec(rec, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], ev);
-                const double s2 = ev.r[0] * ev.r[0] + ev.r[1] * ev.r[1];
-                double rho = s2, w = 1.0;
-                if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, w);
-                cost += 0.5 * rho;
-                if (!isfinite(rho)) bad = 1.0;
-                const double sw = sqrt(w);
-                double J[24];
-#pragma unroll
-                for (int k = 0; k < 24; ++k) J[k] = sw * ev.J[k];
-                store_J<TJ>(b.J_co, z.npad, i, J);
-                const double r0 = sw * ev.r[0], r1 = sw * ev.r[1];
-                b.r_co[2 * int64_t(i)] = r0;
-                b.r_co[2 * int64_t(i) + 1] = r1;
                 double* m0 = M + (2 * t) * kGramCols;
+                double rr[2];
+                if constexpr (!std::is_same<TJ, float>::value) {
+                    ObsEval ev;
+                    evaluate_obs_rec(rec, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], ev);
+                    rr[0] = ev.r[0];
+                    rr[1] = ev.r[1];
+                    const double s2 = rr[0] * rr[0] + rr[1] * rr[1];
+                    double rho = s2, w = 1.0;
+                    if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, w);
+                    cost += 0.5 * rho;
+                    if (!isfinite(rho)) bad = 1.0;
+                    const double sw = sqrt(w);
+                    double J[24];
 #pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    m0[k] = double(round_to_storage<TJ>(J[k]));
-                    m0[kGramCols + k] = double(round_to_storage<TJ>(J[9 + k]));
+                    for (int k = 0; k < 24; ++k) J[k] = sw * ev.J[k];
+                    store_J<TJ>(b.J_co, z.npad, i, J);
+                    rr[0] *= sw;
+                    rr[1] *= sw;
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) {
+                        m0[k] = round_to_storage<TJ>(J[k]);
+                        m0[kGramCols + k] = round_to_storage<TJ>(J[9 + k]);
+                    }
+                } else {
+                    float J[24];
+                    evaluate_obs_f32(rec, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], rr, J);
+                    const double s2 = rr[0] * rr[0] + rr[1] * rr[1];
+                    double rho = s2, w = 1.0;
+                    if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, w);
+                    cost += 0.5 * rho;
+                    if (!isfinite(rho)) bad = 1.0;
+                    const double sw = sqrt(w);
+                    const float swf = float(sw);
+#pragma unroll
+                    for (int k = 0; k < 24; ++k) J[k] = swf * J[k];
+                    store_J_f32(b.J_co, z.npad, i, J);
+                    rr[0] *= sw;
+                    rr[1] *= sw;
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) {
+                        m0[k] = double(J[k]);
+                        m0[kGramCols + k] = double(J[9 + k]);
+                    }
                 }
-                m0[9] = r0;
-                m0[kGramCols + 9] = r1;
+                b.r_co[2 * int64_t(i)] = rr[0];
+                b.r_co[2 * int64_t(i) + 1] = rr[1];
+                m0[9] = rr[0];
+                m0[kGramCols + 9] = rr[1];
             }
             __syncthreads();
             const int rows = 2 * min(kBlock, e - base);
@@ -176,24 +211,53 @@ __global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const dou
             double X[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
-            ObsEval ev;
-            evaluate_obs_rec(b.lin_rec + kCamRec * int64_t(cam), X, b.obs_lo[2 * int64_t(i)],
-                             b.obs_lo[2 * int64_t(i) + 1], ev);
-            double w = 1.0;
-            if (loss == POBA_LOSS_HUBER) {
-                double rho;
-                huber(ev.r[0] * ev.r[0] + ev.r[1] * ev.r[1], delta, rho, w);
+            double a[3], c[3], rr[2];  // J_l rows 0 and 1 as stored, in float64
+            if constexpr (!std::is_same<TJ, float>::value) {
+                ObsEval ev;
+                evaluate_obs_rec(b.lin_rec + kCamRec * int64_t(cam), X, b.obs_lo[2 * int64_t(i)],
+                                 b.obs_lo[2 * int64_t(i) + 1], ev);
+                rr[0] = ev.r[0];
+                rr[1] = ev.r[1];
+                double w = 1.0;
+                if (loss == POBA_LOSS_HUBER) {
+                    double rho;
+                    huber(rr[0] * rr[0] + rr[1] * rr[1], delta, rho, w);
+                }
+                const double sw = sqrt(w);
+                double J[24];
+#pragma unroll
+                for (int k = 0; k < 24; ++k) J[k] = sw * ev.J[k];
+                store_J<TJ>(b.J_lo, z.npad, i, J);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    a[k] = round_to_storage<TJ>(J[18 + k]);
+                    c[k] = round_to_storage<TJ>(J[21 + k]);
+                }
+                rr[0] *= sw;
+                rr[1] *= sw;
+            } else {
+                float J[24];
+                evaluate_obs_f32(b.lin_rec + kCamRec * int64_t(cam), X, b.obs_lo[2 * int64_t(i)],
+                                 b.obs_lo[2 * int64_t(i) + 1], rr, J);
+                double w = 1.0;
+                if (loss == POBA_LOSS_HUBER) {
+                    double rho;
+                    huber(rr[0] * rr[0] + rr[1] * rr[1], delta, rho, w);
+                }
+                const double sw = sqrt(w);
+                const float swf = float(sw);
+#pragma unroll
+                for (int k = 0; k < 24; ++k) J[k] = swf * J[k];
+                store_J_f32(b.J_lo, z.npad, i, J);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    a[k] = double(J[18 + k]);
+                    c[k] = double(J[21 + k]);
+                }
+                rr[0] *= sw;
+                rr[1] *= sw;
             }
-            const double sw = sqrt(w);
-            double J[24];
-#pragma unroll
-            for (int k = 0; k < 24; ++k) J[k] = sw * ev.J[k];
-            store_J<TJ>(b.J_lo, z.npad, i, J);
-#pragma unroll
-            for (int k = 18; k < 24; ++k) J[k] = round_to_storage<TJ>(J[k]);
-            const double r0 = sw * ev.r[0], r1 = sw * ev.r[1];
-            const double* a = J + 18;  // J_l row 0
-            const double* c = J + 21;  // J_l row 1
+            const double r0 = rr[0], r1 = rr[1];
             v[0] = a[0] * a[0] + c[0] * c[0];
             v[1] = a[0] * a[1] + c[0] * c[1];
             v[2] = a[0] * a[2] + c[0] * c[2];

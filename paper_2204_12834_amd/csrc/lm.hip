@@ -80,35 +80,34 @@ constexpr int eval_threads(bool point) { return point ? kWave : kBlock; }
 
 // F(x + dx) and L(0) - L(dx) over all observations, camera-major: one block
 // per camera piece (the camera's record and step are the same for the block);
-// the piece's partial sums go to its slot of piece_red.
+// the piece's partial sums go to its slot of piece_red.  Over stored blocks
+// each thread takes U observations at a time, all their loads (landmark
+// index, then the trial landmark and its step) issued before any of them is
+// evaluated, so the dependent gathers of U observations overlap.
 template <typename TJ, bool PT, int NT>
 __global__ __launch_bounds__(NT) void k_eval(Buffers b, Sizes z, int loss, double delta, const Ctrl* ctrl) {
     __shared__ double lds[(NT / kWave) * 3];
     if (!ctrl->active) return;
     double cost = 0.0, model = 0.0, bad = 0.0;
     const PieceRec pr = b.sched_rec[blockIdx.x];  // piece, its range, camera and problem in one load
-    const int32_t p = pr.p;
-    if (p < 0 || !b.pctl[pr.prob].active) return;
+    // the same for the whole block: wave-uniform values, so the camera's
+    // record and step come through the scalar cache
+    const int32_t p = __builtin_amdgcn_readfirstlane(pr.p);
+    if (p < 0 || !b.pctl[__builtin_amdgcn_readfirstlane(pr.prob)].active) return;
     {
-        const int64_t c = pr.cam;
-        const int32_t a = pr.begin, e = pr.end;
+        const int64_t c = __builtin_amdgcn_readfirstlane(pr.cam);
+        const int32_t a = __builtin_amdgcn_readfirstlane(pr.begin), e = __builtin_amdgcn_readfirstlane(pr.end);
         const double* rec = b.cam_rec + kCamRec * c;
         const double* dp = b.dxp + 9 * c;
-        for (int32_t i = a + threadIdx.x; i < e; i += NT) {
-            const int64_t l = b.co_lm[i];
-            double X[3], px[2];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) X[k] = b.lms_new[3 * l + k];
+        // one observation's terms from its loaded data (added only where `use`)
+        auto term = [&](bool use, const double* X, const double* dl, const double* o, const double* r,
+                        const double* J) {
+            double px[2];
             project_rec(rec, X, px);
-            const double e0 = px[0] - b.obs_co[2 * int64_t(i)], e1 = px[1] - b.obs_co[2 * int64_t(i) + 1];
+            const double e0 = px[0] - o[0], e1 = px[1] - o[1];
             const double s2 = e0 * e0 + e1 * e1;
             double rho = s2, wgt;
             if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, wgt);
-            cost += 0.5 * rho;
-            if (!isfinite(rho)) bad = 1.0;
-            double J[24];
-            Rec<TJ, PT>::template jac<double>(b, z, b.J_co, i, c, J);
-            const double* dl = b.dxl + 3 * l;
             double m0 = J[18] * dl[0] + J[19] * dl[1] + J[20] * dl[2];
             double m1 = J[21] * dl[0] + J[22] * dl[1] + J[23] * dl[2];
 #pragma unroll
@@ -116,8 +115,58 @@ __global__ __launch_bounds__(NT) void k_eval(Buffers b, Sizes z, int loss, doubl
                 m0 += J[k] * dp[k];
                 m1 += J[9 + k] * dp[k];
             }
-            const double r0 = b.r_co[2 * int64_t(i)], r1 = b.r_co[2 * int64_t(i) + 1];
-            model -= r0 * m0 + r1 * m1 + 0.5 * (m0 * m0 + m1 * m1);
+            const double md = r[0] * m0 + r[1] * m1 + 0.5 * (m0 * m0 + m1 * m1);
+            cost += use ? 0.5 * rho : 0.0;
+            model -= use ? md : 0.0;
+            if (use && !isfinite(rho)) bad = 1.0;
+        };
+        if constexpr (PT) {
+            for (int32_t i = a + threadIdx.x; i < e; i += NT) {
+                const int64_t l = b.co_lm[i];
+                double X[3], dl[3], J[24];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    X[k] = b.lms_new[3 * l + k];
+                    dl[k] = b.dxl[3 * l + k];
+                }
+                Rec<TJ, PT>::template jac<double>(b, z, b.J_co, i, c, J);
+                const double o[2] = {b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1]};
+                const double r[2] = {b.r_co[2 * int64_t(i)], b.r_co[2 * int64_t(i) + 1]};
+                term(true, X, dl, o, r, J);
+            }
+        } else {
+            constexpr int U = sizeof(TJ) == 8 ? 1 : 2;  // float64 records: one (registers)
+            for (int32_t base = a + threadIdx.x; base < e; base += U * NT) {
+                int32_t ii[U];
+                bool ok[U];
+                int64_t l[U];
+                RawRec<TJ> raw[U];
+                double X[U][3], dl[U][3], o[U][2], r[U][2];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    ok[u] = base + u * NT < e;
+                    ii[u] = ok[u] ? base + u * NT : a;  // lanes past the piece read its first position
+                    l[u] = b.co_lm[ii[u]];
+                    load_raw<TJ>(b.J_co, z.npad, ii[u], raw[u]);
+                    o[u][0] = b.obs_co[2 * int64_t(ii[u])];
+                    o[u][1] = b.obs_co[2 * int64_t(ii[u]) + 1];
+                    r[u][0] = b.r_co[2 * int64_t(ii[u])];
+                    r[u][1] = b.r_co[2 * int64_t(ii[u]) + 1];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        X[u][k] = b.lms_new[3 * l[u] + k];
+                        dl[u][k] = b.dxl[3 * l[u] + k];
+                    }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    double J[24];
+                    unpack<double>(raw[u], J);
+                    term(ok[u], X[u], dl[u], o[u], r[u], J);
+                }
+            }
         }
     }
     double tot[3] = {cost, model, bad};
@@ -267,10 +316,18 @@ poba_status lm_finish(Problem* p, double* cams, double* lms, poba_lm_state* st, 
             else
                 hipLaunchKernelGGL((k_eval<float, true, eval_threads(true)>), g_tiles, dim3(eval_threads(true)), 0, s, b, z, loss, delta, b.ctrl);
         } else {
+            auto eval = [&](auto tj) {
+                using TJ = decltype(tj);
+                if (small_pieces(p))
+                    hipLaunchKernelGGL((k_eval<TJ, false, kWave>), g_tiles, dim3(kWave), 0, s, b, z, loss, delta, b.ctrl);
+                else
+                    hipLaunchKernelGGL((k_eval<TJ, false, eval_threads(false)>), g_tiles, dim3(eval_threads(false)), 0, s,
+                                       b, z, loss, delta, b.ctrl);
+            };
             switch (p->d.precision) {
-                case POBA_F64: hipLaunchKernelGGL((k_eval<double, false, eval_threads(false)>), g_tiles, dim3(eval_threads(false)), 0, s, b, z, loss, delta, b.ctrl); break;
-                case POBA_F32: hipLaunchKernelGGL((k_eval<float, false, eval_threads(false)>), g_tiles, dim3(eval_threads(false)), 0, s, b, z, loss, delta, b.ctrl); break;
-                default: hipLaunchKernelGGL((k_eval<bf16_t, false, eval_threads(false)>), g_tiles, dim3(eval_threads(false)), 0, s, b, z, loss, delta, b.ctrl); break;
+                case POBA_F64: eval(double()); break;
+                case POBA_F32: eval(float()); break;
+                default: eval(bf16_t()); break;
             }
         }
         hipLaunchKernelGGL(k_eval_final, dim3(unsigned(z.np)), dim3(kBlock), 0, s, b, b.ctrl);

@@ -118,6 +118,8 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.Dp = (double*)take(nc * 9 * 8);
     t.Dl = (double*)take(nl * 3 * 8);
     t.Vinv = take(nl * 6 * z.sbytes);
+    t.vinv64 = (double*)take(nl * 6 * 8);
+    t.ybl = (double*)take(nl * 4 * 8);
     t.s = take(nl * 4 * 8);  // also holds float64 landmark vectors
     t.v = (double*)take(nc * 9 * 8);
     t.vq = take(nc * 24 * 8);  // camera vector (stride 12), or folded camera records (stride 24)

@@ -108,18 +108,27 @@ __global__ __launch_bounds__(kBlock) void k_inv_lm(Buffers b, int32_t nseg, int 
     TS* o = reinterpret_cast<TS*>(b.Vinv) + 6 * int64_t(g);
 #pragma unroll
     for (int k = 0; k < 6; ++k) o[k] = TS(inv[k]);
+    double2* o64 = reinterpret_cast<double2*>(b.vinv64 + 6 * int64_t(g));
+    o64[0] = make_double2(inv[0], inv[1]);
+    o64[1] = make_double2(inv[2], inv[3]);
+    o64[2] = make_double2(inv[4], inv[5]);
     if (!ok) atomicOr(&q.status, POBA_ERR_NOT_SPD);
 }
 
 // y = V_lambda^-1 b_l in float64 (first half of b~) for every non-empty
-// landmark, into the float64 view of s at its segment index.
+// landmark, into the float64 view of s at its segment index, and with a flag
+// 1 into ybl (kept there for the back-substitution; flag 0 for the
+// landmarks of inactive problems, whose step the back-substitution leaves).
 __global__ __launch_bounds__(kBlock) void k_rhs_lm(Buffers b, int32_t nseg, const Ctrl* ctrl) {
     if (!ctrl->active) return;
     const int32_t g = blockIdx.x * kBlock + threadIdx.x;
     if (g >= nseg) return;
     const int64_t l = b.nel[g];
     const PCtrl& q = b.pctl[b.lm_prob[l]];
-    if (!q.active) return;
+    if (!q.active) {
+        b.ybl[4 * int64_t(g) + 3] = 0.0;
+        return;
+    }
     double Vd[6], inv[6], bl[3], y[3], dd[3];
 #pragma unroll
     for (int k = 0; k < 6; ++k) Vd[k] = b.V[6 * l + k];
@@ -133,6 +142,9 @@ __global__ __launch_bounds__(kBlock) void k_rhs_lm(Buffers b, int32_t nseg, cons
     double2* o = reinterpret_cast<double2*>(reinterpret_cast<double*>(b.s) + 4 * int64_t(g));
     o[0] = make_double2(y[0], y[1]);
     o[1] = make_double2(y[2], 0.0);
+    double2* yo = reinterpret_cast<double2*>(b.ybl + 4 * int64_t(g));
+    yo[0] = make_double2(y[0], y[1]);
+    yo[1] = make_double2(y[2], 1.0);
 }
 
 // ------------------------------------------------------------ landmark pass --
@@ -184,9 +196,64 @@ __device__ __forceinline__ void store_s(double* s, int64_t l, const double* y) {
 // gathers of chunk k+1 (camera vector per observation, V^-1 per landmark end)
 // are issued after them, so no wait ever covers a younger load.
 // TJ: record storage, TC: arithmetic, TS: landmark storage and camera copy.
-template <typename TJ, typename TC, typename TS, bool LDS_CAM>
+template <typename TJ, typename TC, typename TS, bool LDS_CAM, typename Tail>
 __device__ __forceinline__ void lm_pass_range(const Buffers& b, const Sizes& z, int64_t t0, int64_t t1,
-                                              const TS* __restrict__ vq, TS* __restrict__ sout);
+                                              const TS* __restrict__ vq, const Tail& tail);
+
+// What the landmark stream does at a segment's tail lane.  The series:
+// s_g = V_g^-1 t_g in the storage type, with V^-1 requested a chunk ahead.
+template <typename TS, typename TC>
+struct SeriesTail {
+    const TS* __restrict__ Vinv;
+    TS* __restrict__ sout;
+    struct Slot {
+        TS A[6];
+    };
+    __device__ __forceinline__ static bool skip(const Ctrl* ctrl) { return ctrl->running == 0; }
+    __device__ __forceinline__ void fetch(int32_t seg, Slot& o) const { load_vinv(Vinv, seg, o.A); }
+    __device__ __forceinline__ void finish(int32_t seg, const Slot& o, const TC* v) const {
+        TC Ac[6], y[3];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Ac[k] = TC(o.A[k]);
+        sym3_apply(Ac, v, y);
+        TS ys[3] = {TS(y[0]), TS(y[1]), TS(y[2])};
+        store_s(sout, seg, ys);
+    }
+};
+
+// The back-substitution (Sec. 4.2, eq. back_substitution, reading R9):
+// dx_l = -(V^-1 b_l + V^-1 t) for the landmark l = nel[g] of segment g, with
+// V^-1 and V^-1 b_l in float64 from the solve's preparation (a flag 0 there
+// marks a landmark of an inactive problem, whose step is left as it was).
+struct BacksubTail {
+    const int32_t* __restrict__ nel;
+    const double* __restrict__ vinv64;
+    const double* __restrict__ ybl;
+    double* __restrict__ dxl;
+    struct Slot {
+        int32_t l;
+        double A[6], y[4];
+    };
+    __device__ __forceinline__ static bool skip(const Ctrl* ctrl) { return ctrl->active == 0; }
+    __device__ __forceinline__ void fetch(int32_t seg, Slot& o) const {
+        o.l = nel[seg];
+        const double2* a = reinterpret_cast<const double2*>(vinv64 + 6 * int64_t(seg));
+        const double2* y = reinterpret_cast<const double2*>(ybl + 4 * int64_t(seg));
+        const double2 a0 = a[0], a1 = a[1], a2 = a[2], y0 = y[0], y1 = y[1];
+        o.A[0] = a0.x; o.A[1] = a0.y; o.A[2] = a1.x; o.A[3] = a1.y; o.A[4] = a2.x; o.A[5] = a2.y;
+        o.y[0] = y0.x; o.y[1] = y0.y; o.y[2] = y1.x; o.y[3] = y1.y;
+    }
+    template <typename TC>
+    __device__ __forceinline__ void finish(int32_t, const Slot& o, const TC* v) const {
+        if (o.y[3] == 0.0) return;
+        const double t[3] = {double(v[0]), double(v[1]), double(v[2])};
+        double w[3];
+        sym3_apply(o.A, t, w);
+        double* d = dxl + 3 * int64_t(o.l);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = -(o.y[k] + w[k]);
+    }
+};
 
 // Camera vector of one observation from the LDS copy (stride 9).
 template <typename TS>
@@ -197,26 +264,25 @@ __device__ __forceinline__ void load_cam_vec_lds(const TS* cv, int64_t cam, TS* 
 
 // Landmark pass over global memory: each wavefront takes `tpw` consecutive
 // tiles; the camera vector is gathered from the L2-resident copy.
-template <typename TJ, typename TC, typename TS>
-__global__ __launch_bounds__(kBlock) void k_lm_pass(Buffers b, Sizes z, int tpw, TS* __restrict__ sout,
-                                                    const Ctrl* ctrl) {
-    if (ctrl->running == 0) return;
+template <typename TJ, typename TC, typename TS, typename Tail>
+__global__ __launch_bounds__(kBlock) void k_lm_pass(Buffers b, Sizes z, int tpw, Tail tail, const Ctrl* ctrl) {
+    if (Tail::skip(ctrl)) return;
     const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
     const int64_t t0 = wave * tpw;
     if (t0 >= z.ntiles) return;
     const int64_t t1 = min(t0 + int64_t(tpw), z.ntiles);
-    lm_pass_range<TJ, TC, TS, false>(b, z, t0, t1, reinterpret_cast<const TS*>(b.vq), sout);
+    lm_pass_range<TJ, TC, TS, false>(b, z, t0, t1, reinterpret_cast<const TS*>(b.vq), tail);
 }
 
 // Landmark pass with the camera vector staged in LDS: as many blocks as fit
 // on the device at once copy the n_c x 9 vector, then every wavefront takes
 // one contiguous range of `per` tiles (one pipeline start per wavefront, and
 // equal work for all).
-template <typename TJ, typename TC, typename TS>
-__global__ __launch_bounds__(kBlock) void k_lm_pass_lds(Buffers b, Sizes z, int64_t per, TS* __restrict__ sout,
+template <typename TJ, typename TC, typename TS, typename Tail>
+__global__ __launch_bounds__(kBlock) void k_lm_pass_lds(Buffers b, Sizes z, int64_t per, Tail tail,
                                                         const Ctrl* ctrl) {
     extern __shared__ unsigned char lds_raw[];
-    if (ctrl->running == 0) return;
+    if (Tail::skip(ctrl)) return;
     TS* cv = reinterpret_cast<TS*>(lds_raw);
     const TS* __restrict__ vq = reinterpret_cast<const TS*>(b.vq);
     {
@@ -238,64 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_lm_pass_lds(Buffers b, Sizes z, int6
     __syncthreads();
     const int64_t t0 = (int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave) * per;
     if (t0 >= z.ntiles) return;
-    lm_pass_range<TJ, TC, TS, true>(b, z, t0, min(t0 + per, z.ntiles), cv, sout);
-}
-
-// One observation's record words as loaded (unpacked to the arithmetic type
-// only where they are used, so that no instruction touches a load in flight).
-template <typename TJ>
-struct RawRec;
-template <>
-struct RawRec<double> {
-    d2v g[12];
-};
-template <>
-struct RawRec<float> {
-    f4v g[6];
-};
-template <>
-struct RawRec<bf16_t> {
-    u4v g[3];
-};
-
-template <typename TJ>
-__device__ __forceinline__ void load_raw(const void* base, int64_t npad, int64_t i, RawRec<TJ>& r) {
-    using G = typename std::remove_reference<decltype(r.g[0])>::type;
-    const G* p = reinterpret_cast<const G*>(base);
-    constexpr int n = sizeof(r.g) / sizeof(r.g[0]);
-#pragma unroll
-    for (int g = 0; g < n; ++g) r.g[g] = __builtin_nontemporal_load(&p[g * npad + i]);
-}
-
-template <typename TC>
-__device__ __forceinline__ void unpack(const RawRec<double>& r, TC* v) {
-#pragma unroll
-    for (int g = 0; g < 12; ++g) {
-        v[2 * g] = TC(r.g[g].x);
-        v[2 * g + 1] = TC(r.g[g].y);
-    }
-}
-template <typename TC>
-__device__ __forceinline__ void unpack(const RawRec<float>& r, TC* v) {
-#pragma unroll
-    for (int g = 0; g < 6; ++g) {
-        v[4 * g] = TC(r.g[g].x);
-        v[4 * g + 1] = TC(r.g[g].y);
-        v[4 * g + 2] = TC(r.g[g].z);
-        v[4 * g + 3] = TC(r.g[g].w);
-    }
-}
-template <typename TC>
-__device__ __forceinline__ void unpack(const RawRec<bf16_t>& r, TC* v) {
-#pragma unroll
-    for (int g = 0; g < 3; ++g) {
-        const uint32_t w4[4] = {r.g[g].x, r.g[g].y, r.g[g].z, r.g[g].w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            v[8 * g + 2 * k] = TC(bf16_to_float(uint16_t(w4[k] & 0xffffu)));
-            v[8 * g + 2 * k + 1] = TC(bf16_to_float(uint16_t(w4[k] >> 16)));
-        }
-    }
+    lm_pass_range<TJ, TC, TS, true>(b, z, t0, min(t0 + per, z.ntiles), cv, tail);
 }
 
 // The stream over a range of tiles in chunks of 64 positions, as a software
@@ -308,11 +317,10 @@ __device__ __forceinline__ void unpack(const RawRec<bf16_t>& r, TC* v) {
 // where the slot is used), and the ring is walked in whole rounds followed by
 // the remaining chunks, so no path reaches a slot's reuse with its load
 // unconsumed.
-template <typename TJ, typename TC, typename TS, bool LDS_CAM>
+template <typename TJ, typename TC, typename TS, bool LDS_CAM, typename Tail>
 __device__ __forceinline__ void lm_pass_range(const Buffers& b, const Sizes& z, int64_t t0, int64_t t1,
-                                              const TS* __restrict__ vq, TS* __restrict__ sout) {
+                                              const TS* __restrict__ vq, const Tail& tail) {
     constexpr int D = sizeof(TJ) == 8 ? 2 : 3;
-    const TS* __restrict__ Vinv = reinterpret_cast<const TS*>(b.Vinv);
     const uint32_t* __restrict__ lo_cam = b.lo_cam;
     const int lane = lane_id();
     const int32_t start = b.tile_start[t0];
@@ -321,7 +329,7 @@ __device__ __forceinline__ void lm_pass_range(const Buffers& b, const Sizes& z, 
     const int32_t nch = (end - start + kWave - 1) / kWave;
     RawRec<TJ> rec[D];
     uint32_t w[D];
-    TS A[2][6];
+    typename Tail::Slot A[2];
     int32_t my_seg[2];
     uint64_t hms[2];
     auto fetch = [&](int u, int32_t c) {
@@ -336,7 +344,7 @@ __device__ __forceinline__ void lm_pass_range(const Buffers& b, const Sizes& z, 
         const uint64_t hm = ballot64(wu & kHeadBit);
         hms[a] = hm;
         my_seg[a] = seg_v + __popcll(hm & mask_upto(lane));
-        if (wu & kTailBit) load_vinv(Vinv, my_seg[a], A[a]);
+        if (wu & kTailBit) tail.fetch(my_seg[a], A[a]);
         seg_v += __popcll(hm);
     };
 #pragma unroll
@@ -376,14 +384,7 @@ __device__ __forceinline__ void lm_pass_range(const Buffers& b, const Sizes& z, 
         const uint64_t hu = hms[a] & mask_upto(lane);
         const int seg_start = hu ? 63 - __builtin_clzll(hu) : 0;
         segmented_scan<TC, 3>(v, lane, seg_start);
-        if (wc & kTailBit) {
-            TC Ac[6], y[3];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) Ac[k] = TC(A[a][k]);
-            sym3_apply(Ac, v, y);
-            TS ys[3] = {TS(y[0]), TS(y[1]), TS(y[2])};
-            store_s(sout, my_seg[a], ys);
-        }
+        if (wc & kTailBit) tail.finish(my_seg[a], A[a], v);
         const int last = min(end - pos, kWave) - 1;
 #pragma unroll
         for (int k = 0; k < 3; ++k) carry[k] = __shfl(v[k], last, kWave);
@@ -415,30 +416,37 @@ __device__ __forceinline__ void lm_pass_range(const Buffers& b, const Sizes& z, 
 // (persistent blocks, a few per compute unit), else gathering it from L2.
 constexpr size_t kLdsCamMax = 64 << 10;
 
-template <typename TJ, typename TC, typename TS>
-void launch_lm_pass(Problem* p, hipStream_t s) {
+template <typename TJ, typename TC, typename TS, typename Tail>
+void launch_lm_stream(Problem* p, const Tail& tail, hipStream_t s) {
     const Buffers& b = p->b;
     const Sizes& z = p->z;
     const int tpw = p->tiles_per_wave;
     const int64_t ngroups = ceil_div(z.ntiles, tpw);
     const size_t lds = size_t(z.nc) * 9 * sizeof(TS);
-    TS* sout = reinterpret_cast<TS*>(b.s);
     if (p->lds_cam && lds <= kLdsCamMax) {
         // as many persistent blocks as fit at once (registers and LDS), at most four per compute unit
         int fit = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, k_lm_pass_lds<TJ, TC, TS>, kBlock, lds) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, k_lm_pass_lds<TJ, TC, TS, Tail>, kBlock, lds) !=
+                hipSuccess ||
             fit < 1)
             fit = 1;
         const int64_t per_cu = std::min<int64_t>(4, fit);
         const int64_t waves = p->n_cus * per_cu * kWavesPerBlock;
         const int64_t per = std::max<int64_t>(1, ceil_div(z.ntiles, waves));
         const int64_t nblk = std::max<int64_t>(1, ceil_div(ceil_div(z.ntiles, per), kWavesPerBlock));
-        hipLaunchKernelGGL((k_lm_pass_lds<TJ, TC, TS>), dim3(unsigned(nblk)), dim3(kBlock), lds, s, b, z, per, sout,
-                           b.ctrl);
+        hipLaunchKernelGGL((k_lm_pass_lds<TJ, TC, TS, Tail>), dim3(unsigned(nblk)), dim3(kBlock), lds, s, b, z, per,
+                           tail, b.ctrl);
     } else {
-        hipLaunchKernelGGL((k_lm_pass<TJ, TC, TS>), dim3(unsigned(ceil_div(ngroups, kWavesPerBlock))), dim3(kBlock), 0,
-                           s, b, z, tpw, sout, b.ctrl);
+        hipLaunchKernelGGL((k_lm_pass<TJ, TC, TS, Tail>), dim3(unsigned(ceil_div(ngroups, kWavesPerBlock))),
+                           dim3(kBlock), 0, s, b, z, tpw, tail, b.ctrl);
     }
+}
+
+template <typename TJ, typename TC, typename TS>
+void launch_lm_pass(Problem* p, hipStream_t s) {
+    const Buffers& b = p->b;
+    launch_lm_stream<TJ, TC, TS>(
+        p, SeriesTail<TS, TC>{reinterpret_cast<const TS*>(b.Vinv), reinterpret_cast<TS*>(b.s)}, s);
 }
 
 // Folded camera data (24 slots) of camera `cam` from LDS or global memory.
@@ -497,11 +505,23 @@ __global__ __launch_bounds__(kBlock) void k_fold_x(Buffers b, Sizes z, const dou
     fold_camera<double>(b.lin_rec + kCamRec * int64_t(c), x + 9 * int64_t(c), b.xq + 24 * int64_t(c));
 }
 
-// Back-substitution dx_l = -V_lambda^-1 (b_l + sum_{i in l} J_l^T J_p x_c) in
-// float64 with V_lambda^-1 recomputed from the float64 V.
-template <typename TJ, bool PT>
-__global__ __launch_bounds__(kBlock) void k_backsub(Buffers b, Sizes z, const double* __restrict__ x,
-                                                    double* __restrict__ dxl, const Ctrl* ctrl) {
+// The camera step x (float64) in the landmark stream's camera-vector layout
+// (stride 12, storage type), for the back-substitution over Jacobian records.
+template <typename TS>
+__global__ __launch_bounds__(kBlock) void k_x_to_vq(Buffers b, Sizes z, const double* __restrict__ x,
+                                                    const Ctrl* ctrl) {
+    if (!ctrl->active) return;
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= int64_t(z.nc) * 9) return;
+    reinterpret_cast<TS*>(b.vq)[12 * (i / 9) + i % 9] = TS(x[i]);
+}
+
+// Back-substitution over point records: dx_l = -V_lambda^-1 (b_l + sum_{i in
+// l} J_l^T J_p x_c) in float64 with V_lambda^-1 recomputed from the float64 V.
+// (Over Jacobian records it is the landmark stream with BacksubTail.)
+template <typename TJ>
+__global__ __launch_bounds__(kBlock) void k_backsub_pt(Buffers b, Sizes z, double* __restrict__ dxl,
+                                                       const Ctrl* ctrl) {
     if (!ctrl->active) return;
     const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
     if (tile >= z.ntiles) return;
@@ -510,26 +530,11 @@ __global__ __launch_bounds__(kBlock) void k_backsub(Buffers b, Sizes z, const do
         [&](int32_t i, bool valid, int32_t cam, int32_t, int32_t, double* v) {
             v[0] = v[1] = v[2] = 0.0;
             if (!valid) return;
-            if constexpr (PT) {
-                // J_l^T J_p x from the point record and the camera's folded x (float64)
-                double P[3], sw, c[24];
-                load_point<TJ, double>(b.J_lo, z.npad, i, P, sw);
-                load_fold(b.xq, int64_t(cam), c);
-                point_lm_term(P, sw, c, v);
-            } else {
-                double J[24];
-                Rec<TJ, PT>::template jac<double>(b, z, b.J_lo, i, cam, J);
-                const double* vc = x + 9 * int64_t(cam);
-                double q0 = 0.0, q1 = 0.0;
-#pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    q0 += J[k] * vc[k];
-                    q1 += J[9 + k] * vc[k];
-                }
-                v[0] = J[18] * q0 + J[21] * q1;
-                v[1] = J[19] * q0 + J[22] * q1;
-                v[2] = J[20] * q0 + J[23] * q1;
-            }
+            // J_l^T J_p x from the point record and the camera's folded x (float64)
+            double P[3], sw, c[24];
+            load_point<TJ, double>(b.J_lo, z.npad, i, P, sw);
+            load_fold(b.xq, int64_t(cam), c);
+            point_lm_term(P, sw, c, v);
         },
         [&](int32_t seg, int32_t lmk, const double* t) {
             const int64_t l = lmk;
@@ -1398,7 +1403,11 @@ void launch_cam_pass(Problem* p, const Buffers& b, const TSin* sin, hipStream_t 
         }
     } else {
         constexpr int NT = cam_pass_threads(sizeof(TJ));
-        hipLaunchKernelGGL((k_cam_pass<TJ, TSin, NT>), g, dim3(NT), 0, s, b, p->z, sin, b.ctrl);
+        if (NT > kWave && small_pieces(p)) {
+            hipLaunchKernelGGL((k_cam_pass<TJ, TSin, kWave>), g, dim3(kWave), 0, s, b, p->z, sin, b.ctrl);
+        } else {
+            hipLaunchKernelGGL((k_cam_pass<TJ, TSin, NT>), g, dim3(NT), 0, s, b, p->z, sin, b.ctrl);
+        }
     }
 }
 
@@ -1476,7 +1485,7 @@ void series_orders(Problem* p, const Buffers& b, int m, double eps, bool last_no
 
 // dx_l = -V^-1 (b_l + W^T x) for the camera step x = b.x, which is copied to
 // dx_cams; the solve info of every active problem to info (may be null).
-template <typename TJ, bool PT>
+template <typename TJ, typename TS, typename TCL, bool PT>
 void solve_backsub(Problem* p, const Buffers& b, double* dx_cams, double* dx_lms, poba_solve_info* info,
                    hipStream_t s) {
     const Sizes& z = p->z;
@@ -1485,8 +1494,15 @@ void solve_backsub(Problem* p, const Buffers& b, double* dx_cams, double* dx_lms
     const dim3 g_lm(unsigned(ceil_div(z.nl, kBlock)));
     const dim3 g_tiles(unsigned(ceil_div(z.ntiles, kWavesPerBlock)));
     ProfScope pr(p, POBA_K_BACKSUB, s);
-    if constexpr (PT) hipLaunchKernelGGL(k_fold_x, g_cam, blk, 0, s, b, z, b.x, b.ctrl);
-    hipLaunchKernelGGL((k_backsub<TJ, PT>), g_tiles, blk, 0, s, b, z, b.x, dx_lms, b.ctrl);
+    if constexpr (PT) {
+        hipLaunchKernelGGL(k_fold_x, g_cam, blk, 0, s, b, z, b.x, b.ctrl);
+        hipLaunchKernelGGL((k_backsub_pt<TJ>), g_tiles, blk, 0, s, b, z, dx_lms, b.ctrl);
+    } else {
+        // the series' landmark stream (its storage and arithmetic types) on x
+        hipLaunchKernelGGL((k_x_to_vq<TS>), dim3(unsigned(ceil_div(int64_t(z.nc) * 9, kBlock))), blk, 0, s, b, z,
+                           b.x, b.ctrl);
+        launch_lm_stream<TJ, TCL, TS>(p, BacksubTail{b.nel, b.vinv64, b.ybl, dx_lms}, s);
+    }
     hipLaunchKernelGGL(k_zero_empty, g_lm, blk, 0, s, b, z, dx_lms, b.ctrl);
     const int64_t nfin = std::max<int64_t>(int64_t(z.nc) * 9, z.np);
     hipLaunchKernelGGL(k_finish, dim3(unsigned(ceil_div(nfin, kBlock))), blk, 0, s, b, z, dx_cams, info, b.ctrl);
@@ -1502,7 +1518,7 @@ poba_status run_solve(Problem* p, int m, double eps, double* dx_cams, double* dx
     if (rhs_l) b.bl = const_cast<double*>(rhs_l);
     solve_prepare<TJ, TS, TCL, PT>(p, b, eps, m == 0, s);
     series_orders<TJ, TS, TCL, PT>(p, b, m, eps, true, s);
-    solve_backsub<TJ, PT>(p, b, dx_cams, dx_lms, info, s);
+    solve_backsub<TJ, TS, TCL, PT>(p, b, dx_cams, dx_lms, info, s);
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }
 
@@ -1788,7 +1804,7 @@ poba_status launch_schur_part64(Problem* p, const double* x, hipStream_t s) {
 poba_status launch_backsub_from_x(Problem* p, double* dx_cams, double* dx_lms, hipStream_t s) {
     return with_types(p, [&](auto t) {
         using T = decltype(t);
-        solve_backsub<typename T::TJ, T::PT>(p, p->b, dx_cams, dx_lms, nullptr, s);
+        solve_backsub<typename T::TJ, typename T::TS, typename T::TCL, T::PT>(p, p->b, dx_cams, dx_lms, nullptr, s);
         return last_error();
     });
 }

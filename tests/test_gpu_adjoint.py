@@ -174,6 +174,37 @@ def test_adjoint_c5_against_central_differences():
         assert abs(g64 - fd) <= 1e-4 * abs(fd) + floor, (kind, idx, fd, g64)
 
 
+@functools.lru_cache(maxsize=None)
+def c5_series_reference():
+    s, obs, gp, gl = c5_case()
+    return adjoint.adjoint(s.cams0, s.lms0, s.obs_cam, s.obs_lm, obs, LAM, gp, gl, m=M)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("records", ["jacobian", "point"])
+def test_adjoint_c5_matches_oracle_series_adjoint(records):
+    """200 cameras, 50,000 landmarks: the GPU adjoint against the oracle's
+    matrix-free one (the same truncated operator, m = 32, lambda = 1, D at
+    the state), float64 <= 1e-9 relative, float32 per coordinate <= 1e-3
+    with the floor of 1e-6 |gbar|_inf times the gradient scale."""
+    s, obs, gp, gl = c5_case()
+    ref = c5_series_reference()
+    _, dxc, dxl, go, gi, zc, zl = _gpu_adjoint(s, obs, gp, gl, "f64", records=records)
+    e = [rel(np_(dxc), ref.dxp), rel(np_(dxl), ref.dxl), rel(np_(zc), ref.zp), rel(np_(zl), ref.zl),
+         rel(np_(go), ref.grad_obs), rel(np_(gi), ref.grad_intr)]
+    log(f"c5 adjoint f64 {records}: dx {e[0]:.1e}/{e[1]:.1e} z {e[2]:.1e}/{e[3]:.1e} "
+        f"grad obs {e[4]:.1e} intrinsics {e[5]:.1e}")
+    assert max(e[:4]) <= 1e-10 and e[4] <= 1e-9 and e[5] <= 1e-9
+    _, _, _, go32, gi32, _, _ = _gpu_adjoint(s, obs, gp, gl, "f32", records=records)
+    floor = 1e-6 * max(np.abs(gp).max(), np.abs(gl).max())
+    for what, got, want in [("obs", np_(go32), ref.grad_obs), ("intrinsics", np_(gi32), ref.grad_intr)]:
+        err = np.abs(got - want)
+        bound = 1e-3 * np.abs(want) + floor * np.abs(want).max()
+        log(f"c5 adjoint f32 {records} {what}: rel {rel(got, want):.2e}, worst err/bound {np.max(err / bound):.2f}")
+        assert np.all(err <= bound), what
+
+
 def test_autograd_function():
     from paper_2204_12834_amd.autograd import damped_step
     from paper_2204_12834_amd.solver import Problem
