@@ -103,20 +103,44 @@ def make_scene(workload, huber=0.0):
         return FileScene(workload[4:]), (huber or None)
     if workload == "c3":
         return synth.config("c3"), 3.0
+    if workload == "c3-angle-axis-x0":  # the earlier initial state (synth._perturb)
+        return synth.config("c3", x0="angle-axis"), 3.0
     if workload == "c3s":  # reduced city for quick checks
         return synth.city_scene(n_cams=300, n_lms=60000, seed=0, name="c3s"), 3.0
     if workload == "c2":
         return synth.config("c2"), None
+    if workload in ("c1", "c5"):  # LM runs on these shapes (--tau-only)
+        return synth.config(workload), None
     raise SystemExit(f"unknown workload {workload}")
+
+
+def pin_one_core():
+    """Pins this process to one core of those it may use; returns its index."""
+    try:
+        cpu = min(os.sched_getaffinity(0))
+        os.sched_setaffinity(0, {cpu})
+        return cpu
+    except (AttributeError, OSError):
+        return None
+
+
+def host_text(cores_used=1):
+    try:
+        model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
+    except Exception:
+        model = "unknown"
+    return f"{cores_used} of {os.cpu_count()} cores, {model}"
 
 
 # --------------------------------------------------------------- CPU leg ----
 
-def cpu_baseline_child(workload, m, sample_lms, huber=0.0):
-    """Oracle (float64 NumPy) series on a landmark subset, single thread."""
+def cpu_baseline_child(workload, m, sample_lms, huber=0.0, gpu_precision="f32", gpu_records="jacobian"):
+    """Oracle (float64 NumPy) series on a landmark subset, single thread,
+    pinned to one core."""
     import numpy as np
     import oracle
     from oracle import camera, lm as olm, schur
+    cpu = pin_one_core()
     scene, delta = make_scene(workload, huber)
     sample_lms = min(sample_lms, scene.n_lms)
     keep = scene.obs_lm < sample_lms
@@ -136,30 +160,62 @@ def cpu_baseline_child(workload, m, sample_lms, huber=0.0):
     t0 = time.perf_counter()
     schur.power_series(Jp, Jl, oc, ol, Uinv, Vinv, bt, m, 0.0)
     dt = time.perf_counter() - t0
-    lmb, camb = series_bytes(int(keep.sum()), sample_lms, "f64")
+    n_keep = int(keep.sum())
+    lmb, camb = series_bytes(n_keep, sample_lms, gpu_precision, gpu_records)
+    lmb64, camb64 = series_bytes(n_keep, sample_lms, "f64")
     out = {"value": m * (lmb + camb) / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-           "sample": f"{workload}: landmarks 0..{sample_lms - 1} ({int(keep.sum())} observations, all "
-                     f"{scene.n_cams} cameras), oracle power series m={m}, float64, "
-                     f"{dt:.1f} s single-threaded; bytes counted with the float64 dual-order formula",
-           "seconds": dt}
-    try:
-        model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
-    except Exception:
-        model = "unknown"
-    out["host"] = f"1 of {os.cpu_count()} cores, {model}"
+           "sample": f"{workload}: landmarks 0..{sample_lms - 1} ({n_keep} observations, all "
+                     f"{scene.n_cams} cameras), oracle power series m={m} in float64, {dt:.1f} s on one pinned "
+                     f"core; GB/s counted with the same byte formula as the GPU line ({gpu_precision} "
+                     f"{gpu_records} records)",
+           "seconds": dt, "value_f64_formula": m * (lmb64 + camb64) / dt / 1e9, "pinned_cpu": cpu,
+           "host": host_text()}
     print(json.dumps(out))
 
 
-def run_cpu_baseline(workload, m, sample_lms, huber=0.0):
+def run_cpu_baseline(workload, m, sample_lms, huber=0.0, precision="f32", records="jacobian"):
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", "--workload", workload, "--m", str(m),
+           "--sample-lms", str(sample_lms), "--huber", str(huber), "--precision", precision, "--records", records]
+    return _oracle_child(cmd, 900)
+
+
+def _oracle_child(cmd, timeout):
     env = dict(os.environ, OMP_NUM_THREADS="1", MKL_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
                HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
-    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", "--workload", workload, "--m", str(m),
-           "--sample-lms", str(sample_lms), "--huber", str(huber)]
-    res = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=900)
+    # the child's progress lines go straight to our stderr
+    res = subprocess.run(cmd, env=env, stdout=subprocess.PIPE, text=True, timeout=timeout)
     if res.returncode != 0:
-        print(res.stderr[-2000:], file=sys.stderr)
+        print(f"[bench] oracle child failed with status {res.returncode}", file=sys.stderr)
         return None
     return json.loads(res.stdout.strip().splitlines()[-1])
+
+
+def oracle_lm_child(workload, m, iters, huber=0.0):
+    """The oracle's LM loop (Sec. 5.1 settings, series order m) from x0 on
+    one pinned core: per-iteration costs and cumulative seconds (the first
+    linearisation included).  iters = 0 runs to termination."""
+    import oracle
+    from oracle import camera, lm as olm
+    cpu = pin_one_core()
+    scene, delta = make_scene(workload, huber)
+    if isinstance(scene, FileScene):
+        obs = scene.obs_xy
+    else:
+        obs = camera.project(scene.cams_gt, scene.lms_gt, scene.obs_cam, scene.obs_lm) + scene.noise
+    opts = olm.LMOptions(m=m, huber_delta=delta, max_iters=iters if iters > 0 else 50)
+    rows = []
+    t0 = time.perf_counter()
+
+    def cb(it, cams_new, lms_new):
+        rows.append({"cost": it.cost, "cost_new": it.cost_new, "accepted": bool(it.accepted), "gain": it.gain,
+                     "lambda": it.lam, "stop_order": it.stop_order, "t_s": time.perf_counter() - t0})
+        print(f"[oracle-lm] {workload} iteration {len(rows)}: F {it.cost:.6e} -> {it.cost_new:.6e} "
+              f"{'accepted' if it.accepted else 'rejected'} at {rows[-1]['t_s']:.1f} s", file=sys.stderr, flush=True)
+
+    res = olm.lm(scene.cams0, scene.lms0, scene.obs_cam, scene.obs_lm, obs, opts, callback=cb)
+    print(json.dumps({"workload": workload, "m": m, "iterations": rows, "converged": bool(res.converged),
+                      "ran_to_termination": iters <= 0 or res.converged or len(rows) < iters,
+                      "pinned_cpu": cpu, "host": host_text()}))
 
 
 # --------------------------------------------------------------- GPU leg ----
@@ -354,6 +410,31 @@ def bench_batched(args, dev):
         return Problem(oc, ol, obs, cat.n_cams, cat.n_lms, precision=prec, piece_size=ps, device=dev,
                        prob_cam_off=co, prob_lm_off=lo)
 
+    if args.graph_only:
+        # only the captured LM step with the default shape, for a kernel trace
+        prob = make(autotune.DEFAULT["piece_size"])
+        prob.linearize(cams0, lms0)
+        autotune.apply(prob, autotune.DEFAULT)
+        cams, lms = cams0.clone(), lms0.clone()
+        st = prob.lm_init(opts)
+        graph = prob.lm_graph(cams, lms, st, 1, opts)
+        times = []
+        for i in range(args.warmup + args.steps):
+            cams.copy_(cams0)
+            lms.copy_(lms0)
+            prob.lm_init(opts, state=st)
+            torch.cuda.synchronize()
+            e0, e1 = _events()
+            e0.record()
+            graph.launch()
+            e1.record()
+            torch.cuda.synchronize()
+            if i >= args.warmup:
+                times.append(e0.elapsed_time(e1))
+        graph.close()
+        print(json.dumps({"mode": "c4 graph only", "graph_ms": [round(t, 4) for t in times],
+                          "warmup": args.warmup, "steps": args.steps, "m": m}), flush=True)
+        return 0
     t_tune = time.perf_counter()
     cfg, prob = autotune.tune(make, prec, cat.n_obs, cat.n_lms, cams0, lms0,
                               log=lambda s: print(s, file=sys.stderr, flush=True))
@@ -716,6 +797,114 @@ def bench_post(args, dev):
     return 0
 
 
+def lm_trace_rows(out, n, lambda0):
+    """The first n iterations of an lm_run: the damping each step used, the
+    trial cost, gain, acceptance and series order, the cost after the
+    iteration and the time since the start."""
+    rows = []
+    lam = lambda0
+    for i, (c, t, st) in enumerate(out[:n]):
+        rows.append({"iteration": i + 1, "lambda_used": lam, "cost_trial": st["cost_new"], "gain": st["gain"],
+                     "model_decrease": st["model_decrease"], "accepted": st["accepted"],
+                     "stop_order": st["stop_order"], "cost_after": c, "t_ms": round(1e3 * t, 3)})
+        lam = st["lambda"]
+    return rows
+
+
+def tau_runs(args, scene, delta, dev):
+    """LM to termination (Sec. 5.1 settings) from x0 for every precision,
+    record kind and series order asked for; f* is the best final cost over
+    all of them, f_tau = f* + 0.01 (f0 - f*) (Sec. 5, performance profiles),
+    and T_1% the time of the first iteration whose cost is at or below it."""
+    import numpy as np
+    import torch
+    from paper_2204_12834_amd.solver import LMOptions
+    precisions = [p for p in args.tau_precisions.split(",") if p]
+    ms = [int(v) for v in (args.tau_m or str(args.m)).split(",")]
+    records = ["jacobian"] + ([] if args.no_point else ["point"])
+    runs, steps_at_x0, traces = {}, {}, {}
+    for m in ms:
+        for rec in records:
+            for prec in precisions:
+                if rec == "point" and prec == "bf16":
+                    continue
+                name = prec if rec == "jacobian" else f"{prec}_point"
+                if len(ms) > 1:
+                    name += f"_m{m}"
+                p2, c0, l0, _ = gpu_setup(scene, delta, prec, dev, rec)
+                # the damped step at x0 (lambda0, fixed order) for the precision comparison
+                p2.linearize(c0, l0)
+                dxc, dxl, _ = p2.power_solve(1e-4, m, 0.0)
+                steps_at_x0[name] = (dxc.cpu().numpy(), dxl.cpu().numpy(), m)
+                o2 = LMOptions(m=m)  # Sec. 5.1 settings, series order m
+                runs[name] = lm_run(p2, c0, l0, o2, 50)
+                traces[name] = lm_trace_rows(runs[name], args.trace_iters, o2.lambda0)
+                print(f"[bench] LM {name}: {len(runs[name])} iterations, final cost {runs[name][-1][0]:.6e}",
+                      file=sys.stderr, flush=True)
+                del p2
+                torch.cuda.empty_cache()
+    # F(x0) from a plain linearisation
+    p3, c0, l0, _ = gpu_setup(scene, delta, "f64", dev)
+    f0 = p3.linearize(c0, l0).item()
+    del p3
+    fstar = min(min(c for c, _, _ in out) for out in runs.values())
+    ftau = fstar + 0.01 * (f0 - fstar)
+    tau = {}
+    for name, out in runs.items():
+        hit = [t for c, t, _ in out if c <= ftau]
+        k = next((i + 1 for i, (c, _, _) in enumerate(out) if c <= ftau), None)
+        tau[name] = {"t_1pct_s": round(hit[0], 4) if hit else None, "iterations": len(out),
+                     "final_cost": out[-1][0], "lm_iter_ms": round(1e3 * out[-1][1] / len(out), 3),
+                     "iters_to_1pct": k,
+                     "ms_per_iter_to_1pct": round(1e3 * hit[0] / k, 3) if hit else None,
+                     "accepted": sum(1 for _, _, st in out if st["accepted"]),
+                     "converged": out[-1][2]["converged"]}
+    prec_err = {}
+    for name, (c_, l_, m) in steps_at_x0.items():
+        ref = next((v for k_, v in steps_at_x0.items() if v[2] == m and k_.split("_")[0] == "f64"
+                    and "point" not in k_), None)
+        if ref is None or ref[0] is c_:
+            continue
+        prec_err[name] = {"dx_cams": float(np.linalg.norm(c_ - ref[0]) / np.linalg.norm(ref[0])),
+                          "dx_lms": float(np.linalg.norm(l_ - ref[1]) / np.linalg.norm(ref[1]))}
+    return {"f0": f0, "f_star": fstar, "f_tau": ftau, "time_to_1pct": tau, "step_error_vs_f64_at_x0": prec_err,
+            "lm_trace": traces}
+
+
+def bench_tau(args, dev):
+    """Time to the 1% cost tolerance only (and, if asked, the oracle's LM on
+    one pinned core beside it): one JSON line."""
+    t_gen = time.perf_counter()
+    scene, delta = make_scene(args.workload, args.huber)
+    print(f"[bench] scene {scene.name}: {scene.n_cams} cams, {scene.n_lms} lms, {scene.n_obs} obs "
+          f"({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
+    res = tau_runs(args, scene, delta, dev)
+    line = {"metric": "LM time to 1% cost tolerance", "workload": scene.name, "n_cams": scene.n_cams,
+            "n_lms": scene.n_lms, "n_obs": scene.n_obs, "huber_delta": delta}
+    line.update(res)
+    if args.oracle_lm >= 0:
+        m = int((args.tau_m or str(args.m)).split(",")[0])
+        cmd = [sys.executable, os.path.abspath(__file__), "--oracle-lm-child", "--workload", args.workload, "--m",
+               str(m), "--oracle-lm", str(args.oracle_lm), "--huber", str(args.huber)]
+        orc = _oracle_child(cmd, 3000)
+        if orc is not None:
+            ftau = res["f_tau"]
+            rows = orc["iterations"]
+            cost_after = [r["cost_new"] if r["accepted"] else r["cost"] for r in rows]
+            hit = next((i for i, c in enumerate(cost_after) if c <= ftau), None)
+            orc["t_1pct_s"] = round(rows[hit]["t_s"], 3) if hit is not None else None
+            gpu = res["time_to_1pct"].get("f64") or res["time_to_1pct"].get(f"f64_m{m}") or {}
+            if hit is None and rows and gpu.get("iters_to_1pct"):
+                # fewer oracle iterations than the GPU float64 run needed: extrapolate
+                per = (rows[-1]["t_s"] - rows[0]["t_s"]) / max(len(rows) - 1, 1) if len(rows) > 1 else rows[0]["t_s"]
+                orc["t_1pct_extrapolated_s"] = round(rows[0]["t_s"] + per * (gpu["iters_to_1pct"] - 1), 3)
+                orc["extrapolation"] = (f"first oracle iteration plus the mean of the timed ones times the "
+                                        f"{gpu['iters_to_1pct']} iterations the GPU float64 run took to f_tau")
+            line["oracle_lm"] = orc
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -731,6 +920,8 @@ def main():
     ap.add_argument("--sample-lms", type=int, default=600000,
                     help="landmarks of the scene the CPU oracle's series runs on (about 10-20 s of CPU work)")
     ap.add_argument("--tpw", type=int, default=0, help="landmark tiles per wavefront (0: library default)")
+    ap.add_argument("--lds-camera", type=int, default=-1,
+                    help="1/0: landmark pass reads the camera vector from LDS / from L2 (-1: library default)")
     ap.add_argument("--sweep-tpw", default="", help="comma list: time the series for each and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tau", action="store_true", help="skip the time-to-tolerance LM runs")
@@ -744,11 +935,25 @@ def main():
     ap.add_argument("--post-cluster", type=int, default=100, help="largest camera cluster of --post")
     ap.add_argument("--post-draws", type=int, default=4,
                     help="--post also runs with this many cluster draws used in turn (0: only new draws)")
+    ap.add_argument("--tau-only", action="store_true",
+                    help="only the time-to-tolerance LM runs on the workload (c1, c2, c3, c5, bal:PATH), then exit")
+    ap.add_argument("--tau-m", default="", help="comma list of series orders for the LM runs (default: --m)")
+    ap.add_argument("--tau-precisions", default="f64,f32,bf16", help="comma list of precisions for the LM runs")
+    ap.add_argument("--trace-iters", type=int, default=5, help="LM iterations listed per run in lm_trace")
+    ap.add_argument("--oracle-lm", type=int, default=-1,
+                    help="with --tau-only: also time the oracle's LM on one pinned core for this many "
+                         "iterations (0: to termination; -1: not at all)")
+    ap.add_argument("--graph-only", action="store_true",
+                    help="with --workload c4: only time the captured LM step (default shape), for kernel traces")
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--oracle-lm-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
 
     if args.cpu_baseline_child:
-        cpu_baseline_child(args.workload, args.m, args.sample_lms, args.huber)
+        cpu_baseline_child(args.workload, args.m, args.sample_lms, args.huber, args.precision, args.records)
+        return 0
+    if args.oracle_lm_child:
+        oracle_lm_child(args.workload, args.m, args.oracle_lm, args.huber)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -762,6 +967,8 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.tau_only:
+        return bench_tau(args, dev)
     if args.workload == "c4":
         return bench_batched(args, dev)
     if args.workload == "c5":
@@ -778,6 +985,8 @@ def main():
     prob, cams0, lms0, obs = gpu_setup(scene, delta, args.precision, dev, args.records)
     if args.tpw:
         prob.set_tuning("tiles_per_wave", args.tpw)
+    if args.lds_camera >= 0:
+        prob.set_tuning("lds_camera", args.lds_camera)
     if args.sweep_tpw:
         prob.linearize(cams0, lms0)
         for tpw in [int(x) for x in args.sweep_tpw.split(",")]:
@@ -816,51 +1025,13 @@ def main():
 
     extra = {}
     if not args.no_tau:
-        runs = {}
-        steps_at_x0 = {}
-        configs = [("f64", "jacobian"), ("f32", "jacobian"), ("bf16", "jacobian")]
-        if not args.no_point:
-            configs += [("f64", "point"), ("f32", "point")]
-        for prec, rec in configs:
-            name = prec if rec == "jacobian" else f"{prec}_point"
-            p2, c0, l0, _ = gpu_setup(scene, delta, prec, dev, rec)
-            # the damped step at x0 (lambda0, fixed order) for the precision comparison
-            p2.linearize(c0, l0)
-            dxc, dxl, _ = p2.power_solve(1e-4, args.m, 0.0)
-            steps_at_x0[name] = (dxc.cpu().numpy(), dxl.cpu().numpy())
-            o2 = LMOptions(m=args.m)  # Sec. 5.1 settings, series order m
-            runs[name] = lm_run(p2, c0, l0, o2, 50)
-            print(f"[bench] LM {name}: {len(runs[name])} iterations, final cost {runs[name][-1][0]:.6e}",
-                  file=sys.stderr, flush=True)
-            del p2
-            torch.cuda.empty_cache()
-        # F(x0) from a plain linearisation
-        p3, c0, l0, _ = gpu_setup(scene, delta, "f64", dev)
-        f0 = p3.linearize(c0, l0).item()
-        del p3
-        fstar = min(min(c for c, _, _ in out) for out in runs.values())
-        ftau = fstar + 0.01 * (f0 - fstar)
-        tau = {}
-        for name, out in runs.items():
-            hit = [t for c, t, _ in out if c <= ftau]
-            tau[name] = {"t_1pct_s": round(hit[0], 4) if hit else None, "iterations": len(out),
-                         "final_cost": out[-1][0], "lm_iter_ms": round(1e3 * out[-1][1] / len(out), 3),
-                         "iters_to_1pct": next((i + 1 for i, (c, _, _) in enumerate(out) if c <= ftau), None)}
-        ref_c, ref_l = steps_at_x0["f64"]
-        prec_err = {}
-        for name, (c_, l_) in steps_at_x0.items():
-            if name == "f64":
-                continue
-            prec_err[name] = {"dx_cams": float(np.linalg.norm(c_ - ref_c) / np.linalg.norm(ref_c)),
-                              "dx_lms": float(np.linalg.norm(l_ - ref_l) / np.linalg.norm(ref_l))}
-        extra = {"f0": f0, "f_star": fstar, "f_tau": ftau, "time_to_1pct": tau,
-                 "step_error_vs_f64_at_x0": prec_err}
+        extra = tau_runs(args, scene, delta, dev)
     if alt is not None:
         extra["point_records"] = alt
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = run_cpu_baseline(args.workload, args.m, args.sample_lms, args.huber)
+        cpu = run_cpu_baseline(args.workload, args.m, args.sample_lms, args.huber, args.precision, args.records)
 
     if isinstance(scene, FileScene):
         loss_text = f"Huber delta {delta:g} px, " if delta else ""

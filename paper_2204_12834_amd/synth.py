@@ -131,19 +131,33 @@ def _so3_exp(w: np.ndarray) -> np.ndarray:
     return np.eye(3)[None] + s * K + (1.0 - c) * (K @ K)
 
 
-def _perturb(rng, cams, lms, rot_sigma=1e-2, pos_sigma=0.1):
+def _perturb(rng, cams, lms, rot_sigma=1e-2, pos_sigma=0.1, x0="centre"):
     """Initial state: every camera turned about its own centre by a rotation
     of angle-axis N(0, rot_sigma^2 I), its centre moved by N(0, pos_sigma^2 I)
     in world units, and every landmark moved by N(0, pos_sigma^2 I).  The
     translation follows from the moved centre, t0 = -R0 c0, so a camera far
-    from the world origin moves no further than one near it."""
-    R = _so3_exp(cams[:, 0:3])
-    centers = -np.einsum("nji,nj->ni", R, cams[:, 3:6])
-    R0 = _so3_exp(rng.normal(0.0, rot_sigma, (cams.shape[0], 3))) @ R
-    c0 = centers + rng.normal(0.0, pos_sigma, (cams.shape[0], 3))
+    from the world origin moves no further than one near it.
+
+    x0 = "angle-axis" instead adds the rotation noise to the angle-axis
+    vector and the position noise to t, both at the other fixed (the earlier
+    initial state, kept to reproduce measurements made with it; it moves a
+    camera's centre by about rot_sigma |t|).  Both draw the same numbers in
+    the same order."""
+    rot = rng.normal(0.0, rot_sigma, (cams.shape[0], 3))
+    pos = rng.normal(0.0, pos_sigma, (cams.shape[0], 3))
     cams0 = cams.copy()
-    cams0[:, 0:3] = _so3_log(R0)
-    cams0[:, 3:6] = -np.einsum("nij,nj->ni", R0, c0)
+    if x0 == "angle-axis":
+        cams0[:, 0:3] += rot
+        cams0[:, 3:6] += pos
+    elif x0 == "centre":
+        R = _so3_exp(cams[:, 0:3])
+        centers = -np.einsum("nji,nj->ni", R, cams[:, 3:6])
+        R0 = _so3_exp(rot) @ R
+        c0 = centers + pos
+        cams0[:, 0:3] = _so3_log(R0)
+        cams0[:, 3:6] = -np.einsum("nij,nj->ni", R0, c0)
+    else:
+        raise ValueError(x0)
     lms0 = lms + rng.normal(0.0, pos_sigma, lms.shape)
     return cams0, lms0
 
@@ -158,7 +172,7 @@ def _finish(name, rng, cams, lms, cam_lists, noise_sigma=1.0, outlier_frac=0.0, 
 
 
 def _finish_arrays(name, rng, cams, lms, obs_cam, obs_lm, noise_sigma=1.0, outlier_frac=0.0,
-                   outlier_px=20.0):
+                   outlier_px=20.0, x0="centre"):
     n = obs_cam.shape[0]
     perm = rng.permutation(n)
     obs_cam = np.ascontiguousarray(obs_cam[perm], dtype=np.int32)
@@ -169,7 +183,7 @@ def _finish_arrays(name, rng, cams, lms, obs_cam, obs_lm, noise_sigma=1.0, outli
         outlier = rng.random(n) < outlier_frac
         phi = rng.uniform(0.0, 2.0 * math.pi, int(outlier.sum()))
         noise[outlier] = outlier_px * np.stack([np.cos(phi), np.sin(phi)], axis=1)
-    cams0, lms0 = _perturb(rng, cams, lms)
+    cams0, lms0 = _perturb(rng, cams, lms, x0=x0)
     return Scene(name, cams, lms, obs_cam, obs_lm, noise, outlier, cams0, lms0)
 
 
@@ -297,7 +311,7 @@ def _trunc_power(rng, alpha, lo, hi, size):
 def city_scene(n_cams: int = 1100, n_lms: int = 780_000, seed: int = 0,
                alpha: float = 2.1397, track=(2, 200), outlier_frac: float = 0.02,
                outlier_px: float = 20.0, chunk: int = 8192, n_cand: int = 64,
-               name: str = "city") -> Scene:
+               name: str = "city", x0: str = "centre") -> Scene:
     """Cameras uniform (by area) on the annulus 40 <= r <= 80, height
     U(1.5, 30), each looking at a target uniform in the disc of radius 20 at
     height U(0, 40).  Landmarks uniform in the cylinder r <= 25, z in [0, 40].
@@ -391,7 +405,7 @@ def city_scene(n_cams: int = 1100, n_lms: int = 780_000, seed: int = 0,
         todo = np.concatenate(redo) if redo else np.zeros(0, np.int64)
     obs_lm = np.concatenate(sel_lm).astype(np.int32) if sel_lm else np.zeros(0, np.int32)
     obs_cam = np.concatenate(sel_cam).astype(np.int32) if sel_cam else np.zeros(0, np.int32)
-    return _finish_arrays(name, rng, cams, lms, obs_cam, obs_lm, 1.0, outlier_frac, outlier_px)
+    return _finish_arrays(name, rng, cams, lms, obs_cam, obs_lm, 1.0, outlier_frac, outlier_px, x0)
 
 
 # ----------------------------------------------------------------------------
@@ -439,7 +453,7 @@ def config(name: str, **kw):
     if name == "c2":
         return ladybug_scene(seed=kw.get("seed", 0), name="c2")
     if name == "c3":
-        return city_scene(seed=kw.get("seed", 0), name="c3")
+        return city_scene(seed=kw.get("seed", 0), name="c3", x0=kw.get("x0", "centre"))
     if name == "c4":
         return batched_scenes(kw.get("n_problems", 256))
     if name == "c5":

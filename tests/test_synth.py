@@ -46,3 +46,26 @@ def test_initial_perturbation_moves_centres_by_the_stated_sigma(name):
     assert abs(ang.mean() - 0.01 * 2.0 * math.sqrt(2.0 / math.pi)) < 0.1 * 0.016
     # intrinsics start at ground truth
     np.testing.assert_array_equal(s.cams0[:, 6:9], s.cams_gt[:, 6:9])
+
+
+def test_angle_axis_initial_state_is_the_earlier_one():
+    """x0 = "angle-axis" (kept to reproduce measurements made with the earlier
+    initial state) adds the noise to the angle-axis vector and to t; it draws
+    the same numbers in the same order as the default, so landmarks, noise
+    and the camera noise itself are shared."""
+    kw = dict(n_cams=60, n_lms=3000, seed=5, name="x0")
+    a = synth.city_scene(**kw)
+    b = synth.city_scene(**kw, x0="angle-axis")
+    np.testing.assert_array_equal(a.lms0, b.lms0)
+    np.testing.assert_array_equal(a.noise, b.noise)
+    d = b.cams0 - b.cams_gt
+    assert np.all(d[:, 6:9] == 0.0)
+    assert abs(d[:, 0:3].std() - 0.01) < 0.002 and abs(d[:, 3:6].std() - 0.1) < 0.02
+    # the centre then moves by about 0.01 |t|, more than the default's 0.1
+    c_gt, _ = _centres(b.cams_gt)
+    shift_b = np.linalg.norm(_centres(b.cams0)[0] - c_gt, axis=1)
+    shift_a = np.linalg.norm(_centres(a.cams0)[0] - c_gt, axis=1)
+    t = np.linalg.norm(b.cams_gt[:, 3:6], axis=1)
+    assert np.median(shift_b / t) > 0.005 and np.median(shift_a) < 0.2
+    with pytest.raises(ValueError):
+        synth.city_scene(**kw, x0="other")
