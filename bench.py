@@ -220,7 +220,7 @@ def oracle_lm_child(workload, m, iters, huber=0.0):
 
 # --------------------------------------------------------------- GPU leg ----
 
-def gpu_setup(scene, delta, precision, dev, records="jacobian"):
+def gpu_setup(scene, delta, precision, dev, records="jacobian", lm_ranges=0):
     import torch
     from paper_2204_12834_amd.solver import Problem, project
     if isinstance(scene, FileScene):
@@ -229,7 +229,8 @@ def gpu_setup(scene, delta, precision, dev, records="jacobian"):
         obs = project(scene.obs_cam, scene.obs_lm, scene.cams_gt, scene.lms_gt, device=dev)
         obs += torch.as_tensor(scene.noise, device=dev)
     prob = Problem(scene.obs_cam, scene.obs_lm, obs, scene.n_cams, scene.n_lms, precision=precision,
-                   loss="huber" if delta else "l2", huber_delta=delta or 0.0, device=dev, records=records)
+                   loss="huber" if delta else "l2", huber_delta=delta or 0.0, device=dev, records=records,
+                   lm_ranges=lm_ranges)
     cams0 = torch.as_tensor(scene.cams0, dtype=torch.float64, device=dev)
     lms0 = torch.as_tensor(scene.lms0, dtype=torch.float64, device=dev)
     return prob, cams0, lms0, obs
@@ -237,7 +238,7 @@ def gpu_setup(scene, delta, precision, dev, records="jacobian"):
 
 def stream_probe(dev, nbytes=1 << 32):
     """Achievable HBM bandwidth of the library's plain streaming kernels
-    (read-only and copy, 4 GiB, best over a few grid sizes)."""
+    (read-only, copy and write-only, 4 GiB, best over a few grid sizes)."""
     import ctypes
     import torch
     from paper_2204_12834_amd import _lib
@@ -246,7 +247,7 @@ def stream_probe(dev, nbytes=1 << 32):
     dst = torch.empty_like(src)
     s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     out = {}
-    for kind, name, moved in [(0, "read", nbytes), (1, "copy", 2 * nbytes)]:
+    for kind, name, moved in [(0, "read", nbytes), (1, "copy", 2 * nbytes), (2, "write", nbytes)]:
         best = 0.0
         for blocks in [512, 768, 1024, 2048, 4096, 8192, 16384]:
             for _ in range(2):
@@ -709,7 +710,7 @@ def bench_post(args, dev):
 
     scene, delta = make_scene(args.workload, args.huber)
     opts = LMOptions(m=args.m)
-    prob, cams0, lms0, obs = gpu_setup(scene, delta, args.precision, dev, args.records)
+    prob, cams0, lms0, obs = gpu_setup(scene, delta, args.precision, dev, args.records, args.lm_ranges)
     lm_run(prob, cams0, lms0, LMOptions(m=args.m, max_iters=2), 2)  # warm
     poba = lm_run(prob, cams0, lms0, opts, 50)
     f0 = prob.linearize(cams0, lms0).item()
@@ -920,6 +921,8 @@ def main():
     ap.add_argument("--sample-lms", type=int, default=600000,
                     help="landmarks of the scene the CPU oracle's series runs on (about 10-20 s of CPU work)")
     ap.add_argument("--tpw", type=int, default=0, help="landmark tiles per wavefront (0: library default)")
+    ap.add_argument("--lm-ranges", type=int, default=0,
+                    help="landmark ranges of the camera-major order (0: automatic, else 1 or a multiple of 8)")
     ap.add_argument("--lds-camera", type=int, default=-1,
                     help="1/0: landmark pass reads the camera vector from LDS / from L2 (-1: library default)")
     ap.add_argument("--sweep-tpw", default="", help="comma list: time the series for each and exit")
@@ -982,7 +985,7 @@ def main():
     print(f"[bench] scene {scene.name}: {scene.n_cams} cams, {scene.n_lms} lms, {scene.n_obs} obs "
           f"({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
 
-    prob, cams0, lms0, obs = gpu_setup(scene, delta, args.precision, dev, args.records)
+    prob, cams0, lms0, obs = gpu_setup(scene, delta, args.precision, dev, args.records, args.lm_ranges)
     if args.tpw:
         prob.set_tuning("tiles_per_wave", args.tpw)
     if args.lds_camera >= 0:
@@ -1061,6 +1064,7 @@ def main():
         "phase_ms_per_step": phases,
         "measured_read_GBps": probe["read_GBps"],
         "measured_copy_GBps": probe["copy_GBps"],
+        "measured_write_GBps": probe["write_GBps"],
         "dominant_vs_measured_read": round(achieved / probe["read_GBps"], 4),
     }
     line.update(extra)

@@ -522,7 +522,8 @@ poba_status poba_profile_read(poba_problem p, double *ms, int64_t *n);
 
 /* Streams `bytes` (a multiple of 16; src 16-byte aligned) from src [dev].
  * kind 0 only reads (dst [dev]: `blocks` floats of sink, written only for a
- * value that ordinary data never sums to); kind 1 copies src to dst [dev].
+ * value that ordinary data never sums to); kind 1 copies src to dst [dev];
+ * kind 2 only writes `bytes` of zeros to dst [dev] (src is not read).
  * blocks <= 0 selects 4096 blocks.  Used to measure the achievable HBM
  * bandwidth and to calibrate byte counters with a transfer of known size. */
 poba_status poba_probe(int32_t kind, const void *src, void *dst, size_t bytes, int32_t blocks,

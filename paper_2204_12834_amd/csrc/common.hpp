@@ -414,7 +414,7 @@ struct Buffers {
     double* cam_rec;      // [nc][24] camera records of the state being evaluated (trial state)
     double* lin_rec;      // [nc][24] camera records of the last linearisation
     double* cams_new;     // [nc][9]
-    double* lms_new;      // [nl][3]
+    double* lm_trial;     // [nl][8] trial landmark x + dx_l (0..2) and its step dx_l (3..5), one 64-byte line
     double* piece_red;    // [npieces_max][3] per-piece partial sums (cost, model, flags)
     double* cam_red;      // [nc][2] per-camera squared norms of v and x
     double* xq;           // [nc][24] folded camera data of the camera step (point-record back-substitution),

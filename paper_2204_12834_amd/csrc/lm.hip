@@ -64,13 +64,38 @@ __global__ __launch_bounds__(kReduceBlock) void k_begin_step(Ctrl* ctrl, PCtrl* 
     }
 }
 
-// cams_new = cams + dx_p, lms_new = lms + dx_l.
+// cams_new = cams + dx_p; per landmark the trial position lms + dx_l and the
+// step dx_l side by side in one 64-byte record, so that the evaluation's
+// gather of both takes one line.
 __global__ __launch_bounds__(kBlock) void k_trial(Buffers b, Sizes z, const double* cams, const double* lms,
                                                   const Ctrl* ctrl) {
     if (!ctrl->active) return;
     const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
     if (i < int64_t(z.nc) * 9) b.cams_new[i] = cams[i] + b.dxp[i];
-    if (i < int64_t(z.nl) * 3) b.lms_new[i] = lms[i] + b.dxl[i];
+    if (i < int64_t(z.nl)) {
+        double d[3], x[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            d[k] = b.dxl[3 * i + k];
+            x[k] = lms[3 * i + k] + d[k];
+        }
+        double2* o = reinterpret_cast<double2*>(b.lm_trial + 8 * i);
+        o[0] = make_double2(x[0], x[1]);
+        o[1] = make_double2(x[2], d[0]);
+        o[2] = make_double2(d[1], d[2]);
+    }
+}
+
+// The trial position and step of landmark l from its record.
+__device__ __forceinline__ void load_lm_trial(const double* t, int64_t l, double* X, double* dl) {
+    const double2* q = reinterpret_cast<const double2*>(t + 8 * l);
+    const double2 a = q[0], c = q[1], e = q[2];
+    X[0] = a.x;
+    X[1] = a.y;
+    X[2] = c.x;
+    dl[0] = c.y;
+    dl[1] = e.x;
+    dl[2] = e.y;
 }
 
 // Threads per piece (measured at the city size): one wavefront over point
@@ -124,11 +149,7 @@ __global__ __launch_bounds__(NT) void k_eval(Buffers b, Sizes z, int loss, doubl
             for (int32_t i = a + threadIdx.x; i < e; i += NT) {
                 const int64_t l = b.co_lm[i];
                 double X[3], dl[3], J[24];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    X[k] = b.lms_new[3 * l + k];
-                    dl[k] = b.dxl[3 * l + k];
-                }
+                load_lm_trial(b.lm_trial, l, X, dl);
                 Rec<TJ, PT>::template jac<double>(b, z, b.J_co, i, c, J);
                 const double o[2] = {b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1]};
                 const double r[2] = {b.r_co[2 * int64_t(i)], b.r_co[2 * int64_t(i) + 1]};
@@ -154,12 +175,7 @@ __global__ __launch_bounds__(NT) void k_eval(Buffers b, Sizes z, int loss, doubl
                     r[u][1] = b.r_co[2 * int64_t(ii[u]) + 1];
                 }
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        X[u][k] = b.lms_new[3 * l[u] + k];
-                        dl[u][k] = b.dxl[3 * l[u] + k];
-                    }
+                for (int u = 0; u < U; ++u) load_lm_trial(b.lm_trial, l[u], X[u], dl[u]);
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     double J[24];
@@ -251,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(Buffers b, Sizes z, double* ca
     }
     if (i < int64_t(z.nl) * 3) {
         const PCtrl& q = b.pctl[b.lm_prob[i / 3]];
-        if (q.active && q.accepted) lms[i] = b.lms_new[i];
+        if (q.active && q.accepted) lms[i] = b.lm_trial[8 * (i / 3) + i % 3];
     }
 }
 

@@ -27,6 +27,12 @@ __global__ __launch_bounds__(kBlock) void k_probe_copy(const f4v* __restrict__ s
         __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+__global__ __launch_bounds__(kBlock) void k_probe_write(f4v* __restrict__ dst, int64_t n4) {
+    const int64_t stride = int64_t(gridDim.x) * kBlock;
+    const f4v z = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n4; i += stride) __builtin_nontemporal_store(z, dst + i);
+}
+
 }  // namespace poba
 
 using namespace poba;
@@ -35,16 +41,18 @@ extern "C" poba_status poba_probe(int32_t kind, const void* src, void* dst, size
                                   poba_stream stream) {
     (void)hipGetLastError();  // report only this call's launch errors
     if (!src || (bytes & 15) || (reinterpret_cast<uintptr_t>(src) & 15)) return POBA_ERR_INVALID_ARG;
-    if (kind == 1 && (!dst || (reinterpret_cast<uintptr_t>(dst) & 15))) return POBA_ERR_INVALID_ARG;
-    if (kind != 0 && kind != 1) return POBA_ERR_INVALID_ARG;
+    if ((kind == 1 || kind == 2) && (!dst || (reinterpret_cast<uintptr_t>(dst) & 15))) return POBA_ERR_INVALID_ARG;
+    if (kind < 0 || kind > 2) return POBA_ERR_INVALID_ARG;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int64_t n4 = int64_t(bytes / 16);
     const unsigned g = unsigned(blocks > 0 ? blocks : 256 * 16);
     if (kind == 0)
         hipLaunchKernelGGL(k_probe_read, dim3(g), dim3(kBlock), 0, s, reinterpret_cast<const f4v*>(src), n4,
                            reinterpret_cast<float*>(dst));
-    else
+    else if (kind == 1)
         hipLaunchKernelGGL(k_probe_copy, dim3(g), dim3(kBlock), 0, s, reinterpret_cast<const f4v*>(src),
                            reinterpret_cast<f4v*>(dst), n4);
+    else
+        hipLaunchKernelGGL(k_probe_write, dim3(g), dim3(kBlock), 0, s, reinterpret_cast<f4v*>(dst), n4);
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }

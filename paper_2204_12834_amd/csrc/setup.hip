@@ -132,7 +132,7 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.cam_rec = (double*)take(nc * 24 * 8);
     t.lin_rec = (double*)take(nc * 24 * 8);
     t.cams_new = (double*)take(nc * 9 * 8);
-    t.lms_new = (double*)take(nl * 3 * 8);
+    t.lm_trial = (double*)take(nl * 8 * 8);
     t.piece_red = (double*)take(size_t(z.npieces_max) * 3 * 8);
     t.cam_red = (double*)take(nc * 2 * 8);
     t.xq = (double*)take(nc * 24 * 8);
