@@ -212,7 +212,14 @@ def oracle_lm_child(workload, m, iters, huber=0.0):
         print(f"[oracle-lm] {workload} iteration {len(rows)}: F {it.cost:.6e} -> {it.cost_new:.6e} "
               f"{'accepted' if it.accepted else 'rejected'} at {rows[-1]['t_s']:.1f} s", file=sys.stderr, flush=True)
 
-    res = olm.lm(scene.cams0, scene.lms0, scene.obs_cam, scene.obs_lm, obs, opts, callback=cb)
+    print(f"[oracle-lm] {workload} scene and observations ready at {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+
+    def progress(stage):
+        print(f"[oracle-lm] {workload} iteration {len(rows) + 1}: {stage} at {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+
+    res = olm.lm(scene.cams0, scene.lms0, scene.obs_cam, scene.obs_lm, obs, opts, callback=cb, progress=progress)
     print(json.dumps({"workload": workload, "m": m, "iterations": rows, "converged": bool(res.converged),
                       "ran_to_termination": iters <= 0 or res.converged or len(rows) < iters,
                       "pinned_cpu": cpu, "host": host_text()}))

@@ -99,22 +99,29 @@ def step_direction(rw, Jp, Jl, obs_cam, obs_lm, n_cams, n_lms, lam, opts, solver
 
 
 def lm(cams0, lms0, obs_cam, obs_lm, obs_xy, opts: LMOptions | None = None, solver="series",
-       callback=None, cluster=None) -> LMResult:
+       callback=None, cluster=None, progress=None) -> LMResult:
+    """callback(iteration, cams_new, lms_new) after every iteration;
+    progress(stage) after the linearisation, the step and the trial cost of
+    every iteration (for reporting only)."""
     opts = opts or LMOptions()
+    report = progress or (lambda stage: None)
     cams = np.array(cams0, dtype=np.float64)
     lms = np.array(lms0, dtype=np.float64)
     n_cams, n_lms = cams.shape[0], lms.shape[0]
     lam, nu = opts.lambda0, 2.0
     F, rw, Jp, Jl = linearize(cams, lms, obs_cam, obs_lm, obs_xy, opts.huber_delta)
+    report("linearised")
     its = []
     converged = False
     for it in range(opts.max_iters):
         cl = cluster(it) if callable(cluster) else cluster  # clusters drawn per iteration (Sec. 5.3)
         dxp, dxl, order = step_direction(rw, Jp, Jl, obs_cam, obs_lm, n_cams, n_lms, lam, opts, solver, cl)
+        report("step")
         cams_new = cams + dxp
         lms_new = lms + dxl
         r_new = camera.residuals(cams_new, lms_new, obs_cam, obs_lm, obs_xy)
         F_new = robust.cost(r_new, opts.huber_delta)
+        report("trial cost")
         L = model_decrease(rw, Jp, Jl, obs_cam, obs_lm, dxp, dxl)
         if math.isfinite(F_new) and L > 0.0:
             rho = (F - F_new) / L
@@ -134,6 +141,7 @@ def lm(cams0, lms0, obs_cam, obs_lm, obs_xy, opts: LMOptions | None = None, solv
                 converged = True
                 break
             F, rw, Jp, Jl = linearize(cams, lms, obs_cam, obs_lm, obs_xy, opts.huber_delta)
+            report("linearised")
         else:
             lam = min(max(lam * nu, opts.lambda_min), opts.lambda_max)
             nu = 2.0 * nu
