@@ -229,6 +229,103 @@ __device__ __forceinline__ void tile_landmarks(const uint32_t* __restrict__ lo_c
     }
 }
 
+// ------------------------------------------- landmark-major stream (pipelined) --
+//
+// The tile loop for kernels whose per-position work needs the landmark's
+// position X and the observation (the landmark-major linearisation): one
+// wavefront walks the tiles [t0, t1) as one stream of 64-position chunks (a
+// range of whole tiles starts at a landmark head, and the open segment is
+// carried across chunks and tiles as in the tile loop).  Three chunks are in
+// flight: while chunk c is evaluated, the landmark positions of chunk c + 1
+// have been requested, and the loads of chunk c + 2 that need nothing of
+// earlier chunks (camera words, observations, the window of the
+// non-empty-landmark list) too; a chunk then waits only for what its own work
+// gathers from L2 (the camera record).
+// obs(i, valid, cam, X, ox, oy, v) fills K values (zero when !valid);
+// tail(seg, l, v) runs at each landmark's last position.
+template <int K, typename Obs, typename Tail>
+__device__ __forceinline__ void lm_tile_stream(const uint32_t* __restrict__ lo_cam,
+                                               const int32_t* __restrict__ tile_start,
+                                               const int32_t* __restrict__ seg_base, const int32_t* __restrict__ nel,
+                                               const double* __restrict__ obs_lo, const double* __restrict__ lms,
+                                               int32_t nl, int64_t t0, int64_t t1, Obs&& obs, Tail&& tail) {
+    const int lane = lane_id();
+    const int32_t start = tile_start[t0];
+    const int32_t end = tile_start[t1];
+    if (start >= end) return;
+    // raw loads of a chunk (camera word, observation, window entry)
+    struct Raw {
+        uint32_t w;
+        double ox, oy;
+        int32_t lw;
+    };
+    auto fetch = [&](int32_t base, int32_t seg_open, Raw& r) {
+        const int32_t i = min(base + lane, end - 1);  // lanes past the end read the last position
+        r.w = lo_cam[i];
+        r.ox = obs_lo[2 * int64_t(i)];
+        r.oy = obs_lo[2 * int64_t(i) + 1];
+        r.lw = nel[min(seg_open + 1 + lane, nl - 1)];
+    };
+    // a located chunk: its heads, each position's landmark and that landmark's position
+    struct Loc {
+        uint64_t hm;
+        int32_t l;
+        double X[3];
+    };
+    auto locate = [&](int32_t base, const Raw& r, int32_t l_prev, Loc& c) {
+        const bool head = base + lane < end && (r.w & kHeadBit);
+        c.hm = ballot64(head);
+        const int nh = __popcll(c.hm & mask_upto(lane));
+        const int32_t lk = __shfl(r.lw, nh > 0 ? nh - 1 : 0, kWave);
+        c.l = nh > 0 ? lk : l_prev;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) c.X[k] = lms[3 * int64_t(c.l) + k];
+    };
+    int32_t seg = seg_base[t0] - 1;  // segment open at the start of the current chunk
+    Raw rc, rn;
+    Loc cur;
+    fetch(start, seg, rc);
+    locate(start, rc, 0, cur);  // a range starts at a head: l_prev is never taken
+    const bool two = start + kWave < end;
+    if (two) fetch(start + kWave, seg + int32_t(__popcll(cur.hm)), rn);
+    double carry[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) carry[k] = 0.0;
+    for (int32_t base = start; base < end; base += kWave) {
+        const int32_t i = base + lane;
+        const bool valid = i < end;
+        const uint32_t wc = valid ? rc.w : 0u;
+        const int last = min(end - base, kWave) - 1;
+        const int32_t seg_next = seg + int32_t(__popcll(cur.hm));
+        // chunk c + 1: landmarks requested; chunk c + 2: raw loads requested
+        const bool more = base + kWave < end;
+        Loc nxt;
+        Raw rn2;
+        if (more) {
+            locate(base + kWave, rn, __shfl(cur.l, last, kWave), nxt);
+            if (base + 2 * kWave < end) fetch(base + 2 * kWave, seg_next + int32_t(__popcll(nxt.hm)), rn2);
+        }
+        double v[K];
+        obs(i, valid, int32_t(wc & kIndexMask), cur.X, rc.ox, rc.oy, v);
+        if (lane == 0 && !(wc & kHeadBit)) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] += carry[k];
+        }
+        const uint64_t hu = cur.hm & mask_upto(lane);
+        const int seg_start = hu ? 63 - __builtin_clzll(hu) : 0;
+        segmented_scan<double, K>(v, lane, seg_start);
+        if (wc & kTailBit) tail(seg + int32_t(__popcll(hu)), cur.l, v);
+#pragma unroll
+        for (int k = 0; k < K; ++k) carry[k] = __shfl(v[k], last, kWave);
+        seg = seg_next;
+        if (more) {
+            rc = rn;
+            cur = nxt;
+            rn = rn2;
+        }
+    }
+}
+
 // --------------------------------------------------------- block reductions --
 
 // Sum of K values over the block; the result is valid in thread 0.  lds holds

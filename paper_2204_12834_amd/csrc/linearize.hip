@@ -189,6 +189,10 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const do
     }
 }
 
+// Landmark-tile groups handled by one wavefront of the landmark-major
+// linearisation (one stream of chunks with three in flight).
+constexpr int kLinTilesPerWave = 4;
+
 // Landmark-major pass: evaluates every observation again from the per-camera
 // records (these stay in L2; gathering the camera-major records through the
 // permutation would read a whole line per 16 bytes), stores the landmark-major
@@ -199,23 +203,19 @@ template <typename TJ>
 __global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
                                                    double delta, const int32_t* gate) {
     if (gate && !*gate) return;
-    const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
-    if (tile >= z.ntiles) return;
-    tile_landmarks<double, 9>(
-        b.lo_cam, b.tile_start, b.seg_base, b.nel, z.nl, tile,
-        [&](int32_t i, bool valid, int32_t cam, int32_t, int32_t lmk, double* v) {
+    const int64_t t0 = (int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave) * kLinTilesPerWave;
+    if (t0 >= z.ntiles) return;
+    const int64_t t1 = min(t0 + kLinTilesPerWave, z.ntiles);
+    lm_tile_stream<9>(
+        b.lo_cam, b.tile_start, b.seg_base, b.nel, b.obs_lo, lms, z.nl, t0, t1,
+        [&](int32_t i, bool valid, int32_t cam, const double* X, double ox, double oy, double* v) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) v[k] = 0.0;
             if (!valid) return;
-            const int64_t l = lmk;
-            double X[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
             double a[3], c[3], rr[2];  // J_l rows 0 and 1 as stored, in float64
             if constexpr (!std::is_same<TJ, float>::value) {
                 ObsEval ev;
-                evaluate_obs_rec(b.lin_rec + kCamRec * int64_t(cam), X, b.obs_lo[2 * int64_t(i)],
-                                 b.obs_lo[2 * int64_t(i) + 1], ev);
+                evaluate_obs_rec(b.lin_rec + kCamRec * int64_t(cam), X, ox, oy, ev);
                 rr[0] = ev.r[0];
                 rr[1] = ev.r[1];
                 double w = 1.0;
@@ -237,8 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const dou
                 rr[1] *= sw;
             } else {
                 float J[24];
-                evaluate_obs_f32(b.lin_rec + kCamRec * int64_t(cam), X, b.obs_lo[2 * int64_t(i)],
-                                 b.obs_lo[2 * int64_t(i) + 1], rr, J);
+                evaluate_obs_f32(b.lin_rec + kCamRec * int64_t(cam), X, ox, oy, rr, J);
                 double w = 1.0;
                 if (loss == POBA_LOSS_HUBER) {
                     double rho;
@@ -366,20 +365,18 @@ template <typename TP>
 __global__ __launch_bounds__(kBlock) void k_lin_lm_pt(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
                                                       double delta, const int32_t* gate) {
     if (gate && !*gate) return;
-    const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
-    if (tile >= z.ntiles) return;
-    tile_landmarks<double, 9>(
-        b.lo_cam, b.tile_start, b.seg_base, b.nel, z.nl, tile,
-        [&](int32_t i, bool valid, int32_t cam, int32_t, int32_t lmk, double* v) {
+    const int64_t t0 = (int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave) * kLinTilesPerWave;
+    if (t0 >= z.ntiles) return;
+    const int64_t t1 = min(t0 + kLinTilesPerWave, z.ntiles);
+    lm_tile_stream<9>(
+        b.lo_cam, b.tile_start, b.seg_base, b.nel, b.obs_lo, lms, z.nl, t0, t1,
+        [&](int32_t i, bool valid, int32_t cam, const double* X, double ox, double oy, double* v) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) v[k] = 0.0;
             if (!valid) return;
-            const int64_t l = lmk;
             const double* rec = b.lin_rec + kCamRec * int64_t(cam);
-            double X[3], P[3], r[2];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
-            camera_point(rec, X, b.obs_lo[2 * int64_t(i)], b.obs_lo[2 * int64_t(i) + 1], P, r);
+            double P[3], r[2];
+            camera_point(rec, X, ox, oy, P, r);
             double w = 1.0;
             if (loss == POBA_LOSS_HUBER) {
                 double rho;
@@ -470,7 +467,7 @@ poba_status launch_linearize_t(Problem* p, const double* cams, const double* lms
     hipLaunchKernelGGL(k_cam_prep, dim3(unsigned(ceil_div(z.nc, kBlock))), dim3(kBlock), 0, s, z, cams, gate,
                        b.lin_rec);
     const unsigned ncb = unsigned(std::max<int64_t>(p->sched_len, 1));
-    const dim3 g_tiles(unsigned(ceil_div(z.ntiles, kWavesPerBlock)));
+    const dim3 g_tiles(unsigned(ceil_div(z.ntiles, int64_t(kWavesPerBlock) * kLinTilesPerWave)));
     bool done = false;
     if constexpr (!std::is_same<TJ, bf16_t>::value) {
         if (z.point) {
