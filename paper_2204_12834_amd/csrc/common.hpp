@@ -254,6 +254,20 @@ __device__ __forceinline__ T dpp(T v) {
     else return dpp_f32<CTRL, ROW_MASK>(v);
 }
 
+// The same exchange for callers that never read the lanes the control does
+// not write (their value is unspecified): no register has to be cleared first.
+template <int CTRL, int ROW_MASK, typename T>
+__device__ __forceinline__ T dpp_masked(T v) {
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const int lo = __builtin_amdgcn_mov_dpp(int(uint32_t(u)), CTRL, ROW_MASK, 0xf, false);
+        const int hi = __builtin_amdgcn_mov_dpp(int(uint32_t(u >> 32)), CTRL, ROW_MASK, 0xf, false);
+        return __builtin_bit_cast(double, (uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, false));
+    }
+}
+
 // Inclusive segmented scan over the wave.  seg_start is the first lane of the
 // calling lane's segment; after the call v[k] holds the sum of v[k] over
 // lanes seg_start..lane.  Within each row of 16 lanes the scan shifts by 1,
@@ -268,7 +282,7 @@ __device__ __forceinline__ void segmented_scan(T* v, int lane, int seg_start) {
     {                                                                      \
         const bool take = rl >= D && lane - D >= seg_start;                \
         _Pragma("unroll") for (int k = 0; k < K; ++k) {                    \
-            const T y = dpp<0x110 | D, 0xf>(v[k]);                         \
+            const T y = dpp_masked<0x110 | D, 0xf>(v[k]);                  \
             if (take) v[k] += y;                                           \
         }                                                                  \
     }
@@ -282,7 +296,7 @@ __device__ __forceinline__ void segmented_scan(T* v, int lane, int seg_start) {
         const bool take = (row == 1 && seg_start <= 15) || (row == 3 && seg_start <= 47);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const T y = dpp<0x142, 0xa>(v[k]);
+            const T y = dpp_masked<0x142, 0xa>(v[k]);
             if (take) v[k] += y;
         }
     }
@@ -290,7 +304,7 @@ __device__ __forceinline__ void segmented_scan(T* v, int lane, int seg_start) {
         const bool take = row >= 2 && seg_start <= 31;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const T y = dpp<0x143, 0xc>(v[k]);
+            const T y = dpp_masked<0x143, 0xc>(v[k]);
             if (take) v[k] += y;
         }
     }

@@ -44,6 +44,9 @@ def test_lm_trajectory_f64(name, records):
     for g, o in zip(trace, ref.iterations):
         assert abs(g["cost"] - (o.cost_new if o.accepted else o.cost)) <= 1e-9 * o.cost
         assert abs(g["cost_new"] - o.cost_new) <= 1e-9 * o.cost_new
+        # the oracle sums r_i.e_i + |e_i|^2/2 per observation; stored blocks
+        # take sum_i r_i.e_i as g.dx with g = (b_p, b_l)
+        assert abs(g["model_decrease"] - o.model_decrease) <= 1e-8 * abs(o.model_decrease)
         if abs(o.gain - opts.eta) > 1e-6:
             assert g["accepted"] == int(o.accepted)
         assert g["stop_order"] == o.stop_order
