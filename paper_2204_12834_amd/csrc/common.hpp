@@ -227,6 +227,11 @@ __device__ __forceinline__ double round_point(double v) { return double(TP(v)); 
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Index of the calling wavefront in its workgroup, as a wave-uniform value
+// (scalar register), so that per-wavefront records, loop bounds and cursors
+// derived from it stay scalar.
+__device__ __forceinline__ int wave_in_block() { return __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave); }
+
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 
 // Mask of lanes 0..lane inclusive.

@@ -203,7 +203,7 @@ template <typename TJ>
 __global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
                                                    double delta, const int32_t* gate) {
     if (gate && !*gate) return;
-    const int64_t t0 = (int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave) * kLinTilesPerWave;
+    const int64_t t0 = (int64_t(blockIdx.x) * kWavesPerBlock + wave_in_block()) * kLinTilesPerWave;
     if (t0 >= z.ntiles) return;
     const int64_t t1 = min(t0 + kLinTilesPerWave, z.ntiles);
     lm_tile_stream<9>(
@@ -365,7 +365,7 @@ template <typename TP>
 __global__ __launch_bounds__(kBlock) void k_lin_lm_pt(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
                                                       double delta, const int32_t* gate) {
     if (gate && !*gate) return;
-    const int64_t t0 = (int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave) * kLinTilesPerWave;
+    const int64_t t0 = (int64_t(blockIdx.x) * kWavesPerBlock + wave_in_block()) * kLinTilesPerWave;
     if (t0 >= z.ntiles) return;
     const int64_t t1 = min(t0 + kLinTilesPerWave, z.ntiles);
     lm_tile_stream<9>(

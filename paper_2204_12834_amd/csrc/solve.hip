@@ -267,7 +267,7 @@ __device__ __forceinline__ void load_cam_vec_lds(const TS* cv, int64_t cam, TS* 
 template <typename TJ, typename TC, typename TS, typename Tail>
 __global__ __launch_bounds__(kBlock) void k_lm_pass(Buffers b, Sizes z, int tpw, Tail tail, const Ctrl* ctrl) {
     if (Tail::skip(ctrl)) return;
-    const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + wave_in_block();
     const int64_t t0 = wave * tpw;
     if (t0 >= z.ntiles) return;
     const int64_t t1 = min(t0 + int64_t(tpw), z.ntiles);
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_lm_pass_lds(Buffers b, Sizes z, int6
         }
     }
     __syncthreads();
-    const int64_t t0 = (int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave) * per;
+    const int64_t t0 = (int64_t(blockIdx.x) * kWavesPerBlock + wave_in_block()) * per;
     if (t0 >= z.ntiles) return;
     lm_pass_range<TJ, TC, TS, true>(b, z, t0, min(t0 + per, z.ntiles), cv, tail);
 }
@@ -523,7 +523,7 @@ template <typename TJ>
 __global__ __launch_bounds__(kBlock) void k_backsub_pt(Buffers b, Sizes z, double* __restrict__ dxl,
                                                        const Ctrl* ctrl) {
     if (!ctrl->active) return;
-    const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + wave_in_block();
     if (tile >= z.ntiles) return;
     tile_landmarks<double, 3, kLookupLate>(
         b.lo_cam, b.tile_start, b.seg_base, b.nel, z.nl, tile,
@@ -950,7 +950,7 @@ __global__ __launch_bounds__(kPtBlock) void k_lm_pass_pt_lds(Buffers b, Sizes z,
         for (int64_t k = threadIdx.x; k < n; k += kPtBlock) dst[k] = src[k];
     }
     __syncthreads();
-    const int64_t wave = int64_t(blockIdx.x) * (kPtBlock / kWave) + threadIdx.x / kWave;
+    const int64_t wave = int64_t(blockIdx.x) * (kPtBlock / kWave) + wave_in_block();
     const int64_t t0 = wave * tiles_per_wave;
     if (t0 >= z.ntiles) return;
     lm_pass_stream_pt<TP, TC, TS>(b, z, t0, min(t0 + tiles_per_wave, z.ntiles), cf, sout);
@@ -961,7 +961,7 @@ template <typename TP, typename TC, typename TS>
 __global__ __launch_bounds__(kBlock) void k_lm_pass_pt(Buffers b, Sizes z, int64_t tiles_per_wave,
                                                        TS* __restrict__ sout, const Ctrl* ctrl) {
     if (ctrl->running == 0) return;
-    const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + wave_in_block();
     const int64_t t0 = wave * tiles_per_wave;
     if (t0 >= z.ntiles) return;
     lm_pass_stream_pt<TP, TC, TS>(b, z, t0, min(t0 + tiles_per_wave, z.ntiles), reinterpret_cast<const TS*>(b.vq),
@@ -1132,7 +1132,10 @@ __global__ __launch_bounds__(NW * kWave) void k_cam_pass_range(Buffers b, Sizes 
     extern __shared__ unsigned char lds_raw[];
     if (ctrl->running == 0) return;
     TS* ls = reinterpret_cast<TS*>(lds_raw);  // [3][spr]
-    const int4 wr = b.cw_rec[int64_t(blockIdx.x) * NW + threadIdx.x / kWave];
+    // the wavefront's record: uniform values, kept in scalar registers so
+    // that the window and batch cursors below are scalar too
+    const int wave = wave_in_block();
+    const int4 wr = b.cw_rec[int64_t(blockIdx.x) * NW + wave];
     const int32_t r = b.cw_rec[int64_t(blockIdx.x) * NW].x;
     const int64_t seg0 = int64_t(r) * spr;
     const int32_t nloc = int32_t(max<int64_t>(0, min<int64_t>(seg0 + spr, nseg) - seg0));
@@ -1308,7 +1311,7 @@ template <typename TS>
 __global__ __launch_bounds__(kBlock) void k_cam_fin_range(Buffers b, Sizes z, int32_t R, const Ctrl* ctrl) {
     if (ctrl->running == 0) return;
     const int lane = lane_id();
-    const int32_t c = blockIdx.x * kFinRangeCams + threadIdx.x / kWave;
+    const int32_t c = blockIdx.x * kFinRangeCams + wave_in_block();
     if (c >= z.nc) return;
     // every load that does not depend on the problem's state is issued before
     // its check, so the camera's data arrive in one round trip
@@ -1585,7 +1588,7 @@ template <typename TJ, bool PT>
 __global__ __launch_bounds__(kBlock) void k_lm_apply64(Buffers b, Sizes z, const double* __restrict__ x,
                                                        const Ctrl* ctrl) {
     if (!ctrl->active) return;
-    const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t tile = int64_t(blockIdx.x) * kWavesPerBlock + wave_in_block();
     if (tile >= z.ntiles) return;
     tile_landmarks<double, 3, kLookupTail>(
         b.lo_cam, b.tile_start, b.seg_base, b.nel, z.nl, tile,
