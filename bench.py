@@ -16,6 +16,12 @@ times come from HIP events that the library records around every launch in
 a second run of the same K steps (those events add gaps between kernels, so
 they stay out of the step time).
 
+The main line runs on point records (the camera-frame point and IRLS weight
+per observation, from which every pass rebuilds the Jacobian blocks), the
+faster of the two record kinds per LM iteration; the same step over stored
+Jacobian blocks is measured beside it (`stored_blocks`).  bfloat16 storage
+exists for Jacobian blocks only, so `--precision bf16` runs stored blocks.
+
 Printed JSON line: `value` is the series throughput in GB/s (algorithmic
 bytes of the m series orders divided by their kernel time); `roofline`
 refers to the dominant kernel; `cpu_baseline` is the float64 oracle's series
@@ -922,8 +928,10 @@ def main():
                     help="c3 (default), c2, c3s, c4, c5, or bal:PATH for a problem in the BAL text format")
     ap.add_argument("--huber", type=float, default=0.0, help="Huber delta in pixels for a bal: workload (0: squared loss)")
     ap.add_argument("--precision", default="f32", choices=["f64", "f32", "bf16"])
-    ap.add_argument("--records", default="jacobian", choices=["jacobian", "point"],
-                    help="per-observation records: Jacobian blocks, or camera-frame points the passes rebuild them from")
+    ap.add_argument("--records", default=None, choices=["jacobian", "point"],
+                    help="per-observation records: Jacobian blocks, or camera-frame points the passes rebuild them "
+                         "from (default: point records for the main line, Jacobian blocks for bf16 and for the "
+                         "other modes)")
     ap.add_argument("--m", type=int, default=32)
     ap.add_argument("--sample-lms", type=int, default=600000,
                     help="landmarks of the scene the CPU oracle's series runs on (about 10-20 s of CPU work)")
@@ -935,7 +943,10 @@ def main():
     ap.add_argument("--sweep-tpw", default="", help="comma list: time the series for each and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tau", action="store_true", help="skip the time-to-tolerance LM runs")
-    ap.add_argument("--no-point", action="store_true", help="skip the point-record measurements")
+    ap.add_argument("--no-alt", action="store_true",
+                    help="main line: skip the same step with the other record kind")
+    ap.add_argument("--no-point", action="store_true",
+                    help="skip the point-record runs of the time-to-tolerance part (implies --no-alt)")
     ap.add_argument("--pcg", action="store_true",
                     help="compare CG on the reduced camera system (Schur-Jacobi and power-series "
                          "preconditioners) with the power series at the first LM points, and exit")
@@ -958,6 +969,12 @@ def main():
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--oracle-lm-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.records is None:
+        main_line = not (args.tau_only or args.workload in ("c4", "c5") or args.pcg or args.post
+                         or args.sweep_tpw or args.cpu_baseline_child or args.oracle_lm_child)
+        args.records = "point" if main_line and args.precision != "bf16" else "jacobian"
+    if args.no_point:
+        args.no_alt = True
 
     if args.cpu_baseline_child:
         cpu_baseline_child(args.workload, args.m, args.sample_lms, args.huber, args.precision, args.records)
@@ -1022,10 +1039,11 @@ def main():
     torch.cuda.empty_cache()
 
     alt = None
-    if args.records == "jacobian" and args.precision != "bf16" and not args.no_point:
-        # the same step with point records (blocks rebuilt in every pass)
-        p2, c2, l2, _ = gpu_setup(scene, delta, args.precision, dev, "point")
-        alt = measure_steps(p2, c2, l2, scene, args, args.precision, "point")
+    other = "jacobian" if args.records == "point" else ("point" if args.precision != "bf16" else None)
+    if other is not None and not args.no_alt:
+        # the same step with the other record kind
+        p2, c2, l2, _ = gpu_setup(scene, delta, args.precision, dev, other)
+        alt = measure_steps(p2, c2, l2, scene, args, args.precision, other)
         alt.pop("prof")
         del p2
         torch.cuda.empty_cache()
@@ -1037,7 +1055,7 @@ def main():
     if not args.no_tau:
         extra = tau_runs(args, scene, delta, dev)
     if alt is not None:
-        extra["point_records"] = alt
+        extra["stored_blocks" if other == "jacobian" else "point_records"] = alt
 
     cpu = None
     if not args.no_cpu_baseline:

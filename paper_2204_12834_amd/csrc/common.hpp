@@ -423,7 +423,8 @@ struct Buffers {
     double* ybl;          // [nseg][4] V^-1 b_l in float64 and 1 (0 for a landmark of an inactive problem)
     void* s;              // [nseg][4] storage type (landmark vector of the series), by segment
     double* v;            // [nc][9] current series term
-    void* vq;             // [nc][12] current term in storage type (gather copy)
+    void* vq;             // [nc][12] current term in storage type (gather copy), or its folded camera data
+                          // at stride kFoldStride (point records)
     double* x;            // [nc][9] series sum
     double* bt;           // [nc][9] reduced right-hand side b~ of the last solve
     double* part;         // [npieces_max][54] per-piece partial sums
@@ -436,7 +437,7 @@ struct Buffers {
     double* lm_trial;     // [nl][8] trial landmark x + dx_l (0..2) and its step dx_l (3..5), one 64-byte line
     double* piece_red;    // [npieces_max][3] per-piece partial sums (cost, model, flags)
     double* cam_red;      // [nc][2] per-camera squared norms of v and x
-    double* xq;           // [nc][24] folded camera data of the camera step (point-record back-substitution),
+    double* xq;           // [nc][kFoldStride] folded camera data of the camera step (point-record back-substitution),
                           // or the camera step at stride 12 (Jacobian-record back-substitution)
     double* cg;           // [5][nc][9] conjugate-gradient vectors x, r, z, p, q
     double* sj;           // [nc][81] inverted diagonal blocks of S (Schur-Jacobi preconditioner)

@@ -30,6 +30,12 @@ struct Rec {
 
 // Per-camera data of the point-record landmark pass for the camera vector v
 // (24 slots): a = J_l(w) v_w, e = v_t - a x t, v_intrinsics, f, k1, k2, R.
+// Cameras are kFoldStride values apart: 28 floats (112 bytes) or 26 doubles
+// (208 bytes), 4 x an odd number of 4-byte words, so that the 16-byte LDS
+// reads of lanes with different cameras start on all the banks that a
+// 16-byte access can start on (with 24 values only a quarter or half of them).
+template <typename TS>
+constexpr int kFoldStride = sizeof(TS) == 4 ? 28 : 26;
 // With them J_p v = J_P (a x P + e) + p (d v_f + f n v_k1 + f n^2 v_k2).
 template <typename TS>
 __device__ __forceinline__ void fold_camera(const double* rec, const double* v, TS* out) {

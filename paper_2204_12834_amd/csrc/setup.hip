@@ -122,7 +122,7 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.ybl = (double*)take(nl * 4 * 8);
     t.s = take(nl * 4 * 8);  // also holds float64 landmark vectors
     t.v = (double*)take(nc * 9 * 8);
-    t.vq = take(nc * 24 * 8);  // camera vector (stride 12), or folded camera records (stride 24)
+    t.vq = take(nc * 28 * 8);  // camera vector (stride 12), or folded camera records (stride kFoldStride)
     t.x = (double*)take(nc * 9 * 8);
     t.bt = (double*)take(nc * 9 * 8);
     t.part = (double*)take(size_t(z.npieces_max) * 54 * 8);
@@ -135,7 +135,7 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.lm_trial = (double*)take(nl * 8 * 8);
     t.piece_red = (double*)take(size_t(z.npieces_max) * 3 * 8);
     t.cam_red = (double*)take(nc * 2 * 8);
-    t.xq = (double*)take(nc * 24 * 8);
+    t.xq = (double*)take(nc * 28 * 8);
     t.cg = (double*)take(5 * nc * 9 * 8);
     t.sj = (double*)take(nc * 81 * 8);
     const size_t np1 = size_t(z.np) + 1;

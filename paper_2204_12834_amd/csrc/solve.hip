@@ -13,6 +13,7 @@
 // Both passes are segmented reductions inside a wavefront or block; camera
 // pieces are combined in a fixed order; no floating-point atomics are used.
 #include <type_traits>
+#include <utility>
 
 #include "device_ops.hpp"
 #include "kernels.hpp"
@@ -453,7 +454,7 @@ void launch_lm_pass(Problem* p, hipStream_t s) {
 template <typename TS, typename TC>
 __device__ __forceinline__ void load_fold(const TS* src, int64_t cam, TC* c) {
     if constexpr (std::is_same<TS, float>::value) {
-        const float4* q = reinterpret_cast<const float4*>(src + 24 * cam);
+        const float4* q = reinterpret_cast<const float4*>(src + kFoldStride<TS> * cam);
 #pragma unroll
         for (int g = 0; g < 6; ++g) {
             const float4 x = q[g];
@@ -463,7 +464,7 @@ __device__ __forceinline__ void load_fold(const TS* src, int64_t cam, TC* c) {
             c[4 * g + 3] = TC(x.w);
         }
     } else {
-        const double2* q = reinterpret_cast<const double2*>(src + 24 * cam);
+        const double2* q = reinterpret_cast<const double2*>(src + kFoldStride<TS> * cam);
 #pragma unroll
         for (int g = 0; g < 12; ++g) {
             const double2 x = q[g];
@@ -502,7 +503,7 @@ __global__ __launch_bounds__(kBlock) void k_fold_x(Buffers b, Sizes z, const dou
     if (!ctrl->active) return;
     const int32_t c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= z.nc) return;
-    fold_camera<double>(b.lin_rec + kCamRec * int64_t(c), x + 9 * int64_t(c), b.xq + 24 * int64_t(c));
+    fold_camera<double>(b.lin_rec + kCamRec * int64_t(c), x + 9 * int64_t(c), b.xq + kFoldStride<double> * int64_t(c));
 }
 
 // The camera step x (float64) in the landmark stream's camera-vector layout
@@ -734,7 +735,7 @@ __global__ __launch_bounds__(kBlock) void k_cam_fin(Buffers b, Sizes z, int mode
         }
         b.cam_red[2 * int64_t(c)] = sv;
         b.cam_red[2 * int64_t(c) + 1] = sx;
-        if (FOLD) fold_camera<TS>(b.lin_rec + kCamRec * int64_t(c), vs[lc], reinterpret_cast<TS*>(b.vq) + 24 * int64_t(c));
+        if (FOLD) fold_camera<TS>(b.lin_rec + kCamRec * int64_t(c), vs[lc], reinterpret_cast<TS*>(b.vq) + kFoldStride<TS> * int64_t(c));
     }
 }
 
@@ -811,7 +812,7 @@ __global__ __launch_bounds__(kBlock) void k_load_v(Buffers b, Sizes z, const dou
         double v[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) v[k] = vin[9 * int64_t(c) + k];
-        fold_camera<TS>(b.lin_rec + kCamRec * int64_t(c), v, reinterpret_cast<TS*>(b.vq) + 24 * int64_t(c));
+        fold_camera<TS>(b.lin_rec + kCamRec * int64_t(c), v, reinterpret_cast<TS*>(b.vq) + kFoldStride<TS> * int64_t(c));
         return;
     }
     TS* vq = reinterpret_cast<TS*>(b.vq) + 12 * int64_t(c);
@@ -946,7 +947,7 @@ __global__ __launch_bounds__(kPtBlock) void k_lm_pass_pt_lds(Buffers b, Sizes z,
         // flight per thread (this kernel has no registers to spare for more)
         const uint4* __restrict__ src = reinterpret_cast<const uint4*>(b.vq);
         uint4* dst = reinterpret_cast<uint4*>(lds_raw);
-        const int64_t n = int64_t(z.nc) * 24 * int64_t(sizeof(TS)) / 16;
+        const int64_t n = int64_t(z.nc) * kFoldStride<TS> * int64_t(sizeof(TS)) / 16;
         for (int64_t k = threadIdx.x; k < n; k += kPtBlock) dst[k] = src[k];
     }
     __syncthreads();
@@ -972,7 +973,7 @@ template <typename TP, typename TC, typename TS>
 void launch_lm_pass_pt(Problem* p, hipStream_t s) {
     const Buffers& b = p->b;
     const Sizes& z = p->z;
-    const size_t lds = size_t(z.nc) * 24 * sizeof(TS);
+    const size_t lds = size_t(z.nc) * kFoldStride<TS> * sizeof(TS);
     TS* sout = reinterpret_cast<TS*>(b.s);
     if (p->lds_cam && lds <= size_t(p->lds_max)) {
         // one block per compute unit; the tiles are split evenly over all wavefronts
@@ -1121,6 +1122,13 @@ __global__ __launch_bounds__(NT) void k_cam_pass_pt(Buffers b, Sizes z, const TS
 // 8: fewer idle lanes in each batch's longest group.
 constexpr int kSetLanes = 16;
 constexpr int kSets = kWave / kSetLanes;  // groups per batch
+constexpr int kRangeRing = 3;             // steps in flight (records of step t + 2 requested at step t)
+
+// f(integral_constant<int, k>) for k in the sequence, unrolled.
+template <typename F, int... k>
+__device__ __forceinline__ void unrolled(F&& f, std::integer_sequence<int, k...>) {
+    (f(std::integral_constant<int, k>{}), ...);
+}
 static_assert(kSetLanes == 16, "a set is one DPP row");
 
 template <typename TS, typename TC>
@@ -1282,26 +1290,22 @@ __global__ __launch_bounds__(NW * kWave) void k_cam_pass_range(Buffers b, Sizes 
             }
             advance(bc, ic);
         };
-        Slot o[3];
+        Slot o[kRangeRing];
         auto step = [&](auto U) {
             constexpr int u = decltype(U)::value;
-            issue(o[(u + 2) % 3]);
-            gather(o[(u + 1) % 3]);
+            issue(o[(u + kRangeRing - 1) % kRangeRing]);
+            gather(o[(u + 1) % kRangeRing]);
             add(o[u]);
         };
-        issue(o[0]);
-        issue(o[1]);
+        unrolled([&](auto K) { issue(o[decltype(K)::value]); }, std::make_integer_sequence<int, kRangeRing - 1>{});
         gather(o[0]);
-        // whole rounds of three steps, then the rest: no path re-enters the
-        // loop with a slot's load unconsumed, so no wait drains the ring
+        // whole rounds of kRangeRing steps, then the rest: no path re-enters
+        // the loop with a slot's load unconsumed, so no wait drains the ring
         int32_t t = 0;
-        for (; t + 3 <= T; t += 3) {
-            step(std::integral_constant<int, 0>{});
-            step(std::integral_constant<int, 1>{});
-            step(std::integral_constant<int, 2>{});
-        }
-        if (t < T) step(std::integral_constant<int, 0>{});
-        if (t + 1 < T) step(std::integral_constant<int, 1>{});
+        for (; t + kRangeRing <= T; t += kRangeRing) unrolled(step, std::make_integer_sequence<int, kRangeRing>{});
+        unrolled([&](auto K) {
+            if (t + decltype(K)::value < T) step(K);
+        }, std::make_integer_sequence<int, kRangeRing - 1>{});
     }
 }
 
@@ -1384,7 +1388,7 @@ __global__ __launch_bounds__(kBlock) void k_cam_fin_range(Buffers b, Sizes z, in
     if (lane == 0) {
         b.cam_red[2 * int64_t(c)] = sv;
         b.cam_red[2 * int64_t(c) + 1] = sx;
-        fold_camera<TS>(rec, vs, reinterpret_cast<TS*>(b.vq) + 24 * int64_t(c));
+        fold_camera<TS>(rec, vs, reinterpret_cast<TS*>(b.vq) + kFoldStride<TS> * int64_t(c));
     }
 }
 
