@@ -429,31 +429,29 @@ __global__ __launch_bounds__(kBlock) void k_cost_final(Buffers b, const int32_t*
     }
 }
 
-// Sums each camera's pieces into the full symmetric U (81) and b_p (9).
+// Sums each camera's pieces into the full symmetric U (81) and b_p (9): one
+// wavefront per camera, lane k < 54 adding partial entry k over the camera's
+// pieces in piece order.
 __global__ __launch_bounds__(kBlock) void k_lin_cam_fin(Buffers b, Sizes z, const int32_t* gate) {
     if (gate && !*gate) return;
-    const int32_t c = blockIdx.x * kBlock + threadIdx.x;
-    if (c >= z.nc) return;
-    double acc[54];
-#pragma unroll
-    for (int k = 0; k < 54; ++k) acc[k] = 0.0;
-    for (int32_t p = b.cam_piece[c]; p < b.cam_piece[c + 1]; ++p) {
-#pragma unroll
-        for (int k = 0; k < 54; ++k) acc[k] += b.part[54 * int64_t(p) + k];
+    const int32_t c = blockIdx.x * kWavesPerBlock + wave_in_block();
+    const int k = lane_id();
+    if (c >= z.nc || k >= 54) return;
+    double acc = 0.0;
+    for (int32_t p = b.cam_piece[c]; p < b.cam_piece[c + 1]; ++p) acc += b.part[54 * int64_t(p) + k];
+    if (k >= 45) {
+        b.bp[9 * int64_t(c) + (k - 45)] = acc;
+        return;
     }
+    int e = k, r = 0;
+    while (e >= 9 - r) {
+        e -= 9 - r;
+        ++r;
+    }
+    const int cc = r + e;
     double* U = b.U + 81 * int64_t(c);
-    int idx = 0;
-#pragma unroll
-    for (int r = 0; r < 9; ++r) {
-#pragma unroll
-        for (int cc = r; cc < 9; ++cc) {
-            U[9 * r + cc] = acc[idx];
-            U[9 * cc + r] = acc[idx];
-            ++idx;
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < 9; ++r) b.bp[9 * int64_t(c) + r] = acc[45 + r];
+    U[9 * r + cc] = acc;
+    U[9 * cc + r] = acc;
 }
 
 template <typename TJ>
@@ -485,7 +483,7 @@ poba_status launch_linearize_t(Problem* p, const double* cams, const double* lms
         hipLaunchKernelGGL(k_cost_final, dim3(unsigned(z.np)), dim3(kBlock), 0, s, b, gate, cost_out, st);
         hipLaunchKernelGGL(k_lin_lm<TJ>, g_tiles, dim3(kBlock), 0, s, b, z, lms, loss, delta, gate);
     }
-    hipLaunchKernelGGL(k_lin_cam_fin, dim3(unsigned(ceil_div(z.nc, kBlock))), dim3(kBlock), 0, s, b, z, gate);
+    hipLaunchKernelGGL(k_lin_cam_fin, dim3(unsigned(ceil_div(z.nc, kWavesPerBlock))), dim3(kBlock), 0, s, b, z, gate);
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
 }
 
