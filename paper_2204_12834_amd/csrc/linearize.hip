@@ -193,29 +193,76 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const do
 // linearisation (one stream of chunks with three in flight).
 constexpr int kLinTilesPerWave = 4;
 
+// Camera records of the landmark-major linearisation staged in LDS: the
+// fields its kernels read (R, t, f, k1, k2 in float64; w, B and E only as
+// float32 values, which is how the float32 blocks use them and what the
+// float64 J_l of point records does not use), 144 bytes per camera (4 x an
+// odd number of 4-byte words, so that lanes with different cameras spread
+// over the banks).  Up to 1,137 cameras fit in 160 KB.
+struct __attribute__((aligned(16))) LinLdsCam {
+    double R[9], t[3], fk[3];
+    float w[3], B, E, pad;
+};
+static_assert(sizeof(LinLdsCam) == 144, "144-byte camera slots");
+constexpr int kLinLdsBlock = 1024;  // one workgroup of 16 wavefronts per compute unit
+
+__device__ __forceinline__ void stage_lin_cams(const double* __restrict__ lin_rec, int32_t nc, LinLdsCam* cams) {
+    for (int32_t c = threadIdx.x; c < nc; c += blockDim.x) {
+        const double* r = lin_rec + kCamRec * int64_t(c);
+        LinLdsCam x;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) x.R[k] = r[13 + k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            x.t[k] = r[3 + k];
+            x.fk[k] = r[6 + k];
+            x.w[k] = float(r[k]);
+        }
+        x.B = float(r[10]);
+        x.E = float(r[22]);
+        x.pad = 0.0f;
+        cams[c] = x;
+    }
+}
+
+// The staged fields at their places in a camera record (the others are not
+// read by the landmark-major linearisation).
+__device__ __forceinline__ const double* lin_cam_from_lds(const LinLdsCam& x, double* rec) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) rec[13 + k] = x.R[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        rec[3 + k] = x.t[k];
+        rec[6 + k] = x.fk[k];
+        rec[k] = double(x.w[k]);
+    }
+    rec[10] = double(x.B);
+    rec[22] = double(x.E);
+    return rec;
+}
+
 // Landmark-major pass: evaluates every observation again from the per-camera
-// records (these stay in L2; gathering the camera-major records through the
-// permutation would read a whole line per 16 bytes), stores the landmark-major
-// records and reduces V = J_l^T J_l (6) and b_l = J_l^T r (3) per landmark
-// segment in float64.  The same contraction-free arithmetic as the
-// camera-major pass gives bit-identical blocks.
-template <typename TJ>
-__global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
-                                                   double delta, const int32_t* gate) {
-    if (gate && !*gate) return;
-    const int64_t t0 = (int64_t(blockIdx.x) * kWavesPerBlock + wave_in_block()) * kLinTilesPerWave;
-    if (t0 >= z.ntiles) return;
-    const int64_t t1 = min(t0 + kLinTilesPerWave, z.ntiles);
+// records (from L2, or staged in LDS where they fit; gathering the
+// camera-major records through the permutation would read a whole line per
+// 16 bytes), stores the landmark-major records and reduces V = J_l^T J_l (6)
+// and b_l = J_l^T r (3) per landmark segment in float64.  The same
+// contraction-free arithmetic as the camera-major pass gives bit-identical
+// blocks.  camrec(cam, tmp) returns camera cam's record (tmp: room for a copy).
+template <typename TJ, typename CamRec>
+__device__ __forceinline__ void lin_lm_tiles(const Buffers& b, const Sizes& z, const double* __restrict__ lms, int loss,
+                                             double delta, int64_t t0, int64_t t1, CamRec&& camrec) {
     lm_tile_stream<9>(
         b.lo_cam, b.tile_start, b.seg_base, b.nel, b.obs_lo, lms, z.nl, t0, t1,
         [&](int32_t i, bool valid, int32_t cam, const double* X, double ox, double oy, double* v) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) v[k] = 0.0;
             if (!valid) return;
+            double tmp[kCamRec];
+            const double* rec = camrec(cam, tmp);
             double a[3], c[3], rr[2];  // J_l rows 0 and 1 as stored, in float64
             if constexpr (!std::is_same<TJ, float>::value) {
                 ObsEval ev;
-                evaluate_obs_rec(b.lin_rec + kCamRec * int64_t(cam), X, ox, oy, ev);
+                evaluate_obs_rec(rec, X, ox, oy, ev);
                 rr[0] = ev.r[0];
                 rr[1] = ev.r[1];
                 double w = 1.0;
@@ -237,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const dou
                 rr[1] *= sw;
             } else {
                 float J[24];
-                evaluate_obs_f32(b.lin_rec + kCamRec * int64_t(cam), X, ox, oy, rr, J);
+                evaluate_obs_f32(rec, X, ox, oy, rr, J);
                 double w = 1.0;
                 if (loss == POBA_LOSS_HUBER) {
                     double rho;
@@ -274,6 +321,35 @@ __global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const dou
 #pragma unroll
             for (int k = 0; k < 3; ++k) b.bl[3 * l + k] = v[6 + k];
         });
+}
+
+template <typename TJ>
+__global__ __launch_bounds__(kBlock) void k_lin_lm(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
+                                                   double delta, const int32_t* gate) {
+    if (gate && !*gate) return;
+    const int64_t t0 = (int64_t(blockIdx.x) * kWavesPerBlock + wave_in_block()) * kLinTilesPerWave;
+    if (t0 >= z.ntiles) return;
+    const int64_t t1 = min(t0 + kLinTilesPerWave, z.ntiles);
+    lin_lm_tiles<TJ>(b, z, lms, loss, delta, t0, t1,
+                     [&](int32_t cam, double*) { return b.lin_rec + kCamRec * int64_t(cam); });
+}
+
+// The same with the camera records staged in LDS (float32 blocks): one
+// workgroup per compute unit, every wavefront one contiguous range of `per`
+// tiles.
+template <typename TJ>
+__global__ __launch_bounds__(kLinLdsBlock) void k_lin_lm_lds(Buffers b, Sizes z, const double* __restrict__ lms,
+                                                            int loss, double delta, const int32_t* gate, int64_t per) {
+    extern __shared__ unsigned char lds_raw[];
+    if (gate && !*gate) return;
+    LinLdsCam* cams = reinterpret_cast<LinLdsCam*>(lds_raw);
+    stage_lin_cams(b.lin_rec, z.nc, cams);
+    __syncthreads();
+    const int64_t t0 = (int64_t(blockIdx.x) * (kLinLdsBlock / kWave) + wave_in_block()) * per;
+    if (t0 >= z.ntiles) return;
+    const int64_t t1 = min(t0 + per, z.ntiles);
+    lin_lm_tiles<TJ>(b, z, lms, loss, delta, t0, t1,
+                     [&](int32_t cam, double* tmp) { return lin_cam_from_lds(cams[cam], tmp); });
 }
 
 // Point records (camera-major pass): stores (P, sqrt(w)) rounded to TP and the
@@ -360,21 +436,18 @@ __global__ __launch_bounds__(kBlock) void k_lin_cam_pt(Buffers b, Sizes z, const
 
 // Point records (landmark-major pass): the same records in landmark-major
 // order (bit-identical to the camera-major ones) and V, b_l per landmark from
-// the rebuilt blocks.
-template <typename TP>
-__global__ __launch_bounds__(kBlock) void k_lin_lm_pt(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
-                                                      double delta, const int32_t* gate) {
-    if (gate && !*gate) return;
-    const int64_t t0 = (int64_t(blockIdx.x) * kWavesPerBlock + wave_in_block()) * kLinTilesPerWave;
-    if (t0 >= z.ntiles) return;
-    const int64_t t1 = min(t0 + kLinTilesPerWave, z.ntiles);
+// the rebuilt blocks (J_l = J_P R needs R, t, f, k1, k2 of the camera only).
+template <typename TP, typename CamRec>
+__device__ __forceinline__ void lin_lm_pt_tiles(const Buffers& b, const Sizes& z, const double* __restrict__ lms,
+                                                int loss, double delta, int64_t t0, int64_t t1, CamRec&& camrec) {
     lm_tile_stream<9>(
         b.lo_cam, b.tile_start, b.seg_base, b.nel, b.obs_lo, lms, z.nl, t0, t1,
         [&](int32_t i, bool valid, int32_t cam, const double* X, double ox, double oy, double* v) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) v[k] = 0.0;
             if (!valid) return;
-            const double* rec = b.lin_rec + kCamRec * int64_t(cam);
+            double tmp[kCamRec];
+            const double* rec = camrec(cam, tmp);
             double P[3], r[2];
             camera_point(rec, X, ox, oy, P, r);
             double w = 1.0;
@@ -407,6 +480,33 @@ __global__ __launch_bounds__(kBlock) void k_lin_lm_pt(Buffers b, Sizes z, const 
 #pragma unroll
             for (int k = 0; k < 3; ++k) b.bl[3 * l + k] = v[6 + k];
         });
+}
+
+template <typename TP>
+__global__ __launch_bounds__(kBlock) void k_lin_lm_pt(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
+                                                      double delta, const int32_t* gate) {
+    if (gate && !*gate) return;
+    const int64_t t0 = (int64_t(blockIdx.x) * kWavesPerBlock + wave_in_block()) * kLinTilesPerWave;
+    if (t0 >= z.ntiles) return;
+    const int64_t t1 = min(t0 + kLinTilesPerWave, z.ntiles);
+    lin_lm_pt_tiles<TP>(b, z, lms, loss, delta, t0, t1,
+                        [&](int32_t cam, double*) { return b.lin_rec + kCamRec * int64_t(cam); });
+}
+
+template <typename TP>
+__global__ __launch_bounds__(kLinLdsBlock) void k_lin_lm_pt_lds(Buffers b, Sizes z, const double* __restrict__ lms,
+                                                               int loss, double delta, const int32_t* gate,
+                                                               int64_t per) {
+    extern __shared__ unsigned char lds_raw[];
+    if (gate && !*gate) return;
+    LinLdsCam* cams = reinterpret_cast<LinLdsCam*>(lds_raw);
+    stage_lin_cams(b.lin_rec, z.nc, cams);
+    __syncthreads();
+    const int64_t t0 = (int64_t(blockIdx.x) * (kLinLdsBlock / kWave) + wave_in_block()) * per;
+    if (t0 >= z.ntiles) return;
+    const int64_t t1 = min(t0 + per, z.ntiles);
+    lin_lm_pt_tiles<TP>(b, z, lms, loss, delta, t0, t1,
+                        [&](int32_t cam, double* tmp) { return lin_cam_from_lds(cams[cam], tmp); });
 }
 
 // F of every problem: its pieces' partial costs in piece order (one block per
@@ -466,6 +566,14 @@ poba_status launch_linearize_t(Problem* p, const double* cams, const double* lms
                        b.lin_rec);
     const unsigned ncb = unsigned(std::max<int64_t>(p->sched_len, 1));
     const dim3 g_tiles(unsigned(ceil_div(z.ntiles, int64_t(kWavesPerBlock) * kLinTilesPerWave)));
+    // landmark-major kernels with the camera records staged in LDS (float32
+    // blocks and point records, where they fit): one workgroup per compute
+    // unit, the tiles split evenly over its wavefronts
+    const size_t lds_cams = size_t(z.nc) * sizeof(LinLdsCam);
+    const bool lm_lds = lds_cams <= size_t(p->lds_max);
+    const int64_t lds_waves = p->n_cus * (kLinLdsBlock / kWave);
+    const int64_t lds_per = std::max<int64_t>(1, ceil_div(z.ntiles, lds_waves));
+    const dim3 g_lds(unsigned(ceil_div(ceil_div(z.ntiles, lds_per), kLinLdsBlock / kWave)));
     bool done = false;
     if constexpr (!std::is_same<TJ, bf16_t>::value) {
         if (z.point) {
@@ -473,7 +581,11 @@ poba_status launch_linearize_t(Problem* p, const double* cams, const double* lms
             if (p->sched_len > 0)
                 hipLaunchKernelGGL(k_lin_cam_pt<TJ>, dim3(ncb), dim3(kBlock), 0, s, b, z, lms, loss, delta, gate);
             hipLaunchKernelGGL(k_cost_final, dim3(unsigned(z.np)), dim3(kBlock), 0, s, b, gate, cost_out, st);
-            hipLaunchKernelGGL(k_lin_lm_pt<TJ>, g_tiles, dim3(kBlock), 0, s, b, z, lms, loss, delta, gate);
+            if (lm_lds)
+                hipLaunchKernelGGL(k_lin_lm_pt_lds<TJ>, g_lds, dim3(kLinLdsBlock), lds_cams, s, b, z, lms, loss, delta,
+                                   gate, lds_per);
+            else
+                hipLaunchKernelGGL(k_lin_lm_pt<TJ>, g_tiles, dim3(kBlock), 0, s, b, z, lms, loss, delta, gate);
             done = true;
         }
     }
@@ -481,7 +593,16 @@ poba_status launch_linearize_t(Problem* p, const double* cams, const double* lms
         if (p->sched_len > 0)
             hipLaunchKernelGGL(k_lin_cam<TJ>, dim3(ncb), dim3(kBlock), 0, s, b, z, lms, loss, delta, gate);
         hipLaunchKernelGGL(k_cost_final, dim3(unsigned(z.np)), dim3(kBlock), 0, s, b, gate, cost_out, st);
-        hipLaunchKernelGGL(k_lin_lm<TJ>, g_tiles, dim3(kBlock), 0, s, b, z, lms, loss, delta, gate);
+        bool staged = false;
+        if constexpr (std::is_same<TJ, float>::value) {
+            // (float64 and bfloat16 blocks read more of the record than is staged)
+            if (lm_lds) {
+                hipLaunchKernelGGL(k_lin_lm_lds<TJ>, g_lds, dim3(kLinLdsBlock), lds_cams, s, b, z, lms, loss, delta,
+                                   gate, lds_per);
+                staged = true;
+            }
+        }
+        if (!staged) hipLaunchKernelGGL(k_lin_lm<TJ>, g_tiles, dim3(kBlock), 0, s, b, z, lms, loss, delta, gate);
     }
     hipLaunchKernelGGL(k_lin_cam_fin, dim3(unsigned(ceil_div(z.nc, kWavesPerBlock))), dim3(kBlock), 0, s, b, z, gate);
     return hipGetLastError() == hipSuccess ? POBA_OK : POBA_ERR_HIP;
