@@ -34,159 +34,140 @@ __global__ __launch_bounds__(kBlock) void k_cam_prep(Sizes z, const double* __re
     for (int k = 0; k < kCamRec; ++k) out[kCamRec * int64_t(c) + k] = rec[k];
 }
 
-// Camera-major pass, one block per camera piece (blocks dealt to the dies as
-// in the camera pass of the series, so the landmark gathers stay die-local).
-// Each observation is evaluated once here: residual, Huber weight, Jacobian
-// blocks; the records and the reweighted residual are stored camera-major and
-// the block's rounded J_p rows go through LDS, where 216 threads (54 entries
-// x 4 groups) accumulate the upper triangle of J_p^T J_p (45) and J_p^T r (9)
-// in float64.  The piece's partial cost goes to its slot of piece_red.
-// Gram accumulation on the matrix cores.  The block's observations are staged
-// in LDS as rows M[2 * kBlock][kGramCols]: per observation its two J_p rows
-// (9 scalars each, as stored) with the reweighted residual in column 9.
-// Wavefront w adds M_w^T M_w over its quarter of the rows into its 16 x 16
-// float64 accumulator, four rows per v_mfma_f64_16x16x4f64: lane l supplies
-// M[r + l / 16][l % 16] as both operands (zero past column 9 and past the
-// valid rows), so the product is M^T M.  Its entry (i, j) sits in lane
-// 16 (i % 4) + j, element i / 4 (or the transposed entry, the same value of
-// the symmetric product).  U is the leading 9 x 9 block and b_p column 9.
-constexpr int kGramCols = 10;
-typedef double gram_acc __attribute__((ext_vector_type(4)));
+// Camera-major pass, one wavefront per camera piece (pieces dealt to the dies
+// as in the camera pass of the series, so the landmark gathers stay
+// die-local).  Each observation is evaluated once here: residual, Huber
+// weight, Jacobian blocks; the records and the reweighted residual are stored
+// camera-major, and every lane adds its observations' rows [J_p row, r] (as
+// stored) to the upper triangle of J_p^T J_p (45) and to J_p^T r (9) in
+// float64 registers; at the end of the piece the wavefront adds its lanes
+// (and the cost) and the last lane writes the piece's partial slots.
+// The products of float32 (or bfloat16) values are exact in float64, so the
+// sums see the blocks as stored.  On this GPU the float64 matrix cores have
+// the vector units' peak, and a 10-column Gram product fills a fifth of a
+// 16 x 16 tile, so the vector units do this sum.
+constexpr int kGramEntries = 54;  // 45 of U (upper triangle, row-major) and 9 of b_p
 
-__device__ __forceinline__ gram_acc gram_rows(const double* M, int r0, int r1, int rows_valid, gram_acc c) {
-    const int lane = lane_id(), kk = lane / 16, col = lane % 16;
-    // two chains of products, added at the end, halve the dependent MFMA
-    // latency; eight rows per round
-    gram_acc d = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-    for (int r = r0; r < r1; r += 8) {
-        const int ra = r + kk, rb = r + 4 + kk;
-        const double xa = (col < kGramCols && ra < rows_valid) ? M[ra * kGramCols + col] : 0.0;
-        const double xb = (col < kGramCols && rb < rows_valid) ? M[rb * kGramCols + col] : 0.0;
-        c = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, xa, c, 0, 0, 0);
-        d = __builtin_amdgcn_mfma_f64_16x16x4f64(xb, xb, d, 0, 0, 0);
+// Adds the rank-one terms of one row (J_p row, residual) to the partial sums.
+__device__ __forceinline__ void gram_add(double* acc, const double* row, double r) {
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+#pragma unroll
+        for (int j = i; j < 9; ++j) {
+            acc[k] = fma(row[i], row[j], acc[k]);
+            ++k;
+        }
     }
-    return c + d;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) acc[45 + i] = fma(row[i], r, acc[45 + i]);
 }
 
-// The 45 upper-triangle entries of U and the 9 of b_p (in the order of the
-// per-piece partial slots) from the four wavefronts' accumulators staged in
-// red[4][64][4], added in wavefront order.
-__device__ __forceinline__ double gram_entry(const double (*red)[kWave][4], int ea, int eb) {
-    const int lane = 16 * (ea % 4) + eb, v = ea / 4;
-    return (red[0][lane][v] + red[1][lane][v]) + (red[2][lane][v] + red[3][lane][v]);
+// Sum of K values over the wavefront into its last lane (DPP shifts within
+// rows of 16, then row broadcasts; the other lanes' results are not used).
+template <int K>
+__device__ __forceinline__ void wave_total_last(double* v) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        v[k] += dpp_masked<0x111, 0xf>(v[k]);
+        v[k] += dpp_masked<0x112, 0xf>(v[k]);
+        v[k] += dpp_masked<0x114, 0xf>(v[k]);
+        v[k] += dpp_masked<0x118, 0xf>(v[k]);
+        v[k] += dpp_masked<0x142, 0xa>(v[k]);
+        v[k] += dpp_masked<0x143, 0xc>(v[k]);
+    }
+}
+
+// The piece's partial sums: acc (54), cost, non-finite flag.
+__device__ __forceinline__ void cam_piece_write(const Buffers& b, int32_t p, double* acc, double cost, double bad) {
+    double tot[kGramEntries + 2];
+#pragma unroll
+    for (int k = 0; k < kGramEntries; ++k) tot[k] = acc[k];
+    tot[kGramEntries] = cost;
+    tot[kGramEntries + 1] = bad;
+    wave_total_last<kGramEntries + 2>(tot);
+    if (lane_id() == kWave - 1) {
+#pragma unroll
+        for (int k = 0; k < kGramEntries; ++k) b.part[kGramEntries * int64_t(p) + k] = tot[k];
+        b.piece_red[3 * int64_t(p)] = tot[kGramEntries];
+        b.piece_red[3 * int64_t(p) + 1] = tot[kGramEntries + 1];
+    }
 }
 
 template <typename TJ>
-__global__ __launch_bounds__(kBlock) void k_lin_cam(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
-                                                    double delta, const int32_t* gate) {
-    __shared__ double M[2 * kBlock * kGramCols];
-    __shared__ double red[kWavesPerBlock][kWave][4];
-    __shared__ double lds[kWavesPerBlock * 2];
-    static_assert(kWavesPerBlock == 4, "four wavefronts share the rows");
+__global__ __launch_bounds__(kWave) void k_lin_cam(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
+                                                   double delta, const int32_t* gate) {
     if (gate && !*gate) return;
-    const int t = threadIdx.x;
-    const int wv = t / kWave;
-    const int ent = t;  // threads 0..53 write the partial entries
-    int ea = 0, eb = 0;
-    if (ent < 45) {
-        int e = ent, row = 0;
-        while (e >= 9 - row) {
-            e -= 9 - row;
-            ++row;
-        }
-        ea = row;
-        eb = row + e;
-    } else {
-        ea = ent - 45;  // b_p: column 9 of the Gram matrix
-        eb = kGramCols - 1;
-    }
-    gram_acc gacc = {0.0, 0.0, 0.0, 0.0};
-    double cost = 0.0, bad = 0.0;
     const PieceRec pr = b.sched_rec[blockIdx.x];  // piece, its range and camera in one load
-    // the same for the whole block: wave-uniform, so the camera record comes
+    // the same for the whole wavefront: uniform, so the camera record comes
     // through the scalar cache once instead of per observation
     const int32_t p = __builtin_amdgcn_readfirstlane(pr.p);
-    if (p >= 0) {
-        const int32_t cam = __builtin_amdgcn_readfirstlane(pr.cam);
-        const int32_t a = __builtin_amdgcn_readfirstlane(pr.begin), e = __builtin_amdgcn_readfirstlane(pr.end);
-        // read before the loop's stores: uniform loads the compiler can keep in scalar registers
-        double rec[kCamRec];
+    if (p < 0) return;
+    const int32_t cam = __builtin_amdgcn_readfirstlane(pr.cam);
+    const int32_t a = __builtin_amdgcn_readfirstlane(pr.begin), e = __builtin_amdgcn_readfirstlane(pr.end);
+    // read before the loop's stores: uniform loads the compiler can keep in scalar registers
+    double rec[kCamRec];
 #pragma unroll
-        for (int k = 0; k < kCamRec; ++k) rec[k] = b.lin_rec[kCamRec * int64_t(cam) + k];
-        for (int32_t base = a; base < e; base += kBlock) {
-            const int32_t i = base + t;
-            if (i < e) {
-                const int64_t l = b.co_lm[i];
-                double X[3];
+    for (int k = 0; k < kCamRec; ++k) rec[k] = b.lin_rec[kCamRec * int64_t(cam) + k];
+    double acc[kGramEntries];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
-                double* m0 = M + (2 * t) * kGramCols;
-                double rr[2];
-                if constexpr (!std::is_same<TJ, float>::value) {
-                    ObsEval ev;
-                    evaluate_obs_rec(rec, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], ev);
-                    rr[0] = ev.r[0];
-                    rr[1] = ev.r[1];
-                    const double s2 = rr[0] * rr[0] + rr[1] * rr[1];
-                    double rho = s2, w = 1.0;
-                    if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, w);
-                    cost += 0.5 * rho;
-                    if (!isfinite(rho)) bad = 1.0;
-                    const double sw = sqrt(w);
-                    double J[24];
+    for (int k = 0; k < kGramEntries; ++k) acc[k] = 0.0;
+    double cost = 0.0, bad = 0.0;
+    for (int32_t i = a + lane_id(); i < e; i += kWave) {
+        const int64_t l = b.co_lm[i];
+        double X[3];
 #pragma unroll
-                    for (int k = 0; k < 24; ++k) J[k] = sw * ev.J[k];
-                    store_J<TJ>(b.J_co, z.npad, i, J);
-                    rr[0] *= sw;
-                    rr[1] *= sw;
+        for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
+        double rr[2], row0[9], row1[9];
+        if constexpr (!std::is_same<TJ, float>::value) {
+            ObsEval ev;
+            evaluate_obs_rec(rec, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], ev);
+            rr[0] = ev.r[0];
+            rr[1] = ev.r[1];
+            const double s2 = rr[0] * rr[0] + rr[1] * rr[1];
+            double rho = s2, w = 1.0;
+            if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, w);
+            cost += 0.5 * rho;
+            if (!isfinite(rho)) bad = 1.0;
+            const double sw = sqrt(w);
+            double J[24];
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) {
-                        m0[k] = round_to_storage<TJ>(J[k]);
-                        m0[kGramCols + k] = round_to_storage<TJ>(J[9 + k]);
-                    }
-                } else {
-                    float J[24];
-                    evaluate_obs_f32(rec, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], rr, J);
-                    const double s2 = rr[0] * rr[0] + rr[1] * rr[1];
-                    double rho = s2, w = 1.0;
-                    if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, w);
-                    cost += 0.5 * rho;
-                    if (!isfinite(rho)) bad = 1.0;
-                    const double sw = sqrt(w);
-                    const float swf = float(sw);
+            for (int k = 0; k < 24; ++k) J[k] = sw * ev.J[k];
+            store_J<TJ>(b.J_co, z.npad, i, J);
+            rr[0] *= sw;
+            rr[1] *= sw;
 #pragma unroll
-                    for (int k = 0; k < 24; ++k) J[k] = swf * J[k];
-                    store_J_f32(b.J_co, z.npad, i, J);
-                    rr[0] *= sw;
-                    rr[1] *= sw;
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) {
-                        m0[k] = double(J[k]);
-                        m0[kGramCols + k] = double(J[9 + k]);
-                    }
-                }
-                b.r_co[2 * int64_t(i)] = rr[0];
-                b.r_co[2 * int64_t(i) + 1] = rr[1];
-                m0[9] = rr[0];
-                m0[kGramCols + 9] = rr[1];
+            for (int k = 0; k < 9; ++k) {
+                row0[k] = round_to_storage<TJ>(J[k]);
+                row1[k] = round_to_storage<TJ>(J[9 + k]);
             }
-            __syncthreads();
-            const int rows = 2 * min(kBlock, e - base);
-            gacc = gram_rows(M, wv * (2 * kBlock / kWavesPerBlock), (wv + 1) * (2 * kBlock / kWavesPerBlock), rows,
-                             gacc);
-            __syncthreads();
-        }
-    }
+        } else {
+            float J[24];
+            evaluate_obs_f32(rec, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], rr, J);
+            const double s2 = rr[0] * rr[0] + rr[1] * rr[1];
+            double rho = s2, w = 1.0;
+            if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, w);
+            cost += 0.5 * rho;
+            if (!isfinite(rho)) bad = 1.0;
+            const double sw = sqrt(w);
+            const float swf = float(sw);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) red[wv][lane_id()][v] = gacc[v];
-    double tot[2] = {cost, bad};
-    block_sum<2>(tot, lds);  // contains barriers (also publishes red)
-    if (p >= 0 && t < 54) b.part[54 * int64_t(p) + t] = gram_entry(red, ea, eb);
-    if (p >= 0 && t == 0) {
-        b.piece_red[3 * int64_t(p)] = tot[0];
-        b.piece_red[3 * int64_t(p) + 1] = tot[1];
+            for (int k = 0; k < 24; ++k) J[k] = swf * J[k];
+            store_J_f32(b.J_co, z.npad, i, J);
+            rr[0] *= sw;
+            rr[1] *= sw;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                row0[k] = double(J[k]);
+                row1[k] = double(J[9 + k]);
+            }
+        }
+        b.r_co[2 * int64_t(i)] = rr[0];
+        b.r_co[2 * int64_t(i) + 1] = rr[1];
+        gram_add(acc, row0, rr[0]);
+        gram_add(acc, row1, rr[1]);
     }
+    cam_piece_write(b, p, acc, cost, bad);
 }
 
 // Landmark-tile groups handled by one wavefront of the landmark-major
@@ -356,82 +337,44 @@ __global__ __launch_bounds__(kLinLdsBlock) void k_lin_lm_lds(Buffers b, Sizes z,
 // reweighted residual, and accumulates U and b_p from the blocks rebuilt in
 // float64 from the rounded record, the blocks every later pass sees.
 template <typename TP>
-__global__ __launch_bounds__(kBlock) void k_lin_cam_pt(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
-                                                       double delta, const int32_t* gate) {
-    __shared__ double M[2 * kBlock * kGramCols];
-    __shared__ double red[kWavesPerBlock][kWave][4];
-    __shared__ double lds[kWavesPerBlock * 2];
+__global__ __launch_bounds__(kWave) void k_lin_cam_pt(Buffers b, Sizes z, const double* __restrict__ lms, int loss,
+                                                      double delta, const int32_t* gate) {
     if (gate && !*gate) return;
-    const int t = threadIdx.x;
-    const int wv = t / kWave;
-    const int ent = t;
-    int ea = 0, eb = 0;
-    if (ent < 45) {
-        int e = ent, row = 0;
-        while (e >= 9 - row) {
-            e -= 9 - row;
-            ++row;
-        }
-        ea = row;
-        eb = row + e;
-    } else {
-        ea = ent - 45;  // b_p: column 9 of the Gram matrix
-        eb = kGramCols - 1;
-    }
-    gram_acc gacc = {0.0, 0.0, 0.0, 0.0};
-    double cost = 0.0, bad = 0.0;
     const PieceRec pr = b.sched_rec[blockIdx.x];  // piece, its range and camera in one load
-    const int32_t p = pr.p;
-    if (p >= 0) {
-        const int32_t cam = pr.cam;
-        const int32_t a = pr.begin, e = pr.end;
-        const double* rec = b.lin_rec + kCamRec * int64_t(cam);
-        for (int32_t base = a; base < e; base += kBlock) {
-            const int32_t i = base + t;
-            if (i < e) {
-                const int64_t l = b.co_lm[i];
-                double X[3], P[3], r[2];
+    const int32_t p = __builtin_amdgcn_readfirstlane(pr.p);
+    if (p < 0) return;
+    const int32_t cam = __builtin_amdgcn_readfirstlane(pr.cam);
+    const int32_t a = __builtin_amdgcn_readfirstlane(pr.begin), e = __builtin_amdgcn_readfirstlane(pr.end);
+    double rec[kCamRec];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
-                camera_point(rec, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], P, r);
-                const double s2 = r[0] * r[0] + r[1] * r[1];
-                double rho = s2, w = 1.0;
-                if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, w);
-                cost += 0.5 * rho;
-                if (!isfinite(rho)) bad = 1.0;
-                store_point<TP>(b.J_co, z.npad, i, P, sqrt(w));
-                double Pr[3] = {round_point<TP>(P[0]), round_point<TP>(P[1]), round_point<TP>(P[2])};
-                const double swr = round_point<TP>(sqrt(w));
-                double J[24];
-                point_jacobian<double>(rec, Pr, swr, J);
-                const double r0 = swr * r[0], r1 = swr * r[1];
-                b.r_co[2 * int64_t(i)] = r0;
-                b.r_co[2 * int64_t(i) + 1] = r1;
-                double* m0 = M + (2 * t) * kGramCols;
+    for (int k = 0; k < kCamRec; ++k) rec[k] = b.lin_rec[kCamRec * int64_t(cam) + k];
+    double acc[kGramEntries];
 #pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    m0[k] = J[k];
-                    m0[kGramCols + k] = J[9 + k];
-                }
-                m0[9] = r0;
-                m0[kGramCols + 9] = r1;
-            }
-            __syncthreads();
-            const int rows = 2 * min(kBlock, e - base);
-            gacc = gram_rows(M, wv * (2 * kBlock / kWavesPerBlock), (wv + 1) * (2 * kBlock / kWavesPerBlock), rows,
-                             gacc);
-            __syncthreads();
-        }
+    for (int k = 0; k < kGramEntries; ++k) acc[k] = 0.0;
+    double cost = 0.0, bad = 0.0;
+    for (int32_t i = a + lane_id(); i < e; i += kWave) {
+        const int64_t l = b.co_lm[i];
+        double X[3], P[3], r[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
+        camera_point(rec, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], P, r);
+        const double s2 = r[0] * r[0] + r[1] * r[1];
+        double rho = s2, w = 1.0;
+        if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, w);
+        cost += 0.5 * rho;
+        if (!isfinite(rho)) bad = 1.0;
+        store_point<TP>(b.J_co, z.npad, i, P, sqrt(w));
+        double Pr[3] = {round_point<TP>(P[0]), round_point<TP>(P[1]), round_point<TP>(P[2])};
+        const double swr = round_point<TP>(sqrt(w));
+        double J[24];
+        point_jacobian<double>(rec, Pr, swr, J);
+        const double r0v = swr * r[0], r1v = swr * r[1];
+        b.r_co[2 * int64_t(i)] = r0v;
+        b.r_co[2 * int64_t(i) + 1] = r1v;
+        gram_add(acc, J, r0v);
+        gram_add(acc, J + 9, r1v);
     }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) red[wv][lane_id()][v] = gacc[v];
-    double tot[2] = {cost, bad};
-    block_sum<2>(tot, lds);  // contains barriers (also publishes red)
-    if (p >= 0 && t < 54) b.part[54 * int64_t(p) + t] = gram_entry(red, ea, eb);
-    if (p >= 0 && t == 0) {
-        b.piece_red[3 * int64_t(p)] = tot[0];
-        b.piece_red[3 * int64_t(p) + 1] = tot[1];
-    }
+    cam_piece_write(b, p, acc, cost, bad);
 }
 
 // Point records (landmark-major pass): the same records in landmark-major
@@ -579,7 +522,7 @@ poba_status launch_linearize_t(Problem* p, const double* cams, const double* lms
         if (z.point) {
             // point records in the precision of TJ (double or float)
             if (p->sched_len > 0)
-                hipLaunchKernelGGL(k_lin_cam_pt<TJ>, dim3(ncb), dim3(kBlock), 0, s, b, z, lms, loss, delta, gate);
+                hipLaunchKernelGGL(k_lin_cam_pt<TJ>, dim3(ncb), dim3(kWave), 0, s, b, z, lms, loss, delta, gate);
             hipLaunchKernelGGL(k_cost_final, dim3(unsigned(z.np)), dim3(kBlock), 0, s, b, gate, cost_out, st);
             if (lm_lds)
                 hipLaunchKernelGGL(k_lin_lm_pt_lds<TJ>, g_lds, dim3(kLinLdsBlock), lds_cams, s, b, z, lms, loss, delta,
@@ -591,7 +534,7 @@ poba_status launch_linearize_t(Problem* p, const double* cams, const double* lms
     }
     if (!done) {
         if (p->sched_len > 0)
-            hipLaunchKernelGGL(k_lin_cam<TJ>, dim3(ncb), dim3(kBlock), 0, s, b, z, lms, loss, delta, gate);
+            hipLaunchKernelGGL(k_lin_cam<TJ>, dim3(ncb), dim3(kWave), 0, s, b, z, lms, loss, delta, gate);
         hipLaunchKernelGGL(k_cost_final, dim3(unsigned(z.np)), dim3(kBlock), 0, s, b, gate, cost_out, st);
         bool staged = false;
         if constexpr (std::is_same<TJ, float>::value) {
