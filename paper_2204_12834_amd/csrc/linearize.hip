@@ -113,15 +113,32 @@ __global__ __launch_bounds__(kWave) void k_lin_cam(Buffers b, Sizes z, const dou
 #pragma unroll
     for (int k = 0; k < kGramEntries; ++k) acc[k] = 0.0;
     double cost = 0.0, bad = 0.0;
-    for (int32_t i = a + lane_id(); i < e; i += kWave) {
-        const int64_t l = b.co_lm[i];
-        double X[3];
+    // the next observation's landmark position and observation are requested
+    // before this one is evaluated (positions past the piece read its last)
+    auto at = [&](int32_t i) { return min(i, e - 1); };
+    double X[3], ox, oy;
+    {
+        const int32_t i0 = at(a + lane_id());
+        const int64_t l = b.co_lm[i0];
 #pragma unroll
         for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
+        ox = b.obs_co[2 * int64_t(i0)];
+        oy = b.obs_co[2 * int64_t(i0) + 1];
+    }
+    for (int32_t i = a + lane_id(); i < e; i += kWave) {
+        double Xn[3], oxn, oyn;
+        {
+            const int32_t i1 = at(i + kWave);
+            const int64_t l = b.co_lm[i1];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Xn[k] = lms[3 * l + k];
+            oxn = b.obs_co[2 * int64_t(i1)];
+            oyn = b.obs_co[2 * int64_t(i1) + 1];
+        }
         double rr[2], row0[9], row1[9];
         if constexpr (!std::is_same<TJ, float>::value) {
             ObsEval ev;
-            evaluate_obs_rec(rec, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], ev);
+            evaluate_obs_rec(rec, X, ox, oy, ev);
             rr[0] = ev.r[0];
             rr[1] = ev.r[1];
             const double s2 = rr[0] * rr[0] + rr[1] * rr[1];
@@ -143,7 +160,7 @@ __global__ __launch_bounds__(kWave) void k_lin_cam(Buffers b, Sizes z, const dou
             }
         } else {
             float J[24];
-            evaluate_obs_f32(rec, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], rr, J);
+            evaluate_obs_f32(rec, X, ox, oy, rr, J);
             const double s2 = rr[0] * rr[0] + rr[1] * rr[1];
             double rho = s2, w = 1.0;
             if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, w);
@@ -166,6 +183,10 @@ __global__ __launch_bounds__(kWave) void k_lin_cam(Buffers b, Sizes z, const dou
         b.r_co[2 * int64_t(i) + 1] = rr[1];
         gram_add(acc, row0, rr[0]);
         gram_add(acc, row1, rr[1]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) X[k] = Xn[k];
+        ox = oxn;
+        oy = oyn;
     }
     cam_piece_write(b, p, acc, cost, bad);
 }
@@ -352,12 +373,28 @@ __global__ __launch_bounds__(kWave) void k_lin_cam_pt(Buffers b, Sizes z, const 
 #pragma unroll
     for (int k = 0; k < kGramEntries; ++k) acc[k] = 0.0;
     double cost = 0.0, bad = 0.0;
-    for (int32_t i = a + lane_id(); i < e; i += kWave) {
-        const int64_t l = b.co_lm[i];
-        double X[3], P[3], r[2];
+    auto at = [&](int32_t i) { return min(i, e - 1); };
+    double X[3], ox, oy;
+    {
+        const int32_t i0 = at(a + lane_id());
+        const int64_t l = b.co_lm[i0];
 #pragma unroll
         for (int k = 0; k < 3; ++k) X[k] = lms[3 * l + k];
-        camera_point(rec, X, b.obs_co[2 * int64_t(i)], b.obs_co[2 * int64_t(i) + 1], P, r);
+        ox = b.obs_co[2 * int64_t(i0)];
+        oy = b.obs_co[2 * int64_t(i0) + 1];
+    }
+    for (int32_t i = a + lane_id(); i < e; i += kWave) {
+        double Xn[3], oxn, oyn;
+        {
+            const int32_t i1 = at(i + kWave);
+            const int64_t l = b.co_lm[i1];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Xn[k] = lms[3 * l + k];
+            oxn = b.obs_co[2 * int64_t(i1)];
+            oyn = b.obs_co[2 * int64_t(i1) + 1];
+        }
+        double P[3], r[2];
+        camera_point(rec, X, ox, oy, P, r);
         const double s2 = r[0] * r[0] + r[1] * r[1];
         double rho = s2, w = 1.0;
         if (loss == POBA_LOSS_HUBER) huber(s2, delta, rho, w);
@@ -373,6 +410,10 @@ __global__ __launch_bounds__(kWave) void k_lin_cam_pt(Buffers b, Sizes z, const 
         b.r_co[2 * int64_t(i) + 1] = r1v;
         gram_add(acc, J, r0v);
         gram_add(acc, J + 9, r1v);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) X[k] = Xn[k];
+        ox = oxn;
+        oy = oyn;
     }
     cam_piece_write(b, p, acc, cost, bad);
 }
