@@ -398,6 +398,7 @@ struct Buffers {
     int32_t* cam_piece;   // [nc+1] first piece of each camera
     int32_t* grp_off;     // [nc*R+1] camera-major offsets of the (camera, range) groups
     int32_t* grp_piece;   // [nc*R+1] first piece of each group
+    int32_t* dgrp_off;    // [nc*8+1] camera-major offsets of the (camera, die) groups (point records, R % 8 == 0)
     int32_t* sched;       // [kXcds*npieces_max] camera-pass block -> piece (-1: idle)
     PieceRec* sched_rec;  // [kXcds*npieces_max] the same slots with their piece data
     int4* cw_rec;         // [R*kMaxRangeBlocks*kMaxCwWaves] range-staged camera pass: per wavefront

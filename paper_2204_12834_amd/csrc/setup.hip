@@ -101,6 +101,7 @@ size_t layout(const poba_desc* d, const Sizes& z, char* base, Buffers* b, size_t
     t.cam_piece = (int32_t*)take((nc + 1) * 4);
     t.grp_off = (int32_t*)take((nc * size_t(z.ranges_max) + 1) * 4);
     t.grp_piece = (int32_t*)take((nc * size_t(z.ranges_max) + 1) * 4);
+    t.dgrp_off = (int32_t*)take((nc * kXcds + 1) * 4);
     t.sched = (int32_t*)take(size_t(kXcds) * size_t(z.npieces_max) * 4);
     t.sched_rec = (PieceRec*)take(size_t(kXcds) * size_t(z.npieces_max) * sizeof(PieceRec));
     t.cw_rec = (int4*)take(size_t(z.ranges_max) * kMaxRangeBlocks * kMaxCwWaves * sizeof(int4));
@@ -312,6 +313,16 @@ __global__ void k_piece_fill(const int32_t* grp_off, const int32_t* grp_piece, i
         piece_end[p] = min(s + piece, b);
         piece_grp[p] = g;
     }
+}
+
+// First camera-major position of each (camera, die) group: camera c's
+// observations in the ranges [g R / 8, (g + 1) R / 8), the ranges whose
+// series passes run on die g (R a multiple of 8).
+__global__ void k_die_group_off(const int32_t* grp_off, int32_t nc, int32_t R, int32_t* dgrp_off) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t n = int64_t(nc) * kXcds;
+    if (i > n) return;
+    dgrp_off[i] = i == n ? grp_off[int64_t(nc) * R] : grp_off[(i / kXcds) * R + (i % kXcds) * (R / kXcds)];
 }
 
 // cam_piece[c] = first piece of camera c (pieces are ordered by camera, range).
@@ -634,13 +645,19 @@ static poba_status create_impl(const poba_desc* d, int32_t n_problems, const int
     hipLaunchKernelGGL(k_cam_off, dim3(grid_for(z.nc + 1)), dim3(kBlock), 0, s, b.grp_off, z.nc, R, b.cam_off);
 
     // camera pieces: at most `piece` observations of one (camera, range)
-    // group; with range-staged camera passes of one camera (the series passes
-    // then walk the groups themselves, and the per-piece kernels keep pieces
-    // of the full size)
-    const int32_t Rp = p->range_lds_ok ? 1 : R;
+    // group; with range-staged camera passes (the series passes then walk the
+    // groups themselves) of one camera and the ranges of one die, so that the
+    // per-piece kernels keep larger pieces and their landmark gathers stay
+    // within the die's eighth of the landmarks (or of one camera where R is
+    // not a multiple of 8)
+    const bool die_groups = p->range_lds_ok && R % kXcds == 0;
+    const int32_t Rp = p->range_lds_ok ? (die_groups ? kXcds : 1) : R;
+    if (die_groups)
+        hipLaunchKernelGGL(k_die_group_off, dim3(grid_for(int64_t(z.nc) * kXcds + 1)), dim3(kBlock), 0, s, b.grp_off,
+                           z.nc, R, b.dgrp_off);
     {
-        const int32_t* goff = p->range_lds_ok ? b.cam_off : b.grp_off;
-        const int64_t ngp = p->range_lds_ok ? int64_t(z.nc) : ngrp;
+        const int32_t* goff = p->range_lds_ok ? (die_groups ? b.dgrp_off : b.cam_off) : b.grp_off;
+        const int64_t ngp = int64_t(z.nc) * Rp;
         int32_t* counts = b.sched;  // scratch until the schedule is written
         hipLaunchKernelGGL(k_piece_counts, dim3(grid_for(ngp + 1)), dim3(kBlock), 0, s, goff, int32_t(ngp), z.piece,
                            counts);
