@@ -540,7 +540,9 @@ def bench_batched(args, dev):
                        "batched_eager_default_shape": round(default_ms, 3),
                        "one_handle_per_problem": round(solo_ms, 3)},
         "speedup_graph_vs_per_problem": round(solo_ms / graph_ms, 2),
-        "tuned": {kk: cfg[kk] for kk in ("piece_size", "tiles_per_wave", "lds_camera", "us_per_order") if kk in cfg},
+        "tuned": {kk: cfg[kk] for kk in ("piece_size", "tiles_per_wave", "lds_camera", "us_per_order", "spread",
+                                        "default_us_per_order", "default_spread", "candidates", "cached")
+                  if kk in cfg},
         "tune_seconds": round(t_tune, 1),
         "phase_ms_per_step": {name: round(v[0], 4) for name, v in prof.items()},
     }

@@ -555,6 +555,92 @@ __global__ __launch_bounds__(kBlock) void k_backsub_pt(Buffers b, Sizes z, doubl
         });
 }
 
+// The same with the camera step's folded data staged in LDS (where 144 bytes
+// per camera fit): a, e, v_intrinsics, f, k1, k2 of the fold, and w, A, B and
+// |w|^2 of the linearisation's camera record, from which each observation
+// rebuilds R with the operations of make_cam_record (so R is the same to the
+// bit).  One workgroup per compute unit; every wavefront walks one contiguous
+// range of tiles.
+struct __attribute__((aligned(16))) BacksubLdsCam {
+    double c[12];  // fold slots 0..11
+    double w[3], A, B, th2;
+};
+static_assert(sizeof(BacksubLdsCam) == 144, "144-byte camera slots");
+constexpr int kBacksubLdsBlock = 1024;
+
+template <typename TJ>
+__global__ __launch_bounds__(kBacksubLdsBlock) void k_backsub_pt_lds(Buffers b, Sizes z, double* __restrict__ dxl,
+                                                                    const Ctrl* ctrl, int64_t per) {
+    extern __shared__ unsigned char lds_raw[];
+    if (!ctrl->active) return;
+    BacksubLdsCam* cams = reinterpret_cast<BacksubLdsCam*>(lds_raw);
+    for (int32_t c = threadIdx.x; c < z.nc; c += blockDim.x) {
+        const double* f = b.xq + kFoldStride<double> * int64_t(c);
+        const double* r = b.lin_rec + kCamRec * int64_t(c);
+        BacksubLdsCam x;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) x.c[k] = f[k];
+        x.w[0] = r[0];
+        x.w[1] = r[1];
+        x.w[2] = r[2];
+        x.A = r[9];
+        x.B = r[10];
+        {
+#pragma clang fp contract(off)
+            x.th2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        }
+        cams[c] = x;
+    }
+    __syncthreads();
+    const int64_t t0 = (int64_t(blockIdx.x) * (kBacksubLdsBlock / kWave) + wave_in_block()) * per;
+    const int64_t t1 = min(t0 + per, z.ntiles);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        tile_landmarks<double, 3, kLookupLate>(
+            b.lo_cam, b.tile_start, b.seg_base, b.nel, z.nl, tile,
+            [&](int32_t i, bool valid, int32_t cam, int32_t, int32_t, double* v) {
+                v[0] = v[1] = v[2] = 0.0;
+                if (!valid) return;
+                double P[3], sw, c[24];
+                load_point<TJ, double>(b.J_lo, z.npad, i, P, sw);
+                const BacksubLdsCam& x = cams[cam];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) c[k] = x.c[k];
+                {
+#pragma clang fp contract(off)
+                    const double* w = x.w;
+                    const double A = x.A, B = x.B, th2 = x.th2;
+                    double* R = c + 12;
+                    R[0] = 1.0 + B * (w[0] * w[0] - th2);
+                    R[4] = 1.0 + B * (w[1] * w[1] - th2);
+                    R[8] = 1.0 + B * (w[2] * w[2] - th2);
+                    R[1] = -A * w[2] + B * w[0] * w[1];
+                    R[3] = A * w[2] + B * w[0] * w[1];
+                    R[2] = A * w[1] + B * w[0] * w[2];
+                    R[6] = -A * w[1] + B * w[0] * w[2];
+                    R[5] = -A * w[0] + B * w[1] * w[2];
+                    R[7] = A * w[0] + B * w[1] * w[2];
+                }
+                point_lm_term(P, sw, c, v);
+            },
+            [&](int32_t seg, int32_t lmk, const double* t) {
+                const int64_t l = lmk;
+                const PCtrl& q = b.pctl[b.lm_prob[l]];
+                if (!q.active) return;
+                double Vd[6], inv[6], rhs[3], y[3], dd[3];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) Vd[k] = b.V[6 * l + k];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) dd[k] = b.Dl[3 * int64_t(seg) + k];
+                inv3_damped(Vd, q.lambda, dd, inv);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) rhs[k] = b.bl[3 * l + k] + t[k];
+                sym3_apply(inv, rhs, y);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) dxl[3 * l + k] = -y[k];
+            });
+    }
+}
+
 // Landmarks without observations get dx_l = -V^-1 b_l = 0.
 __global__ __launch_bounds__(kBlock) void k_zero_empty(Buffers b, Sizes z, double* dxl, const Ctrl* ctrl) {
     if (!ctrl->active) return;
@@ -1509,7 +1595,16 @@ void solve_backsub(Problem* p, const Buffers& b, double* dx_cams, double* dx_lms
     ProfScope pr(p, POBA_K_BACKSUB, s);
     if constexpr (PT) {
         hipLaunchKernelGGL(k_fold_x, g_cam, blk, 0, s, b, z, b.x, b.ctrl);
-        hipLaunchKernelGGL((k_backsub_pt<TJ>), g_tiles, blk, 0, s, b, z, dx_lms, b.ctrl);
+        const size_t lds = size_t(z.nc) * sizeof(BacksubLdsCam);
+        if (lds <= size_t(p->lds_max)) {
+            const int64_t waves = p->n_cus * (kBacksubLdsBlock / kWave);
+            const int64_t per = std::max<int64_t>(1, ceil_div(z.ntiles, waves));
+            const int64_t nblk = ceil_div(ceil_div(z.ntiles, per), kBacksubLdsBlock / kWave);
+            hipLaunchKernelGGL((k_backsub_pt_lds<TJ>), dim3(unsigned(nblk)), dim3(kBacksubLdsBlock), lds, s, b, z,
+                               dx_lms, b.ctrl, per);
+        } else {
+            hipLaunchKernelGGL((k_backsub_pt<TJ>), g_tiles, blk, 0, s, b, z, dx_lms, b.ctrl);
+        }
     } else {
         // the series' landmark stream (its storage and arithmetic types) on x
         hipLaunchKernelGGL((k_x_to_vq<TS>), dim3(unsigned(ceil_div(int64_t(z.nc) * 9, kBlock))), blk, 0, s, b, z,
