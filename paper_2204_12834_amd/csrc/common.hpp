@@ -273,6 +273,34 @@ __device__ __forceinline__ T dpp_masked(T v) {
     }
 }
 
+// Copies n 16-byte units from global memory to LDS (dst, from the block's
+// dynamic LDS) with the global-to-LDS load: each instruction moves one
+// contiguous KB per wavefront (lane i to the wavefront's LDS base + 16 i), no
+// registers hold the data, so every unit of the copy is in flight at once.
+// Ends with the block synchronised and the data visible to every wavefront.
+// blockDim.x must be a multiple of the wavefront size.
+__device__ __forceinline__ void copy_to_lds(const uint4* __restrict__ src, uint4* dst, int64_t n) {
+    const int64_t wave_base = int64_t(threadIdx.x) - lane_id();
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x)
+        __builtin_amdgcn_global_load_lds(src + k, dst + (k - threadIdx.x + wave_base), 16, 0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// v plus the value of v D lanes lower in its row of 16 (DPP row_shr:D), for
+// callers that use the result only in lanes with D <= lane % 16.  For 4-byte
+// values the shift fills the other lanes with 0, which lets the compiler fold
+// it into the add (one DPP add instead of a DPP move and an add).
+template <int D, typename T>
+__device__ __forceinline__ T dpp_row_shr_add(T v) {
+    if constexpr (sizeof(T) == 8) {
+        return v + dpp_masked<0x110 | D, 0xf>(v);
+    } else {
+        return v + __builtin_bit_cast(
+                       T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x110 | D, 0xf, 0xf, false));
+    }
+}
+
 // Inclusive segmented scan over the wave.  seg_start is the first lane of the
 // calling lane's segment; after the call v[k] holds the sum of v[k] over
 // lanes seg_start..lane.  Within each row of 16 lanes the scan shifts by 1,
@@ -287,8 +315,8 @@ __device__ __forceinline__ void segmented_scan(T* v, int lane, int seg_start) {
     {                                                                      \
         const bool take = rl >= D && lane - D >= seg_start;                \
         _Pragma("unroll") for (int k = 0; k < K; ++k) {                    \
-            const T y = dpp_masked<0x110 | D, 0xf>(v[k]);                  \
-            if (take) v[k] += y;                                           \
+            const T y = dpp_row_shr_add<D>(v[k]);                          \
+            if (take) v[k] = y;                                            \
         }                                                                  \
     }
     POBA_ROW_STEP(1)
@@ -296,9 +324,9 @@ __device__ __forceinline__ void segmented_scan(T* v, int lane, int seg_start) {
     POBA_ROW_STEP(4)
     POBA_ROW_STEP(8)
 #undef POBA_ROW_STEP
-    const int row = lane >> 4;
     {
-        const bool take = (row == 1 && seg_start <= 15) || (row == 3 && seg_start <= 47);
+        // rows 1 and 3 read lane 16 * row - 1, the lane before their row
+        const bool take = (lane & 16) && seg_start < (lane & 48);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const T y = dpp_masked<0x142, 0xa>(v[k]);
@@ -306,7 +334,7 @@ __device__ __forceinline__ void segmented_scan(T* v, int lane, int seg_start) {
         }
     }
     {
-        const bool take = row >= 2 && seg_start <= 31;
+        const bool take = lane >= 32 && seg_start <= 31;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const T y = dpp_masked<0x143, 0xc>(v[k]);

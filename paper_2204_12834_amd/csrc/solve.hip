@@ -1028,15 +1028,10 @@ __global__ __launch_bounds__(kPtBlock) void k_lm_pass_pt_lds(Buffers b, Sizes z,
     extern __shared__ unsigned char lds_raw[];
     if (ctrl->running == 0) return;
     TS* cf = reinterpret_cast<TS*>(lds_raw);
-    {
-        // 16-byte units (24 values per camera make whole units); one unit in
-        // flight per thread (this kernel has no registers to spare for more)
-        const uint4* __restrict__ src = reinterpret_cast<const uint4*>(b.vq);
-        uint4* dst = reinterpret_cast<uint4*>(lds_raw);
-        const int64_t n = int64_t(z.nc) * kFoldStride<TS> * int64_t(sizeof(TS)) / 16;
-        for (int64_t k = threadIdx.x; k < n; k += kPtBlock) dst[k] = src[k];
-    }
-    __syncthreads();
+    // 16-byte units (a camera's padded fold makes whole units)
+    static_assert(kFoldStride<TS> * sizeof(TS) % 16 == 0, "whole 16-byte units per camera");
+    copy_to_lds(reinterpret_cast<const uint4*>(b.vq), reinterpret_cast<uint4*>(lds_raw),
+                int64_t(z.nc) * kFoldStride<TS> * int64_t(sizeof(TS)) / 16);
     const int64_t wave = int64_t(blockIdx.x) * (kPtBlock / kWave) + wave_in_block();
     const int64_t t0 = wave * tiles_per_wave;
     if (t0 >= z.ntiles) return;
