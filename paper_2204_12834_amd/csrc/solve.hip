@@ -555,29 +555,24 @@ __global__ __launch_bounds__(kBlock) void k_backsub_pt(Buffers b, Sizes z, doubl
         });
 }
 
-// The same with the camera step's folded data staged in LDS (where 144 bytes
-// per camera fit): a, e, v_intrinsics, f, k1, k2 of the fold, and w, A, B and
-// |w|^2 of the linearisation's camera record, from which each observation
-// rebuilds R with the operations of make_cam_record (so R is the same to the
-// bit).  One workgroup per compute unit; every wavefront walks one contiguous
-// range of tiles.
-struct __attribute__((aligned(16))) BacksubLdsCam {
-    double c[12];  // fold slots 0..11
+// Compact float64 folded camera data for LDS (144 bytes per camera): slots
+// 0..11 of the fold (a, e, v_intrinsics, f, k1, k2) and w, A, B and |w|^2 of
+// the linearisation's camera record, from which each observation rebuilds R
+// with the operations of make_cam_record (so R is the same to the bit).
+struct __attribute__((aligned(16))) CompactFold {
+    double c[12];
     double w[3], A, B, th2;
 };
-static_assert(sizeof(BacksubLdsCam) == 144, "144-byte camera slots");
-constexpr int kBacksubLdsBlock = 1024;
+static_assert(sizeof(CompactFold) == 144, "144-byte camera slots");
 
-template <typename TJ>
-__global__ __launch_bounds__(kBacksubLdsBlock) void k_backsub_pt_lds(Buffers b, Sizes z, double* __restrict__ dxl,
-                                                                    const Ctrl* ctrl, int64_t per) {
-    extern __shared__ unsigned char lds_raw[];
-    if (!ctrl->active) return;
-    BacksubLdsCam* cams = reinterpret_cast<BacksubLdsCam*>(lds_raw);
-    for (int32_t c = threadIdx.x; c < z.nc; c += blockDim.x) {
-        const double* f = b.xq + kFoldStride<double> * int64_t(c);
-        const double* r = b.lin_rec + kCamRec * int64_t(c);
-        BacksubLdsCam x;
+// The block stages the compact fold of every camera from a float64 fold
+// (stride kFoldStride<double>) and the camera records; ends synchronised.
+__device__ __forceinline__ void stage_compact_fold(const double* __restrict__ fold, const double* __restrict__ lin_rec,
+                                                   int32_t nc, CompactFold* cams) {
+    for (int32_t c = threadIdx.x; c < nc; c += blockDim.x) {
+        const double* f = fold + kFoldStride<double> * int64_t(c);
+        const double* r = lin_rec + kCamRec * int64_t(c);
+        CompactFold x;
 #pragma unroll
         for (int k = 0; k < 12; ++k) x.c[k] = f[k];
         x.w[0] = r[0];
@@ -592,6 +587,41 @@ __global__ __launch_bounds__(kBacksubLdsBlock) void k_backsub_pt_lds(Buffers b, 
         cams[c] = x;
     }
     __syncthreads();
+}
+
+// The 24-slot fold of one camera from its compact form (slots 21..23 unused).
+__device__ __forceinline__ void load_compact_fold(const CompactFold& x, double* c) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) c[k] = x.c[k];
+    {
+#pragma clang fp contract(off)
+        const double* w = x.w;
+        const double A = x.A, B = x.B, th2 = x.th2;
+        double* R = c + 12;
+        R[0] = 1.0 + B * (w[0] * w[0] - th2);
+        R[4] = 1.0 + B * (w[1] * w[1] - th2);
+        R[8] = 1.0 + B * (w[2] * w[2] - th2);
+        R[1] = -A * w[2] + B * w[0] * w[1];
+        R[3] = A * w[2] + B * w[0] * w[1];
+        R[2] = A * w[1] + B * w[0] * w[2];
+        R[6] = -A * w[1] + B * w[0] * w[2];
+        R[5] = -A * w[0] + B * w[1] * w[2];
+        R[7] = A * w[0] + B * w[1] * w[2];
+    }
+}
+
+// Back-substitution over point records with the camera step's compact fold
+// staged in LDS (where it fits).  One workgroup per compute unit; every
+// wavefront walks one contiguous range of tiles.
+constexpr int kBacksubLdsBlock = 1024;
+
+template <typename TJ>
+__global__ __launch_bounds__(kBacksubLdsBlock) void k_backsub_pt_lds(Buffers b, Sizes z, double* __restrict__ dxl,
+                                                                    const Ctrl* ctrl, int64_t per) {
+    extern __shared__ unsigned char lds_raw[];
+    if (!ctrl->active) return;
+    CompactFold* cams = reinterpret_cast<CompactFold*>(lds_raw);
+    stage_compact_fold(b.xq, b.lin_rec, z.nc, cams);
     const int64_t t0 = (int64_t(blockIdx.x) * (kBacksubLdsBlock / kWave) + wave_in_block()) * per;
     const int64_t t1 = min(t0 + per, z.ntiles);
     for (int64_t tile = t0; tile < t1; ++tile) {
@@ -602,24 +632,7 @@ __global__ __launch_bounds__(kBacksubLdsBlock) void k_backsub_pt_lds(Buffers b, 
                 if (!valid) return;
                 double P[3], sw, c[24];
                 load_point<TJ, double>(b.J_lo, z.npad, i, P, sw);
-                const BacksubLdsCam& x = cams[cam];
-#pragma unroll
-                for (int k = 0; k < 12; ++k) c[k] = x.c[k];
-                {
-#pragma clang fp contract(off)
-                    const double* w = x.w;
-                    const double A = x.A, B = x.B, th2 = x.th2;
-                    double* R = c + 12;
-                    R[0] = 1.0 + B * (w[0] * w[0] - th2);
-                    R[4] = 1.0 + B * (w[1] * w[1] - th2);
-                    R[8] = 1.0 + B * (w[2] * w[2] - th2);
-                    R[1] = -A * w[2] + B * w[0] * w[1];
-                    R[3] = A * w[2] + B * w[0] * w[1];
-                    R[2] = A * w[1] + B * w[0] * w[2];
-                    R[6] = -A * w[1] + B * w[0] * w[2];
-                    R[5] = -A * w[0] + B * w[1] * w[2];
-                    R[7] = A * w[0] + B * w[1] * w[2];
-                }
+                load_compact_fold(cams[cam], c);
                 point_lm_term(P, sw, c, v);
             },
             [&](int32_t seg, int32_t lmk, const double* t) {
@@ -924,14 +937,14 @@ __global__ __launch_bounds__(kBlock) void k_load_v(Buffers b, Sizes z, const dou
 // when chunk c is done, and the V^-1 of the landmarks ending in chunk
 // c + kPtAhead when chunk c starts; each request is consumed at least
 // kPtAhead chunks later, so with in-order completion no wait covers a load
-// issued in the last kPtAhead chunks.  `fold` holds the folded camera data,
-// in LDS or in global memory.
+// issued in the last kPtAhead chunks.  fold_at(c, cd) gives the folded
+// data of camera c (from LDS or from global memory).
 constexpr int kPtDepth = 4;
 constexpr int kPtAhead = 2;
 
-template <typename TP, typename TC, typename TS>
+template <typename TP, typename TC, typename TS, typename FoldAt>
 __device__ __forceinline__ void lm_pass_stream_pt(const Buffers& b, const Sizes& z, int64_t t0, int64_t t1,
-                                                  const TS* __restrict__ fold, TS* __restrict__ sout) {
+                                                  const FoldAt& fold_at, TS* __restrict__ sout) {
     const TS* __restrict__ Vinv = reinterpret_cast<const TS*>(b.Vinv);
     const uint32_t* __restrict__ lo_cam = b.lo_cam;
     const int lane = lane_id();
@@ -976,7 +989,7 @@ __device__ __forceinline__ void lm_pass_stream_pt(const Buffers& b, const Sizes&
         TC v[3] = {TC(0), TC(0), TC(0)};
         if (pos + lane < end) {
             TC cd[24];
-            load_fold(fold, int64_t(wc & kIndexMask), cd);
+            fold_at(int64_t(wc & kIndexMask), cd);
             point_lm_term(P[u], sw[u], cd, v);
         }
         const uint64_t hm = ballot64(wc & kHeadBit);
@@ -1035,7 +1048,29 @@ __global__ __launch_bounds__(kPtBlock) void k_lm_pass_pt_lds(Buffers b, Sizes z,
     const int64_t wave = int64_t(blockIdx.x) * (kPtBlock / kWave) + wave_in_block();
     const int64_t t0 = wave * tiles_per_wave;
     if (t0 >= z.ntiles) return;
-    lm_pass_stream_pt<TP, TC, TS>(b, z, t0, min(t0 + tiles_per_wave, z.ntiles), cf, sout);
+    lm_pass_stream_pt<TP, TC, TS>(
+        b, z, t0, min(t0 + tiles_per_wave, z.ntiles), [&](int64_t c, TC* cd) { load_fold(cf, c, cd); }, sout);
+}
+
+// Float64 series with the compact fold in LDS (144 bytes per camera, where the
+// full 208-byte fold does not fit): R is rebuilt per observation.  Blocks of
+// eight wavefronts, one per compute unit: the float64 pipeline needs about
+// 170 registers per lane.
+constexpr int kPtCompactBlock = 512;
+
+template <typename TP>
+__global__ __launch_bounds__(kPtCompactBlock) void k_lm_pass_pt_compact(Buffers b, Sizes z, int64_t tiles_per_wave,
+                                                                  double* __restrict__ sout, const Ctrl* ctrl) {
+    extern __shared__ unsigned char lds_raw[];
+    if (ctrl->running == 0) return;
+    CompactFold* cams = reinterpret_cast<CompactFold*>(lds_raw);
+    stage_compact_fold(reinterpret_cast<const double*>(b.vq), b.lin_rec, z.nc, cams);
+    const int64_t wave = int64_t(blockIdx.x) * (kPtCompactBlock / kWave) + wave_in_block();
+    const int64_t t0 = wave * tiles_per_wave;
+    if (t0 >= z.ntiles) return;
+    lm_pass_stream_pt<TP, double, double>(
+        b, z, t0, min(t0 + tiles_per_wave, z.ntiles),
+        [&](int64_t c, double* cd) { load_compact_fold(cams[c], cd); }, sout);
 }
 
 // Folded camera data gathered from global memory (L2-resident).
@@ -1046,8 +1081,9 @@ __global__ __launch_bounds__(kBlock) void k_lm_pass_pt(Buffers b, Sizes z, int64
     const int64_t wave = int64_t(blockIdx.x) * kWavesPerBlock + wave_in_block();
     const int64_t t0 = wave * tiles_per_wave;
     if (t0 >= z.ntiles) return;
-    lm_pass_stream_pt<TP, TC, TS>(b, z, t0, min(t0 + tiles_per_wave, z.ntiles), reinterpret_cast<const TS*>(b.vq),
-                                  sout);
+    const TS* __restrict__ fold = reinterpret_cast<const TS*>(b.vq);
+    lm_pass_stream_pt<TP, TC, TS>(
+        b, z, t0, min(t0 + tiles_per_wave, z.ntiles), [&](int64_t c, TC* cd) { load_fold(fold, c, cd); }, sout);
 }
 
 template <typename TP, typename TC, typename TS>
@@ -1056,13 +1092,23 @@ void launch_lm_pass_pt(Problem* p, hipStream_t s) {
     const Sizes& z = p->z;
     const size_t lds = size_t(z.nc) * kFoldStride<TS> * sizeof(TS);
     TS* sout = reinterpret_cast<TS*>(b.s);
-    if (p->lds_cam && lds <= size_t(p->lds_max)) {
+    constexpr bool f64 = std::is_same<TS, double>::value && std::is_same<TC, double>::value;
+    const size_t lds_compact = size_t(z.nc) * sizeof(CompactFold);
+    const bool full = p->lds_cam && lds <= size_t(p->lds_max);
+    const bool compact = f64 && !full && p->lds_cam && lds_compact <= size_t(p->lds_max);
+    if (full || compact) {
         // one block per compute unit; the tiles are split evenly over all wavefronts
-        const int64_t waves = p->n_cus * (kPtBlock / kWave);
+        const int block = full ? kPtBlock : kPtCompactBlock;
+        const int64_t waves = p->n_cus * (block / kWave);
         const int64_t per = std::max<int64_t>(1, ceil_div(z.ntiles, waves));
-        const int64_t nblk = ceil_div(ceil_div(z.ntiles, per), kPtBlock / kWave);
-        hipLaunchKernelGGL((k_lm_pass_pt_lds<TP, TC, TS>), dim3(unsigned(nblk)), dim3(kPtBlock), lds, s, b, z, per,
-                           sout, b.ctrl);
+        const int64_t nblk = ceil_div(ceil_div(z.ntiles, per), block / kWave);
+        if (full) {
+            hipLaunchKernelGGL((k_lm_pass_pt_lds<TP, TC, TS>), dim3(unsigned(nblk)), dim3(block), lds, s, b, z, per,
+                               sout, b.ctrl);
+        } else if constexpr (f64) {
+            hipLaunchKernelGGL((k_lm_pass_pt_compact<TP>), dim3(unsigned(nblk)), dim3(block), lds_compact, s, b, z,
+                               per, sout, b.ctrl);
+        }
     } else {
         const int64_t per = p->tiles_per_wave;
         hipLaunchKernelGGL((k_lm_pass_pt<TP, TC, TS>), dim3(unsigned(ceil_div(ceil_div(z.ntiles, per), kWavesPerBlock))),
@@ -1590,7 +1636,7 @@ void solve_backsub(Problem* p, const Buffers& b, double* dx_cams, double* dx_lms
     ProfScope pr(p, POBA_K_BACKSUB, s);
     if constexpr (PT) {
         hipLaunchKernelGGL(k_fold_x, g_cam, blk, 0, s, b, z, b.x, b.ctrl);
-        const size_t lds = size_t(z.nc) * sizeof(BacksubLdsCam);
+        const size_t lds = size_t(z.nc) * sizeof(CompactFold);
         if (lds <= size_t(p->lds_max)) {
             const int64_t waves = p->n_cus * (kBacksubLdsBlock / kWave);
             const int64_t per = std::max<int64_t>(1, ceil_div(z.ntiles, waves));

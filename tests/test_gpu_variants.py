@@ -3,13 +3,17 @@
 The landmark pass of each series order (W^T v gathered per landmark, then
 V^-1, Sec. 4.3 eqs. S_approx, x_approx) has two forms per record kind:
 
-  camera vector staged in LDS    k_lm_pass_lds      stored blocks, n_c * 9 * s <= 64 KB
-                                 k_lm_pass_pt_lds   point records, n_c * 24 * s <= the LDS budget
-  camera vector gathered from L2 k_lm_pass          stored blocks, otherwise (or lds_camera = 0)
-                                 k_lm_pass_pt       point records, otherwise (or lds_camera = 0)
+  camera vector staged in LDS    k_lm_pass_lds         stored blocks, n_c * 9 * s <= 64 KB
+                                 k_lm_pass_pt_lds      point records, n_c * f * s <= the LDS budget
+                                 k_lm_pass_pt_compact  float64 point records, otherwise where
+                                                       n_c * 144 <= the LDS budget (R rebuilt
+                                                       per observation)
+  camera vector gathered from L2 k_lm_pass             stored blocks, otherwise (or lds_camera = 0)
+                                 k_lm_pass_pt          point records, otherwise (or lds_camera = 0)
 
-(s: bytes per vector scalar; the LDS budget is the device's per-workgroup
-limit, 160 KB on gfx950).  The L2 forms give each wavefront tiles_per_wave
+(s: bytes per vector scalar; f: the folded camera's padded stride, 28
+scalars in float32 and 26 in float64; the LDS budget is the device's
+per-workgroup limit, 160 KB on gfx950).  The L2 forms give each wavefront tiles_per_wave
 64-observation landmark tiles.  These tests reach the L2 forms three ways:
 forced through the tuning call, automatically on a ring of 2,048 cameras
 (147 KB / 74 KB of float64 / float32 camera vector, 393 KB / 197 KB folded),
@@ -55,7 +59,18 @@ SMALL = {"city_small": city_small, "ladybug_small": ladybug_small}
 
 def _lm_pass_in_lds(n_cams, precision, records):
     s = 8 if precision == "f64" else 4
-    return n_cams * 9 * s <= 64 * 1024 if records == "jacobian" else n_cams * 24 * s <= 160 * 1024
+    if records == "jacobian":
+        return n_cams * 9 * s <= 64 * 1024
+    if precision == "f64":
+        return n_cams * 144 <= 160 * 1024
+    return n_cams * 28 * s <= 160 * 1024
+
+
+@functools.lru_cache(maxsize=None)
+def ring_1k():
+    # 1,000 cameras: the float64 fold (208 KB) does not fit LDS, its compact
+    # form (144 KB) does
+    return Case(synth.ring_scene(1000, 8000, (2, 6), seed=13, name="ring_1k"))
 
 
 def _check_step(prob, case, lam, m, tol, what):
@@ -138,6 +153,27 @@ def test_many_cameras_switch_to_l2(precision, records):
         _check_step(prob, case, lam, m, TOL[precision], f"ring_2k {precision} {records}")
 
 
+def test_f64_point_compact_fold():
+    """1,000 cameras in float64 over point records: the landmark pass and the
+    back-substitution stage the compact fold and rebuild R per observation;
+    against the oracle, and against the L2 form (lds_camera = 0), which
+    differs only in summation order."""
+    case = ring_1k()
+    n = case.scene.n_cams
+    assert n * 26 * 8 > 160 * 1024 and _lm_pass_in_lds(n, "f64", "point")
+    cams, lms = case.state()
+    out = []
+    for lds in [1, 0]:
+        prob = case.problem("f64", records="point")
+        prob.set_tuning("lds_camera", lds)
+        prob.linearize(cams, lms)
+        for lam, m in [(1e-4, 20), (1.0, 8)]:
+            _check_step(prob, case, lam, m, TOL["f64"], f"ring_1k f64 point lds_camera={lds}")
+        dxp, dxl, _ = prob.power_solve(1e-3, 16, 0.0)
+        out.append((np_(dxp).copy(), np_(dxl).copy()))
+    assert rel(out[1][0], out[0][0]) <= 1e-12 and rel(out[1][1], out[0][1]) <= 1e-12
+
+
 @pytest.mark.parametrize("tpw", [1, 8])
 def test_many_cameras_ragged_piece_ranges(tpw):
     """2,048 cameras with split camera pieces and landmark ranges, through
@@ -210,8 +246,9 @@ def city_full_ref(lam, m):
                                                ("f32", "point")])
 def test_city_full_size(precision, records):
     """The city workload at full size, automatic pieces, ranges and pass
-    forms (float64: the L2 landmark pass; float32: the LDS one), against the
-    oracle at m = 3, eps = 0."""
+    forms (float64 stored blocks: the L2 landmark pass; float64 point records:
+    the compact fold in LDS; float32: the LDS pass), against the oracle at
+    m = 3, eps = 0."""
     case = city_full()
     s = case.scene
     prob = case.problem(precision, records=records)
