@@ -712,14 +712,19 @@ static poba_status create_impl(const poba_desc* d, int32_t n_problems, const int
         if (hipStreamSynchronize(s) != hipSuccess) return fail(POBA_ERR_HIP);
     }
     // range-staged camera pass: G workgroups per landmark range (one per
-    // compute unit in all), each with range_pass_waves wavefronts; a range's
-    // non-empty (camera, range) groups are cut, in camera order, into runs of
-    // about equal observation counts, one per wavefront, and each run is
-    // listed longest group first (so that the groups a wavefront serves side
-    // by side have similar lengths).  Neighbouring ranges run on the same die
-    // (workgroups are dealt to the dies in turn), so the cache lines that two
-    // adjacent groups of one camera share, and the staged slices, are fetched
-    // into one L2.  Group sums of empty groups stay zero.
+    // compute unit in all), each with range_pass_waves wavefronts.  A range's
+    // non-empty (camera, range) groups are sorted longest first and dealt to
+    // its G workgroups in turn; each workgroup cuts its share, in that order,
+    // into batches of kSets groups (a batch takes as many steps as its first,
+    // longest group needs) and gives each batch to the wavefront with the
+    // fewest steps so far (longest processing time first), so its wavefronts
+    // end close together.  A wavefront's list is its batches in the order it
+    // got them; only the workgroup's last batch can hold fewer than kSets
+    // groups, and it is the last of its wavefront's list.  Neighbouring
+    // ranges run on the same die (workgroups are dealt to the dies in turn),
+    // so the cache lines that two adjacent groups of one camera share, and
+    // the staged slices, are fetched into one L2.  Group sums of empty groups
+    // stay zero.
     if (p->range_lds_ok) {
         std::vector<int32_t> go(size_t(ngrp) + 1);
         std::vector<int32_t> cprob(size_t(z.nc));
@@ -731,41 +736,46 @@ static poba_status create_impl(const poba_desc* d, int32_t n_problems, const int
         int64_t G = std::max<int64_t>(1, (p->n_cus + R / 2) / R);
         G = std::min<int64_t>(G, kMaxRangeBlocks);
         G = std::min<int64_t>(G, std::max<int64_t>(1, N / (int64_t(R) * waves * 256)));
-        const int64_t W = G * waves;
         const int64_t nblk = int64_t(R) * G;
         const int64_t per_die = R % kXcds == 0 ? R / kXcds : 0;  // consecutive ranges per die
         std::vector<int4> rec(size_t(nblk) * waves);
         std::vector<int4> list;
         list.reserve(size_t(ngrp));
         std::vector<std::pair<int32_t, int32_t>> grp;  // (length, camera) of the range's non-empty groups
+        std::vector<std::vector<int32_t>> mine(static_cast<size_t>(waves));  // per wavefront: its groups (indices into grp)
+        std::vector<int64_t> load(static_cast<size_t>(waves));
         for (int32_t r = 0; r < R; ++r) {
             grp.clear();
-            int64_t tot = 0;
             for (int32_t c = 0; c < z.nc; ++c) {
                 const int32_t len = go[size_t(c) * R + r + 1] - go[size_t(c) * R + r];
-                if (len > 0) {
-                    grp.emplace_back(len, c);
-                    tot += len;
-                }
+                if (len > 0) grp.emplace_back(len, c);
             }
-            // run w ends at the first group where the running count reaches (w+1)/W of the range
-            size_t gi = 0;
-            int64_t cum = 0;
-            for (int64_t w = 0; w < W; ++w) {
-                const size_t g0 = gi;
-                while (gi < grp.size() && (w == W - 1 || cum * W < (w + 1) * tot)) cum += grp[gi++].first;
-                std::stable_sort(grp.begin() + g0, grp.begin() + gi,
-                                 [](const std::pair<int32_t, int32_t>& x, const std::pair<int32_t, int32_t>& y) {
-                                     return x.first > y.first;
-                                 });
-                const int32_t begin = int32_t(list.size());
-                for (size_t q = g0; q < gi; ++q) {
-                    const int32_t c = grp[q].second;
-                    list.push_back(make_int4(c, go[size_t(c) * R + r], grp[q].first, cprob[size_t(c)]));
+            std::stable_sort(grp.begin(), grp.end(),
+                             [](const std::pair<int32_t, int32_t>& x, const std::pair<int32_t, int32_t>& y) {
+                                 return x.first > y.first;
+                             });
+            for (int64_t j = 0; j < G; ++j) {
+                // the workgroup's share: groups j, j + G, j + 2G, ... of the sorted list
+                for (auto& m : mine) m.clear();
+                std::fill(load.begin(), load.end(), 0);
+                for (size_t q0 = size_t(j); q0 < grp.size(); q0 += size_t(G) * kSets) {
+                    const int64_t steps = (grp[q0].first + kSetLanes - 1) / kSetLanes;
+                    const size_t w = size_t(std::min_element(load.begin(), load.end()) - load.begin());
+                    load[w] += steps;
+                    for (int k = 0; k < kSets; ++k) {
+                        const size_t q = q0 + size_t(k) * size_t(G);
+                        if (q < grp.size()) mine[w].push_back(int32_t(q));
+                    }
                 }
-                const int64_t j = w / waves;
                 const int64_t blk = per_die ? ((r % per_die) * G + j) * kXcds + r / per_die : int64_t(r) * G + j;
-                rec[size_t(blk) * waves + size_t(w % waves)] = make_int4(r, begin, int32_t(list.size()), 0);
+                for (int w = 0; w < waves; ++w) {
+                    const int32_t begin = int32_t(list.size());
+                    for (const int32_t q : mine[size_t(w)]) {
+                        const int32_t c = grp[size_t(q)].second;
+                        list.push_back(make_int4(c, go[size_t(c) * R + r], grp[size_t(q)].first, cprob[size_t(c)]));
+                    }
+                    rec[size_t(blk) * waves + size_t(w)] = make_int4(r, begin, int32_t(list.size()), 0);
+                }
             }
         }
         if (int64_t(list.size()) > ngrp) return fail(POBA_ERR_STATE);

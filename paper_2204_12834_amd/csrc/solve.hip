@@ -1230,10 +1230,10 @@ __global__ __launch_bounds__(NT) void k_cam_pass_pt(Buffers b, Sizes z, const TS
 // Camera pass over point records with the landmark vector staged in LDS,
 // one landmark range r per workgroup of NW wavefronts.  The workgroup copies
 // its range's slice of s into LDS (structure of arrays); each wavefront then
-// walks its list of (camera, r) groups (non-empty, sorted by length, longest
-// first) in windows of 64: lane k of a window holds group k's run in the
-// camera-major order and its camera data.  A window is taken in batches of
-// four groups; in a batch each set of sixteen lanes (one DPP row) serves one
+// walks its list of (camera, r) groups (non-empty; consecutive fours are the
+// batches that set-up dealt to it, longest first) in windows of 64: lane k of
+// a window holds group k's run in the camera-major order and its camera data.
+// A window is taken in batches of four groups; in a batch each set of sixteen lanes (one DPP row) serves one
 // group, sixteen consecutive observations per step (records from global
 // memory, s from LDS), each lane summing its terms; at the batch's last step
 // every set adds its sixteen lanes (DPP shifts within the row) and its last
@@ -1244,11 +1244,7 @@ __global__ __launch_bounds__(NT) void k_cam_pass_pt(Buffers b, Sizes z, const TS
 // while step t is added (a ring of three unrolled slots; lanes past their
 // group read position 0 with weight 0, so every load is unconditional).
 // Cameras of inactive or stopped problems contribute no group.
-// Lanes per group in a batch.  With groups of about 70 observations (the
-// city workload), sets of 16 take 13% fewer steps per wavefront than sets of
-// 8: fewer idle lanes in each batch's longest group.
-constexpr int kSetLanes = 16;
-constexpr int kSets = kWave / kSetLanes;  // groups per batch
+static_assert(kSets * kSetLanes == kWave, "a batch's sets fill the wavefront");
 constexpr int kRangeRing = 3;             // steps in flight (records of step t + 2 requested at step t)
 
 // f(integral_constant<int, k>) for k in the sequence, unrolled.
