@@ -349,14 +349,27 @@ __device__ __forceinline__ void segmented_scan(T* v, int lane, int seg_start) {
     }
 }
 
-// Butterfly sum over the wave (every lane gets the total).
-template <typename T, int K>
-__device__ __forceinline__ void wave_sum(T* v) {
+// Sum of K values over the wavefront into its last lane (DPP shifts within
+// rows of 16, then row broadcasts; the other lanes' results are not used).
+template <int K>
+__device__ __forceinline__ void wave_total_last(double* v) {
 #pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], d, kWave);
+    for (int k = 0; k < K; ++k) {
+        v[k] += dpp_masked<0x111, 0xf>(v[k]);
+        v[k] += dpp_masked<0x112, 0xf>(v[k]);
+        v[k] += dpp_masked<0x114, 0xf>(v[k]);
+        v[k] += dpp_masked<0x118, 0xf>(v[k]);
+        v[k] += dpp_masked<0x142, 0xa>(v[k]);
+        v[k] += dpp_masked<0x143, 0xc>(v[k]);
     }
+}
+
+// The value of x in lane l (l the same in every lane): a wave-uniform result.
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(u)), l));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(u >> 32)), l));
+    return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
 }
 
 // Error-free sum (Knuth TwoSum) for compensated float64 accumulation.

@@ -338,10 +338,10 @@ __device__ __forceinline__ void lm_tile_stream(const uint32_t* __restrict__ lo_c
 // kWavesPerBlock * K doubles.
 template <int K>
 __device__ __forceinline__ void block_sum(double* v, double* lds) {
-    wave_sum<double, K>(v);
+    wave_total_last<K>(v);
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int nw = blockDim.x / kWave;
-    if (lane == 0) {
+    if (lane == kWave - 1) {
 #pragma unroll
         for (int k = 0; k < K; ++k) lds[w * K + k] = v[k];
     }

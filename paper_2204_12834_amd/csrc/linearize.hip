@@ -63,21 +63,6 @@ __device__ __forceinline__ void gram_add(double* acc, const double* row, double 
     for (int i = 0; i < 9; ++i) acc[45 + i] = fma(row[i], r, acc[45 + i]);
 }
 
-// Sum of K values over the wavefront into its last lane (DPP shifts within
-// rows of 16, then row broadcasts; the other lanes' results are not used).
-template <int K>
-__device__ __forceinline__ void wave_total_last(double* v) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        v[k] += dpp_masked<0x111, 0xf>(v[k]);
-        v[k] += dpp_masked<0x112, 0xf>(v[k]);
-        v[k] += dpp_masked<0x114, 0xf>(v[k]);
-        v[k] += dpp_masked<0x118, 0xf>(v[k]);
-        v[k] += dpp_masked<0x142, 0xa>(v[k]);
-        v[k] += dpp_masked<0x143, 0xc>(v[k]);
-    }
-}
-
 // The piece's partial sums: acc (54), cost, non-finite flag.
 __device__ __forceinline__ void cam_piece_write(const Buffers& b, int32_t p, double* acc, double cost, double bad) {
     double tot[kGramEntries + 2];

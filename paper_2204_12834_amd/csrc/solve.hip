@@ -1201,8 +1201,13 @@ __global__ __launch_bounds__(NT) void k_cam_pass_pt(Buffers b, Sizes z, const TS
     double acc[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc[k] = double(accl[k]);
-    if constexpr (NT == kWave) wave_sum<double, 9>(acc);
-    else block_sum<9>(acc, lds);
+    if constexpr (NT == kWave) {
+        wave_total_last<9>(acc);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[k] = readlane_f64(acc[k], kWave - 1);
+    } else {
+        block_sum<9>(acc, lds);
+    }
     if (threadIdx.x == 0) {
         // rotation part: J_l(w)^T times the accumulated (P - t) x h
         const double w0 = rec[0], w1 = rec[1], w2 = rec[2], B = rec[10], E = rec[22];
@@ -1434,7 +1439,8 @@ __global__ __launch_bounds__(NW * kWave) void k_cam_pass_range(Buffers b, Sizes 
 
 // Camera finish after a range-staged pass (series mode), one wavefront per
 // camera: the camera's group sums over the landmark ranges (lane-strided in
-// range order, then a butterfly over the wave, bit-identical on every lane),
+// range order, then DPP shifts into the last lane, read back as wave-uniform
+// values),
 // the rotation part multiplied by J_l(w)^T, then v_c = U^-1 u_c, x_c += v_c,
 // the squared norms of v_c and x_c, and the folded camera data of v_c.
 // Cameras of inactive or stopped problems are left alone.
@@ -1472,7 +1478,9 @@ __global__ __launch_bounds__(kBlock) void k_cam_fin_range(Buffers b, Sizes z, in
         const PCtrl& q = b.pctl[prob];
         if (!q.active || q.stopped) return;
     }
-    wave_sum<double, 9>(a);
+    wave_total_last<9>(a);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) a[k] = readlane_f64(a[k], kWave - 1);
     double u[9];
     {
         // J_l(w)^T times the accumulated (P - t) x h
@@ -1503,8 +1511,8 @@ __global__ __launch_bounds__(kBlock) void k_cam_fin_range(Buffers b, Sizes z, in
     double vs[9], sv = 0.0, sx = 0.0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        vs[k] = __shfl(v, k, kWave);
-        const double xk = __shfl(xn, k, kWave);
+        vs[k] = readlane_f64(v, k);
+        const double xk = readlane_f64(xn, k);
         sv += vs[k] * vs[k];
         sx += xk * xk;
     }
