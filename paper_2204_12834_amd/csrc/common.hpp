@@ -364,12 +364,22 @@ __device__ __forceinline__ void wave_total_last(double* v) {
     }
 }
 
-// The value of x in lane l (l the same in every lane): a wave-uniform result.
+// The value of x in lane l (l the same in every lane): a wave-uniform result,
+// read without a trip through LDS.
 __device__ __forceinline__ double readlane_f64(double x, int l) {
     const uint64_t u = __builtin_bit_cast(uint64_t, x);
     const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(u)), l));
     const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(u >> 32)), l));
     return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T readlane(T x, int l) {
+    if constexpr (sizeof(T) == 8) {
+        return __builtin_bit_cast(T, readlane_f64(__builtin_bit_cast(double, x), l));
+    } else {
+        static_assert(sizeof(T) == 4, "4- or 8-byte values");
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+    }
 }
 
 // Error-free sum (Knuth TwoSum) for compensated float64 accumulation.

@@ -229,8 +229,8 @@ __device__ __forceinline__ void tile_landmarks(const uint32_t* __restrict__ lo_c
         const int last = min(end - base, kWave) - 1;
         if (w & kTailBit) tail(my_seg, LOOKUP == kLookupTail ? nel[my_seg] : l, v);
 #pragma unroll
-        for (int k = 0; k < K; ++k) carry[k] = __shfl(v[k], last, kWave);
-        if constexpr (LOOKUP != kLookupTail) l_open = __shfl(l, last, kWave);
+        for (int k = 0; k < K; ++k) carry[k] = readlane(v[k], last);
+        if constexpr (LOOKUP != kLookupTail) l_open = readlane(l, last);
         seg += __popcll(hm);
     }
 }
@@ -308,7 +308,7 @@ __device__ __forceinline__ void lm_tile_stream(const uint32_t* __restrict__ lo_c
         Loc nxt;
         Raw rn2;
         if (more) {
-            locate(base + kWave, rn, __shfl(cur.l, last, kWave), nxt);
+            locate(base + kWave, rn, readlane(cur.l, last), nxt);
             if (base + 2 * kWave < end) fetch(base + 2 * kWave, seg_next + int32_t(__popcll(nxt.hm)), rn2);
         }
         double v[K];
@@ -322,7 +322,7 @@ __device__ __forceinline__ void lm_tile_stream(const uint32_t* __restrict__ lo_c
         segmented_scan<double, K>(v, lane, seg_start);
         if (wc & kTailBit) tail(seg + int32_t(__popcll(hu)), cur.l, v);
 #pragma unroll
-        for (int k = 0; k < K; ++k) carry[k] = __shfl(v[k], last, kWave);
+        for (int k = 0; k < K; ++k) carry[k] = readlane(v[k], last);
         seg = seg_next;
         if (more) {
             rc = rn;
@@ -370,20 +370,35 @@ __device__ __forceinline__ void store_block_partial(const double* v, double* par
 
 // Single-block sum of the first K entries of n partial records (record q at
 // partials[q * stride]) in record order, with compensated (TwoSum)
-// per-thread accumulation; the totals are valid in thread 0.
+// per-thread accumulation; the totals are valid in thread 0.  Each thread
+// requests its next kSumAhead records before adding them (in the same order),
+// so their loads are in flight together instead of one round trip each.
+constexpr int kSumAhead = 8;
+
 template <int K>
 __device__ __forceinline__ void sum_partials(const double* partials, uint32_t n, double* out, double* lds,
                                              int stride = K) {
     double s[K], e[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) s[k] = e[k] = 0.0;
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    for (uint32_t i0 = threadIdx.x; i0 < n; i0 += kSumAhead * blockDim.x) {
+        double v[kSumAhead][K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double t, err;
-            two_sum(s[k], partials[size_t(i) * stride + k], t, err);
-            s[k] = t;
-            e[k] += err;
+        for (int u = 0; u < kSumAhead; ++u) {
+            const uint32_t i = i0 + uint32_t(u) * blockDim.x;
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[u][k] = i < n ? partials[size_t(i) * stride + k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSumAhead; ++u) {
+            if (i0 + uint32_t(u) * blockDim.x >= n) break;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                double t, err;
+                two_sum(s[k], v[u][k], t, err);
+                s[k] = t;
+                e[k] += err;
+            }
         }
     }
 #pragma unroll

@@ -388,7 +388,7 @@ __device__ __forceinline__ void lm_pass_range(const Buffers& b, const Sizes& z, 
         if (wc & kTailBit) tail.finish(my_seg[a], A[a], v);
         const int last = min(end - pos, kWave) - 1;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) carry[k] = __shfl(v[k], last, kWave);
+        for (int k = 0; k < 3; ++k) carry[k] = readlane(v[k], last);
         fetch(u, c + D);
     };
     // rounds of lcm(D, 2) chunks keep both rings aligned
@@ -1012,7 +1012,7 @@ __device__ __forceinline__ void lm_pass_stream_pt(const Buffers& b, const Sizes&
         }
         const int last = min(end - pos, kWave) - 1;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) carry[k] = __shfl(v[k], last, kWave);
+        for (int k = 0; k < 3; ++k) carry[k] = readlane(v[k], last);
         seg += __popcll(hm);
         fetch(u, c + kPtDepth);
     };
@@ -1349,17 +1349,27 @@ __global__ __launch_bounds__(NW * kWave) void k_cam_pass_range(Buffers b, Sizes 
         };
         int bi = 0, ii = -1;  // issue cursor (batch, step)
         advance(bi, ii);
+        // the issue batch's group of this lane's set: its run, fetched again
+        // only when the cursor enters the next batch
+        int32_t gs = 0, gl = 0;
+        auto issue_group = [&]() {
+            const int g = (bi < nbat ? bi : 0) * kSets + set;
+            gs = __shfl(start, g, kWave);
+            gl = __shfl(len, g, kWave);
+        };
+        issue_group();
         auto issue = [&](Slot& o) {
             const bool live = bi < nbat;
-            const int g = (live ? bi : 0) * kSets + set;
-            const int32_t gs = __shfl(start, g, kWave);
-            const int32_t gl = __shfl(len, g, kWave);
             const int32_t j = ii * kSetLanes + sl;
             o.valid = live && j < gl;
             const int32_t mem = o.valid ? gs + j : 0;
             o.seg = co_seg[mem];
             load_point<TP, TC>(b.J_co, z.npad, mem, o.P, o.sw);
-            if (live) advance(bi, ii);
+            if (live) {
+                const int b0 = bi;
+                advance(bi, ii);
+                if (bi != b0) issue_group();
+            }
         };
         auto gather = [&](Slot& o) {
             const int32_t l = o.seg - int32_t(seg0);
