@@ -610,50 +610,6 @@ __device__ __forceinline__ void load_compact_fold(const CompactFold& x, double* 
     }
 }
 
-// Back-substitution over point records with the camera step's compact fold
-// staged in LDS (where it fits).  One workgroup per compute unit; every
-// wavefront walks one contiguous range of tiles.
-constexpr int kBacksubLdsBlock = 1024;
-
-template <typename TJ>
-__global__ __launch_bounds__(kBacksubLdsBlock) void k_backsub_pt_lds(Buffers b, Sizes z, double* __restrict__ dxl,
-                                                                    const Ctrl* ctrl, int64_t per) {
-    extern __shared__ unsigned char lds_raw[];
-    if (!ctrl->active) return;
-    CompactFold* cams = reinterpret_cast<CompactFold*>(lds_raw);
-    stage_compact_fold(b.xq, b.lin_rec, z.nc, cams);
-    const int64_t t0 = (int64_t(blockIdx.x) * (kBacksubLdsBlock / kWave) + wave_in_block()) * per;
-    const int64_t t1 = min(t0 + per, z.ntiles);
-    for (int64_t tile = t0; tile < t1; ++tile) {
-        tile_landmarks<double, 3, kLookupLate>(
-            b.lo_cam, b.tile_start, b.seg_base, b.nel, z.nl, tile,
-            [&](int32_t i, bool valid, int32_t cam, int32_t, int32_t, double* v) {
-                v[0] = v[1] = v[2] = 0.0;
-                if (!valid) return;
-                double P[3], sw, c[24];
-                load_point<TJ, double>(b.J_lo, z.npad, i, P, sw);
-                load_compact_fold(cams[cam], c);
-                point_lm_term(P, sw, c, v);
-            },
-            [&](int32_t seg, int32_t lmk, const double* t) {
-                const int64_t l = lmk;
-                const PCtrl& q = b.pctl[b.lm_prob[l]];
-                if (!q.active) return;
-                double Vd[6], inv[6], rhs[3], y[3], dd[3];
-#pragma unroll
-                for (int k = 0; k < 6; ++k) Vd[k] = b.V[6 * l + k];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) dd[k] = b.Dl[3 * int64_t(seg) + k];
-                inv3_damped(Vd, q.lambda, dd, inv);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) rhs[k] = b.bl[3 * l + k] + t[k];
-                sym3_apply(inv, rhs, y);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) dxl[3 * l + k] = -y[k];
-            });
-    }
-}
-
 // Landmarks without observations get dx_l = -V^-1 b_l = 0.
 __global__ __launch_bounds__(kBlock) void k_zero_empty(Buffers b, Sizes z, double* dxl, const Ctrl* ctrl) {
     if (!ctrl->active) return;
@@ -938,14 +894,15 @@ __global__ __launch_bounds__(kBlock) void k_load_v(Buffers b, Sizes z, const dou
 // c + kPtAhead when chunk c starts; each request is consumed at least
 // kPtAhead chunks later, so with in-order completion no wait covers a load
 // issued in the last kPtAhead chunks.  fold_at(c, cd) gives the folded
-// data of camera c (from LDS or from global memory).
+// data of camera c (from LDS or from global memory); the tail (the series'
+// s = V^-1 t, or the back-substitution's step) fetches its data for the
+// segments ending in chunk c + kPtAhead and finishes each segment.
 constexpr int kPtDepth = 4;
 constexpr int kPtAhead = 2;
 
-template <typename TP, typename TC, typename TS, typename FoldAt>
+template <typename TP, typename TC, typename FoldAt, typename Tail>
 __device__ __forceinline__ void lm_pass_stream_pt(const Buffers& b, const Sizes& z, int64_t t0, int64_t t1,
-                                                  const FoldAt& fold_at, TS* __restrict__ sout) {
-    const TS* __restrict__ Vinv = reinterpret_cast<const TS*>(b.Vinv);
+                                                  const FoldAt& fold_at, const Tail& tail) {
     const uint32_t* __restrict__ lo_cam = b.lo_cam;
     const int lane = lane_id();
     const int32_t start = b.tile_start[t0];
@@ -955,7 +912,7 @@ __device__ __forceinline__ void lm_pass_stream_pt(const Buffers& b, const Sizes&
     const int32_t nch = (end - start + kWave - 1) / kWave;  // chunks of 64 positions
     uint32_t w[kPtDepth];
     TC P[kPtDepth][3], sw[kPtDepth];
-    TS A[kPtDepth][6];
+    typename Tail::Slot A[kPtDepth];
     // records of chunk c into slot u; every load is unconditional (lanes past
     // the end read the last position and are masked where the slot is used),
     // so a slot's registers are only ever written by its own loads
@@ -970,7 +927,7 @@ __device__ __forceinline__ void lm_pass_stream_pt(const Buffers& b, const Sizes&
         const uint32_t wu = flags(u, c);
         const uint64_t hm = ballot64(wu & kHeadBit);
         const int32_t my = seg_v + __popcll(hm & mask_upto(lane));
-        if (wu & kTailBit) load_vinv(Vinv, my, A[u]);
+        if (wu & kTailBit) tail.fetch(my, A[u]);
         seg_v += __popcll(hm);
     };
 #pragma unroll
@@ -1002,14 +959,7 @@ __device__ __forceinline__ void lm_pass_stream_pt(const Buffers& b, const Sizes&
         const uint64_t hu = hm & mask_upto(lane);
         const int seg_start = hu ? 63 - __builtin_clzll(hu) : 0;
         segmented_scan<TC, 3>(v, lane, seg_start);
-        if (wc & kTailBit) {
-            TC Ac[6], y[3];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) Ac[k] = TC(A[u][k]);
-            sym3_apply(Ac, v, y);
-            TS ys[3] = {TS(y[0]), TS(y[1]), TS(y[2])};
-            store_s(sout, seg + __popcll(hu), ys);
-        }
+        if (wc & kTailBit) tail.finish(seg + __popcll(hu), A[u], v);
         const int last = min(end - pos, kWave) - 1;
 #pragma unroll
         for (int k = 0; k < 3; ++k) carry[k] = readlane(v[k], last);
@@ -1048,8 +998,9 @@ __global__ __launch_bounds__(kPtBlock) void k_lm_pass_pt_lds(Buffers b, Sizes z,
     const int64_t wave = int64_t(blockIdx.x) * (kPtBlock / kWave) + wave_in_block();
     const int64_t t0 = wave * tiles_per_wave;
     if (t0 >= z.ntiles) return;
-    lm_pass_stream_pt<TP, TC, TS>(
-        b, z, t0, min(t0 + tiles_per_wave, z.ntiles), [&](int64_t c, TC* cd) { load_fold(cf, c, cd); }, sout);
+    lm_pass_stream_pt<TP, TC>(b, z, t0, min(t0 + tiles_per_wave, z.ntiles),
+                              [&](int64_t c, TC* cd) { load_fold(cf, c, cd); },
+                              SeriesTail<TS, TC>{reinterpret_cast<const TS*>(b.Vinv), sout});
 }
 
 // Float64 series with the compact fold in LDS (144 bytes per camera, where the
@@ -1068,9 +1019,27 @@ __global__ __launch_bounds__(kPtCompactBlock) void k_lm_pass_pt_compact(Buffers 
     const int64_t wave = int64_t(blockIdx.x) * (kPtCompactBlock / kWave) + wave_in_block();
     const int64_t t0 = wave * tiles_per_wave;
     if (t0 >= z.ntiles) return;
-    lm_pass_stream_pt<TP, double, double>(
-        b, z, t0, min(t0 + tiles_per_wave, z.ntiles),
-        [&](int64_t c, double* cd) { load_compact_fold(cams[c], cd); }, sout);
+    lm_pass_stream_pt<TP, double>(b, z, t0, min(t0 + tiles_per_wave, z.ntiles),
+                                  [&](int64_t c, double* cd) { load_compact_fold(cams[c], cd); },
+                                  SeriesTail<double, double>{reinterpret_cast<const double*>(b.Vinv), sout});
+}
+
+// Back-substitution over point records as the same stream: the camera
+// step's compact fold in LDS, dx_l = -(V^-1 b_l + V^-1 t) at each segment's
+// tail from the float64 V^-1 and V^-1 b_l of the solve's preparation
+// (BacksubTail), all in float64.
+template <typename TP>
+__global__ __launch_bounds__(kPtCompactBlock) void k_backsub_pt_stream(Buffers b, Sizes z, int64_t tiles_per_wave,
+                                                                       BacksubTail tail, const Ctrl* ctrl) {
+    extern __shared__ unsigned char lds_raw[];
+    if (BacksubTail::skip(ctrl)) return;
+    CompactFold* cams = reinterpret_cast<CompactFold*>(lds_raw);
+    stage_compact_fold(b.xq, b.lin_rec, z.nc, cams);
+    const int64_t wave = int64_t(blockIdx.x) * (kPtCompactBlock / kWave) + wave_in_block();
+    const int64_t t0 = wave * tiles_per_wave;
+    if (t0 >= z.ntiles) return;
+    lm_pass_stream_pt<TP, double>(b, z, t0, min(t0 + tiles_per_wave, z.ntiles),
+                                  [&](int64_t c, double* cd) { load_compact_fold(cams[c], cd); }, tail);
 }
 
 // Folded camera data gathered from global memory (L2-resident).
@@ -1082,8 +1051,9 @@ __global__ __launch_bounds__(kBlock) void k_lm_pass_pt(Buffers b, Sizes z, int64
     const int64_t t0 = wave * tiles_per_wave;
     if (t0 >= z.ntiles) return;
     const TS* __restrict__ fold = reinterpret_cast<const TS*>(b.vq);
-    lm_pass_stream_pt<TP, TC, TS>(
-        b, z, t0, min(t0 + tiles_per_wave, z.ntiles), [&](int64_t c, TC* cd) { load_fold(fold, c, cd); }, sout);
+    lm_pass_stream_pt<TP, TC>(b, z, t0, min(t0 + tiles_per_wave, z.ntiles),
+                              [&](int64_t c, TC* cd) { load_fold(fold, c, cd); },
+                              SeriesTail<TS, TC>{reinterpret_cast<const TS*>(b.Vinv), sout});
 }
 
 template <typename TP, typename TC, typename TS>
@@ -1651,12 +1621,13 @@ void solve_backsub(Problem* p, const Buffers& b, double* dx_cams, double* dx_lms
     if constexpr (PT) {
         hipLaunchKernelGGL(k_fold_x, g_cam, blk, 0, s, b, z, b.x, b.ctrl);
         const size_t lds = size_t(z.nc) * sizeof(CompactFold);
-        if (lds <= size_t(p->lds_max)) {
-            const int64_t waves = p->n_cus * (kBacksubLdsBlock / kWave);
+        if (p->lds_cam && lds <= size_t(p->lds_max)) {
+            // one block per compute unit; the tiles are split evenly over all wavefronts
+            const int64_t waves = p->n_cus * (kPtCompactBlock / kWave);
             const int64_t per = std::max<int64_t>(1, ceil_div(z.ntiles, waves));
-            const int64_t nblk = ceil_div(ceil_div(z.ntiles, per), kBacksubLdsBlock / kWave);
-            hipLaunchKernelGGL((k_backsub_pt_lds<TJ>), dim3(unsigned(nblk)), dim3(kBacksubLdsBlock), lds, s, b, z,
-                               dx_lms, b.ctrl, per);
+            const int64_t nblk = ceil_div(ceil_div(z.ntiles, per), kPtCompactBlock / kWave);
+            hipLaunchKernelGGL((k_backsub_pt_stream<TJ>), dim3(unsigned(nblk)), dim3(kPtCompactBlock), lds, s, b, z,
+                               per, BacksubTail{b.nel, b.vinv64, b.ybl, dx_lms}, b.ctrl);
         } else {
             hipLaunchKernelGGL((k_backsub_pt<TJ>), g_tiles, blk, 0, s, b, z, dx_lms, b.ctrl);
         }
