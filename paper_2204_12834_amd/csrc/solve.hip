@@ -83,8 +83,12 @@ __global__ __launch_bounds__(kBlock) void k_inv_cam(Buffers b, Sizes z, int damp
 }
 
 // V_lambda^-1 of every non-empty landmark in float64, stored in the landmark
-// storage type at the landmark's segment index.  The damping diagonal goes to
-// (or, when `frozen`, comes from) Dl at the same index.
+// storage type and in float64 at the landmark's segment index, and
+// y = V_lambda^-1 b_l (first half of b~) into the float64 view of s and into
+// ybl with a flag 1 (kept there for the back-substitution; flag 0 for the
+// landmarks of inactive problems, whose step the back-substitution leaves).
+// The damping diagonal goes to (or, when `frozen`, comes from) Dl at the same
+// index.
 template <typename TS>
 __global__ __launch_bounds__(kBlock) void k_inv_lm(Buffers b, int32_t nseg, int damping, int frozen,
                                                    const Ctrl* ctrl) {
@@ -93,10 +97,15 @@ __global__ __launch_bounds__(kBlock) void k_inv_lm(Buffers b, int32_t nseg, int 
     if (g >= nseg) return;
     const int64_t l = b.nel[g];
     PCtrl& q = b.pctl[b.lm_prob[l]];
-    if (!q.active) return;
-    double Vd[6], inv[6], dd[3];
+    if (!q.active) {
+        b.ybl[4 * int64_t(g) + 3] = 0.0;
+        return;
+    }
+    double Vd[6], inv[6], dd[3], bl[3], y[3];
 #pragma unroll
     for (int k = 0; k < 6; ++k) Vd[k] = b.V[6 * l + k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) bl[k] = b.bl[3 * l + k];
     if (frozen) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) dd[k] = b.Dl[3 * int64_t(g) + k];
@@ -114,35 +123,10 @@ __global__ __launch_bounds__(kBlock) void k_inv_lm(Buffers b, int32_t nseg, int 
     o64[1] = make_double2(inv[2], inv[3]);
     o64[2] = make_double2(inv[4], inv[5]);
     if (!ok) atomicOr(&q.status, POBA_ERR_NOT_SPD);
-}
-
-// y = V_lambda^-1 b_l in float64 (first half of b~) for every non-empty
-// landmark, into the float64 view of s at its segment index, and with a flag
-// 1 into ybl (kept there for the back-substitution; flag 0 for the
-// landmarks of inactive problems, whose step the back-substitution leaves).
-__global__ __launch_bounds__(kBlock) void k_rhs_lm(Buffers b, int32_t nseg, const Ctrl* ctrl) {
-    if (!ctrl->active) return;
-    const int32_t g = blockIdx.x * kBlock + threadIdx.x;
-    if (g >= nseg) return;
-    const int64_t l = b.nel[g];
-    const PCtrl& q = b.pctl[b.lm_prob[l]];
-    if (!q.active) {
-        b.ybl[4 * int64_t(g) + 3] = 0.0;
-        return;
-    }
-    double Vd[6], inv[6], bl[3], y[3], dd[3];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) Vd[k] = b.V[6 * l + k];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        bl[k] = b.bl[3 * l + k];
-        dd[k] = b.Dl[3 * int64_t(g) + k];
-    }
-    inv3_damped(Vd, q.lambda, dd, inv);
     sym3_apply(inv, bl, y);
-    double2* o = reinterpret_cast<double2*>(reinterpret_cast<double*>(b.s) + 4 * int64_t(g));
-    o[0] = make_double2(y[0], y[1]);
-    o[1] = make_double2(y[2], 0.0);
+    double2* so = reinterpret_cast<double2*>(reinterpret_cast<double*>(b.s) + 4 * int64_t(g));
+    so[0] = make_double2(y[0], y[1]);
+    so[1] = make_double2(y[2], 0.0);
     double2* yo = reinterpret_cast<double2*>(b.ybl + 4 * int64_t(g));
     yo[0] = make_double2(y[0], y[1]);
     yo[1] = make_double2(y[2], 1.0);
@@ -1560,10 +1544,6 @@ void solve_prepare(Problem* p, const Buffers& b, double eps, bool norms0, hipStr
         ProfScope pr(p, POBA_K_INVERSE, s);
         hipLaunchKernelGGL(k_inv_cam, g_cam, blk, 0, s, b, z, damping, frozen, b.ctrl);
         hipLaunchKernelGGL(k_inv_lm<TS>, g_seg, blk, 0, s, b, nseg, damping, frozen, b.ctrl);
-    }
-    {
-        ProfScope pr(p, POBA_K_OTHER, s);
-        hipLaunchKernelGGL(k_rhs_lm, g_seg, blk, 0, s, b, nseg, b.ctrl);
     }
     if (p->npieces > 0) {
         // the reduced right-hand side (not a series order)
